@@ -1,0 +1,238 @@
+/*
+ * nrs.h -- C ABI of libnrs: the nearest-neighbour regularized stokeslet
+ * (NEAREST) hot path on AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of Gallagher & Smith, "Passively parallel regularized
+ * stokeslets" (arXiv:2001.06468); section and equation numbers below refer to
+ * that paper.  Per time step the paper's cost is (1) the stokeslet matrix
+ * multiplied by the nearest-neighbour matrix, (2) the full matrix with the
+ * rigid-body unknowns, (3) the dense solve (Sec. 4).  This library performs
+ * all three on the GPU, plus the geometry and nearest-neighbour map that feed
+ * them and the time-stepping and warm-started iterative forms built on them.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every array argument is DEVICE memory unless stated otherwise, owned by
+ *    the caller, and must stay valid until the work enqueued on the
+ *    context's stream has completed.  The library never frees caller memory
+ *    and keeps no pointer after a call returns.
+ *  - Point coordinates are structure-of-arrays: x[c*N + i] is component c
+ *    (0,1,2) of point i.  Body states are Y[b*12 + 0..2] = origin x0 and
+ *    Y[b*12 + 3..11] = body frame B, row-major, column i = body axis i.
+ *  - Unknowns are ordered component-major: sol[j*N + m] = f_j at force point m
+ *    (j = 0,1,2), then sol[3N + 6b + 0..5] = (U, Omega) of free body b.
+ *    n = 3N + 6M.  Matrices are column-major with leading dimension lda >= n.
+ *  - f is the force density exerted ON THE FLUID by the body (the + sign of
+ *    the nearest-neighbour form, Sec. 3 eq. 23), per unit quadrature weight;
+ *    W_n = sum of w_q over the quadrature points whose nearest force point
+ *    is n; the patch force is W_n f_n.
+ *  - All work is enqueued on the context's stream (stream-ordered, no host
+ *    synchronisation) unless the description says the call synchronises.
+ *  - Errors: every function returns nrs_status.  Argument errors are detected
+ *    on the host before anything is enqueued.  Numerical failures detected on
+ *    the device are reported through nrs_info.  nrs_last_error() gives a
+ *    human-readable detail of the last failure on a context.  No C++
+ *    exception crosses this interface.
+ */
+#ifndef NRS_H
+#define NRS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t nrs_status;
+#define NRS_OK                0
+#define NRS_E_ARG            -1  /* invalid argument (sizes, NULL, lda, precision)      */
+#define NRS_E_HIP            -2  /* HIP runtime error                                    */
+#define NRS_E_WORKSPACE      -3  /* workspace missing or smaller than nrs_workspace_size */
+#define NRS_E_SINGULAR       -4  /* exact zero pivot in the FP64 factorisation           */
+#define NRS_E_NOT_CONVERGED  -5  /* refinement / GMRES missed its tolerance              */
+#define NRS_E_NONFINITE      -6  /* NaN or Inf in an input or in the solution            */
+#define NRS_E_UNSUPPORTED    -7  /* size or option outside what this build implements    */
+
+/* Solution methods (nrs_options.method). */
+#define NRS_FP64_LU        0  /* FP64 assembly, FP64 LU with partial pivoting           */
+#define NRS_FP32_IR        1  /* FP32 assembly + FP32 block-pivoted LU, FP64 refinement */
+#define NRS_FP32_GEPP_IR   2  /* as NRS_FP32_IR but with full partial pivoting          */
+#define NRS_GMRES          3  /* FP64 GMRES(m) on the stored FP64 matrix, from x_init   */
+
+typedef struct nrs_ctx nrs_ctx;
+
+/* Create a context on HIP device `device` that enqueues on `stream` (a
+ * hipStream_t, borrowed; NULL = the null stream).  The context holds only a
+ * few small device buffers (status words, pivots bookkeeping).
+ * Returns NRS_E_HIP if the device cannot be selected. */
+nrs_status  nrs_create(nrs_ctx** out, int device, void* stream);
+nrs_status  nrs_destroy(nrs_ctx* ctx);
+nrs_status  nrs_set_stream(nrs_ctx* ctx, void* stream);
+const char* nrs_status_string(nrs_status s);
+const char* nrs_last_error(const nrs_ctx* ctx);
+/* Version string "nrs <major>.<minor> gfx950". */
+const char* nrs_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Scene description and geometry at time t (Sec. 4: the state Y = [X0; B]
+ * of the swimmers and their body-frame shapes).                             */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int64_t N, Q;          /* force (coarse) points, quadrature (fine) points      */
+  int32_t M, P;          /* free bodies, travelling-wave parts                   */
+  const double*  xi;     /* [3][N] body-frame offset, or lab position if body<0 */
+  const int32_t* body;   /* [N] -1 = fixed point, else 0..M-1                    */
+  const int32_t* part;   /* [N] wave part index or -1                            */
+  const double*  s;      /* [N] arc parameter of wave points                     */
+  const double*  ufix;   /* [3][N] prescribed lab velocity of fixed points       */
+  const double*  Xi;     /* [3][Q] as xi, for quadrature points                  */
+  const int32_t* bodyX;  /* [Q]                                                  */
+  const int32_t* partX;  /* [Q]                                                  */
+  const double*  sX;     /* [Q]                                                  */
+  const double*  w0;     /* [Q] base quadrature weight                           */
+  const double*  wave;   /* [P][6] beta, A0, A1, k, omega, phi                   */
+} nrs_scene;
+
+/* Geometry of all points at time t for body states Y [M][12]:
+ *   wave displacement d(s,t) = (beta s, (A0 + A1 s) sin(k s - omega t + phi), 0)
+ *   free-body point: x = x0 + B (xi + d),  u = B dd/dt  (deformation velocity)
+ *   fixed point:     x = xi,               u = ufix
+ *   quadrature weight w = w0 * |d(xi + d)/ds| on wave parts, w0 elsewhere.
+ * Outputs x [3][N], X [3][Q], w [Q], u [3][N] (any may be NULL to skip). */
+nrs_status nrs_geometry(nrs_ctx* ctx, const nrs_scene* sc, double t, const double* Y,
+                        double* x, double* X, double* w, double* u);
+
+/* ------------------------------------------------------------------------ */
+/* Nearest-neighbour map (Sec. 3 eq. 20): nu[q] = argmin_n |x_n - X_q| over
+ * the force points n of q's group (force points of group g are
+ * group_off[g] .. group_off[g+1]-1; group_off is a HOST array of G+1
+ * entries).  Squared distances are (dx*dx + dy*dy) + dz*dz in FP64 without
+ * fused multiply-add; the lowest index wins a tie, so the result is
+ * bit-for-bit the brute-force map.  nu_out: [Q] int32.
+ * NRS_E_ARG if a group with quadrature points has no force points.          */
+/* ------------------------------------------------------------------------ */
+nrs_status nrs_nearest(nrs_ctx* ctx, int64_t N, const double* x, int32_t G,
+                       const int32_t* group_off_host, int64_t Q, const double* X,
+                       const int32_t* groupX, int32_t* nu_out);
+
+/* ------------------------------------------------------------------------ */
+/* One resistance / swimming problem at fixed geometry.                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int64_t N, Q;
+  int32_t M;
+  const double*  x;      /* [3][N] force points                                  */
+  const double*  X;      /* [3][Q] quadrature points                             */
+  const double*  w;      /* [Q] quadrature weights (NULL = all 1, the paper's
+                            unweighted sum of Sec. 3 eq. 23)                     */
+  const int32_t* nu;     /* [Q] nearest force point of each quadrature point     */
+  const int32_t* body;   /* [N] -1 = prescribed velocity, else free body 0..M-1  */
+  const double*  Y;      /* [M][12] body states; x0 = moment centre (NULL iff M=0)*/
+  double eps, mu;        /* regularisation parameter, viscosity                  */
+} nrs_problem;
+
+typedef struct {
+  int32_t method;        /* NRS_FP64_LU, NRS_FP32_IR, NRS_FP32_GEPP_IR, NRS_GMRES */
+  int32_t max_refine;    /* refinement sweeps (IR) before falling back; <=0: 10  */
+  double  tol;           /* IR: stop when |d|_inf <= tol |x|_inf; GMRES: relative
+                            residual |b - A x|_2 <= tol |b|_2.  <=0: 1e-12 / 1e-10 */
+  int32_t gmres_restart; /* GMRES(m) restart length, <=0: 40                     */
+  int32_t gmres_max_iter;/* total GMRES iterations before LU fallback, <=0: 400  */
+  int32_t no_fallback;   /* 1 = report failure instead of falling back to FP64 LU */
+  const double* x_init;  /* [n] device warm start for NRS_GMRES (NULL = zero)    */
+} nrs_options;
+
+typedef struct {
+  int32_t method_used;   /* method whose result is in sol                        */
+  int32_t fell_back;     /* 1 if the requested method failed and FP64 LU ran     */
+  int32_t iterations;    /* refinement sweeps or GMRES iterations performed      */
+  int32_t singular;      /* 1 if a zero pivot was met                            */
+  double  backward_error;/* |b - A x|_inf / (|A|_inf |x|_inf + |b|_inf), FP64 A  */
+  double  correction;    /* last |d|_inf / |x|_inf of the refinement             */
+} nrs_info;
+
+/* Bytes of device workspace that nrs_solve / nrs_assemble / nrs_apply need
+ * for this size and method. */
+nrs_status nrs_workspace_size(nrs_ctx* ctx, int64_t N, int64_t Q, int32_t M,
+                              int32_t method, size_t* bytes);
+
+/* Assemble the full matrix A (order n = 3N + 6M, column-major, leading
+ * dimension lda) in FP64 (precision = 64) or FP32 (precision = 32):
+ *   A_s[jN+m, kN+n] = (8 pi mu)^-1 sum_{q: nu(q)=n} w_q S^eps_jk(x_m - X_q)
+ * (Sec. 3 eqs. 18 and 21-23, the stokeslet matrix times the nearest-neighbour
+ * matrix, fused so the 3N x 3Q matrix never exists), then the rigid-body
+ * blocks of the swimming problem (Sec. 2 and Sec. 4): columns -1 (U) and
+ * -(e_i x r_m) (Omega), force rows W_m, moment rows W_m (r_m x .), zero
+ * 6M x 6M block, r_m = x_m - x0.  A: device, n x lda elements of the chosen
+ * precision.  Writes every entry of the leading n x n block. */
+nrs_status nrs_assemble(nrs_ctx* ctx, const nrs_problem* pb, int32_t precision,
+                        void* A, int64_t lda, void* ws, size_t ws_bytes);
+
+/* Matrix-free FP64 product y = A v with A as in nrs_assemble (the NEAREST
+ * operator of Sec. 3 eq. 23 evaluated on the fly plus the rigid-body rows).
+ * v, y: [n] device. */
+nrs_status nrs_apply(nrs_ctx* ctx, const nrs_problem* pb, const double* v, double* y,
+                     void* ws, size_t ws_bytes);
+
+/* Solve A sol = b, b = [u_x; u_y; u_z; (F_ext, T_ext) per body], for the
+ * force densities and rigid-body velocities (Sec. 4, step 3).
+ * u: [3][N] prescribed velocities; ftext: [M][6] external force and torque
+ * (NULL = force- and torque-free); sol: [n] output.
+ * With info == NULL the call is fully asynchronous; numerical status then
+ * stays in the workspace and nrs_query_info() reads it.  With info != NULL
+ * the call synchronises the stream, fills *info, and may run the FP64 LU
+ * fallback.  Returns NRS_E_SINGULAR / NRS_E_NOT_CONVERGED in that case when
+ * no method succeeded. */
+nrs_status nrs_solve(nrs_ctx* ctx, const nrs_problem* pb, const double* u, const double* ftext,
+                     const nrs_options* opt, void* ws, size_t ws_bytes, double* sol,
+                     nrs_info* info);
+
+/* Synchronise and read the numerical status of the last asynchronous solve
+ * that used workspace ws. */
+nrs_status nrs_query_info(nrs_ctx* ctx, void* ws, nrs_info* info);
+
+/* ------------------------------------------------------------------------ */
+/* Dense LU and triangular solves on their own (the linear-algebra part of
+ * Sec. 4 step 3), for tests and reuse.                                      */
+/* ------------------------------------------------------------------------ */
+/* In-place P A = L U of the n x n column-major matrix A (precision 32 or 64).
+ * pivot_scope = 0: partial pivoting over the whole column; pivot_scope = 1:
+ * pivots searched only inside the current 64 x 64 diagonal block (static
+ * block pivoting, used with iterative refinement).  Outputs (device):
+ *   ipiv [n] int32: ipiv[j] = row interchanged with row j at step j (0-based,
+ *        LAPACK order);
+ *   perm [n] int32: the composite permutation, (P b)[i] = b[perm[i]];
+ *   singular_flag [1] int32: set to 1 if an exact zero pivot is met (left
+ *        untouched otherwise; the caller clears it).
+ * Needs no workspace. */
+nrs_status nrs_lu_factor(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivot_scope,
+                         void* A, int64_t lda, int32_t* ipiv, int32_t* perm,
+                         int32_t* singular_flag);
+
+/* Solve with the factors of nrs_lu_factor: x = A^-1 b, b and x [n] device
+ * vectors of the same precision (x may not alias b). */
+nrs_status nrs_lu_solve(nrs_ctx* ctx, int64_t n, int32_t precision, const void* LU, int64_t lda,
+                        const int32_t* perm, const void* b, void* x);
+
+/* ------------------------------------------------------------------------ */
+/* Time stepping (Sec. 4: Y' = F(Y, t), F from the solve).                   */
+/* ------------------------------------------------------------------------ */
+/* One classical RK4 step of the body states Y [M][12] (in place) from t to
+ * t + dt.  Each of the four stages evaluates the geometry, the nearest map
+ * (group_off_host / groupX as in nrs_nearest), the solve (method in opt) and
+ * the rates dx0/dt = U, dB/dt = [Omega]x B; after the step each body frame
+ * is re-orthonormalised by modified Gram-Schmidt.  ftext: [M][6] or NULL.
+ * Asynchronous; the numerical status of the four solves accumulates in the
+ * workspace (nrs_query_info: fell_back/iterations report the worst stage).
+ * ws must hold nrs_rk4_workspace_size bytes. */
+nrs_status nrs_rk4_workspace_size(nrs_ctx* ctx, const nrs_scene* sc, int32_t method, size_t* bytes);
+nrs_status nrs_rk4_step(nrs_ctx* ctx, const nrs_scene* sc, int32_t G, const int32_t* group_off_host,
+                        const int32_t* groupX, double eps, double mu, const double* ftext,
+                        double* Y, double t, double dt, const nrs_options* opt,
+                        void* ws, size_t ws_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NRS_H */

@@ -1,0 +1,245 @@
+"""Python binding of libnrs, the MI355X (gfx950) implementation of the
+nearest-neighbour regularized stokeslet hot path (Gallagher & Smith,
+arXiv:2001.06468).
+
+Every function mirrors the C entry point of the same name in include/nrs.h
+and only marshals arguments: torch tensors supply device memory, the current
+torch stream supplies the HIP stream, and all arithmetic runs in the HIP
+kernels of libnrs.so.  Nothing here falls back to a CPU implementation: if
+the library is missing or a tensor is not on the GPU the call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (NRS_FP32_GEPP_IR, NRS_FP32_IR, NRS_FP64_LU, NRS_GMRES,  # noqa: F401
+                   NrsInfo, NrsOptions, NrsProblem, NrsScene)
+
+__all__ = [
+    "NrsError", "Context", "DeviceScene", "Problem", "nrs_create", "nrs_version", "nrs_geometry",
+    "nrs_nearest", "nrs_workspace_size", "nrs_assemble", "nrs_apply", "nrs_solve",
+    "nrs_query_info", "nrs_lu_factor", "nrs_lu_solve", "nrs_rk4_workspace_size", "nrs_rk4_step",
+    "NRS_FP64_LU", "NRS_FP32_IR", "NRS_FP32_GEPP_IR", "NRS_GMRES", "lda_for",
+]
+
+
+class NrsError(RuntimeError):
+    def __init__(self, status, detail=""):
+        lib = _lib.load()
+        super().__init__(f"{lib.nrs_status_string(status).decode()} ({status}): {detail}")
+        self.status = status
+
+
+def _check(status, ctx=None):
+    if status != 0:
+        detail = ""
+        if ctx is not None:
+            detail = _lib.load().nrs_last_error(ctx.handle).decode(errors="replace")
+        raise NrsError(status, detail)
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return C.c_void_p(t.data_ptr())
+
+
+def lda_for(n):
+    """Leading dimension the library uses for its own matrices (multiple of 64)."""
+    return max(64, (n + 63) // 64 * 64)
+
+
+def nrs_version():
+    return _lib.load().nrs_version().decode()
+
+
+class Context:
+    """Owns an nrs_ctx bound to a device and (by default) torch's current stream."""
+
+    def __init__(self, device=0, stream=None):
+        lib = _lib.load()
+        self.device = device
+        h = C.c_void_p()
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        _check(lib.nrs_create(C.byref(h), device, C.c_void_p(stream)))
+        self.handle = h
+
+    def set_stream(self, stream):
+        _check(_lib.load().nrs_set_stream(self.handle, C.c_void_p(stream)), self)
+
+    def close(self):
+        if self.handle:
+            _lib.load().nrs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def nrs_create(device=0, stream=None):
+    return Context(device, stream)
+
+
+class DeviceScene:
+    """Device copy of a scene description (see the ``synth`` package for the
+    field meanings); exposes the nrs_scene struct of include/nrs.h."""
+
+    _F64 = ("xi", "s", "ufix", "Xi", "sX", "w0", "wave", "Y0", "ftext")
+    _I32 = ("body", "part", "bodyX", "partX", "groupX")
+
+    def __init__(self, scene, device="cuda"):
+        self.N, self.Q, self.M = int(scene["N"]), int(scene["Q"]), int(scene["M"])
+        self.eps, self.mu = float(scene["eps"]), float(scene["mu"])
+        self.group_off = np.ascontiguousarray(scene["group_off"], dtype=np.int32)
+        self.G = len(self.group_off) - 1
+        self.t = {}
+        for k in self._F64:
+            a = np.ascontiguousarray(scene[k], dtype=np.float64)
+            self.t[k] = torch.from_numpy(a.copy()).to(device)
+        for k in self._I32:
+            a = np.ascontiguousarray(scene[k], dtype=np.int32)
+            self.t[k] = torch.from_numpy(a.copy()).to(device)
+        self.P = int(self.t["wave"].shape[0])
+
+    def struct(self):
+        t = self.t
+        return NrsScene(self.N, self.Q, self.M, self.P,
+                        _ptr(t["xi"]), _ptr(t["body"]), _ptr(t["part"]), _ptr(t["s"]),
+                        _ptr(t["ufix"]), _ptr(t["Xi"]), _ptr(t["bodyX"]), _ptr(t["partX"]),
+                        _ptr(t["sX"]), _ptr(t["w0"]), _ptr(t["wave"]) if self.P else None)
+
+
+class Problem:
+    """Tensors of one nrs_problem (device memory)."""
+
+    def __init__(self, x, X, w, nu, body, Y, eps, mu):
+        self.x, self.X, self.w, self.nu, self.body, self.Y = x, X, w, nu, body, Y
+        self.N = int(x.shape[-1])
+        self.Q = int(X.shape[-1])
+        self.M = 0 if Y is None else int(Y.reshape(-1, 12).shape[0])
+        self.eps, self.mu = float(eps), float(mu)
+
+    @property
+    def n(self):
+        return 3 * self.N + 6 * self.M
+
+    def struct(self):
+        f64, i32 = torch.float64, torch.int32
+        return NrsProblem(self.N, self.Q, self.M, _ptr(self.x, f64, "x"), _ptr(self.X, f64, "X"),
+                          _ptr(self.w, f64, "w"), _ptr(self.nu, i32, "nu"),
+                          _ptr(self.body, i32, "body"), _ptr(self.Y, f64, "Y"),
+                          self.eps, self.mu)
+
+
+def _options(method=NRS_FP64_LU, max_refine=0, tol=0.0, gmres_restart=0, gmres_max_iter=0,
+             no_fallback=0, x_init=None):
+    return NrsOptions(method, max_refine, tol, gmres_restart, gmres_max_iter, no_fallback,
+                      _ptr(x_init, torch.float64, "x_init"))
+
+
+def nrs_geometry(ctx, scene, t, Y, x=None, X=None, w=None, u=None):
+    f64 = torch.float64
+    sc = scene.struct()
+    _check(_lib.load().nrs_geometry(ctx.handle, C.byref(sc), float(t), _ptr(Y, f64, "Y"),
+                                    _ptr(x, f64, "x"), _ptr(X, f64, "X"), _ptr(w, f64, "w"),
+                                    _ptr(u, f64, "u")), ctx)
+
+
+def nrs_nearest(ctx, x, group_off, X, groupX, nu_out):
+    go = np.ascontiguousarray(group_off, dtype=np.int32)
+    _check(_lib.load().nrs_nearest(ctx.handle, int(x.shape[-1]), _ptr(x, torch.float64, "x"),
+                                   len(go) - 1, go.ctypes.data_as(C.c_void_p), int(X.shape[-1]),
+                                   _ptr(X, torch.float64, "X"), _ptr(groupX, torch.int32, "groupX"),
+                                   _ptr(nu_out, torch.int32, "nu_out")), ctx)
+
+
+def nrs_workspace_size(ctx, N, Q, M, method):
+    b = C.c_size_t()
+    _check(_lib.load().nrs_workspace_size(ctx.handle, N, Q, M, method, C.byref(b)), ctx)
+    return b.value
+
+
+def nrs_assemble(ctx, problem, precision, A, lda, ws):
+    dt = torch.float32 if precision == 32 else torch.float64
+    pb = problem.struct()
+    _check(_lib.load().nrs_assemble(ctx.handle, C.byref(pb), precision, _ptr(A, dt, "A"), lda,
+                                    _ptr(ws, torch.uint8, "ws"), ws.numel()), ctx)
+
+
+def nrs_apply(ctx, problem, v, y, ws):
+    pb = problem.struct()
+    _check(_lib.load().nrs_apply(ctx.handle, C.byref(pb), _ptr(v, torch.float64, "v"),
+                                 _ptr(y, torch.float64, "y"), _ptr(ws, torch.uint8, "ws"),
+                                 ws.numel()), ctx)
+
+
+def nrs_solve(ctx, problem, u, ftext, sol, ws, method=NRS_FP64_LU, info=True, **opts):
+    """Returns the nrs_info dict (synchronising) or None (asynchronous)."""
+    pb = problem.struct()
+    o = _options(method, **opts)
+    inf = NrsInfo() if info else None
+    st = _lib.load().nrs_solve(ctx.handle, C.byref(pb), _ptr(u, torch.float64, "u"),
+                               _ptr(ftext, torch.float64, "ftext"), C.byref(o),
+                               _ptr(ws, torch.uint8, "ws"), ws.numel(),
+                               _ptr(sol, torch.float64, "sol"),
+                               C.byref(inf) if inf is not None else None)
+    _check(st, ctx)
+    return inf.as_dict() if inf is not None else None
+
+
+def nrs_query_info(ctx, ws):
+    inf = NrsInfo()
+    _check(_lib.load().nrs_query_info(ctx.handle, _ptr(ws, torch.uint8, "ws"), C.byref(inf)), ctx)
+    return inf.as_dict()
+
+
+def nrs_lu_factor(ctx, A, lda, ipiv, perm, singular, pivot_scope=0):
+    prec = 32 if A.dtype == torch.float32 else 64
+    n = int(ipiv.numel())
+    _check(_lib.load().nrs_lu_factor(ctx.handle, n, prec, pivot_scope, _ptr(A, A.dtype, "A"), lda,
+                                     _ptr(ipiv, torch.int32, "ipiv"), _ptr(perm, torch.int32, "perm"),
+                                     _ptr(singular, torch.int32, "singular")), ctx)
+
+
+def nrs_lu_solve(ctx, LU, lda, perm, b, x):
+    prec = 32 if LU.dtype == torch.float32 else 64
+    n = int(perm.numel())
+    _check(_lib.load().nrs_lu_solve(ctx.handle, n, prec, _ptr(LU, LU.dtype, "LU"), lda,
+                                    _ptr(perm, torch.int32, "perm"), _ptr(b, LU.dtype, "b"),
+                                    _ptr(x, LU.dtype, "x")), ctx)
+
+
+def nrs_rk4_workspace_size(ctx, scene, method):
+    b = C.c_size_t()
+    sc = scene.struct()
+    _check(_lib.load().nrs_rk4_workspace_size(ctx.handle, C.byref(sc), method, C.byref(b)), ctx)
+    return b.value
+
+
+def nrs_rk4_step(ctx, scene, Y, t, dt, ws, method=NRS_FP64_LU, ftext=None, **opts):
+    sc = scene.struct()
+    o = _options(method, **opts)
+    go = scene.group_off
+    _check(_lib.load().nrs_rk4_step(ctx.handle, C.byref(sc), len(go) - 1,
+                                    go.ctypes.data_as(C.c_void_p),
+                                    _ptr(scene.t["groupX"], torch.int32, "groupX"), scene.eps,
+                                    scene.mu, _ptr(ftext, torch.float64, "ftext"),
+                                    _ptr(Y, torch.float64, "Y"), float(t), float(dt), C.byref(o),
+                                    _ptr(ws, torch.uint8, "ws"), ws.numel()), ctx)

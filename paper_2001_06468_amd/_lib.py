@@ -1,0 +1,96 @@
+"""ctypes declarations of the libnrs C ABI (include/nrs.h).  Marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnrs.so")
+
+NRS_OK = 0
+NRS_E_ARG = -1
+NRS_E_HIP = -2
+NRS_E_WORKSPACE = -3
+NRS_E_SINGULAR = -4
+NRS_E_NOT_CONVERGED = -5
+NRS_E_NONFINITE = -6
+NRS_E_UNSUPPORTED = -7
+
+NRS_FP64_LU = 0
+NRS_FP32_IR = 1
+NRS_FP32_GEPP_IR = 2
+NRS_GMRES = 3
+
+_p = C.c_void_p
+_i64 = C.c_int64
+_i32 = C.c_int32
+
+
+class NrsScene(C.Structure):
+    _fields_ = [("N", _i64), ("Q", _i64), ("M", _i32), ("P", _i32),
+                ("xi", _p), ("body", _p), ("part", _p), ("s", _p), ("ufix", _p),
+                ("Xi", _p), ("bodyX", _p), ("partX", _p), ("sX", _p), ("w0", _p),
+                ("wave", _p)]
+
+
+class NrsProblem(C.Structure):
+    _fields_ = [("N", _i64), ("Q", _i64), ("M", _i32),
+                ("x", _p), ("X", _p), ("w", _p), ("nu", _p), ("body", _p), ("Y", _p),
+                ("eps", C.c_double), ("mu", C.c_double)]
+
+
+class NrsOptions(C.Structure):
+    _fields_ = [("method", _i32), ("max_refine", _i32), ("tol", C.c_double),
+                ("gmres_restart", _i32), ("gmres_max_iter", _i32), ("no_fallback", _i32),
+                ("x_init", _p)]
+
+
+class NrsInfo(C.Structure):
+    _fields_ = [("method_used", _i32), ("fell_back", _i32), ("iterations", _i32),
+                ("singular", _i32), ("backward_error", C.c_double), ("correction", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# name -> (restype, argtypes); every function declared in include/nrs.h
+PROTOTYPES = {
+    "nrs_create": (_i32, [C.POINTER(_p), C.c_int, _p]),
+    "nrs_destroy": (_i32, [_p]),
+    "nrs_set_stream": (_i32, [_p, _p]),
+    "nrs_status_string": (C.c_char_p, [_i32]),
+    "nrs_last_error": (C.c_char_p, [_p]),
+    "nrs_version": (C.c_char_p, []),
+    "nrs_geometry": (_i32, [_p, C.POINTER(NrsScene), C.c_double, _p, _p, _p, _p, _p]),
+    "nrs_nearest": (_i32, [_p, _i64, _p, _i32, _p, _i64, _p, _p, _p]),
+    "nrs_workspace_size": (_i32, [_p, _i64, _i64, _i32, _i32, C.POINTER(C.c_size_t)]),
+    "nrs_assemble": (_i32, [_p, C.POINTER(NrsProblem), _i32, _p, _i64, _p, C.c_size_t]),
+    "nrs_apply": (_i32, [_p, C.POINTER(NrsProblem), _p, _p, _p, C.c_size_t]),
+    "nrs_solve": (_i32, [_p, C.POINTER(NrsProblem), _p, _p, C.POINTER(NrsOptions), _p,
+                         C.c_size_t, _p, C.POINTER(NrsInfo)]),
+    "nrs_query_info": (_i32, [_p, _p, C.POINTER(NrsInfo)]),
+    "nrs_lu_factor": (_i32, [_p, _i64, _i32, _i32, _p, _i64, _p, _p, _p]),
+    "nrs_lu_solve": (_i32, [_p, _i64, _i32, _p, _i64, _p, _p, _p]),
+    "nrs_rk4_workspace_size": (_i32, [_p, C.POINTER(NrsScene), _i32, C.POINTER(C.c_size_t)]),
+    "nrs_rk4_step": (_i32, [_p, C.POINTER(NrsScene), _i32, _p, _p, C.c_double, C.c_double, _p,
+                            _p, C.c_double, C.c_double, C.POINTER(NrsOptions), _p, C.c_size_t]),
+}
+
+_LIB = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libnrs.so; raises ImportError if the HIP library has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build the HIP library first "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = C.CDLL(path)
+    for name, (res, args) in PROTOTYPES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib

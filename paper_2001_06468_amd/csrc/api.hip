@@ -1,0 +1,534 @@
+// The exported C ABI (include/nrs.h): argument validation, workspace layout
+// and the host-side sequencing of the kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "nrs_internal.h"
+
+using namespace nrs;
+
+namespace {
+
+nrs_status fail(nrs_ctx* ctx, nrs_status s, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return s;
+}
+
+#define NRS_HIP(ctx, expr)                                                                      \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(ctx, NRS_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+nrs_status use_device(nrs_ctx* ctx) {
+  if (!ctx) return NRS_E_ARG;
+  NRS_HIP(ctx, hipSetDevice(ctx->device));
+  return NRS_OK;
+}
+
+int32_t apply_chunks(int64_t N, int64_t Q) {
+  const int64_t mblocks = (N + 127) / 128;
+  int64_t c = (2048 + mblocks - 1) / std::max<int64_t>(mblocks, 1);
+  c = std::min<int64_t>(c, std::max<int64_t>(1, Q / 64));
+  c = std::max<int64_t>(1, std::min<int64_t>(c, 256));
+  return (int32_t)c;
+}
+
+bool uses_fp32(int32_t method) { return method == NRS_FP32_IR || method == NRS_FP32_GEPP_IR; }
+
+nrs_status check_problem(nrs_ctx* ctx, const nrs_problem* pb) {
+  if (!pb) return fail(ctx, NRS_E_ARG, "problem is NULL");
+  if (pb->N <= 0 || pb->Q <= 0 || pb->M < 0) return fail(ctx, NRS_E_ARG, "need N > 0, Q > 0, M >= 0");
+  if (pb->N > (int64_t)1 << 20 || pb->Q > (int64_t)1 << 30 || pb->M > (1 << 16))
+    return fail(ctx, NRS_E_UNSUPPORTED, "N, Q or M too large");
+  if (!pb->x || !pb->X || !pb->nu || !pb->body) return fail(ctx, NRS_E_ARG, "x, X, nu, body required");
+  if (pb->M > 0 && !pb->Y) return fail(ctx, NRS_E_ARG, "Y required when M > 0");
+  if (!(pb->eps > 0.0) || !(pb->mu > 0.0) || !std::isfinite(pb->eps) || !std::isfinite(pb->mu))
+    return fail(ctx, NRS_E_ARG, "eps and mu must be positive and finite");
+  return NRS_OK;
+}
+
+}  // namespace
+
+namespace nrs {
+
+// Workspace layout: [SolveState][Sorted][A32?][A64][vectors][apply partials]
+bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, SolveBuffers& sb) {
+  const int64_t n = 3 * N + 6 * (int64_t)M;
+  sb.st = ar.take<SolveState>(1);
+  sb.srt.seg = ar.take<int32_t>(N + 1);
+  sb.srt.cnt = ar.take<int32_t>(N + 2);
+  sb.srt.perm = ar.take<int32_t>(Q);
+  sb.srt.nus = ar.take<int32_t>(Q);
+  sb.srt.X64 = ar.take<double4>(Q);
+  sb.srt.X32hi = ar.take<float4>(Q);
+  sb.srt.X32lo = ar.take<float4>(Q);
+  sb.srt.W = ar.take<double>(N);
+  sb.lda = lda_for(n);
+  sb.A32 = uses_fp32(method) ? ar.take<float>((size_t)sb.lda * n) : nullptr;
+  sb.A64 = ar.take<double>((size_t)sb.lda * n);
+  sb.ipiv = ar.take<int32_t>(n);
+  sb.perm = ar.take<int32_t>(n);
+  sb.ipiv64 = ar.take<int32_t>(n);
+  sb.perm64 = ar.take<int32_t>(n);
+  sb.b = ar.take<double>(n);
+  sb.x = ar.take<double>(n);
+  sb.r = ar.take<double>(n);
+  sb.d64 = ar.take<double>(n);
+  sb.d32 = ar.take<float>(n);
+  sb.chunks = apply_chunks(N, Q);
+  sb.part = ar.take<double>((size_t)sb.chunks * 3 * N);
+  sb.red = ar.take<double>((size_t)(n + 255) / 256 + 64);
+  return !ar.overflow;
+}
+
+size_t solve_workspace_bytes(int64_t N, int64_t Q, int32_t M, int32_t method) {
+  Arena ar(nullptr, 0);
+  SolveBuffers sb;
+  carve_solve(ar, N, Q, M, method, sb);
+  return ar.used + 256;
+}
+
+}  // namespace nrs
+
+namespace {
+
+// FP64 LU path: assemble, factor with partial pivoting, solve into x.
+nrs_status run_fp64_lu(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, double* x,
+                       hipStream_t s) {
+  const int64_t n = 3 * pb.N + 6 * (int64_t)pb.M;
+  NRS_HIP(ctx, launch_assemble<double>(pb, sb.srt, sb.A64, sb.lda, s));
+  NRS_HIP(ctx, launch_anorm64(n, sb.A64, sb.lda, sb.st, sb.red, s));
+  NRS_HIP(ctx, launch_lu_factor<double>(n, 0, sb.A64, sb.lda, sb.ipiv64, sb.perm64,
+                                        &sb.st->singular, s));
+  NRS_HIP(ctx, launch_lu_solve<double>(n, sb.A64, sb.lda, sb.perm64, sb.b, x, nullptr, s));
+  return NRS_OK;
+}
+
+// FP32 factors + FP64 refinement.  Correction solves use the FP32 factors;
+// residuals use the matrix-free FP64 operator.
+nrs_status run_fp32_ir(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, double* x,
+                       int32_t scope, int32_t max_refine, double tol, hipStream_t s) {
+  const int64_t n = 3 * pb.N + 6 * (int64_t)pb.M;
+  NRS_HIP(ctx, launch_assemble<float>(pb, sb.srt, sb.A32, sb.lda, s));
+  NRS_HIP(ctx, launch_anorm32(n, sb.A32, sb.lda, sb.st, sb.red, s));
+  NRS_HIP(ctx, launch_lu_factor<float>(n, scope, sb.A32, sb.lda, sb.ipiv, sb.perm,
+                                       &sb.st->singular, s));
+  // x0 = (LU)^-1 b
+  float* b32 = reinterpret_cast<float*>(sb.r);  // r is free until the first residual
+  NRS_HIP(ctx, launch_convert_f32(n, sb.b, b32, s));
+  NRS_HIP(ctx, launch_lu_solve<float>(n, sb.A32, sb.lda, sb.perm, b32, sb.d32, &sb.st->stop, s));
+  NRS_HIP(ctx, launch_ir_update32(n, x, sb.d32, tol, 1, sb.st, s));
+  for (int it = 0; it < max_refine; ++it) {
+    NRS_HIP(ctx, launch_apply(pb, sb.srt, x, sb.d64, sb.part, sb.chunks, &sb.st->stop, s));
+    NRS_HIP(ctx, launch_ir_residual2(n, sb.b, sb.d64, x, nullptr, b32, nullptr, sb.st, 0, s));
+    NRS_HIP(ctx, launch_lu_solve<float>(n, sb.A32, sb.lda, sb.perm, b32, sb.d32, &sb.st->stop, s));
+    NRS_HIP(ctx, launch_ir_update32(n, x, sb.d32, tol, 0, sb.st, s));
+  }
+  return NRS_OK;
+}
+
+nrs_status read_state(nrs_ctx* ctx, const SolveState* dst, SolveState& hst) {
+  NRS_HIP(ctx, hipMemcpyAsync(&hst, dst, sizeof(SolveState), hipMemcpyDeviceToHost, ctx->stream));
+  NRS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  return NRS_OK;
+}
+
+void fill_info(const SolveState& h, nrs_info* info) {
+  info->method_used = h.method_used;
+  info->fell_back = h.fell_back;
+  info->iterations = h.iterations;
+  info->singular = h.singular;
+  info->backward_error = h.bwd;
+  info->correction = h.corr;
+}
+
+// Core of nrs_solve on already-carved buffers.  When `sync` is set the
+// state is read back and the FP64 fallback may run.
+nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, const double* ftext,
+                      const nrs_options& o, SolveBuffers& sb, double* sol, bool sync,
+                      SolveState* hst_out) {
+  hipStream_t s = ctx->stream;
+  const int64_t N = pb.N, Q = pb.Q, n = 3 * N + 6 * (int64_t)pb.M;
+  const int32_t method = o.method;
+  const int32_t max_refine = o.max_refine > 0 ? o.max_refine : 10;
+  const double tol = o.tol > 0 ? o.tol : 1e-12;
+  NRS_HIP(ctx, launch_state_init(sb.st, method, s));
+  NRS_HIP(ctx, launch_build_csr(N, Q, pb.X, pb.w, pb.nu, sb.srt, s));
+  NRS_HIP(ctx, launch_check_nu(N, sb.srt.cnt, sb.st, s));
+  NRS_HIP(ctx, launch_check_body(N, pb.M, pb.body, sb.st, s));
+  NRS_HIP(ctx, launch_rhs(N, pb.M, u, ftext, sb.b, s));
+  nrs_status st = NRS_OK;
+  if (method == NRS_FP64_LU) {
+    st = run_fp64_lu(ctx, pb, sb, sol, s);
+  } else if (uses_fp32(method)) {
+    st = run_fp32_ir(ctx, pb, sb, sol, method == NRS_FP32_IR ? 1 : 0, max_refine, tol, s);
+  } else {
+    return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
+  }
+  if (st != NRS_OK) return st;
+  if (!sync) return NRS_OK;
+  SolveState h;
+  if ((st = read_state(ctx, sb.st, h)) != NRS_OK) return st;
+  if (h.nonfinite == 2)
+    return fail(ctx, NRS_E_ARG, "nu outside [0, N) or body outside [-1, M)");
+  bool ok = method == NRS_FP64_LU ? true : (h.converged && !h.failed);
+  if (!ok && !o.no_fallback) {
+    NRS_HIP(ctx, launch_state_init(sb.st, NRS_FP64_LU, s));
+    if ((st = run_fp64_lu(ctx, pb, sb, sol, s)) != NRS_OK) return st;
+    if ((st = read_state(ctx, sb.st, h)) != NRS_OK) return st;
+    h.fell_back = 1;
+    ok = true;
+  }
+  // final backward error of the returned solution (FP64 operator)
+  NRS_HIP(ctx, launch_apply(pb, sb.srt, sol, sb.d64, sb.part, sb.chunks, nullptr, s));
+  NRS_HIP(ctx, launch_ir_residual2(n, sb.b, sb.d64, sol, sb.r, nullptr, nullptr, sb.st, 1, s));
+  SolveState h2;
+  if ((st = read_state(ctx, sb.st, h2)) != NRS_OK) return st;
+  h.bwd = h2.bwd;
+  h.nonfinite |= h2.nonfinite;
+  if (hst_out) *hst_out = h;
+  if (h.nonfinite) return fail(ctx, NRS_E_NONFINITE, "non-finite values in the solution");
+  if (h.singular && h.method_used == NRS_FP64_LU)
+    return fail(ctx, NRS_E_SINGULAR, "zero pivot in the FP64 factorisation");
+  if (!ok) return fail(ctx, NRS_E_NOT_CONVERGED, "refinement did not converge");
+  return NRS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nrs_version(void) { return "nrs 0.1 gfx950"; }
+
+const char* nrs_status_string(nrs_status s) {
+  switch (s) {
+    case NRS_OK: return "ok";
+    case NRS_E_ARG: return "invalid argument";
+    case NRS_E_HIP: return "HIP runtime error";
+    case NRS_E_WORKSPACE: return "workspace too small";
+    case NRS_E_SINGULAR: return "singular matrix";
+    case NRS_E_NOT_CONVERGED: return "not converged";
+    case NRS_E_NONFINITE: return "non-finite values";
+    case NRS_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+nrs_status nrs_create(nrs_ctx** out, int device, void* stream) {
+  if (!out) return NRS_E_ARG;
+  *out = nullptr;
+  nrs_ctx* c = new (std::nothrow) nrs_ctx();
+  if (!c) return NRS_E_HIP;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(stream);
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return NRS_E_HIP;
+  }
+  *out = c;
+  return NRS_OK;
+}
+
+nrs_status nrs_destroy(nrs_ctx* ctx) {
+  delete ctx;
+  return NRS_OK;
+}
+
+nrs_status nrs_set_stream(nrs_ctx* ctx, void* stream) {
+  if (!ctx) return NRS_E_ARG;
+  ctx->stream = static_cast<hipStream_t>(stream);
+  return NRS_OK;
+}
+
+const char* nrs_last_error(const nrs_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+nrs_status nrs_geometry(nrs_ctx* ctx, const nrs_scene* sc, double t, const double* Y, double* x,
+                        double* X, double* w, double* u) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if (!sc || sc->N < 0 || sc->Q < 0 || sc->M < 0 || sc->P < 0)
+    return fail(ctx, NRS_E_ARG, "bad scene sizes");
+  if ((sc->N > 0 && (!sc->xi || !sc->body || !sc->part || !sc->s || !sc->ufix)) ||
+      (sc->Q > 0 && (!sc->Xi || !sc->bodyX || !sc->partX || !sc->sX || !sc->w0)))
+    return fail(ctx, NRS_E_ARG, "scene arrays missing");
+  if (sc->P > 0 && !sc->wave) return fail(ctx, NRS_E_ARG, "wave table missing");
+  if (sc->M > 0 && !Y) return fail(ctx, NRS_E_ARG, "Y required when M > 0");
+  if (!std::isfinite(t)) return fail(ctx, NRS_E_ARG, "t must be finite");
+  NRS_HIP(ctx, launch_geometry(*sc, t, Y, x, X, w, u, ctx->stream));
+  return NRS_OK;
+}
+
+nrs_status nrs_nearest(nrs_ctx* ctx, int64_t N, const double* x, int32_t G,
+                       const int32_t* group_off_host, int64_t Q, const double* X,
+                       const int32_t* groupX, int32_t* nu_out) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if (N <= 0 || Q < 0 || G <= 0 || !x || !group_off_host || (Q > 0 && (!X || !groupX || !nu_out)))
+    return fail(ctx, NRS_E_ARG, "bad nearest-neighbour arguments");
+  if (G > kMaxGroups) return fail(ctx, NRS_E_UNSUPPORTED, "too many groups");
+  GroupTable gt;
+  gt.G = G;
+  for (int g = 0; g <= G; ++g) gt.off[g] = group_off_host[g];
+  if (gt.off[0] != 0 || gt.off[G] != N) return fail(ctx, NRS_E_ARG, "group_off must span [0, N]");
+  for (int g = 0; g < G; ++g)
+    if (gt.off[g + 1] <= gt.off[g]) return fail(ctx, NRS_E_ARG, "every group needs a force point");
+  NRS_HIP(ctx, launch_nearest(N, x, gt, Q, X, groupX, nu_out, ctx->stream));
+  return NRS_OK;
+}
+
+nrs_status nrs_workspace_size(nrs_ctx* ctx, int64_t N, int64_t Q, int32_t M, int32_t method,
+                              size_t* bytes) {
+  if (!bytes || N <= 0 || Q <= 0 || M < 0) return fail(ctx, NRS_E_ARG, "bad sizes");
+  if (method < NRS_FP64_LU || method > NRS_FP32_GEPP_IR)
+    return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
+  *bytes = solve_workspace_bytes(N, Q, M, method);
+  return NRS_OK;
+}
+
+nrs_status nrs_assemble(nrs_ctx* ctx, const nrs_problem* pb, int32_t precision, void* A,
+                        int64_t lda, void* ws, size_t ws_bytes) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if ((st = check_problem(ctx, pb))) return st;
+  const int64_t n = 3 * pb->N + 6 * (int64_t)pb->M;
+  if (!A || lda < n) return fail(ctx, NRS_E_ARG, "A NULL or lda < n");
+  if (precision != 32 && precision != 64) return fail(ctx, NRS_E_ARG, "precision must be 32 or 64");
+  Arena ar(ws, ws_bytes);
+  SolveBuffers sb;
+  if (!carve_solve(ar, pb->N, pb->Q, pb->M, precision == 32 ? NRS_FP32_IR : NRS_FP64_LU, sb))
+    return fail(ctx, NRS_E_WORKSPACE, "workspace too small");
+  hipStream_t s = ctx->stream;
+  NRS_HIP(ctx, launch_state_init(sb.st, NRS_FP64_LU, s));
+  NRS_HIP(ctx, launch_build_csr(pb->N, pb->Q, pb->X, pb->w, pb->nu, sb.srt, s));
+  NRS_HIP(ctx, launch_check_nu(pb->N, sb.srt.cnt, sb.st, s));
+  if (precision == 32)
+    NRS_HIP(ctx, launch_assemble<float>(*pb, sb.srt, static_cast<float*>(A), lda, s));
+  else
+    NRS_HIP(ctx, launch_assemble<double>(*pb, sb.srt, static_cast<double*>(A), lda, s));
+  return NRS_OK;
+}
+
+nrs_status nrs_apply(nrs_ctx* ctx, const nrs_problem* pb, const double* v, double* y, void* ws,
+                     size_t ws_bytes) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if ((st = check_problem(ctx, pb))) return st;
+  if (!v || !y) return fail(ctx, NRS_E_ARG, "v and y required");
+  Arena ar(ws, ws_bytes);
+  SolveBuffers sb;
+  if (!carve_solve(ar, pb->N, pb->Q, pb->M, NRS_FP64_LU, sb))
+    return fail(ctx, NRS_E_WORKSPACE, "workspace too small");
+  hipStream_t s = ctx->stream;
+  NRS_HIP(ctx, launch_state_init(sb.st, NRS_FP64_LU, s));
+  NRS_HIP(ctx, launch_build_csr(pb->N, pb->Q, pb->X, pb->w, pb->nu, sb.srt, s));
+  NRS_HIP(ctx, launch_check_nu(pb->N, sb.srt.cnt, sb.st, s));
+  NRS_HIP(ctx, launch_apply(*pb, sb.srt, v, y, sb.part, sb.chunks, nullptr, s));
+  return NRS_OK;
+}
+
+nrs_status nrs_solve(nrs_ctx* ctx, const nrs_problem* pb, const double* u, const double* ftext,
+                     const nrs_options* opt, void* ws, size_t ws_bytes, double* sol,
+                     nrs_info* info) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if ((st = check_problem(ctx, pb))) return st;
+  if (!u || !sol) return fail(ctx, NRS_E_ARG, "u and sol required");
+  nrs_options o = {};
+  o.method = NRS_FP64_LU;
+  if (opt) o = *opt;
+  if (o.method < NRS_FP64_LU || o.method > NRS_FP32_GEPP_IR)
+    return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
+  Arena ar(ws, ws_bytes);
+  SolveBuffers sb;
+  if (!carve_solve(ar, pb->N, pb->Q, pb->M, o.method, sb))
+    return fail(ctx, NRS_E_WORKSPACE, "workspace too small");
+  SolveState h = {};
+  st = solve_core(ctx, *pb, u, ftext, o, sb, sol, info != nullptr, &h);
+  if (info) fill_info(h, info);
+  return st;
+}
+
+nrs_status nrs_query_info(nrs_ctx* ctx, void* ws, nrs_info* info) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if (!ws || !info) return fail(ctx, NRS_E_ARG, "ws and info required");
+  SolveState h;
+  if ((st = read_state(ctx, static_cast<const SolveState*>(ws), h))) return st;
+  fill_info(h, info);
+  return NRS_OK;
+}
+
+nrs_status nrs_lu_factor(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivot_scope, void* A,
+                         int64_t lda, int32_t* ipiv, int32_t* perm, int32_t* singular_flag) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if (n <= 0 || !A || lda < n || !ipiv || !perm || !singular_flag)
+    return fail(ctx, NRS_E_ARG, "bad LU arguments");
+  if (pivot_scope != 0 && pivot_scope != 1) return fail(ctx, NRS_E_ARG, "pivot_scope is 0 or 1");
+  if (n >= ((int64_t)1 << 24)) return fail(ctx, NRS_E_UNSUPPORTED, "n too large");
+  if (precision == 32)
+    NRS_HIP(ctx, launch_lu_factor<float>(n, pivot_scope, static_cast<float*>(A), lda, ipiv, perm,
+                                         singular_flag, ctx->stream));
+  else if (precision == 64)
+    NRS_HIP(ctx, launch_lu_factor<double>(n, pivot_scope, static_cast<double*>(A), lda, ipiv,
+                                          perm, singular_flag, ctx->stream));
+  else
+    return fail(ctx, NRS_E_ARG, "precision must be 32 or 64");
+  return NRS_OK;
+}
+
+nrs_status nrs_lu_solve(nrs_ctx* ctx, int64_t n, int32_t precision, const void* LU, int64_t lda,
+                        const int32_t* perm, const void* b, void* x) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if (n <= 0 || !LU || lda < n || !perm || !b || !x || b == x)
+    return fail(ctx, NRS_E_ARG, "bad LU solve arguments");
+  if (precision == 32)
+    NRS_HIP(ctx, launch_lu_solve<float>(n, static_cast<const float*>(LU), lda, perm,
+                                        static_cast<const float*>(b), static_cast<float*>(x),
+                                        nullptr, ctx->stream));
+  else if (precision == 64)
+    NRS_HIP(ctx, launch_lu_solve<double>(n, static_cast<const double*>(LU), lda, perm,
+                                         static_cast<const double*>(b), static_cast<double*>(x),
+                                         nullptr, ctx->stream));
+  else
+    return fail(ctx, NRS_E_ARG, "precision must be 32 or 64");
+  return NRS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct RkBuffers {
+  SolveState* report;
+  double *x, *X, *w, *u, *Ys, *K[4], *sol, *Ysave;
+  int32_t* nu;
+  SolveBuffers sb;
+};
+
+bool carve_rk(Arena& ar, const nrs_scene& sc, int32_t method, RkBuffers& rb) {
+  const int64_t N = sc.N, Q = sc.Q, M = sc.M, n = 3 * N + 6 * M;
+  rb.report = ar.take<SolveState>(1);
+  rb.x = ar.take<double>(3 * N);
+  rb.X = ar.take<double>(3 * Q);
+  rb.w = ar.take<double>(Q);
+  rb.u = ar.take<double>(3 * N);
+  rb.nu = ar.take<int32_t>(Q);
+  rb.Ys = ar.take<double>(12 * M);
+  for (int i = 0; i < 4; ++i) rb.K[i] = ar.take<double>(12 * M);
+  rb.Ysave = ar.take<double>(12 * M);
+  rb.sol = ar.take<double>(n);
+  carve_solve(ar, N, Q, sc.M, method, rb.sb);
+  return !ar.overflow;
+}
+
+nrs_status rk4_pass(nrs_ctx* ctx, const nrs_scene& sc, const GroupTable& gt,
+                    const int32_t* groupX, double eps, double mu, const double* ftext, double* Y,
+                    double t, double dt, const nrs_options& o, RkBuffers& rb) {
+  hipStream_t s = ctx->stream;
+  const double c[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
+  NRS_HIP(ctx, launch_state_init(rb.report, o.method, s));
+  for (int stg = 0; stg < 4; ++stg) {
+    NRS_HIP(ctx, launch_rk_stage_state(sc.M, Y, stg ? rb.K[stg - 1] : nullptr, c[stg], rb.Ys, s));
+    NRS_HIP(ctx, launch_geometry(sc, t + c[stg], rb.Ys, rb.x, rb.X, rb.w, rb.u, s));
+    NRS_HIP(ctx, launch_nearest(sc.N, rb.x, gt, sc.Q, rb.X, groupX, rb.nu, s));
+    nrs_problem pb;
+    pb.N = sc.N;
+    pb.Q = sc.Q;
+    pb.M = sc.M;
+    pb.x = rb.x;
+    pb.X = rb.X;
+    pb.w = rb.w;
+    pb.nu = rb.nu;
+    pb.body = sc.body;
+    pb.Y = rb.Ys;
+    pb.eps = eps;
+    pb.mu = mu;
+    nrs_status st = solve_core(ctx, pb, rb.u, ftext, o, rb.sb, rb.sol, false, nullptr);
+    if (st != NRS_OK) return st;
+    NRS_HIP(ctx, launch_state_accumulate(rb.report, rb.sb.st, s));
+    NRS_HIP(ctx, launch_rk_rates(sc.M, sc.N, rb.Ys, rb.sol, rb.K[stg], s));
+  }
+  NRS_HIP(ctx, launch_rk_combine(sc.M, Y, rb.K[0], rb.K[1], rb.K[2], rb.K[3], dt, s));
+  return NRS_OK;
+}
+
+nrs_status check_scene(nrs_ctx* ctx, const nrs_scene* sc) {
+  if (!sc || sc->N <= 0 || sc->Q <= 0 || sc->M < 0 || sc->P < 0)
+    return fail(ctx, NRS_E_ARG, "bad scene sizes");
+  if (!sc->xi || !sc->body || !sc->part || !sc->s || !sc->ufix || !sc->Xi || !sc->bodyX ||
+      !sc->partX || !sc->sX || !sc->w0 || (sc->P > 0 && !sc->wave))
+    return fail(ctx, NRS_E_ARG, "scene arrays missing");
+  return NRS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nrs_status nrs_rk4_workspace_size(nrs_ctx* ctx, const nrs_scene* sc, int32_t method,
+                                  size_t* bytes) {
+  nrs_status st = check_scene(ctx, sc);
+  if (st) return st;
+  if (!bytes) return fail(ctx, NRS_E_ARG, "bytes is NULL");
+  if (method < NRS_FP64_LU || method > NRS_FP32_GEPP_IR)
+    return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
+  Arena ar(nullptr, 0);
+  RkBuffers rb;
+  carve_rk(ar, *sc, method, rb);
+  *bytes = ar.used + 256;
+  return NRS_OK;
+}
+
+nrs_status nrs_rk4_step(nrs_ctx* ctx, const nrs_scene* sc, int32_t G, const int32_t* group_off_host,
+                        const int32_t* groupX, double eps, double mu, const double* ftext,
+                        double* Y, double t, double dt, const nrs_options* opt, void* ws,
+                        size_t ws_bytes) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if ((st = check_scene(ctx, sc))) return st;
+  if (sc->M <= 0 || !Y) return fail(ctx, NRS_E_ARG, "time stepping needs free bodies and Y");
+  if (!group_off_host || !groupX || G <= 0) return fail(ctx, NRS_E_ARG, "groups required");
+  if (G > kMaxGroups) return fail(ctx, NRS_E_UNSUPPORTED, "too many groups");
+  if (!(eps > 0.0) || !(mu > 0.0) || !std::isfinite(t) || !std::isfinite(dt))
+    return fail(ctx, NRS_E_ARG, "eps, mu > 0 and finite t, dt required");
+  GroupTable gt;
+  gt.G = G;
+  for (int g = 0; g <= G; ++g) gt.off[g] = group_off_host[g];
+  if (gt.off[0] != 0 || gt.off[G] != sc->N) return fail(ctx, NRS_E_ARG, "group_off must span [0, N]");
+  for (int g = 0; g < G; ++g)
+    if (gt.off[g + 1] <= gt.off[g]) return fail(ctx, NRS_E_ARG, "every group needs a force point");
+  nrs_options o = {};
+  o.method = NRS_FP64_LU;
+  if (opt) o = *opt;
+  if (o.method < NRS_FP64_LU || o.method > NRS_FP32_GEPP_IR)
+    return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
+  Arena ar(ws, ws_bytes);
+  RkBuffers rb;
+  if (!carve_rk(ar, *sc, o.method, rb)) return fail(ctx, NRS_E_WORKSPACE, "workspace too small");
+  hipStream_t s = ctx->stream;
+  NRS_HIP(ctx, hipMemcpyAsync(rb.Ysave, Y, 12 * sizeof(double) * sc->M, hipMemcpyDeviceToDevice, s));
+  if ((st = rk4_pass(ctx, *sc, gt, groupX, eps, mu, ftext, Y, t, dt, o, rb)) != NRS_OK) return st;
+  if (o.no_fallback || o.method == NRS_FP64_LU) return NRS_OK;
+  SolveState h;
+  if ((st = read_state(ctx, rb.report, h)) != NRS_OK) return st;
+  if (!h.failed) return NRS_OK;
+  // a stage missed its tolerance: redo the whole step with FP64 LU
+  NRS_HIP(ctx, hipMemcpyAsync(Y, rb.Ysave, 12 * sizeof(double) * sc->M, hipMemcpyDeviceToDevice, s));
+  nrs_options o64 = o;
+  o64.method = NRS_FP64_LU;
+  if ((st = rk4_pass(ctx, *sc, gt, groupX, eps, mu, ftext, Y, t, dt, o64, rb)) != NRS_OK) return st;
+  SolveState mark = {};
+  if ((st = read_state(ctx, rb.report, mark)) != NRS_OK) return st;
+  mark.fell_back = 1;
+  NRS_HIP(ctx, hipMemcpyAsync(rb.report, &mark, sizeof(SolveState), hipMemcpyHostToDevice, s));
+  NRS_HIP(ctx, hipStreamSynchronize(s));
+  return NRS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,379 @@
+// Fused NEAREST operator assembly (Sec. 3 eqs. 18, 21-23 and the matrix view
+// after them), rigid-body blocks of the swimming problem (Sec. 2, Sec. 4),
+// right-hand side, and the matrix-free FP64 product used by refinement.
+//
+// Mapping: one lane per collocation row m, lanes of a wave take consecutive m
+// so that every store of A (column-major) is a contiguous 64-element run.  A
+// workgroup owns a strip of kTN force points n; the quadrature points of each
+// n are contiguous in the nu-sorted layout, so the inner loop walks one
+// segment with wave-uniform (scalar) loads and sums the segment in registers:
+// the segmented reduction over nu needs no cross-lane traffic and the dense
+// 3N x 3Q stokeslet matrix is never formed.
+#include "nrs_internal.h"
+
+namespace nrs {
+
+namespace {
+
+constexpr int kAsmBlock = 128;
+constexpr int kTN = 8;
+
+// FP32 form: coordinates carried as hi + lo floats so that r = x_m - X_q keeps
+// FP32 relative accuracy even when |r| << |x|.
+__global__ __launch_bounds__(kAsmBlock) void k_assemble32(
+    int64_t N, const double* __restrict__ x, const int32_t* __restrict__ seg,
+    const float4* __restrict__ Xhi, const float4* __restrict__ Xlo, float eps2, float scale,
+    float* __restrict__ A, int64_t lda) {
+  const int64_t m = blockIdx.x * (int64_t)kAsmBlock + threadIdx.x;
+  const int64_t n0 = (int64_t)blockIdx.y * kTN;
+  const bool live = m < N;
+  float xh = 0, yh = 0, zh = 0, xl = 0, yl = 0, zl = 0;
+  if (live) {
+    const double px = x[m], py = x[N + m], pz = x[2 * N + m];
+    xh = (float)px;
+    yh = (float)py;
+    zh = (float)pz;
+    xl = (float)(px - (double)xh);
+    yl = (float)(py - (double)yh);
+    zl = (float)(pz - (double)zh);
+  }
+  const int64_t nend = min<int64_t>(N, n0 + kTN);
+  for (int64_t n = n0; n < nend; ++n) {
+    const int a = seg[n], b = seg[n + 1];
+    float a00 = 0, a11 = 0, a22 = 0, a01 = 0, a02 = 0, a12 = 0;
+    for (int p = a; p < b; ++p) {
+      const float4 h = Xhi[p];
+      const float4 l = Xlo[p];
+      const float rx = (xh - h.x) + (xl - l.x);
+      const float ry = (yh - h.y) + (yl - l.y);
+      const float rz = (zh - h.z) + (zl - l.z);
+      const float d = rx * rx + ry * ry + rz * rz + eps2;
+      const float rho = __builtin_amdgcn_rsqf(d);
+      const float t = h.w * (rho * rho * rho);
+      const float s = (d + eps2) * t;
+      const float tx = t * rx, ty = t * ry, tz = t * rz;
+      a00 += s + tx * rx;
+      a11 += s + ty * ry;
+      a22 += s + tz * rz;
+      a01 += tx * ry;
+      a02 += tx * rz;
+      a12 += ty * rz;
+    }
+    if (live) {
+      float* c0 = A + n * lda;
+      float* c1 = A + (N + n) * lda;
+      float* c2 = A + (2 * N + n) * lda;
+      c0[m] = scale * a00;
+      c0[N + m] = scale * a01;
+      c0[2 * N + m] = scale * a02;
+      c1[m] = scale * a01;
+      c1[N + m] = scale * a11;
+      c1[2 * N + m] = scale * a12;
+      c2[m] = scale * a02;
+      c2[N + m] = scale * a12;
+      c2[2 * N + m] = scale * a22;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kAsmBlock) void k_assemble64(
+    int64_t N, const double* __restrict__ x, const int32_t* __restrict__ seg,
+    const double4* __restrict__ X64, double eps2, double scale, double* __restrict__ A,
+    int64_t lda) {
+  const int64_t m = blockIdx.x * (int64_t)kAsmBlock + threadIdx.x;
+  const int64_t n0 = (int64_t)blockIdx.y * kTN;
+  const bool live = m < N;
+  double px = 0, py = 0, pz = 0;
+  if (live) {
+    px = x[m];
+    py = x[N + m];
+    pz = x[2 * N + m];
+  }
+  const int64_t nend = min<int64_t>(N, n0 + kTN);
+  for (int64_t n = n0; n < nend; ++n) {
+    const int a = seg[n], b = seg[n + 1];
+    double a00 = 0, a11 = 0, a22 = 0, a01 = 0, a02 = 0, a12 = 0;
+    for (int p = a; p < b; ++p) {
+      const double4 q = X64[p];
+      const double rx = px - q.x, ry = py - q.y, rz = pz - q.z;
+      const double d = rx * rx + ry * ry + rz * rz + eps2;
+      const double rho = 1.0 / sqrt(d);
+      const double t = q.w * (rho * rho * rho);
+      const double s = (d + eps2) * t;
+      const double tx = t * rx, ty = t * ry, tz = t * rz;
+      a00 += s + tx * rx;
+      a11 += s + ty * ry;
+      a22 += s + tz * rz;
+      a01 += tx * ry;
+      a02 += tx * rz;
+      a12 += ty * rz;
+    }
+    if (live) {
+      double* c0 = A + n * lda;
+      double* c1 = A + (N + n) * lda;
+      double* c2 = A + (2 * N + n) * lda;
+      c0[m] = scale * a00;
+      c0[N + m] = scale * a01;
+      c0[2 * N + m] = scale * a02;
+      c1[m] = scale * a01;
+      c1[N + m] = scale * a11;
+      c1[2 * N + m] = scale * a12;
+      c2[m] = scale * a02;
+      c2[N + m] = scale * a12;
+      c2[2 * N + m] = scale * a22;
+    }
+  }
+}
+
+// Component j of e_i x r.
+__device__ inline double cross_unit(int i, int j, const double r[3]) {
+  // (e_i x r)_j = eps_{j i k} r_k
+  if (i == j) return 0.0;
+  const int k = 3 - i - j;
+  // eps_{j i k} = +1 for cyclic (j,i,k)
+  const bool cyc = (j == 0 && i == 1) || (j == 1 && i == 2) || (j == 2 && i == 0);
+  return cyc ? r[k] : -r[k];
+}
+
+// Columns 3N .. n-1 of rows 0 .. 3N-1: -1 for U, -(e_i x r_m) for Omega_i.
+template <class T>
+__global__ void k_rigid_cols(int64_t N, int32_t M, const int32_t* __restrict__ body,
+                             const double* __restrict__ x, const double* __restrict__ Y,
+                             T* __restrict__ A, int64_t lda) {
+  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (row >= 3 * N) return;
+  const int j = (int)(row / N);
+  const int64_t m = row - j * N;
+  const int b = (body[m] >= 0 && body[m] < M) ? body[m] : -1;
+  double r[3] = {0, 0, 0};
+  if (b >= 0) {
+    r[0] = x[m] - Y[12 * b + 0];
+    r[1] = x[N + m] - Y[12 * b + 1];
+    r[2] = x[2 * N + m] - Y[12 * b + 2];
+  }
+  for (int s = 0; s < M; ++s) {
+    T* col = A + (3 * N + 6 * (int64_t)s) * lda + row;
+    for (int c = 0; c < 6; ++c) {
+      double v = 0.0;
+      if (s == b) v = c < 3 ? (c == j ? -1.0 : 0.0) : -cross_unit(c - 3, j, r);
+      col[c * lda] = (T)v;
+    }
+  }
+}
+
+// Rows 3N .. n-1 (all columns): force rows W_m delta_jk, moment rows
+// W_m (r_m x e_k)_i, zero in the rigid-rigid block.
+template <class T>
+__global__ void k_rigid_rows(int64_t N, int32_t M, const int32_t* __restrict__ body,
+                             const double* __restrict__ x, const double* __restrict__ Y,
+                             const double* __restrict__ W, T* __restrict__ A, int64_t lda) {
+  const int64_t rr = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;  // rigid row
+  const int64_t nrows = 6 * (int64_t)M;
+  if (rr >= nrows) return;
+  const int s = (int)(rr / 6), c = (int)(rr % 6);
+  const int64_t n = 3 * N + nrows;
+  const int64_t row = 3 * N + rr;
+  const int64_t col0 = blockIdx.y * (int64_t)256;
+  const int64_t col1 = min<int64_t>(n, col0 + 256);
+  for (int64_t col = col0; col < col1; ++col) {
+    double v = 0.0;
+    if (col < 3 * N) {
+      const int k = (int)(col / N);
+      const int64_t m = col - k * N;
+      if (body[m] == s) {
+        if (c < 3) {
+          v = (c == k) ? W[m] : 0.0;
+        } else {
+          const double r[3] = {x[m] - Y[12 * s], x[N + m] - Y[12 * s + 1],
+                               x[2 * N + m] - Y[12 * s + 2]};
+          // (r x e_k)_i = -(e_k x r)_i
+          v = -W[m] * cross_unit(k, c - 3, r);
+        }
+      }
+    }
+    A[row + col * lda] = (T)v;
+  }
+}
+
+__global__ void k_rhs(int64_t N, int32_t M, const double* __restrict__ u,
+                      const double* __restrict__ ft, double* __restrict__ b) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t n = 3 * N + 6 * (int64_t)M;
+  if (i >= n) return;
+  if (i < 3 * N)
+    b[i] = u[i];
+  else
+    b[i] = ft ? ft[i - 3 * N] : 0.0;
+}
+
+// Matrix-free FP64 NEAREST product, stage 1: lane m sums
+// S^eps(x_m - X_p) w_p f[nu_p] over one chunk of the nu-sorted points.
+constexpr int kApplyBlock = 128;
+__global__ __launch_bounds__(kApplyBlock) void k_apply_part(
+    int64_t N, int64_t chunk, const int32_t* __restrict__ seg, const double* __restrict__ x,
+    const double4* __restrict__ X64, const int32_t* __restrict__ nus,
+    const double* __restrict__ v, double eps2, double* __restrict__ part,
+    const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
+  const int64_t m = blockIdx.x * (int64_t)kApplyBlock + threadIdx.x;
+  const int64_t Qv = seg[N];  // points with a valid nearest index
+  const int64_t p0 = blockIdx.y * chunk;
+  const int64_t p1 = min<int64_t>(Qv, p0 + chunk);
+  double px = 0, py = 0, pz = 0;
+  if (m < N) {
+    px = x[m];
+    py = x[N + m];
+    pz = x[2 * N + m];
+  }
+  double ux = 0, uy = 0, uz = 0;
+  for (int64_t p = p0; p < p1; ++p) {
+    const double4 q = X64[p];
+    const int nn = nus[p];
+    const double fx = q.w * v[nn], fy = q.w * v[N + nn], fz = q.w * v[2 * N + nn];
+    const double rx = px - q.x, ry = py - q.y, rz = pz - q.z;
+    const double d = rx * rx + ry * ry + rz * rz + eps2;
+    const double rho = 1.0 / sqrt(d);
+    const double t = rho * rho * rho;
+    const double rf = rx * fx + ry * fy + rz * fz;
+    const double s = d + eps2;
+    ux += t * (s * fx + rx * rf);
+    uy += t * (s * fy + ry * rf);
+    uz += t * (s * fz + rz * rf);
+  }
+  if (m < N) {
+    double* out = part + blockIdx.y * 3 * N;
+    out[m] = ux;
+    out[N + m] = uy;
+    out[2 * N + m] = uz;
+  }
+}
+
+// Stage 2 for the 3N velocity rows: sum the chunks in order, scale, subtract
+// the rigid-body motion U + Omega x r_m of free-body points.
+__global__ void k_apply_rows(int64_t N, int32_t M, int32_t chunks, const double* __restrict__ part,
+                             double scale, const double* __restrict__ x,
+                             const int32_t* __restrict__ body, const double* __restrict__ Y,
+                             const double* __restrict__ v, double* __restrict__ y,
+                             const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
+  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (row >= 3 * N) return;
+  double acc = 0.0;
+  for (int c = 0; c < chunks; ++c) acc += part[c * 3 * N + row];
+  acc *= scale;
+  const int j = (int)(row / N);
+  const int64_t m = row - j * N;
+  const int b = (body[m] >= 0 && body[m] < M) ? body[m] : -1;
+  if (b >= 0) {
+    const double r[3] = {x[m] - Y[12 * b], x[N + m] - Y[12 * b + 1], x[2 * N + m] - Y[12 * b + 2]};
+    const double* uw = v + 3 * N + 6 * b;
+    acc -= uw[j];
+    for (int i = 0; i < 3; ++i) acc -= uw[3 + i] * cross_unit(i, j, r);
+  }
+  y[row] = acc;
+}
+
+// Stage 2 for the 6M rigid rows: one workgroup per body, fixed-order
+// reduction of W_m f_m and W_m r_m x f_m.
+constexpr int kBodyBlock = 256;
+__global__ __launch_bounds__(kBodyBlock) void k_apply_body(
+    int64_t N, const int32_t* __restrict__ body, const double* __restrict__ x,
+    const double* __restrict__ Y, const double* __restrict__ W, const double* __restrict__ v,
+    double* __restrict__ y, const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
+  const int s = blockIdx.x;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t m = threadIdx.x; m < N; m += kBodyBlock) {
+    if (body[m] != s) continue;
+    const double f[3] = {W[m] * v[m], W[m] * v[N + m], W[m] * v[2 * N + m]};
+    const double r[3] = {x[m] - Y[12 * s], x[N + m] - Y[12 * s + 1], x[2 * N + m] - Y[12 * s + 2]};
+    acc[0] += f[0];
+    acc[1] += f[1];
+    acc[2] += f[2];
+    acc[3] += r[1] * f[2] - r[2] * f[1];
+    acc[4] += r[2] * f[0] - r[0] * f[2];
+    acc[5] += r[0] * f[1] - r[1] * f[0];
+  }
+  __shared__ double red[6][kBodyBlock];
+  for (int c = 0; c < 6; ++c) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int off = kBodyBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off)
+      for (int c = 0; c < 6; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) y[3 * N + 6 * s + threadIdx.x] = red[threadIdx.x][0];
+}
+
+inline dim3 grid1(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)); }
+
+}  // namespace
+
+template <>
+hipError_t launch_assemble<float>(const nrs_problem& pb, const Sorted& srt, float* A,
+                                  int64_t lda, hipStream_t s) {
+  const int64_t N = pb.N;
+  const int64_t n = 3 * N + 6 * (int64_t)pb.M;
+  const float scale = (float)(1.0 / (8.0 * kPi * pb.mu));
+  if (N > 0) {
+    dim3 g((unsigned)((N + kAsmBlock - 1) / kAsmBlock), (unsigned)((N + kTN - 1) / kTN));
+    hipLaunchKernelGGL(k_assemble32, g, dim3(kAsmBlock), 0, s, N, pb.x, srt.seg, srt.X32hi,
+                       srt.X32lo, (float)(pb.eps * pb.eps), scale, A, lda);
+  }
+  if (pb.M > 0) {
+    hipLaunchKernelGGL(k_rigid_cols<float>, grid1(3 * N, 256), dim3(256), 0, s, N, pb.M, pb.body,
+                       pb.x, pb.Y, A, lda);
+    dim3 g(grid1(6 * (int64_t)pb.M, 64).x, (unsigned)((n + 255) / 256));
+    hipLaunchKernelGGL(k_rigid_rows<float>, g, dim3(64), 0, s, N, pb.M, pb.body, pb.x, pb.Y,
+                       srt.W, A, lda);
+  }
+  return hipGetLastError();
+}
+
+template <>
+hipError_t launch_assemble<double>(const nrs_problem& pb, const Sorted& srt, double* A,
+                                   int64_t lda, hipStream_t s) {
+  const int64_t N = pb.N;
+  const int64_t n = 3 * N + 6 * (int64_t)pb.M;
+  const double scale = 1.0 / (8.0 * kPi * pb.mu);
+  if (N > 0) {
+    dim3 g((unsigned)((N + kAsmBlock - 1) / kAsmBlock), (unsigned)((N + kTN - 1) / kTN));
+    hipLaunchKernelGGL(k_assemble64, g, dim3(kAsmBlock), 0, s, N, pb.x, srt.seg, srt.X64,
+                       pb.eps * pb.eps, scale, A, lda);
+  }
+  if (pb.M > 0) {
+    hipLaunchKernelGGL(k_rigid_cols<double>, grid1(3 * N, 256), dim3(256), 0, s, N, pb.M,
+                       pb.body, pb.x, pb.Y, A, lda);
+    dim3 g(grid1(6 * (int64_t)pb.M, 64).x, (unsigned)((n + 255) / 256));
+    hipLaunchKernelGGL(k_rigid_rows<double>, g, dim3(64), 0, s, N, pb.M, pb.body, pb.x, pb.Y,
+                       srt.W, A, lda);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs(int64_t N, int32_t M, const double* u, const double* ftext, double* b,
+                      hipStream_t s) {
+  const int64_t n = 3 * N + 6 * (int64_t)M;
+  hipLaunchKernelGGL(k_rhs, grid1(n, 256), dim3(256), 0, s, N, M, u, ftext, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply(const nrs_problem& pb, const Sorted& srt, const double* v, double* y,
+                        double* part, int32_t chunks, const int32_t* stop, hipStream_t s) {
+  const int64_t N = pb.N, Q = pb.Q;
+  const int64_t chunk = (Q + chunks - 1) / chunks;
+  if (N > 0) {
+    dim3 g((unsigned)((N + kApplyBlock - 1) / kApplyBlock), (unsigned)chunks);
+    hipLaunchKernelGGL(k_apply_part, g, dim3(kApplyBlock), 0, s, N, chunk, srt.seg, pb.x, srt.X64,
+                       srt.nus, v, pb.eps * pb.eps, part, stop);
+    hipLaunchKernelGGL(k_apply_rows, grid1(3 * N, 256), dim3(256), 0, s, N, pb.M, chunks, part,
+                       1.0 / (8.0 * kPi * pb.mu), pb.x, pb.body, pb.Y, v, y, stop);
+  }
+  if (pb.M > 0) {
+    hipLaunchKernelGGL(k_apply_body, dim3(pb.M), dim3(kBodyBlock), 0, s, N, pb.body, pb.x, pb.Y,
+                       srt.W, v, y, stop);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace nrs

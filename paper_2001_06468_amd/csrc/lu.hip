@@ -1,0 +1,417 @@
+// Dense LU factorisation with row pivoting and triangular solves (the
+// linear-algebra step 3 of Sec. 4), FP32 and FP64.
+//
+// Right-looking blocked algorithm with panel width kNb:
+//   panel   : one workgroup factors the n-k x jb panel (pivot search over the
+//             whole column, or only inside the diagonal block for static block
+//             pivoting);
+//   swap    : one wavefront per column applies the panel's row interchanges
+//             (lanes hold the jb pivot rows, interchanges with rows below the
+//             panel are resolved in registers) and, right of the panel, solves
+//             with the unit lower jb x jb block (the U12 row block);
+//   update  : A22 -= L21 U12 on the matrix cores (16x16x4 MFMA, FP32 or FP64),
+//             128 x 128 output tile per workgroup.
+// The composite row permutation is carried along as an extra column so that
+// solves can gather the right-hand side in one pass.
+#include <algorithm>
+
+#include "nrs_internal.h"
+
+namespace nrs {
+
+namespace {
+
+constexpr int kNb = 64;
+constexpr int kPanelThreads = 1024;
+
+template <class T>
+__device__ inline T absval(T v) {
+  return v < T(0) ? -v : v;
+}
+
+template <class T>
+__global__ __launch_bounds__(kPanelThreads) void k_getf2(int64_t n, int64_t k, int jb, int scope,
+                                                         T* __restrict__ A, int64_t lda,
+                                                         int32_t* __restrict__ ipiv,
+                                                         int32_t* __restrict__ sing) {
+  __shared__ T s_val[kPanelThreads / 64];
+  __shared__ int64_t s_idx[kPanelThreads / 64];
+  __shared__ int64_t s_piv;
+  __shared__ T s_row[kNb];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int64_t kend = k + jb;
+  const int64_t rend = scope ? kend : n;
+  for (int64_t j = k; j < kend; ++j) {
+    T* colj = A + j * lda;
+    T best = T(-1);
+    int64_t bi = j;
+    for (int64_t i = j + tid; i < rend; i += kPanelThreads) {
+      const T v = absval(colj[i]);
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const T ov = __shfl_xor(best, off);
+      const int64_t oi = __shfl_xor(bi, off);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      s_val[wid] = best;
+      s_idx[wid] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      T b = s_val[0];
+      int64_t bidx = s_idx[0];
+      for (int w = 1; w < kPanelThreads / 64; ++w) {
+        if (s_val[w] > b || (s_val[w] == b && s_idx[w] < bidx)) {
+          b = s_val[w];
+          bidx = s_idx[w];
+        }
+      }
+      s_piv = bidx;
+      ipiv[j] = (int32_t)bidx;
+    }
+    __syncthreads();
+    const int64_t p = s_piv;
+    if (p != j && tid < jb) {
+      T* c = A + (k + tid) * lda;
+      const T t = c[j];
+      c[j] = c[p];
+      c[p] = t;
+    }
+    __syncthreads();
+    const int w = (int)(kend - j);
+    if (tid < w) s_row[tid] = A[j + (j + tid) * lda];
+    __syncthreads();
+    const T piv = s_row[0];
+    if (piv == T(0)) {
+      if (tid == 0) *sing = 1;
+      continue;
+    }
+    for (int64_t i = j + 1 + tid; i < n; i += kPanelThreads) {
+      const T l = colj[i] / piv;
+      colj[i] = l;
+      for (int c = 1; c < w; ++c) A[i + (j + c) * lda] -= l * s_row[c];
+    }
+    __syncthreads();
+  }
+}
+
+// Columns handled: [0, k) (interchanges only), [k+jb, n) (interchanges and
+// the unit-lower solve), and the permutation column (interchanges only).
+template <class T>
+__global__ __launch_bounds__(256) void k_laswp_trsm(int64_t n, int64_t k, int jb,
+                                                    T* __restrict__ A, int64_t lda,
+                                                    const int32_t* __restrict__ ipiv,
+                                                    int32_t* __restrict__ perm) {
+  __shared__ T sL[kNb * kNb];
+  __shared__ int32_t sp[kNb];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x < jb) sp[threadIdx.x] = ipiv[k + threadIdx.x];
+  for (int e = threadIdx.x; e < jb * jb; e += 256) {
+    const int r = e % jb, c = e / jb;
+    sL[e] = A[(k + r) + (k + c) * lda];
+  }
+  __syncthreads();
+  const int64_t nleft = k, nright = n - k - jb;
+  const int64_t cid = blockIdx.x * 4 + w;
+  if (cid > nleft + nright) return;
+  const bool is_perm = cid == nleft + nright;
+  const bool solve = !is_perm && cid >= nleft;
+  T* col = nullptr;
+  if (!is_perm) col = A + (cid < nleft ? cid : cid + jb) * lda;
+  const int64_t kend = k + jb;
+  const bool mine = lane < jb;
+  T reg = T(0), slot = T(0), outval = T(0);
+  int64_t pl = -1;
+  bool outside = false, final_w = false;
+  if (mine) {
+    pl = sp[lane];
+    outside = pl >= kend;
+    final_w = outside;
+    reg = is_perm ? (T)perm[k + lane] : col[k + lane];
+    if (outside) slot = is_perm ? (T)perm[pl] : col[pl];
+  }
+  for (int j = 0; j < jb; ++j) {
+    const int64_t p = sp[j];
+    if (p < kend) {
+      const int pj = (int)(p - k);
+      if (pj != j) {
+        const T a = __shfl(reg, j);
+        const T b = __shfl(reg, pj);
+        if (lane == j) reg = b;
+        if (lane == pj) reg = a;
+      }
+    } else {
+      const T a = __shfl(reg, j);
+      const T b = __shfl(slot, j);
+      if (lane == j) {
+        reg = b;
+        outval = a;
+      }
+      if (mine && lane > j && pl == p) slot = a;
+      if (mine && lane < j && pl == p) final_w = false;
+    }
+  }
+  if (solve) {
+    for (int t = 0; t < jb; ++t) {
+      const T xt = __shfl(reg, t);
+      if (mine && lane > t) reg -= sL[lane + t * jb] * xt;
+    }
+  }
+  if (mine) {
+    if (is_perm) {
+      perm[k + lane] = (int32_t)reg;
+      if (final_w) perm[pl] = (int32_t)outval;
+    } else {
+      col[k + lane] = reg;
+      if (final_w) col[pl] = outval;
+    }
+  }
+}
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef floatx4 acc_t;
+  static __device__ inline acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<double> {
+  typedef doublex4 acc_t;
+  static __device__ inline acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+constexpr int kGT = 128;       // output tile edge per workgroup
+constexpr int kGK = 32;        // k-chunk staged in LDS
+constexpr int kGPad = 16;      // LDS row padding (elements)
+constexpr int kGS = kGT + kGPad;
+
+// C (m x nc) -= A (m x K) * B (K x nc); all column-major with leading dim lda.
+// 256 threads = 2 x 2 waves, each wave a 64 x 64 sub-tile of 4 x 4 MFMA blocks.
+// MFMA 16x16x4 operand layout: lane l holds A[l%16][l/16] and B[l/16][l%16];
+// output register r of lane l is C[4*(l/16)+r][l%16].
+template <class T>
+__global__ __launch_bounds__(256) void k_gemm_update(int64_t m, int64_t nc, int K,
+                                                     const T* __restrict__ Ap,
+                                                     const T* __restrict__ Bp,
+                                                     T* __restrict__ C, int64_t lda) {
+  __shared__ T As[kGK * kGS];
+  __shared__ T Bs[kGK * kGS];
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int64_t i0 = blockIdx.x * (int64_t)kGT, j0 = blockIdx.y * (int64_t)kGT;
+  const int wr = (wid >> 1) * 64, wc = (wid & 1) * 64;
+  acc_t acc[4][4];
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+      for (int r = 0; r < 4; ++r) acc[a][b][r] = T(0);
+  for (int kc = 0; kc < K; kc += kGK) {
+    {  // A tile: 128 rows x kGK columns -> As[kk][row]
+      const int row = tid & 127, cg = tid >> 7;
+      const int64_t gi = i0 + row;
+      for (int c = cg; c < kGK; c += 2) {
+        const int gk = kc + c;
+        T v = T(0);
+        if (gi < m && gk < K) v = Ap[gi + (int64_t)gk * lda];
+        As[c * kGS + row] = v;
+      }
+    }
+    {  // B tile: kGK rows x 128 columns -> Bs[kk][col]
+      const int kk = tid & (kGK - 1), cg = tid / kGK;
+      const int gk = kc + kk;
+      for (int c = cg; c < kGT; c += 256 / kGK) {
+        const int64_t gj = j0 + c;
+        T v = T(0);
+        if (gj < nc && gk < K) v = Bp[gk + gj * lda];
+        Bs[kk * kGS + c] = v;
+      }
+    }
+    __syncthreads();
+    for (int kk = 0; kk < kGK; kk += 4) {
+      const int kr = kk + (lane >> 4), li = lane & 15;
+      T av[4], bv[4];
+      for (int a = 0; a < 4; ++a) av[a] = As[kr * kGS + wr + a * 16 + li];
+      for (int b = 0; b < 4; ++b) bv[b] = Bs[kr * kGS + wc + b * 16 + li];
+      for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::run(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  const int lr = 4 * (lane >> 4), lc = lane & 15;
+  for (int a = 0; a < 4; ++a) {
+    for (int b = 0; b < 4; ++b) {
+      const int64_t gj = j0 + wc + b * 16 + lc;
+      if (gj >= nc) continue;
+      T* cc = C + gj * lda;
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = i0 + wr + a * 16 + lr + r;
+        if (gi < m) cc[gi] -= acc[a][b][r];
+      }
+    }
+  }
+}
+
+__global__ void k_iota(int32_t* p, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+
+template <class T>
+__global__ void k_gather(int64_t n, const int32_t* __restrict__ perm, const T* __restrict__ b,
+                         T* __restrict__ x, const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] = b[perm[i]];
+}
+
+// Sequential composition of LAPACK-style interchanges into a permutation
+// (used only when a caller supplies ipiv without the permutation column).
+__global__ void k_ipiv_to_perm(int64_t n, const int32_t* __restrict__ ipiv, int32_t* perm) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+  for (int64_t j = 0; j < n; ++j) {
+    const int32_t p = ipiv[j];
+    const int32_t t = perm[j];
+    perm[j] = perm[p];
+    perm[p] = t;
+  }
+}
+
+constexpr int kTrsvThreads = 1024;
+constexpr int kTb = 64;
+
+// Single-workgroup blocked forward substitution with the unit lower factor.
+template <class T>
+__global__ __launch_bounds__(kTrsvThreads) void k_trsv_lower(int64_t n,
+                                                             const T* __restrict__ LU,
+                                                             int64_t lda, T* __restrict__ x,
+                                                             const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
+  __shared__ T xs[kTb];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int64_t k = 0; k < n; k += kTb) {
+    const int jb = (int)min<int64_t>(kTb, n - k);
+    if (wid == 0) {
+      T v = lane < jb ? x[k + lane] : T(0);
+      for (int t = 0; t < jb; ++t) {
+        const T xt = __shfl(v, t);
+        if (lane > t && lane < jb) v -= LU[(k + lane) + (k + t) * lda] * xt;
+      }
+      if (lane < jb) {
+        x[k + lane] = v;
+        xs[lane] = v;
+      }
+    }
+    __syncthreads();
+    for (int64_t i = k + jb + tid; i < n; i += kTrsvThreads) {
+      T s = T(0);
+      for (int t = 0; t < jb; ++t) s += LU[i + (k + t) * lda] * xs[t];
+      x[i] -= s;
+    }
+    __syncthreads();
+  }
+}
+
+// Single-workgroup blocked backward substitution with the upper factor.
+template <class T>
+__global__ __launch_bounds__(kTrsvThreads) void k_trsv_upper(int64_t n,
+                                                             const T* __restrict__ LU,
+                                                             int64_t lda, T* __restrict__ x,
+                                                             const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
+  __shared__ T xs[kTb];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int64_t nblk = (n + kTb - 1) / kTb;
+  for (int64_t bk = nblk - 1; bk >= 0; --bk) {
+    const int64_t k = bk * kTb;
+    const int jb = (int)min<int64_t>(kTb, n - k);
+    if (wid == 0) {
+      T v = lane < jb ? x[k + lane] : T(0);
+      for (int t = jb - 1; t >= 0; --t) {
+        if (lane == t) v = v / LU[(k + t) + (k + t) * lda];
+        const T xt = __shfl(v, t);
+        if (lane < t) v -= LU[(k + lane) + (k + t) * lda] * xt;
+      }
+      if (lane < jb) {
+        x[k + lane] = v;
+        xs[lane] = v;
+      }
+    }
+    __syncthreads();
+    for (int64_t i = tid; i < k; i += kTrsvThreads) {
+      T s = T(0);
+      for (int t = 0; t < jb; ++t) s += LU[i + (k + t) * lda] * xs[t];
+      x[i] -= s;
+    }
+    __syncthreads();
+  }
+}
+
+inline dim3 grid1(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)); }
+
+}  // namespace
+
+template <class T>
+hipError_t launch_lu_factor(int64_t n, int32_t scope, T* A, int64_t lda, int32_t* ipiv,
+                            int32_t* perm, int32_t* sing, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_iota, grid1(n, 256), dim3(256), 0, s, perm, n);
+  for (int64_t k = 0; k < n; k += kNb) {
+    const int jb = (int)std::min<int64_t>(kNb, n - k);
+    hipLaunchKernelGGL(k_getf2<T>, dim3(1), dim3(kPanelThreads), 0, s, n, k, jb, scope, A, lda,
+                       ipiv, sing);
+    const int64_t ncols = (n - jb) + 1;
+    hipLaunchKernelGGL(k_laswp_trsm<T>, grid1(ncols, 4), dim3(256), 0, s, n, k, jb, A, lda,
+                       ipiv, perm);
+    const int64_t rest = n - k - jb;
+    if (rest > 0) {
+      dim3 g((unsigned)((rest + kGT - 1) / kGT), (unsigned)((rest + kGT - 1) / kGT));
+      hipLaunchKernelGGL(k_gemm_update<T>, g, dim3(256), 0, s, rest, rest, jb,
+                         A + (k + jb) + k * lda, A + k + (k + jb) * lda,
+                         A + (k + jb) + (k + jb) * lda, lda);
+    }
+  }
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t launch_lu_solve(int64_t n, const T* LU, int64_t lda, const int32_t* perm, const T* b,
+                           T* x, const int32_t* stop, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather<T>, grid1(n, 256), dim3(256), 0, s, n, perm, b, x, stop);
+  hipLaunchKernelGGL(k_trsv_lower<T>, dim3(1), dim3(kTrsvThreads), 0, s, n, LU, lda, x, stop);
+  hipLaunchKernelGGL(k_trsv_upper<T>, dim3(1), dim3(kTrsvThreads), 0, s, n, LU, lda, x, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_ipiv_to_perm(int64_t n, const int32_t* ipiv, int32_t* perm, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_ipiv_to_perm, dim3(1), dim3(64), 0, s, n, ipiv, perm);
+  return hipGetLastError();
+}
+
+template hipError_t launch_lu_factor<float>(int64_t, int32_t, float*, int64_t, int32_t*, int32_t*,
+                                            int32_t*, hipStream_t);
+template hipError_t launch_lu_factor<double>(int64_t, int32_t, double*, int64_t, int32_t*,
+                                             int32_t*, int32_t*, hipStream_t);
+template hipError_t launch_lu_solve<float>(int64_t, const float*, int64_t, const int32_t*,
+                                           const float*, float*, const int32_t*, hipStream_t);
+template hipError_t launch_lu_solve<double>(int64_t, const double*, int64_t, const int32_t*,
+                                            const double*, double*, const int32_t*, hipStream_t);
+
+}  // namespace nrs

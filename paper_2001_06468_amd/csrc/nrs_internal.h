@@ -1,0 +1,153 @@
+// Internal declarations shared by the libnrs translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/nrs.h"
+
+struct nrs_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+};
+
+namespace nrs {
+
+constexpr int kMaxGroups = 512;
+constexpr double kPi = 3.14159265358979323846;
+
+struct GroupTable {
+  int32_t G;
+  int32_t off[kMaxGroups + 1];
+};
+
+// Solve status words kept in the workspace (device) so that an asynchronous
+// solve can be inspected later.
+struct SolveState {
+  int32_t converged;    // refinement / GMRES reached its tolerance
+  int32_t failed;       // refinement diverged or stagnated
+  int32_t iterations;
+  int32_t singular;     // zero pivot met
+  int32_t method_used;
+  int32_t fell_back;
+  int32_t nonfinite;
+  int32_t stop;         // converged || failed: refinement kernels become no-ops
+  double bwd;           // normwise backward error of the last residual
+  double corr;          // last |d|/|x|
+  double prev_corr;
+  double anorm;         // |A|_inf of the FP64 operator (estimated from the FP32 copy)
+};
+
+// Bump allocator over a caller-provided workspace.
+struct Arena {
+  char* base;
+  size_t cap;
+  size_t used = 0;
+  bool overflow = false;
+  Arena(void* b, size_t c) : base(static_cast<char*>(b)), cap(c) {}
+  template <class T>
+  T* take(size_t count) {
+    size_t off = (used + 255) & ~size_t(255);
+    size_t bytes = count * sizeof(T);
+    used = off + bytes;
+    if (base == nullptr || used > cap) {
+      overflow = true;
+      return nullptr;
+    }
+    return reinterpret_cast<T*>(base + off);
+  }
+};
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+inline int64_t lda_for(int64_t n) { return round_up(n < 1 ? 1 : n, 64); }
+
+// Sorted quadrature data, produced by build_csr.
+struct Sorted {
+  int32_t* seg;      // [N+1] segment offsets into the sorted order
+  int32_t* perm;     // [Q] original index of sorted point p
+  int32_t* nus;      // [Q] nearest force point of sorted point p
+  double4* X64;      // [Q] (x, y, z, w) in FP64
+  float4* X32hi;     // [Q] (x_hi, y_hi, z_hi, w) in FP32
+  float4* X32lo;     // [Q] (x_lo, y_lo, z_lo, 0): x = x_hi + x_lo to FP32 x FP32 precision
+  double* W;         // [N] patch weights
+  int32_t* cnt;      // [N+2] scratch; cnt[N+1] counts quadrature points with nu out of range
+};
+
+// All device buffers of one solve, carved from the workspace.
+struct SolveBuffers {
+  Sorted srt;
+  float* A32;        // lda x n (FP32 path)
+  double* A64;       // lda x n (FP64 path / fallback)
+  int64_t lda;
+  int32_t* ipiv;     // [n]
+  int32_t* perm;     // [n] composite row permutation of the factorisation
+  int32_t* perm64;   // [n] same for the FP64 fallback factors
+  int32_t* ipiv64;
+  double* b;         // [n]
+  double* x;         // [n] current solution
+  double* r;         // [n] residual
+  float* d32;        // [n]
+  double* d64;       // [n]
+  double* part;      // [chunks][3N] partial products of the matrix-free apply
+  double* red;       // [64] reduction scratch
+  SolveState* st;
+  int32_t chunks;
+};
+
+size_t solve_workspace_bytes(int64_t N, int64_t Q, int32_t M, int32_t method);
+bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, SolveBuffers& sb);
+
+// ---- kernels / launchers (each returns hipError_t of the launch) ----
+hipError_t launch_geometry(const nrs_scene& sc, double t, const double* Y, double* x, double* X,
+                           double* w, double* u, hipStream_t s);
+hipError_t launch_nearest(int64_t N, const double* x, const GroupTable& gt, int64_t Q,
+                          const double* X, const int32_t* groupX, int32_t* nu, hipStream_t s);
+hipError_t launch_build_csr(int64_t N, int64_t Q, const double* X, const double* w,
+                            const int32_t* nu, Sorted& srt, hipStream_t s);
+template <class T>
+hipError_t launch_assemble(const nrs_problem& pb, const Sorted& srt, T* A, int64_t lda,
+                           hipStream_t s);
+hipError_t launch_rhs(int64_t N, int32_t M, const double* u, const double* ftext, double* b,
+                      hipStream_t s);
+hipError_t launch_apply(const nrs_problem& pb, const Sorted& srt, const double* v, double* y,
+                        double* part, int32_t chunks, const int32_t* stop, hipStream_t s);
+template <class T>
+hipError_t launch_lu_factor(int64_t n, int32_t scope, T* A, int64_t lda, int32_t* ipiv,
+                            int32_t* perm, int32_t* sing, hipStream_t s);
+template <class T>
+hipError_t launch_lu_solve(int64_t n, const T* LU, int64_t lda, const int32_t* perm, const T* b,
+                           T* x, const int32_t* stop, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
+hipError_t launch_ipiv_to_perm(int64_t n, const int32_t* ipiv, int32_t* perm, hipStream_t s);
+
+// refinement helpers
+hipError_t launch_state_init(SolveState* st, int32_t method, hipStream_t s);
+hipError_t launch_anorm32(int64_t n, const float* A, int64_t lda, SolveState* st, double* red,
+                          hipStream_t s);
+hipError_t launch_anorm64(int64_t n, const double* A, int64_t lda, SolveState* st, double* red,
+                          hipStream_t s);
+hipError_t launch_ir_residual2(int64_t n, const double* b, const double* Ax, const double* x,
+                               double* r, float* r32, double* r64, SolveState* st, int force,
+                               hipStream_t s);
+hipError_t launch_ir_update32(int64_t n, double* x, const float* d, double tol, int32_t first,
+                              SolveState* st, hipStream_t s);
+hipError_t launch_convert_f32(int64_t n, const double* a, float* b, hipStream_t s);
+hipError_t launch_check_nu(int64_t N, const int32_t* cnt, SolveState* st, hipStream_t s);
+hipError_t launch_check_body(int64_t N, int32_t M, const int32_t* body, SolveState* st,
+                             hipStream_t s);
+hipError_t launch_state_accumulate(SolveState* total, const SolveState* stage, hipStream_t s);
+
+// time stepping
+hipError_t launch_rk_stage_state(int32_t M, const double* Y, const double* K, double a,
+                                 double* Ys, hipStream_t s);
+hipError_t launch_rk_rates(int32_t M, int64_t N, const double* Ys, const double* sol, double* K,
+                           hipStream_t s);
+hipError_t launch_rk_combine(int32_t M, double* Y, const double* K1, const double* K2,
+                             const double* K3, const double* K4, double dt, hipStream_t s);
+
+}  // namespace nrs

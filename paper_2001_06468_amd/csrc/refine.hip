@@ -1,0 +1,315 @@
+// Mixed-precision iterative refinement (FP32 factors, FP64 residual and
+// update), status bookkeeping, and the RK4 time-stepping kernels (Sec. 4:
+// Y' = F(Y, t) with Y = [X0; B]).
+#include "nrs_internal.h"
+
+namespace nrs {
+
+namespace {
+
+constexpr int kRedThreads = 1024;
+
+__device__ inline double block_max(double v, double* sh) {
+  const int tid = threadIdx.x;
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  if ((tid & 63) == 0) sh[tid >> 6] = v;
+  __syncthreads();
+  if (tid < 64) {
+    double w = tid < (int)(blockDim.x >> 6) ? sh[tid] : 0.0;
+    for (int off = 32; off > 0; off >>= 1) w = fmax(w, __shfl_xor(w, off));
+    if (tid == 0) sh[0] = w;
+  }
+  __syncthreads();
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline bool finite(double v) { return v == v && fabs(v) <= 1.7976931348623157e308; }
+
+__global__ void k_state_init(SolveState* st, int32_t method) {
+  if (threadIdx.x == 0) {
+    SolveState z = {};
+    z.method_used = method;
+    *st = z;
+  }
+}
+
+// |A|_inf = max_i sum_j |a_ij| (column-major), stage 1: one row per thread.
+template <class T>
+__global__ void k_rowsum(int64_t n, const T* __restrict__ A, int64_t lda, double* red) {
+  __shared__ double sh[64];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  double s = 0.0;
+  if (i < n)
+    for (int64_t j = 0; j < n; ++j) s += fabs((double)A[i + j * lda]);
+  const double m = block_max(s, sh);
+  if (threadIdx.x == 0) red[blockIdx.x] = m;
+}
+
+__global__ void k_rowsum_final(int nblk, const double* red, SolveState* st) {
+  __shared__ double sh[64];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) v = fmax(v, red[i]);
+  v = block_max(v, sh);
+  if (threadIdx.x == 0) st->anorm = v;
+}
+
+// r = b - A x (FP64), r in the correction precision; backward error from
+// |r|, |x| (x is the solution the residual was taken at) and |b|.
+__global__ __launch_bounds__(kRedThreads) void k_ir_residual(int64_t n,
+                                                             const double* __restrict__ b,
+                                                             const double* __restrict__ Ax,
+                                                             const double* __restrict__ x,
+                                                             double* __restrict__ r,
+                                                             float* __restrict__ r32,
+                                                             double* __restrict__ r64,
+                                                             SolveState* st, int force) {
+  __shared__ double sh[64];
+  if (!force && (st->converged || st->failed)) return;
+  double rmax = 0.0, bmax = 0.0, xmax = 0.0;
+  bool ok = true;
+  for (int64_t i = threadIdx.x; i < n; i += kRedThreads) {
+    const double v = b[i] - Ax[i];
+    ok = ok && finite(v);
+    if (r) r[i] = v;
+    if (r32) r32[i] = (float)v;
+    if (r64) r64[i] = v;
+    rmax = fmax(rmax, fabs(v));
+    bmax = fmax(bmax, fabs(b[i]));
+    xmax = fmax(xmax, fabs(x[i]));
+  }
+  rmax = block_max(rmax, sh);
+  bmax = block_max(bmax, sh);
+  xmax = block_max(xmax, sh);
+  const int bad = __syncthreads_or(!ok);
+  if (threadIdx.x == 0) {
+    const double den = st->anorm * xmax + bmax;
+    st->bwd = den > 0.0 ? rmax / den : 0.0;
+    if (bad) {
+      st->nonfinite = 1;
+      st->failed = 1;
+      st->stop = 1;
+    }
+  }
+}
+
+// x += d; convergence when |d|_inf <= tol |x|_inf; failure when the
+// correction stops contracting or turns non-finite.
+template <class T>
+__global__ __launch_bounds__(kRedThreads) void k_ir_update(int64_t n, double* __restrict__ x,
+                                                           const T* __restrict__ d, double tol,
+                                                           int32_t first, SolveState* st) {
+  __shared__ double sh[64];
+  if (st->converged || st->failed) return;
+  double dmax = 0.0, xmax = 0.0;
+  bool ok = true;
+  for (int64_t i = threadIdx.x; i < n; i += kRedThreads) {
+    const double dv = (double)d[i];
+    const double xv = first ? dv : x[i] + dv;
+    ok = ok && finite(xv);
+    x[i] = xv;
+    dmax = fmax(dmax, fabs(dv));
+    xmax = fmax(xmax, fabs(xv));
+  }
+  dmax = block_max(dmax, sh);
+  xmax = block_max(xmax, sh);
+  const int bad = __syncthreads_or(!ok);
+  if (threadIdx.x == 0) {
+    const double c = xmax > 0.0 ? dmax / xmax : 0.0;
+    st->iterations += 1;
+    if (bad) {
+      st->nonfinite = 1;
+      st->failed = 1;
+    } else if (!first) {
+      if (c <= tol) {
+        st->converged = 1;
+      } else if (st->iterations > 2 && c > 0.9 * st->prev_corr) {
+        st->failed = 1;
+      }
+    }
+    st->prev_corr = first ? 1.0 : c;
+    st->corr = c;
+    st->stop = st->converged || st->failed;
+  }
+}
+
+template <class T>
+__global__ void k_convert(int64_t n, const double* __restrict__ a, T* __restrict__ b) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (T)a[i];
+}
+
+__global__ void k_check_nu(int64_t N, const int32_t* cnt, SolveState* st) {
+  if (threadIdx.x == 0 && cnt[N + 1] > 0) {
+    st->nonfinite = 2;
+    st->failed = 1;
+    st->stop = 1;
+  }
+}
+
+// body[m] must lie in [-1, M): anything else is an argument error.
+__global__ void k_check_body(int64_t N, int32_t M, const int32_t* __restrict__ body,
+                             SolveState* st) {
+  const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (m < N && (body[m] < -1 || body[m] >= M)) {
+    st->nonfinite = 2;
+    st->failed = 1;
+    st->stop = 1;
+  }
+}
+
+// ---- time stepping ----
+
+__global__ void k_rk_stage_state(int32_t M, const double* __restrict__ Y,
+                                 const double* __restrict__ K, double a, double* __restrict__ Ys) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 12 * M) Ys[i] = K ? Y[i] + a * K[i] : Y[i];
+}
+
+// dx0/dt = U; dB/dt = [Omega]x B (column i of B is body axis i).
+__global__ void k_rk_rates(int32_t M, int64_t N, const double* __restrict__ Ys,
+                           const double* __restrict__ sol, double* __restrict__ K) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= M) return;
+  const double* uw = sol + 3 * N + 6 * (int64_t)b;
+  const double* B = Ys + 12 * b + 3;
+  double* k = K + 12 * b;
+  k[0] = uw[0];
+  k[1] = uw[1];
+  k[2] = uw[2];
+  const double o0 = uw[3], o1 = uw[4], o2 = uw[5];
+  for (int c = 0; c < 3; ++c) {
+    const double e0 = B[0 * 3 + c], e1 = B[1 * 3 + c], e2 = B[2 * 3 + c];
+    k[3 + 0 * 3 + c] = o1 * e2 - o2 * e1;
+    k[3 + 1 * 3 + c] = o2 * e0 - o0 * e2;
+    k[3 + 2 * 3 + c] = o0 * e1 - o1 * e0;
+  }
+}
+
+// Y += dt/6 (K1 + 2 K2 + 2 K3 + K4), then modified Gram-Schmidt on the
+// columns of each body frame.
+__global__ void k_rk_combine(int32_t M, double* __restrict__ Y, const double* __restrict__ K1,
+                             const double* __restrict__ K2, const double* __restrict__ K3,
+                             const double* __restrict__ K4, double dt) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= M) return;
+  double* y = Y + 12 * b;
+  for (int i = 0; i < 12; ++i) {
+    const int j = 12 * b + i;
+    y[i] = y[i] + (dt / 6.0) * (K1[j] + 2.0 * K2[j] + 2.0 * K3[j] + K4[j]);
+  }
+  double c[3][3];
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) c[k][r] = y[3 + 3 * r + k];
+  double n0 = sqrt(c[0][0] * c[0][0] + c[0][1] * c[0][1] + c[0][2] * c[0][2]);
+  for (int r = 0; r < 3; ++r) c[0][r] /= n0;
+  double p = c[0][0] * c[1][0] + c[0][1] * c[1][1] + c[0][2] * c[1][2];
+  for (int r = 0; r < 3; ++r) c[1][r] -= p * c[0][r];
+  double n1 = sqrt(c[1][0] * c[1][0] + c[1][1] * c[1][1] + c[1][2] * c[1][2]);
+  for (int r = 0; r < 3; ++r) c[1][r] /= n1;
+  p = c[0][0] * c[2][0] + c[0][1] * c[2][1] + c[0][2] * c[2][2];
+  for (int r = 0; r < 3; ++r) c[2][r] -= p * c[0][r];
+  p = c[1][0] * c[2][0] + c[1][1] * c[2][1] + c[1][2] * c[2][2];
+  for (int r = 0; r < 3; ++r) c[2][r] -= p * c[1][r];
+  double n2 = sqrt(c[2][0] * c[2][0] + c[2][1] * c[2][1] + c[2][2] * c[2][2]);
+  for (int r = 0; r < 3; ++r) c[2][r] /= n2;
+  for (int r = 0; r < 3; ++r)
+    for (int k = 0; k < 3; ++k) y[3 + 3 * r + k] = c[k][r];
+}
+
+// Fold one stage's solve status into the step report.
+__global__ void k_state_accumulate(SolveState* total, const SolveState* stage) {
+  if (threadIdx.x != 0) return;
+  total->iterations = max(total->iterations, stage->iterations);
+  total->failed |= stage->failed || (!stage->converged && stage->method_used != NRS_FP64_LU);
+  total->singular |= stage->singular;
+  total->nonfinite |= stage->nonfinite;
+  total->fell_back |= stage->fell_back;
+  total->bwd = fmax(total->bwd, stage->bwd);
+  total->corr = fmax(total->corr, stage->corr);
+  total->method_used = stage->method_used;
+  total->converged = !total->failed;
+}
+
+inline dim3 grid1(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)); }
+
+}  // namespace
+
+hipError_t launch_state_init(SolveState* st, int32_t method, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, st, method);
+  return hipGetLastError();
+}
+
+hipError_t launch_anorm32(int64_t n, const float* A, int64_t lda, SolveState* st, double* red,
+                          hipStream_t s) {
+  const int nb = (int)((n + 255) / 256);
+  hipLaunchKernelGGL(k_rowsum<float>, dim3(nb), dim3(256), 0, s, n, A, lda, red);
+  hipLaunchKernelGGL(k_rowsum_final, dim3(1), dim3(256), 0, s, nb, red, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_anorm64(int64_t n, const double* A, int64_t lda, SolveState* st, double* red,
+                          hipStream_t s) {
+  const int nb = (int)((n + 255) / 256);
+  hipLaunchKernelGGL(k_rowsum<double>, dim3(nb), dim3(256), 0, s, n, A, lda, red);
+  hipLaunchKernelGGL(k_rowsum_final, dim3(1), dim3(256), 0, s, nb, red, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_ir_residual2(int64_t n, const double* b, const double* Ax, const double* x,
+                               double* r, float* r32, double* r64, SolveState* st, int force,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_ir_residual, dim3(1), dim3(kRedThreads), 0, s, n, b, Ax, x, r, r32, r64,
+                     st, force);
+  return hipGetLastError();
+}
+
+hipError_t launch_ir_update32(int64_t n, double* x, const float* d, double tol, int32_t first,
+                              SolveState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_ir_update<float>, dim3(1), dim3(kRedThreads), 0, s, n, x, d, tol, first,
+                     st);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_f32(int64_t n, const double* a, float* b, hipStream_t s) {
+  hipLaunchKernelGGL(k_convert<float>, grid1(n, 256), dim3(256), 0, s, n, a, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_nu(int64_t N, const int32_t* cnt, SolveState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_nu, dim3(1), dim3(64), 0, s, N, cnt, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_body(int64_t N, int32_t M, const int32_t* body, SolveState* st,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_check_body, grid1(N, 256), dim3(256), 0, s, N, M, body, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_rk_stage_state(int32_t M, const double* Y, const double* K, double a,
+                                 double* Ys, hipStream_t s) {
+  hipLaunchKernelGGL(k_rk_stage_state, grid1(12 * (int64_t)M, 256), dim3(256), 0, s, M, Y, K, a,
+                     Ys);
+  return hipGetLastError();
+}
+
+hipError_t launch_rk_rates(int32_t M, int64_t N, const double* Ys, const double* sol, double* K,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_rk_rates, grid1(M, 64), dim3(64), 0, s, M, N, Ys, sol, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_rk_combine(int32_t M, double* Y, const double* K1, const double* K2,
+                             const double* K3, const double* K4, double dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_rk_combine, grid1(M, 64), dim3(64), 0, s, M, Y, K1, K2, K3, K4, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_accumulate(SolveState* total, const SolveState* stage, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_accumulate, dim3(1), dim3(64), 0, s, total, stage);
+  return hipGetLastError();
+}
+
+}  // namespace nrs

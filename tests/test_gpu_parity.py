@@ -1,0 +1,292 @@
+"""Parity of every C-ABI entry point with the CPU FP64 oracle on the same
+seeded inputs (MI355X).  Tolerances:
+  geometry, FP64 assembly, FP64 apply : 1e-13 relative to the largest entry
+    (different summation order only);
+  FP32 assembly : 4e-6 of the largest entry (about 30 FP32 ulps: a 16-term
+    segment sum of products with a hardware reciprocal square root);
+  nearest map : bit-exact (integer);
+  solves : relative 2-norm error of forces and of (U, Omega) <= 1e-8, the
+    target stated for the refined forms.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2001_06468_amd as nrs
+    from gpu_util import T, prepare, oracle_system, workspace, gpu_solve, rel_force_errors, DEV
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = nrs.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _scenes_small():
+    return [
+        ("sphere_nc4_nq16", synth.sphere_scene(4, 16)),
+        ("filaments_M5", synth.filament_scene(5, seed=0)),
+        ("sperm_K2_h8", synth.sperm_channel_scene(2, h=1.0 / 8, seed=1, Nh=30, Qh=300)),
+        ("rodwall_700", synth.rod_wall_batch(1, seed=3, lo=700, hi=700)[0]),
+        ("sphere_free", synth.sphere_scene(3, 9, free=True, force=np.array([0, 0, -1.0]))),
+    ]
+
+
+SCENES = _scenes_small()
+
+
+def test_library_version():
+    assert nrs.nrs_version().startswith("nrs ")
+
+
+@pytest.mark.parametrize("name,scene", SCENES, ids=[s[0] for s in SCENES])
+def test_geometry(ctx, name, scene):
+    rng = np.random.default_rng(7)
+    Y = scene["Y0"].copy()
+    if scene["M"]:
+        Y[:, :3] += 0.01 * rng.normal(size=(scene["M"], 3))
+    t = 0.83
+    x, X, w, u = oracle.geometry(scene, t, Y)
+    ds = nrs.DeviceScene(scene)
+    gx = torch.empty(3 * scene["N"], dtype=torch.float64, device=DEV)
+    gX = torch.empty(3 * scene["Q"], dtype=torch.float64, device=DEV)
+    gw = torch.empty(scene["Q"], dtype=torch.float64, device=DEV)
+    gu = torch.empty(3 * scene["N"], dtype=torch.float64, device=DEV)
+    nrs.nrs_geometry(ctx, ds, t, T(Y) if scene["M"] else None, gx, gX, gw, gu)
+    for g, r in ((gx, x), (gX, X), (gw, w), (gu, u)):
+        g = g.cpu().numpy().reshape(r.shape)
+        assert np.max(np.abs(g - r)) <= 1e-13 * max(1.0, np.max(np.abs(r)))
+
+
+@pytest.mark.parametrize("name,scene", SCENES, ids=[s[0] for s in SCENES])
+def test_nearest_bit_exact(ctx, name, scene):
+    x, X, _, _ = oracle.geometry(scene, 0.4, scene["Y0"])
+    ref = oracle.nearest(x, X, scene["group_off"], scene["groupX"])
+    nu = torch.empty(scene["Q"], dtype=torch.int32, device=DEV)
+    nrs.nrs_nearest(ctx, T(x), scene["group_off"], T(X), T(scene["groupX"], torch.int32), nu)
+    np.testing.assert_array_equal(nu.cpu().numpy(), ref)
+
+
+def test_nearest_ties_and_ragged(ctx):
+    """Exact ties resolve to the lowest index; several groups; Q not a
+    multiple of the block size."""
+    x = np.array([[1.0, -1.0, 0.0, 5.0, 5.0], [0, 0, 1.0, 0, 0], [0, 0, 0, 1.0, -1.0]])
+    X = np.zeros((3, 301))
+    X[0, 200:] = 5.0
+    gX = np.zeros(301, np.int32)
+    gX[200:] = 1
+    go = np.array([0, 3, 5], np.int32)
+    ref = oracle.nearest(x, X, go, gX)
+    assert ref[0] == 0 and ref[250] == 3
+    nu = torch.empty(301, dtype=torch.int32, device=DEV)
+    nrs.nrs_nearest(ctx, T(x), go, T(X), T(gX, torch.int32), nu)
+    np.testing.assert_array_equal(nu.cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("name,scene", SCENES, ids=[s[0] for s in SCENES])
+@pytest.mark.parametrize("precision", [64, 32])
+def test_assemble(ctx, name, scene, precision):
+    pb, host = prepare(scene, 0.2)
+    A_ref, _ = oracle_system(scene, host)
+    n = pb.n
+    lda = nrs.lda_for(n) + 3
+    dt = torch.float64 if precision == 64 else torch.float32
+    A = torch.full((n, lda), float("nan"), dtype=dt, device=DEV)  # column-major: row = column
+    ws = workspace(ctx, pb, nrs.NRS_FP64_LU if precision == 64 else nrs.NRS_FP32_IR)
+    nrs.nrs_assemble(ctx, pb, precision, A, lda, ws)
+    G = A.cpu().numpy().astype(np.float64)[:, :n].T
+    assert np.all(np.isfinite(G))
+    scale = np.max(np.abs(A_ref))
+    err = np.max(np.abs(G - A_ref)) / scale
+    assert err <= (1e-13 if precision == 64 else 4e-6), err
+
+
+@pytest.mark.parametrize("name,scene", SCENES, ids=[s[0] for s in SCENES])
+def test_apply_fp64(ctx, name, scene):
+    pb, host = prepare(scene, 0.9)
+    A_ref, _ = oracle_system(scene, host)
+    v = np.random.default_rng(2).normal(size=pb.n)
+    y = torch.empty(pb.n, dtype=torch.float64, device=DEV)
+    nrs.nrs_apply(ctx, pb, T(v), y, workspace(ctx, pb, nrs.NRS_FP64_LU))
+    ref = A_ref @ v
+    scale = np.max(np.abs(A_ref) @ np.abs(v))
+    assert np.max(np.abs(y.cpu().numpy() - ref)) <= 1e-13 * scale
+
+
+def _lu_check(A0, LU, perm, scope, nb=64, tol=1e-12):
+    n = A0.shape[0]
+    L = np.tril(LU, -1) + np.eye(n)
+    U = np.triu(LU)
+    PA = A0[perm]
+    err = np.max(np.abs(PA - L @ U)) / np.max(np.abs(A0))
+    assert err <= tol * n, err
+    if scope == 0:
+        assert np.max(np.abs(np.tril(LU, -1))) <= 1.0 + 1e-12
+    else:
+        for k in range(0, n, nb):
+            blk = LU[k:k + nb, k:k + nb]
+            assert np.max(np.abs(np.tril(blk, -1)), initial=0.0) <= 1.0 + 1e-6
+
+
+@pytest.mark.parametrize("n", [1, 7, 63, 64, 65, 130, 300, 515])
+@pytest.mark.parametrize("precision", [64, 32])
+@pytest.mark.parametrize("scope", [0, 1])
+def test_lu_factor_and_solve(ctx, n, precision, scope):
+    rng = np.random.default_rng(n)
+    A0 = rng.normal(size=(n, n)) + (n ** 0.5) * np.eye(n) * (scope == 1)
+    dt = torch.float64 if precision == 64 else torch.float32
+    lda = nrs.lda_for(n) + 5
+    A = torch.zeros((n, lda), dtype=dt, device=DEV)
+    A[:, :n] = torch.from_numpy(A0.T.copy()).to(dt)
+    ipiv = torch.empty(n, dtype=torch.int32, device=DEV)
+    perm = torch.empty(n, dtype=torch.int32, device=DEV)
+    sing = torch.zeros(1, dtype=torch.int32, device=DEV)
+    nrs.nrs_lu_factor(ctx, A, lda, ipiv, perm, sing, pivot_scope=scope)
+    LU = A.cpu().numpy().astype(np.float64)[:, :n].T
+    p = perm.cpu().numpy()
+    piv = ipiv.cpu().numpy()
+    # the permutation is the composition of the LAPACK-style interchanges
+    q = np.arange(n)
+    for j in range(n):
+        q[[j, piv[j]]] = q[[piv[j], j]]
+    np.testing.assert_array_equal(p, q)
+    assert sing.item() == 0
+    A0c = A0.astype(np.float32).astype(np.float64) if precision == 32 else A0
+    _lu_check(A0c, LU, p, scope, tol=1e-13 if precision == 64 else 3e-6)
+    b = rng.normal(size=n)
+    xs = torch.empty(n, dtype=dt, device=DEV)
+    nrs.nrs_lu_solve(ctx, A, lda, perm, T(b, dt), xs)
+    ref = np.linalg.solve(A0c, b)
+    err = np.linalg.norm(xs.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err <= (1e-10 if precision == 64 else 1e-3 * max(1, n / 100))
+
+
+def test_lu_singular_flag(ctx):
+    n = 70
+    A0 = np.random.default_rng(0).normal(size=(n, n))
+    A0[:, 5] = 0.0
+    A = torch.from_numpy(A0.T.copy()).to(DEV)
+    ipiv = torch.empty(n, dtype=torch.int32, device=DEV)
+    perm = torch.empty(n, dtype=torch.int32, device=DEV)
+    sing = torch.zeros(1, dtype=torch.int32, device=DEV)
+    nrs.nrs_lu_factor(ctx, A, n, ipiv, perm, sing)
+    assert sing.item() == 1
+
+
+SOLVE_CASES = [
+    ("sphere_c1", lambda: synth.sphere_scene(4, 16)),
+    ("filaments_M1", lambda: synth.filament_scene(1, seed=0)),
+    ("filaments_M5", lambda: synth.filament_scene(5, seed=1)),
+    ("sperm_K2_h8", lambda: synth.sperm_channel_scene(2, h=1.0 / 8, seed=1, Nh=30, Qh=300)),
+    ("rodwall_700", lambda: synth.rod_wall_batch(1, seed=3, lo=700, hi=700)[0]),
+]
+
+
+@pytest.mark.parametrize("name,mk", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
+@pytest.mark.parametrize("method", ["FP64_LU", "FP32_IR", "FP32_GEPP_IR"])
+def test_solve_matches_oracle(ctx, name, mk, method):
+    scene = mk()
+    pb, host = prepare(scene, 0.3)
+    A_ref, b_ref = oracle_system(scene, host)
+    ref = np.linalg.solve(A_ref, b_ref)
+    m = getattr(nrs, "NRS_" + method)
+    sol, info = gpu_solve(ctx, scene, pb, host, m)
+    ef, eg = rel_force_errors(sol, ref, scene["N"])
+    assert ef <= 1e-8 and eg <= 1e-8, (ef, eg, info)
+    assert info["fell_back"] == 0
+    assert info["backward_error"] <= 1e-14
+    if method != "FP64_LU":
+        assert info["iterations"] >= 2
+
+
+def test_sphere_drag_on_gpu(ctx):
+    scene = synth.sphere_scene(4, 16)
+    pb, host = prepare(scene)
+    sol, _ = gpu_solve(ctx, scene, pb, host, nrs.NRS_FP32_IR)
+    W = oracle.patch_weights(host["w"], host["nu"], scene["N"])
+    F = (W * sol[:scene["N"]]).sum()
+    assert abs(F / (6 * math.pi) - 1) < 0.02
+
+
+def test_c2_full_size_parity(ctx):
+    """25 filaments (n = 3150), the time-stepping workload, full parity."""
+    scene = synth.filament_scene(25, seed=0)
+    pb, host = prepare(scene, 0.0)
+    A_ref, b_ref = oracle_system(scene, host)
+    ref = np.linalg.solve(A_ref, b_ref)
+    for m in (nrs.NRS_FP64_LU, nrs.NRS_FP32_IR):
+        sol, info = gpu_solve(ctx, scene, pb, host, m)
+        ef, eg = rel_force_errors(sol, ref, scene["N"])
+        assert ef <= 1e-8 and eg <= 1e-8, (m, ef, eg, info)
+
+
+def test_solve_is_deterministic(ctx):
+    scene = synth.filament_scene(5, seed=2)
+    pb, host = prepare(scene, 1.1)
+    s1, _ = gpu_solve(ctx, scene, pb, host, nrs.NRS_FP32_IR)
+    s2, _ = gpu_solve(ctx, scene, pb, host, nrs.NRS_FP32_IR)
+    np.testing.assert_array_equal(s1, s2)
+
+
+@pytest.mark.parametrize("method", ["FP64_LU", "FP32_IR"])
+def test_rk4_step_matches_oracle(ctx, method):
+    scene = synth.filament_scene(5, seed=0)
+    ds = nrs.DeviceScene(scene)
+    m = getattr(nrs, "NRS_" + method)
+    ws = torch.empty(nrs.nrs_rk4_workspace_size(ctx, ds, m), dtype=torch.uint8, device=DEV)
+    Y = T(scene["Y0"])
+    Yo = scene["Y0"].copy()
+    dt = 2 * math.pi / 100
+    for step in range(2):
+        nrs.nrs_rk4_step(ctx, ds, Y, step * dt, dt, ws, method=m)
+        Yo = oracle.rk4_step(scene, Yo, step * dt, dt)
+    info = nrs.nrs_query_info(ctx, ws)
+    assert info["fell_back"] == 0
+    err = np.max(np.abs(Y.cpu().numpy().reshape(-1, 12) - Yo))
+    assert err <= 1e-10, err
+
+
+def test_errors_are_reported(ctx):
+    scene = synth.filament_scene(1, seed=0)
+    pb, host = prepare(scene)
+    ws = workspace(ctx, pb, nrs.NRS_FP32_IR)
+    sol = torch.empty(pb.n, dtype=torch.float64, device=DEV)
+    with pytest.raises(nrs.NrsError, match="workspace"):
+        nrs.nrs_solve(ctx, pb, T(host["u"]), None, sol, ws[:1000], method=nrs.NRS_FP32_IR)
+    bad = nrs.Problem(pb.x, pb.X, pb.w, T(np.full(pb.Q, pb.N + 3), torch.int32), pb.body, pb.Y,
+                      pb.eps, pb.mu)
+    with pytest.raises(nrs.NrsError, match="invalid argument"):
+        nrs.nrs_solve(ctx, bad, T(host["u"]), None, sol, ws, method=nrs.NRS_FP32_IR)
+    xn = host["x"].copy()
+    xn[0, 3] = np.nan
+    pbn = nrs.Problem(T(xn), pb.X, pb.w, pb.nu, pb.body, pb.Y, pb.eps, pb.mu)
+    with pytest.raises(nrs.NrsError, match="non-finite"):
+        nrs.nrs_solve(ctx, pbn, T(host["u"]), None, sol, ws, method=nrs.NRS_FP64_LU)
+    with pytest.raises(nrs.NrsError, match="invalid argument"):
+        nrs.nrs_solve(ctx, nrs.Problem(pb.x, pb.X, pb.w, pb.nu, pb.body, pb.Y, -1.0, 1.0),
+                      T(host["u"]), None, sol, ws)
+    with pytest.raises(ValueError):
+        nrs.nrs_solve(ctx, pb, torch.from_numpy(host["u"].ravel()), None, sol, ws)
+
+
+def test_minimal_problem(ctx):
+    """One force point, one quadrature point: A = (8 pi mu)^-1 S^eps(0) w."""
+    x = np.array([[0.3], [0.1], [-0.2]])
+    pb = nrs.Problem(T(x), T(x.copy()), T(np.array([0.5])), T(np.array([0]), torch.int32),
+                     T(np.array([-1]), torch.int32), None, 0.1, 2.0)
+    ws = workspace(ctx, pb, nrs.NRS_FP32_IR)
+    sol = torch.empty(3, dtype=torch.float64, device=DEV)
+    u = np.array([1.0, -2.0, 0.5])
+    nrs.nrs_solve(ctx, pb, T(u), None, sol, ws, method=nrs.NRS_FP32_IR)
+    a = 0.5 * (2.0 / 0.1) / (8 * math.pi * 2.0)
+    np.testing.assert_allclose(sol.cpu().numpy(), u / a, rtol=1e-12)
