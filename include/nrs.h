@@ -196,24 +196,32 @@ nrs_status nrs_query_info(nrs_ctx* ctx, void* ws, nrs_info* info);
 /* Dense LU and triangular solves on their own (the linear-algebra part of
  * Sec. 4 step 3), for tests and reuse.                                      */
 /* ------------------------------------------------------------------------ */
-/* In-place P A = L U of the n x n column-major matrix A (precision 32 or 64).
- * pivot_scope = 0: partial pivoting over the whole column; pivot_scope = 1:
- * pivots searched only inside the current 64 x 64 diagonal block (static
- * block pivoting, used with iterative refinement).  Outputs (device):
+/* In-place LU factorisation of the n x n column-major matrix A (precision 32
+ * or 64), n <= 262144.
+ * pivot_scope = 0: partial pivoting over the whole column, P A = L U.
+ * pivot_scope = 1: static block pivoting for use with iterative refinement:
+ *   pivots are searched only inside each 64 x 64 diagonal tile, and those
+ *   interchanges are not applied to the L tiles left of the diagonal; block
+ *   row m (rows 64m .. 64m+63) then satisfies
+ *     P_m (A_m - sum_{k<m} L_mk U_k) = L_mm U_m   on the columns >= 64m.
+ * Outputs (device):
  *   ipiv [n] int32: ipiv[j] = row interchanged with row j at step j (0-based,
- *        LAPACK order);
- *   perm [n] int32: the composite permutation, (P b)[i] = b[perm[i]];
+ *        LAPACK order; for scope 1 the interchanges stay inside a tile);
+ *   perm [n] int32: scope 0: the composite permutation, (P b)[i] = b[perm[i]];
+ *        scope 1: logical row i of its tile came from original row perm[i];
  *   singular_flag [1] int32: set to 1 if an exact zero pivot is met (left
  *        untouched otherwise; the caller clears it).
- * Needs no workspace. */
+ * Needs no workspace (the context keeps a few zeroed synchronisation words).
+ * Asynchronous. */
 nrs_status nrs_lu_factor(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivot_scope,
                          void* A, int64_t lda, int32_t* ipiv, int32_t* perm,
                          int32_t* singular_flag);
 
-/* Solve with the factors of nrs_lu_factor: x = A^-1 b, b and x [n] device
- * vectors of the same precision (x may not alias b). */
-nrs_status nrs_lu_solve(nrs_ctx* ctx, int64_t n, int32_t precision, const void* LU, int64_t lda,
-                        const int32_t* perm, const void* b, void* x);
+/* Solve with the factors of nrs_lu_factor (same pivot_scope and perm):
+ * x = A^-1 b, b and x [n] device vectors of the same precision (x may not
+ * alias b).  Asynchronous. */
+nrs_status nrs_lu_solve(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivot_scope,
+                        const void* LU, int64_t lda, const int32_t* perm, const void* b, void* x);
 
 /* ------------------------------------------------------------------------ */
 /* Time stepping (Sec. 4: Y' = F(Y, t), F from the solve).                   */

@@ -218,10 +218,10 @@ def nrs_lu_factor(ctx, A, lda, ipiv, perm, singular, pivot_scope=0):
                                      _ptr(singular, torch.int32, "singular")), ctx)
 
 
-def nrs_lu_solve(ctx, LU, lda, perm, b, x):
+def nrs_lu_solve(ctx, LU, lda, perm, b, x, pivot_scope=0):
     prec = 32 if LU.dtype == torch.float32 else 64
     n = int(perm.numel())
-    _check(_lib.load().nrs_lu_solve(ctx.handle, n, prec, _ptr(LU, LU.dtype, "LU"), lda,
+    _check(_lib.load().nrs_lu_solve(ctx.handle, n, prec, pivot_scope, _ptr(LU, LU.dtype, "LU"), lda,
                                     _ptr(perm, torch.int32, "perm"), _ptr(b, LU.dtype, "b"),
                                     _ptr(x, LU.dtype, "x")), ctx)
 

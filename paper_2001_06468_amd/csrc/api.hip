@@ -39,6 +39,21 @@ int32_t apply_chunks(int64_t N, int64_t Q) {
 
 bool uses_fp32(int32_t method) { return method == NRS_FP32_IR || method == NRS_FP32_GEPP_IR; }
 
+// Grow the context's zero-initialised synchronisation words to fit order n.
+nrs_status ctx_sync_words(nrs_ctx* ctx, int64_t n) {
+  const int64_t nt = lu_tiles_nt(n);
+  const int64_t need = 1 + trsv_sync_ints(n) + 4 + nt * nt;
+  if (ctx->tsync_cap >= need) return NRS_OK;
+  NRS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (ctx->tsync) NRS_HIP(ctx, hipFree(ctx->tsync));
+  ctx->tsync = nullptr;
+  ctx->tsync_cap = 0;
+  NRS_HIP(ctx, hipMalloc(&ctx->tsync, need * sizeof(int32_t)));
+  NRS_HIP(ctx, hipMemset(ctx->tsync, 0, need * sizeof(int32_t)));
+  ctx->tsync_cap = need;
+  return NRS_OK;
+}
+
 nrs_status check_problem(nrs_ctx* ctx, const nrs_problem* pb) {
   if (!pb) return fail(ctx, NRS_E_ARG, "problem is NULL");
   if (pb->N <= 0 || pb->Q <= 0 || pb->M < 0) return fail(ctx, NRS_E_ARG, "need N > 0, Q > 0, M >= 0");
@@ -46,6 +61,8 @@ nrs_status check_problem(nrs_ctx* ctx, const nrs_problem* pb) {
     return fail(ctx, NRS_E_UNSUPPORTED, "N, Q or M too large");
   if (!pb->x || !pb->X || !pb->nu || !pb->body) return fail(ctx, NRS_E_ARG, "x, X, nu, body required");
   if (pb->M > 0 && !pb->Y) return fail(ctx, NRS_E_ARG, "Y required when M > 0");
+  if (3 * pb->N + 6 * (int64_t)pb->M > 262144)
+    return fail(ctx, NRS_E_UNSUPPORTED, "more than 262144 unknowns");
   if (!(pb->eps > 0.0) || !(pb->mu > 0.0) || !std::isfinite(pb->eps) || !std::isfinite(pb->mu))
     return fail(ctx, NRS_E_ARG, "eps and mu must be positive and finite");
   return NRS_OK;
@@ -81,7 +98,9 @@ bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, Sol
   sb.d32 = ar.take<float>(n);
   sb.chunks = apply_chunks(N, Q);
   sb.part = ar.take<double>((size_t)sb.chunks * 3 * N);
-  sb.red = ar.take<double>((size_t)(n + 255) / 256 + 64);
+  sb.red = ar.take<double>(rowsum_scratch(n));
+  sb.tsync = ar.take<int32_t>(trsv_sync_ints(n));
+  sb.lu_done = ar.take<int32_t>(lu_tiles_nt(n) * lu_tiles_nt(n));
   return !ar.overflow;
 }
 
@@ -102,9 +121,10 @@ nrs_status run_fp64_lu(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, do
   const int64_t n = 3 * pb.N + 6 * (int64_t)pb.M;
   NRS_HIP(ctx, launch_assemble<double>(pb, sb.srt, sb.A64, sb.lda, s));
   NRS_HIP(ctx, launch_anorm64(n, sb.A64, sb.lda, sb.st, sb.red, s));
-  NRS_HIP(ctx, launch_lu_factor<double>(n, 0, sb.A64, sb.lda, sb.ipiv64, sb.perm64,
-                                        &sb.st->singular, s));
-  NRS_HIP(ctx, launch_lu_solve<double>(n, sb.A64, sb.lda, sb.perm64, sb.b, x, nullptr, s));
+  NRS_HIP(ctx, lu_factor_any<double>(n, 0, sb.A64, sb.lda, sb.ipiv64, sb.perm64,
+                                      &sb.st->singular, sb.lu_done, sb.st->lu_ctl, s));
+  NRS_HIP(ctx, launch_lu_solve<double>(n, 0, sb.A64, sb.lda, sb.perm64, sb.b, x, sb.tsync,
+                                       &sb.st->sync_err, nullptr, s));
   return NRS_OK;
 }
 
@@ -115,17 +135,19 @@ nrs_status run_fp32_ir(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, do
   const int64_t n = 3 * pb.N + 6 * (int64_t)pb.M;
   NRS_HIP(ctx, launch_assemble<float>(pb, sb.srt, sb.A32, sb.lda, s));
   NRS_HIP(ctx, launch_anorm32(n, sb.A32, sb.lda, sb.st, sb.red, s));
-  NRS_HIP(ctx, launch_lu_factor<float>(n, scope, sb.A32, sb.lda, sb.ipiv, sb.perm,
-                                       &sb.st->singular, s));
+  NRS_HIP(ctx, lu_factor_any<float>(n, scope, sb.A32, sb.lda, sb.ipiv, sb.perm,
+                                     &sb.st->singular, sb.lu_done, sb.st->lu_ctl, s));
   // x0 = (LU)^-1 b
   float* b32 = reinterpret_cast<float*>(sb.r);  // r is free until the first residual
   NRS_HIP(ctx, launch_convert_f32(n, sb.b, b32, s));
-  NRS_HIP(ctx, launch_lu_solve<float>(n, sb.A32, sb.lda, sb.perm, b32, sb.d32, &sb.st->stop, s));
+  NRS_HIP(ctx, launch_lu_solve<float>(n, scope, sb.A32, sb.lda, sb.perm, b32, sb.d32, sb.tsync,
+                                      &sb.st->sync_err, &sb.st->stop, s));
   NRS_HIP(ctx, launch_ir_update32(n, x, sb.d32, tol, 1, sb.st, s));
   for (int it = 0; it < max_refine; ++it) {
     NRS_HIP(ctx, launch_apply(pb, sb.srt, x, sb.d64, sb.part, sb.chunks, &sb.st->stop, s));
     NRS_HIP(ctx, launch_ir_residual2(n, sb.b, sb.d64, x, nullptr, b32, nullptr, sb.st, 0, s));
-    NRS_HIP(ctx, launch_lu_solve<float>(n, sb.A32, sb.lda, sb.perm, b32, sb.d32, &sb.st->stop, s));
+    NRS_HIP(ctx, launch_lu_solve<float>(n, scope, sb.A32, sb.lda, sb.perm, b32, sb.d32,
+                                        sb.tsync, &sb.st->sync_err, &sb.st->stop, s));
     NRS_HIP(ctx, launch_ir_update32(n, x, sb.d32, tol, 0, sb.st, s));
   }
   return NRS_OK;
@@ -157,6 +179,8 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
   const int32_t max_refine = o.max_refine > 0 ? o.max_refine : 10;
   const double tol = o.tol > 0 ? o.tol : 1e-12;
   NRS_HIP(ctx, launch_state_init(sb.st, method, s));
+  NRS_HIP(ctx, launch_fill_i32(sb.tsync, 0, trsv_sync_ints(n), s));
+  NRS_HIP(ctx, launch_fill_i32(sb.lu_done, 0, lu_tiles_nt(n) * lu_tiles_nt(n), s));
   NRS_HIP(ctx, launch_build_csr(N, Q, pb.X, pb.w, pb.nu, sb.srt, s));
   NRS_HIP(ctx, launch_check_nu(N, sb.srt.cnt, sb.st, s));
   NRS_HIP(ctx, launch_check_body(N, pb.M, pb.body, sb.st, s));
@@ -190,7 +214,9 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
   if ((st = read_state(ctx, sb.st, h2)) != NRS_OK) return st;
   h.bwd = h2.bwd;
   h.nonfinite |= h2.nonfinite;
+  h.sync_err |= h2.sync_err | h.lu_ctl[2] | h2.lu_ctl[2];
   if (hst_out) *hst_out = h;
+  if (h.sync_err) return fail(ctx, NRS_E_HIP, "LU / triangular solve: a bounded wait timed out");
   if (h.nonfinite) return fail(ctx, NRS_E_NONFINITE, "non-finite values in the solution");
   if (h.singular && h.method_used == NRS_FP64_LU)
     return fail(ctx, NRS_E_SINGULAR, "zero pivot in the FP64 factorisation");
@@ -234,6 +260,10 @@ nrs_status nrs_create(nrs_ctx** out, int device, void* stream) {
 }
 
 nrs_status nrs_destroy(nrs_ctx* ctx) {
+  if (ctx) {
+    hipSetDevice(ctx->device);
+    if (ctx->tsync) hipFree(ctx->tsync);
+  }
   delete ctx;
   return NRS_OK;
 }
@@ -369,31 +399,38 @@ nrs_status nrs_lu_factor(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t piv
   if (n <= 0 || !A || lda < n || !ipiv || !perm || !singular_flag)
     return fail(ctx, NRS_E_ARG, "bad LU arguments");
   if (pivot_scope != 0 && pivot_scope != 1) return fail(ctx, NRS_E_ARG, "pivot_scope is 0 or 1");
-  if (n >= ((int64_t)1 << 24)) return fail(ctx, NRS_E_UNSUPPORTED, "n too large");
+  if (n > 262144) return fail(ctx, NRS_E_UNSUPPORTED, "n too large");
+  if ((st = ctx_sync_words(ctx, n))) return st;
+  int32_t* ctl = ctx->tsync + 1 + trsv_sync_ints(n);
+  int32_t* done = ctl + 4;
   if (precision == 32)
-    NRS_HIP(ctx, launch_lu_factor<float>(n, pivot_scope, static_cast<float*>(A), lda, ipiv, perm,
-                                         singular_flag, ctx->stream));
+    NRS_HIP(ctx, lu_factor_any<float>(n, pivot_scope, static_cast<float*>(A), lda, ipiv, perm,
+                                      singular_flag, done, ctl, ctx->stream));
   else if (precision == 64)
-    NRS_HIP(ctx, launch_lu_factor<double>(n, pivot_scope, static_cast<double*>(A), lda, ipiv,
-                                          perm, singular_flag, ctx->stream));
+    NRS_HIP(ctx, lu_factor_any<double>(n, pivot_scope, static_cast<double*>(A), lda, ipiv, perm,
+                                       singular_flag, done, ctl, ctx->stream));
   else
     return fail(ctx, NRS_E_ARG, "precision must be 32 or 64");
   return NRS_OK;
 }
 
-nrs_status nrs_lu_solve(nrs_ctx* ctx, int64_t n, int32_t precision, const void* LU, int64_t lda,
-                        const int32_t* perm, const void* b, void* x) {
+nrs_status nrs_lu_solve(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivot_scope,
+                        const void* LU, int64_t lda, const int32_t* perm, const void* b, void* x) {
   nrs_status st = use_device(ctx);
   if (st) return st;
   if (n <= 0 || !LU || lda < n || !perm || !b || !x || b == x)
     return fail(ctx, NRS_E_ARG, "bad LU solve arguments");
+  if (pivot_scope != 0 && pivot_scope != 1) return fail(ctx, NRS_E_ARG, "pivot_scope is 0 or 1");
+  if (n > 262144) return fail(ctx, NRS_E_UNSUPPORTED, "n too large");
+  if ((st = ctx_sync_words(ctx, n))) return st;
   if (precision == 32)
-    NRS_HIP(ctx, launch_lu_solve<float>(n, static_cast<const float*>(LU), lda, perm,
+    NRS_HIP(ctx, launch_lu_solve<float>(n, pivot_scope, static_cast<const float*>(LU), lda, perm,
                                         static_cast<const float*>(b), static_cast<float*>(x),
-                                        nullptr, ctx->stream));
+                                        ctx->tsync + 1, ctx->tsync, nullptr, ctx->stream));
   else if (precision == 64)
-    NRS_HIP(ctx, launch_lu_solve<double>(n, static_cast<const double*>(LU), lda, perm,
-                                         static_cast<const double*>(b), static_cast<double*>(x),
+    NRS_HIP(ctx, launch_lu_solve<double>(n, pivot_scope, static_cast<const double*>(LU), lda,
+                                         perm, static_cast<const double*>(b),
+                                         static_cast<double*>(x), ctx->tsync + 1, ctx->tsync,
                                          nullptr, ctx->stream));
   else
     return fail(ctx, NRS_E_ARG, "precision must be 32 or 64");

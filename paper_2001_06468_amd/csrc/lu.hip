@@ -1,10 +1,10 @@
 // Dense LU factorisation with row pivoting and triangular solves (the
 // linear-algebra step 3 of Sec. 4), FP32 and FP64.
 //
-// Right-looking blocked algorithm with panel width kNb:
+// This file holds the partial-pivoting form (GEPP); static block pivoting
+// lives in lu_tiles.hip.  Right-looking blocked algorithm with panel width kNb:
 //   panel   : one workgroup factors the n-k x jb panel (pivot search over the
-//             whole column, or only inside the diagonal block for static block
-//             pivoting);
+//             whole column);
 //   swap    : one wavefront per column applies the panel's row interchanges
 //             (lanes hold the jb pivot rows, interchanges with rows below the
 //             panel are resolved in registers) and, right of the panel, solves
@@ -104,7 +104,8 @@ __global__ __launch_bounds__(kPanelThreads) void k_getf2(int64_t n, int64_t k, i
 }
 
 // Columns handled: [0, k) (interchanges only), [k+jb, n) (interchanges and
-// the unit-lower solve), and the permutation column (interchanges only).
+// the unit-lower solve for U12), and the permutation column (interchanges
+// only): one wavefront per column.
 template <class T>
 __global__ __launch_bounds__(256) void k_laswp_trsm(int64_t n, int64_t k, int jb,
                                                     T* __restrict__ A, int64_t lda,
@@ -181,12 +182,16 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 template <class T>
 struct Mfma;
+// Output row held in register r of lane l (column is l % 16): the FP32
+// instruction gives each lane four consecutive rows, the FP64 one rows
+// l/16 + 4r (measured on gfx950).
 template <>
 struct Mfma<float> {
   typedef floatx4 acc_t;
   static __device__ inline acc_t run(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 template <>
 struct Mfma<double> {
@@ -194,6 +199,7 @@ struct Mfma<double> {
   static __device__ inline acc_t run(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
 constexpr int kGT = 128;       // output tile edge per workgroup
@@ -204,7 +210,7 @@ constexpr int kGS = kGT + kGPad;
 // C (m x nc) -= A (m x K) * B (K x nc); all column-major with leading dim lda.
 // 256 threads = 2 x 2 waves, each wave a 64 x 64 sub-tile of 4 x 4 MFMA blocks.
 // MFMA 16x16x4 operand layout: lane l holds A[l%16][l/16] and B[l/16][l%16];
-// output register r of lane l is C[4*(l/16)+r][l%16].
+// the output row of register r is Mfma<T>::row(l, r), the column l%16.
 template <class T>
 __global__ __launch_bounds__(256) void k_gemm_update(int64_t m, int64_t nc, int K,
                                                      const T* __restrict__ Ap,
@@ -252,14 +258,14 @@ __global__ __launch_bounds__(256) void k_gemm_update(int64_t m, int64_t nc, int 
     }
     __syncthreads();
   }
-  const int lr = 4 * (lane >> 4), lc = lane & 15;
+  const int lc = lane & 15;
   for (int a = 0; a < 4; ++a) {
     for (int b = 0; b < 4; ++b) {
       const int64_t gj = j0 + wc + b * 16 + lc;
       if (gj >= nc) continue;
       T* cc = C + gj * lda;
       for (int r = 0; r < 4; ++r) {
-        const int64_t gi = i0 + wr + a * 16 + lr + r;
+        const int64_t gi = i0 + wr + a * 16 + Mfma<T>::row(lane, r);
         if (gi < m) cc[gi] -= acc[a][b][r];
       }
     }
@@ -271,12 +277,13 @@ __global__ void k_iota(int32_t* p, int64_t n) {
   if (i < n) p[i] = (int32_t)i;
 }
 
+// x = b[perm] (perm may be NULL: plain copy)
 template <class T>
 __global__ void k_gather(int64_t n, const int32_t* __restrict__ perm, const T* __restrict__ b,
                          T* __restrict__ x, const int32_t* __restrict__ stop) {
   if (stop && *stop) return;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i < n) x[i] = b[perm[i]];
+  if (i < n) x[i] = perm ? b[perm[i]] : b[i];
 }
 
 // Sequential composition of LAPACK-style interchanges into a permutation
@@ -292,73 +299,110 @@ __global__ void k_ipiv_to_perm(int64_t n, const int32_t* __restrict__ ipiv, int3
   }
 }
 
-constexpr int kTrsvThreads = 1024;
+// Multi-workgroup triangular solves.  Row block b (64 rows) is owned by one
+// workgroup; blocks are handed out by an atomic ticket in dispatch order, so
+// a workgroup only ever waits for blocks whose owners are already running.
+// It folds in the contribution of each solved block as its flag appears,
+// then solves its diagonal block with one wavefront and publishes it.
+// sync[0] = ticket, sync[1] = finished count, sync[2 + b] = flag of block b;
+// the last workgroup to finish clears them, so the buffer is zero between
+// calls (it must be zero before the first).  Waits are bounded: a wait that
+// times out sets *err and the kernel still runs to completion.
 constexpr int kTb = 64;
+constexpr int kTrsvThreads = 256;
+constexpr int64_t kSpinLimit = 1 << 22;
 
-// Single-workgroup blocked forward substitution with the unit lower factor.
-template <class T>
-__global__ __launch_bounds__(kTrsvThreads) void k_trsv_lower(int64_t n,
-                                                             const T* __restrict__ LU,
-                                                             int64_t lda, T* __restrict__ x,
-                                                             const int32_t* __restrict__ stop) {
-  if (stop && *stop) return;
-  __shared__ T xs[kTb];
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  for (int64_t k = 0; k < n; k += kTb) {
-    const int jb = (int)min<int64_t>(kTb, n - k);
-    if (wid == 0) {
-      T v = lane < jb ? x[k + lane] : T(0);
-      for (int t = 0; t < jb; ++t) {
-        const T xt = __shfl(v, t);
-        if (lane > t && lane < jb) v -= LU[(k + lane) + (k + t) * lda] * xt;
-      }
-      if (lane < jb) {
-        x[k + lane] = v;
-        xs[lane] = v;
-      }
-    }
-    __syncthreads();
-    for (int64_t i = k + jb + tid; i < n; i += kTrsvThreads) {
-      T s = T(0);
-      for (int t = 0; t < jb; ++t) s += LU[i + (k + t) * lda] * xs[t];
-      x[i] -= s;
-    }
-    __syncthreads();
-  }
+__device__ inline int32_t ld_relaxed(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_release(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Single-workgroup blocked backward substitution with the upper factor.
-template <class T>
-__global__ __launch_bounds__(kTrsvThreads) void k_trsv_upper(int64_t n,
-                                                             const T* __restrict__ LU,
-                                                             int64_t lda, T* __restrict__ x,
-                                                             const int32_t* __restrict__ stop) {
+// LOCALP: the factors come from the tile LU with static block pivoting; the
+// interchanges of block row b (lperm, block-local) are applied to the
+// partial result b_b - sum_k L_bk y_k before the diagonal solve.
+template <class T, bool UPPER, bool LOCALP>
+__global__ __launch_bounds__(kTrsvThreads) void k_trsv(int64_t n, const T* __restrict__ LU,
+                                                       int64_t lda, T* __restrict__ x,
+                                                       int32_t* __restrict__ sync,
+                                                       const int32_t* __restrict__ stop,
+                                                       int32_t* __restrict__ err,
+                                                       const int32_t* __restrict__ lperm) {
   if (stop && *stop) return;
-  __shared__ T xs[kTb];
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  __shared__ int s_t;
+  __shared__ T s_part[kTrsvThreads / 64][kTb];
+  __shared__ T s_x[kTb];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t nblk = (n + kTb - 1) / kTb;
-  for (int64_t bk = nblk - 1; bk >= 0; --bk) {
-    const int64_t k = bk * kTb;
-    const int jb = (int)min<int64_t>(kTb, n - k);
-    if (wid == 0) {
-      T v = lane < jb ? x[k + lane] : T(0);
-      for (int t = jb - 1; t >= 0; --t) {
-        if (lane == t) v = v / LU[(k + t) + (k + t) * lda];
-        const T xt = __shfl(v, t);
-        if (lane < t) v -= LU[(k + lane) + (k + t) * lda] * xt;
+  if (tid == 0) s_t = atomicAdd(&sync[0], 1);
+  __syncthreads();
+  const int64_t t = s_t;
+  const int64_t b = UPPER ? nblk - 1 - t : t;
+  const int64_t r0 = b * kTb;
+  const int rows = (int)min<int64_t>(kTb, n - r0);
+  const int64_t row = r0 + lane;
+  int32_t* flags = sync + 2;
+  T acc = T(0);
+  const int64_t jfirst = UPPER ? nblk - 1 : 0;
+  const int64_t jstep = UPPER ? -1 : 1;
+  for (int64_t j = jfirst; j != b; j += jstep) {
+    if (tid == 0) {
+      int64_t spins = 0;
+      while (ld_relaxed(&flags[j]) == 0) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+          atomicExch(err, 1);
+          break;
+        }
       }
-      if (lane < jb) {
-        x[k + lane] = v;
-        xs[lane] = v;
-      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
-    for (int64_t i = tid; i < k; i += kTrsvThreads) {
-      T s = T(0);
-      for (int t = 0; t < jb; ++t) s += LU[i + (k + t) * lda] * xs[t];
-      x[i] -= s;
+    // wave w covers columns j*64 + w*16 .. +16 of this block row
+    const int64_t c0 = j * kTb + w * 16;
+    const int cn = (int)max<int64_t>(0, min<int64_t>(16, n - c0));
+    if (row < n) {
+      for (int c = 0; c < cn; ++c) acc += LU[row + (c0 + c) * lda] * x[c0 + c];
     }
-    __syncthreads();
+  }
+  s_part[w][lane] = acc;
+  __syncthreads();
+  if (w == 0) {
+    T v = T(0);
+    if (lane < rows) {
+      v = x[row];
+      for (int q = 0; q < kTrsvThreads / 64; ++q) v -= s_part[q][lane];
+    }
+    if (LOCALP && !UPPER) {
+      s_x[lane] = v;
+      __builtin_amdgcn_wave_barrier();
+      if (lane < rows) v = s_x[lperm[row] - r0];
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (!UPPER) {
+      for (int c = 0; c < rows; ++c) {
+        const T xc = __shfl(v, c);
+        if (lane > c && lane < rows) v -= LU[row + (r0 + c) * lda] * xc;
+      }
+    } else {
+      for (int c = rows - 1; c >= 0; --c) {
+        if (lane == c) v = v / LU[row + (r0 + c) * lda];
+        const T xc = __shfl(v, c);
+        if (lane < c) v -= LU[row + (r0 + c) * lda] * xc;
+      }
+    }
+    if (lane < rows) x[row] = v;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    st_release(&flags[b], 1);
+    const int32_t done = atomicAdd(&sync[1], 1);
+    if (done == nblk - 1) {
+      for (int64_t q = 0; q < nblk; ++q) flags[q] = 0;
+      sync[0] = 0;
+      sync[1] = 0;
+    }
   }
 }
 
@@ -366,18 +410,19 @@ inline dim3 grid1(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)); 
 
 }  // namespace
 
+// Blocked LU with partial pivoting over whole columns (GEPP).
 template <class T>
-hipError_t launch_lu_factor(int64_t n, int32_t scope, T* A, int64_t lda, int32_t* ipiv,
-                            int32_t* perm, int32_t* sing, hipStream_t s) {
+hipError_t launch_lu_factor(int64_t n, T* A, int64_t lda, int32_t* ipiv, int32_t* perm,
+                            int32_t* sing, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_iota, grid1(n, 256), dim3(256), 0, s, perm, n);
   for (int64_t k = 0; k < n; k += kNb) {
     const int jb = (int)std::min<int64_t>(kNb, n - k);
-    hipLaunchKernelGGL(k_getf2<T>, dim3(1), dim3(kPanelThreads), 0, s, n, k, jb, scope, A, lda,
-                       ipiv, sing);
+    hipLaunchKernelGGL(k_getf2<T>, dim3(1), dim3(kPanelThreads), 0, s, n, k, jb, 0, A, lda, ipiv,
+                       sing);
     const int64_t ncols = (n - jb) + 1;
-    hipLaunchKernelGGL(k_laswp_trsm<T>, grid1(ncols, 4), dim3(256), 0, s, n, k, jb, A, lda,
-                       ipiv, perm);
+    hipLaunchKernelGGL(k_laswp_trsm<T>, dim3((unsigned)((ncols + 3) / 4)), dim3(256), 0, s, n, k,
+                       jb, A, lda, ipiv, perm);
     const int64_t rest = n - k - jb;
     if (rest > 0) {
       dim3 g((unsigned)((rest + kGT - 1) / kGT), (unsigned)((rest + kGT - 1) / kGT));
@@ -390,12 +435,21 @@ hipError_t launch_lu_factor(int64_t n, int32_t scope, T* A, int64_t lda, int32_t
 }
 
 template <class T>
-hipError_t launch_lu_solve(int64_t n, const T* LU, int64_t lda, const int32_t* perm, const T* b,
-                           T* x, const int32_t* stop, hipStream_t s) {
+hipError_t launch_lu_solve(int64_t n, int32_t scope, const T* LU, int64_t lda,
+                           const int32_t* perm, const T* b, T* x, int32_t* sync, int32_t* err,
+                           const int32_t* stop, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gather<T>, grid1(n, 256), dim3(256), 0, s, n, perm, b, x, stop);
-  hipLaunchKernelGGL(k_trsv_lower<T>, dim3(1), dim3(kTrsvThreads), 0, s, n, LU, lda, x, stop);
-  hipLaunchKernelGGL(k_trsv_upper<T>, dim3(1), dim3(kTrsvThreads), 0, s, n, LU, lda, x, stop);
+  const unsigned nblk = (unsigned)((n + kTb - 1) / kTb);
+  hipLaunchKernelGGL(k_gather<T>, grid1(n, 256), dim3(256), 0, s, n, scope ? nullptr : perm, b,
+                     x, stop);
+  if (scope)
+    hipLaunchKernelGGL((k_trsv<T, false, true>), dim3(nblk), dim3(kTrsvThreads), 0, s, n, LU,
+                       lda, x, sync, stop, err, perm);
+  else
+    hipLaunchKernelGGL((k_trsv<T, false, false>), dim3(nblk), dim3(kTrsvThreads), 0, s, n, LU,
+                       lda, x, sync, stop, err, perm);
+  hipLaunchKernelGGL((k_trsv<T, true, false>), dim3(nblk), dim3(kTrsvThreads), 0, s, n, LU, lda,
+                     x, sync, stop, err, perm);
   return hipGetLastError();
 }
 
@@ -405,13 +459,15 @@ hipError_t launch_ipiv_to_perm(int64_t n, const int32_t* ipiv, int32_t* perm, hi
   return hipGetLastError();
 }
 
-template hipError_t launch_lu_factor<float>(int64_t, int32_t, float*, int64_t, int32_t*, int32_t*,
+template hipError_t launch_lu_factor<float>(int64_t, float*, int64_t, int32_t*, int32_t*,
                                             int32_t*, hipStream_t);
-template hipError_t launch_lu_factor<double>(int64_t, int32_t, double*, int64_t, int32_t*,
-                                             int32_t*, int32_t*, hipStream_t);
-template hipError_t launch_lu_solve<float>(int64_t, const float*, int64_t, const int32_t*,
-                                           const float*, float*, const int32_t*, hipStream_t);
-template hipError_t launch_lu_solve<double>(int64_t, const double*, int64_t, const int32_t*,
-                                            const double*, double*, const int32_t*, hipStream_t);
+template hipError_t launch_lu_factor<double>(int64_t, double*, int64_t, int32_t*, int32_t*,
+                                             int32_t*, hipStream_t);
+template hipError_t launch_lu_solve<float>(int64_t, int32_t, const float*, int64_t,
+                                           const int32_t*, const float*, float*, int32_t*,
+                                           int32_t*, const int32_t*, hipStream_t);
+template hipError_t launch_lu_solve<double>(int64_t, int32_t, const double*, int64_t,
+                                            const int32_t*, const double*, double*, int32_t*,
+                                            int32_t*, const int32_t*, hipStream_t);
 
 }  // namespace nrs

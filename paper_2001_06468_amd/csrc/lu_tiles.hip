@@ -1,0 +1,434 @@
+// Persistent tile LU with static block pivoting (the dense solve of Sec. 4,
+// step 3), for one system or a batch of independent systems of different
+// sizes in a single launch.
+//
+// The matrix is cut into 64 x 64 tiles.  Tile (i, j) is finished by exactly
+// one task, in "band" m = min(i, j):
+//   update : C = A_ij - sum_{k<m} L_ik U_kj   (matrix cores, 16x16x4 MFMA),
+//            each rank-64 term folded in as soon as its two tiles are final;
+//   then    i == j : partial pivoting inside the tile (one wavefront, rows in
+//                    registers, pivot rows relabelled instead of moved);
+//           i <  j : U_mj = L_mm^-1 P_m C   (one lane per column);
+//           i >  j : L_im = C U_mm^-1       (one lane per row).
+// Tasks are numbered band by band (system by system inside a band), which is
+// a topological order; each workgroup of the single launch takes its task
+// number from an atomic ticket, so a task only waits for tasks whose owners
+// already run.  Every wait is bounded (a timeout raises ctl[2] and the kernel
+// still completes), and the last workgroup to finish clears the ticket and
+// all completion flags.
+//
+// Because interchanges stay inside a diagonal tile, L tiles left of the
+// diagonal keep the unpermuted row order: block row m satisfies
+//   P_m (A_m - sum_{k<m} L_mk U_k) = L_mm U_m   (columns >= m),
+// and the forward substitution applies P_m after the block-row update.
+#include <algorithm>
+#include <vector>
+
+#include "nrs_internal.h"
+
+namespace nrs {
+
+namespace {
+
+constexpr int TB = 64;
+constexpr int kLuThreads = 256;
+constexpr int kLS = 80;  // LDS row stride of the MFMA staging tiles
+constexpr int kCS = 65;  // LDS column stride of the working tile
+constexpr int64_t kLuSpin = 1 << 22;
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct Mf;
+template <>
+struct Mf<float> {
+  typedef floatx4 acc_t;
+  static __device__ inline acc_t run(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <>
+struct Mf<double> {
+  typedef doublex4 acc_t;
+  static __device__ inline acc_t run(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+__device__ inline void wait_flag(const int32_t* f, int32_t* err) {
+  int64_t spins = 0;
+  while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    __builtin_amdgcn_s_sleep(2);
+    if (++spins > kLuSpin) {
+      atomicExch(err, 1);
+      break;
+    }
+  }
+}
+
+template <class T>
+__device__ inline T ld_pad(const T* A, int64_t lda, int64_t n, int64_t r, int64_t c) {
+  if (r < n && c < n) return A[r + c * lda];
+  return r == c ? T(1) : T(0);
+}
+
+template <class T>
+__device__ inline uint64_t pivot_key(T v, int lane) {
+  const double a = fabs((double)v);
+  const uint64_t bits = (uint64_t)__double_as_longlong(a);
+  return (bits & ~uint64_t(127)) | 64u | (uint64_t)(63 - lane);
+}
+
+// Small and working arrays first so their LDS offsets fit the 16-bit
+// immediate offset of ds instructions.
+template <class T>
+struct Shared {
+  T Cs[TB * kCS];
+  T row[TB];
+  unsigned long long key[TB];
+  int32_t perm[TB];
+  int32_t task[4];
+  T Ls[TB * kLS];
+  T Us[TB * kLS];
+};
+
+// Partial pivoting inside the diagonal tile held in S.Cs (one wavefront).
+template <class T>
+__device__ __attribute__((noinline)) void diag_factor(Shared<T>& S, const LuSys<T>& sy, int64_t m, int32_t* sing) {
+  const int lane = threadIdx.x;  // caller: wave 0 only
+  T v[TB];
+#pragma unroll
+  for (int c = 0; c < TB; ++c) v[c] = S.Cs[c * kCS + lane];
+  S.key[lane] = 0ull;
+  __builtin_amdgcn_wave_barrier();
+  bool used = false;
+  int myj = 0;
+  bool zero = false;
+#pragma unroll
+  for (int j = 0; j < TB; ++j) {
+    const unsigned long long key = used ? 0ull : (unsigned long long)pivot_key(v[j], lane);
+    atomicMax(&S.key[j], key);
+    __builtin_amdgcn_wave_barrier();
+    const unsigned long long best = S.key[j];
+    const int p = 63 - (int)(best & 63ull);
+    const T piv = __shfl(v[j], p);
+    if (lane == p) {
+#pragma unroll
+      for (int c = j + 1; c < TB; ++c) S.row[c] = v[c];
+      used = true;
+      myj = j;
+    }
+    if (lane == 0) S.perm[j] = p;
+    __builtin_amdgcn_wave_barrier();
+    if (piv == T(0)) {
+      zero = true;
+    } else if (!used) {
+      const T l = v[j] / piv;
+      v[j] = l;
+#pragma unroll
+      for (int c = j + 1; c < TB; ++c) v[c] -= l * S.row[c];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (zero && lane == 0) atomicExch(sing, 1);
+  // this lane holds logical row myj of the factors
+#pragma unroll
+  for (int c = 0; c < TB; ++c) S.Cs[c * kCS + myj] = v[c];
+  // permutation of this block row: logical row j <- original row perm[j]
+  const int64_t r0 = m * TB;
+  const int64_t gj = r0 + lane;
+  if (gj < sy.n) sy.lperm[gj] = (int32_t)(r0 + S.perm[lane]);
+}
+
+// U_mj = L_mm^-1 P_m C, in place in the working tile S.Cs (one wavefront,
+// lane = column); L_mm is staged row-major in S.Ls, the permutation in S.perm.
+template <class T>
+__device__ __attribute__((noinline)) void col_solve(Shared<T>& S) {
+  const int lane = threadIdx.x & 63;
+  T x[TB];
+#pragma unroll
+  for (int r = 0; r < TB; ++r) x[r] = S.Cs[lane * kCS + S.perm[r]];
+#pragma unroll
+  for (int r = 1; r < TB; ++r) {
+    T sum = x[r];
+#pragma unroll
+    for (int q = 0; q < r; ++q) sum -= S.Ls[r * kLS + q] * x[q];
+    x[r] = sum;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int r = 0; r < TB; ++r) S.Cs[lane * kCS + r] = x[r];
+}
+
+// L_im = C U_mm^-1, in place in S.Cs (one wavefront, lane = row).  With
+// U = D Uh (D its diagonal, Uh unit upper), Y = C Uh^-1 by substitution and
+// L = Y D^-1.  S.Us holds Uh column-major, S.row the reciprocals of D.
+template <class T>
+__device__ __attribute__((noinline)) void row_solve(Shared<T>& S) {
+  const int lane = threadIdx.x & 63;
+  T x[TB];
+#pragma unroll
+  for (int c = 0; c < TB; ++c) x[c] = S.Cs[c * kCS + lane];
+#pragma unroll
+  for (int c = 1; c < TB; ++c) {
+    T sum = x[c];
+#pragma unroll
+    for (int q = 0; q < c; ++q) sum -= x[q] * S.Us[c * kLS + q];
+    x[c] = sum;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int c = 0; c < TB; ++c) S.Cs[c * kCS + lane] = x[c] * S.row[c];
+}
+
+// LAPACK-style interchange sequence of one diagonal tile (lane 0).
+template <class T>
+__device__ void diag_ipiv(Shared<T>& S, const LuSys<T>& sy, int64_t m) {
+  if (threadIdx.x != 0 || !sy.ipiv) return;
+  int pos[TB], at[TB];  // pos[orig] = current position, at[position] = orig row
+  for (int r = 0; r < TB; ++r) pos[r] = at[r] = r;
+  const int64_t r0 = m * TB;
+  for (int j = 0; j < TB; ++j) {
+    const int orig = S.perm[j];
+    const int q = pos[orig];
+    if (r0 + j < sy.n) sy.ipiv[r0 + j] = (int32_t)(r0 + q);
+    const int oj = at[j];
+    at[j] = orig;
+    pos[orig] = j;
+    at[q] = oj;
+    pos[oj] = q;
+  }
+}
+
+// One tile task: update, then factor / solve, store, publish.
+template <class T>
+__device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
+                                                   int64_t j, int64_t m, int32_t* err) {
+  typedef typename Mf<T>::acc_t acc_t;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t nt = sy.nt, n = sy.n, lda = sy.lda;
+    T* A = sy.A;
+    // ---- update: acc = sum_{k<m} L_ik U_kj ----
+    acc_t acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[a][b][r] = T(0);
+    const int qi = (w >> 1) * 32, qj = (w & 1) * 32;
+    for (int64_t k = 0; k < m; ++k) {
+      if (tid == 0) {
+        wait_flag(&sy.done[i * nt + k], err);
+        wait_flag(&sy.done[k * nt + j], err);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      __syncthreads();
+      {
+        const int r = tid & 63, c0 = tid >> 6;
+#pragma unroll 4
+        for (int q = 0; q < 16; ++q) {
+          const int c = c0 + 4 * q;
+          S.Ls[c * kLS + r] = ld_pad(A, lda, n, i * TB + r, k * TB + c);
+          S.Us[r * kLS + c] = ld_pad(A, lda, n, k * TB + r, j * TB + c);
+        }
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int kk = 0; kk < TB; kk += 4) {
+        const int kr = kk + (lane >> 4), li = lane & 15;
+        const T a0 = S.Ls[kr * kLS + qi + li], a1 = S.Ls[kr * kLS + qi + 16 + li];
+        const T b0 = S.Us[kr * kLS + qj + li], b1 = S.Us[kr * kLS + qj + 16 + li];
+        acc[0][0] = Mf<T>::run(a0, b0, acc[0][0]);
+        acc[0][1] = Mf<T>::run(a0, b1, acc[0][1]);
+        acc[1][0] = Mf<T>::run(a1, b0, acc[1][0]);
+        acc[1][1] = Mf<T>::run(a1, b1, acc[1][1]);
+      }
+    }
+    // ---- C = A_ij - acc into the working tile ----
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rr = qi + a * 16 + Mf<T>::row(lane, r);
+          const int cc = qj + b * 16 + (lane & 15);
+          S.Cs[cc * kCS + rr] = ld_pad(A, lda, n, i * TB + rr, j * TB + cc) - acc[a][b][r];
+        }
+    if (i != j) {
+      if (tid == 0) {
+        wait_flag(&sy.done[m * nt + m], err);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+    }
+    __syncthreads();
+    if (i == j) {
+      if (w == 0) diag_factor<T>(S, sy, m, sy.sing);
+    } else if (i < j) {
+      // U_mj = L_mm^-1 P_m C; L_mm staged row-major, lane = column
+      for (int e = tid; e < TB * TB; e += kLuThreads) {
+        const int r = e / TB, c = e % TB;
+        S.Ls[r * kLS + c] = ld_pad(A, lda, n, m * TB + r, m * TB + c);
+      }
+      if (tid < TB) {
+        const int64_t g = m * TB + tid;
+        S.perm[tid] = g < n ? (int)(sy.lperm[g] - m * TB) : tid;
+      }
+      __syncthreads();
+      if (w == 0) col_solve<T>(S);
+    } else {
+      // L_im = C U_mm^-1; U_mm staged column-major, lane = row
+      // Uh = D^-1 U staged column-major, 1 / diag in S.row
+      for (int e = tid; e < TB * TB; e += kLuThreads) {
+        const int c = e / TB, r = e % TB;
+        const T d = ld_pad(A, lda, n, m * TB + r, m * TB + r);
+        S.Us[c * kLS + r] = ld_pad(A, lda, n, m * TB + r, m * TB + c) / d;
+        if (r == c) S.row[c] = T(1) / d;
+      }
+      __syncthreads();
+      if (w == 0) row_solve<T>(S);
+    }
+    __syncthreads();
+    {  // store the finished tile, one column per 64 threads (coalesced)
+      const int64_t rr = i * TB + lane;
+      if (rr < n) {
+        for (int c = w; c < TB; c += kLuThreads / TB) {
+          const int64_t cc = j * TB + c;
+          if (cc < n) A[rr + cc * lda] = S.Cs[c * kCS + lane];
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      __hip_atomic_store(&sy.done[i * nt + j], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// One workgroup per task.  The ticket, not blockIdx, decides the task, so a
+// workgroup only waits for tasks taken by workgroups that already run.
+template <class T>
+__global__ __launch_bounds__(kLuThreads) void k_lu_tiles(LuBatch<T> bt, int32_t* ctl) {
+  __shared__ Shared<T> S;
+  const int tid = threadIdx.x;
+  const int32_t B = bt.B;
+  int32_t* err = ctl + 2;
+  if (tid == 0) S.task[0] = atomicAdd(&ctl[0], 1);
+  __syncthreads();
+  const int32_t t = S.task[0];
+  if (t < bt.total) {
+    // (band, system) of the ticket: last prefix entry <= t.  One system:
+    // band m starts at m (2 nt - m).
+    int m, s, p;
+    if (bt.sys == nullptr) {
+      const int64_t ntt = bt.one.nt;
+      int lo = 0, hi = (int)ntt;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)mid * (2 * ntt - mid) <= t) lo = mid; else hi = mid;
+      }
+      m = lo;
+      s = 0;
+      p = (int)(t - (int64_t)lo * (2 * ntt - lo));
+    } else {
+      int lo = 0, hi = bt.nbands * B;  // pref[lo] <= t < pref[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (bt.pref[mid] <= t) lo = mid; else hi = mid;
+      }
+      m = lo / B;
+      s = lo % B;
+      p = t - bt.pref[lo];
+    }
+    int64_t i, j;
+    if (p == 0) {
+      i = j = m;
+    } else if (p & 1) {
+      i = m;
+      j = m + (p + 1) / 2;
+    } else {
+      i = m + p / 2;
+      j = m;
+    }
+    const LuSys<T> sy = bt.sys ? bt.sys[s] : bt.one;
+    run_task<T>(S, sy, i, j, m, err);
+    if (i == j) diag_ipiv<T>(S, sy, m);
+  }
+  // the last workgroup to finish clears the ticket and every flag
+  __syncthreads();
+  if (tid == 0) S.task[1] = atomicAdd(&ctl[1], 1);
+  __syncthreads();
+  if (S.task[1] == (int)gridDim.x - 1) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    for (int q = 0; q < B; ++q) {
+      const LuSys<T> sy = bt.sys ? bt.sys[q] : bt.one;
+      const int64_t nf = (int64_t)sy.nt * sy.nt;
+      for (int64_t e = tid; e < nf; e += kLuThreads) sy.done[e] = 0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      ctl[0] = 0;
+      ctl[1] = 0;
+    }
+  }
+}
+
+}  // namespace
+
+// Ticket prefix over (band, system): pref[b*B + s] = first ticket of band b
+// of system s; band b of a system with nt tiles has 2(nt-b)-1 tasks.
+void lu_task_prefix(const int32_t* nts, int32_t B, std::vector<int32_t>& pref, int32_t& nbands) {
+  nbands = 0;
+  for (int s = 0; s < B; ++s) nbands = std::max(nbands, nts[s]);
+  pref.assign((size_t)nbands * B + 1, 0);
+  int32_t acc = 0;
+  for (int b = 0; b < nbands; ++b)
+    for (int s = 0; s < B; ++s) {
+      pref[(size_t)b * B + s] = acc;
+      if (b < nts[s]) acc += 2 * (nts[s] - b) - 1;
+    }
+  pref[(size_t)nbands * B] = acc;
+}
+
+template <class T>
+hipError_t launch_lu_tiles(const LuBatch<T>& bt, int32_t* ctl, hipStream_t s) {
+  if (bt.total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_lu_tiles<T>, dim3((unsigned)bt.total), dim3(kLuThreads), 0, s, bt, ctl);
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t lu_factor_any(int64_t n, int32_t scope, T* A, int64_t lda, int32_t* ipiv,
+                         int32_t* perm, int32_t* sing, int32_t* done, int32_t* ctl,
+                         hipStream_t s) {
+  if (scope == 0) return launch_lu_factor<T>(n, A, lda, ipiv, perm, sing, s);
+  LuBatch<T> bt;
+  const int64_t nt = lu_tiles_nt(n);
+  bt.one.A = A;
+  bt.one.lda = lda;
+  bt.one.n = n;
+  bt.one.nt = nt;
+  bt.one.lperm = perm;
+  bt.one.ipiv = ipiv;
+  bt.one.done = done;
+  bt.one.sing = sing;
+  bt.sys = nullptr;
+  bt.pref = nullptr;
+  bt.B = 1;
+  bt.nbands = (int32_t)nt;
+  bt.total = (int32_t)(nt * nt);
+  return launch_lu_tiles<T>(bt, ctl, s);
+}
+
+template hipError_t lu_factor_any<float>(int64_t, int32_t, float*, int64_t, int32_t*, int32_t*,
+                                         int32_t*, int32_t*, int32_t*, hipStream_t);
+template hipError_t lu_factor_any<double>(int64_t, int32_t, double*, int64_t, int32_t*, int32_t*,
+                                          int32_t*, int32_t*, int32_t*, hipStream_t);
+template hipError_t launch_lu_tiles<float>(const LuBatch<float>&, int32_t*, hipStream_t);
+template hipError_t launch_lu_tiles<double>(const LuBatch<double>&, int32_t*, hipStream_t);
+
+}  // namespace nrs

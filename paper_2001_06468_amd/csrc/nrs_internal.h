@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/nrs.h"
 
@@ -13,6 +14,11 @@ struct nrs_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string last_error;
+  // zero-initialised synchronisation words for nrs_lu_factor / nrs_lu_solve:
+  // [0] solve timeout flag, [1..] triangular-solve words, then the tile-LU
+  // control words [4] and tile flags [nt*nt]; kept zero by the kernels
+  int32_t* tsync = nullptr;
+  int64_t tsync_cap = 0;
 };
 
 namespace nrs {
@@ -35,7 +41,10 @@ struct SolveState {
   int32_t method_used;
   int32_t fell_back;
   int32_t nonfinite;
-  int32_t stop;         // converged || failed: refinement kernels become no-ops
+  int32_t stop;
+  int32_t sync_err;     // a bounded wait in the triangular solves timed out
+  int32_t pad2;
+  int32_t lu_ctl[4];    // tile LU: ticket, exit count, wait-timeout flag         // converged || failed: refinement kernels become no-ops
   double bwd;           // normwise backward error of the last residual
   double corr;          // last |d|/|x|
   double prev_corr;
@@ -64,6 +73,9 @@ struct Arena {
 
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 inline int64_t lda_for(int64_t n) { return round_up(n < 1 ? 1 : n, 64); }
+// doubles of scratch the |A|_inf kernels need
+inline int64_t rowsum_chunks(int64_t n) { return n <= 4096 ? (n + 255) / 256 : 16; }
+inline int64_t rowsum_scratch(int64_t n) { return rowsum_chunks(n) * n + 1024; }
 
 // Sorted quadrature data, produced by build_csr.
 struct Sorted {
@@ -93,13 +105,42 @@ struct SolveBuffers {
   float* d32;        // [n]
   double* d64;       // [n]
   double* part;      // [chunks][3N] partial products of the matrix-free apply
-  double* red;       // [64] reduction scratch
+  double* red;       // reduction scratch
+  int32_t* tsync;    // triangular-solve synchronisation words (zero between calls)
+  int32_t* lu_done;  // [nt*nt] tile flags of the tile LU
   SolveState* st;
   int32_t chunks;
 };
 
 size_t solve_workspace_bytes(int64_t N, int64_t Q, int32_t M, int32_t method);
 bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, SolveBuffers& sb);
+
+// One system of the persistent tile LU (64 x 64 tiles, static block pivoting).
+template <class T>
+struct LuSys {
+  T* A;             // column-major, leading dimension lda
+  int64_t lda;
+  int64_t n;
+  int64_t nt;       // tiles per dimension, ceil(n / 64)
+  int32_t* lperm;   // [n] block-local permutation: logical row r <- original row lperm[r]
+  int32_t* ipiv;    // [n] LAPACK-style interchanges (may be NULL)
+  int32_t* done;    // [nt * nt] tile completion flags, zero before the launch
+  int32_t* sing;    // set to 1 on an exact zero pivot
+};
+template <class T>
+struct LuBatch {
+  LuSys<T> one;            // used when sys == NULL (single system)
+  const LuSys<T>* sys;     // device array of B systems, or NULL
+  const int32_t* pref;     // device ticket prefix over (band, system), or NULL
+  int32_t B;
+  int32_t nbands;
+  int32_t total;           // number of tasks
+};
+// ctl: [0] ticket, [1] exit count (both zero before launch, cleared by the
+// kernel), [2] sticky wait-timeout flag
+template <class T>
+hipError_t launch_lu_tiles(const LuBatch<T>& bt, int32_t* ctl, hipStream_t s);
+void lu_task_prefix(const int32_t* nts, int32_t B, std::vector<int32_t>& pref, int32_t& nbands);
 
 // ---- kernels / launchers (each returns hipError_t of the launch) ----
 hipError_t launch_geometry(const nrs_scene& sc, double t, const double* Y, double* x, double* X,
@@ -116,11 +157,21 @@ hipError_t launch_rhs(int64_t N, int32_t M, const double* u, const double* ftext
 hipError_t launch_apply(const nrs_problem& pb, const Sorted& srt, const double* v, double* y,
                         double* part, int32_t chunks, const int32_t* stop, hipStream_t s);
 template <class T>
-hipError_t launch_lu_factor(int64_t n, int32_t scope, T* A, int64_t lda, int32_t* ipiv,
-                            int32_t* perm, int32_t* sing, hipStream_t s);
+hipError_t launch_lu_factor(int64_t n, T* A, int64_t lda, int32_t* ipiv, int32_t* perm,
+                            int32_t* sing, hipStream_t s);
+// Factor with scope 0 (GEPP, lu.hip) or 1 (tile LU with static block
+// pivoting, lu_tiles.hip; done [nt*nt] and ctl [4] zero before the call).
 template <class T>
-hipError_t launch_lu_solve(int64_t n, const T* LU, int64_t lda, const int32_t* perm, const T* b,
-                           T* x, const int32_t* stop, hipStream_t s);
+hipError_t lu_factor_any(int64_t n, int32_t scope, T* A, int64_t lda, int32_t* ipiv,
+                         int32_t* perm, int32_t* sing, int32_t* done, int32_t* ctl,
+                         hipStream_t s);
+inline int64_t lu_tiles_nt(int64_t n) { return (n + 63) / 64; }
+template <class T>
+hipError_t launch_lu_solve(int64_t n, int32_t scope, const T* LU, int64_t lda,
+                           const int32_t* perm, const T* b, T* x, int32_t* sync, int32_t* err,
+                           const int32_t* stop, hipStream_t s);
+// ints of the zero-initialised synchronisation buffer launch_lu_solve needs
+inline int64_t trsv_sync_ints(int64_t n) { return 2 + (n + 63) / 64; }
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
 hipError_t launch_ipiv_to_perm(int64_t n, const int32_t* ipiv, int32_t* perm, hipStream_t s);

@@ -35,14 +35,27 @@ __global__ void k_state_init(SolveState* st, int32_t method) {
   }
 }
 
-// |A|_inf = max_i sum_j |a_ij| (column-major), stage 1: one row per thread.
+// |A|_inf = max_i sum_j |a_ij| (column-major).  Stage 1: thread = row,
+// grid.y = column chunk, partial sums part[chunk][row]; stage 2: per-row sum
+// of the chunks in order and block maxima; stage 3: maximum of the maxima.
 template <class T>
-__global__ void k_rowsum(int64_t n, const T* __restrict__ A, int64_t lda, double* red) {
+__global__ void k_rowsum(int64_t n, const T* __restrict__ A, int64_t lda, int64_t cw,
+                         double* __restrict__ part) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j0 = blockIdx.y * cw, j1 = min<int64_t>(n, j0 + cw);
+  double s = 0.0;
+  for (int64_t j = j0; j < j1; ++j) s += fabs((double)A[i + j * lda]);
+  part[blockIdx.y * n + i] = s;
+}
+
+__global__ void k_rowsum_rows(int64_t n, int64_t chunks, const double* __restrict__ part,
+                              double* __restrict__ red) {
   __shared__ double sh[64];
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   double s = 0.0;
   if (i < n)
-    for (int64_t j = 0; j < n; ++j) s += fabs((double)A[i + j * lda]);
+    for (int64_t c = 0; c < chunks; ++c) s += part[c * n + i];
   const double m = block_max(s, sh);
   if (threadIdx.x == 0) red[blockIdx.x] = m;
 }
@@ -241,20 +254,29 @@ hipError_t launch_state_init(SolveState* st, int32_t method, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <class T>
+static hipError_t anorm(int64_t n, const T* A, int64_t lda, SolveState* st, double* scratch,
+                        hipStream_t s) {
+  const int64_t chunks = rowsum_chunks(n);
+  const int64_t cw = (n + chunks - 1) / chunks;
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  double* part = scratch;
+  double* red = scratch + chunks * n;  // nb <= 1024 maxima for n <= 262144
+  hipLaunchKernelGGL(k_rowsum<T>, dim3(nb, (unsigned)chunks), dim3(256), 0, s, n, A, lda, cw,
+                     part);
+  hipLaunchKernelGGL(k_rowsum_rows, dim3(nb), dim3(256), 0, s, n, chunks, part, red);
+  hipLaunchKernelGGL(k_rowsum_final, dim3(1), dim3(256), 0, s, (int)nb, red, st);
+  return hipGetLastError();
+}
+
 hipError_t launch_anorm32(int64_t n, const float* A, int64_t lda, SolveState* st, double* red,
                           hipStream_t s) {
-  const int nb = (int)((n + 255) / 256);
-  hipLaunchKernelGGL(k_rowsum<float>, dim3(nb), dim3(256), 0, s, n, A, lda, red);
-  hipLaunchKernelGGL(k_rowsum_final, dim3(1), dim3(256), 0, s, nb, red, st);
-  return hipGetLastError();
+  return anorm<float>(n, A, lda, st, red, s);
 }
 
 hipError_t launch_anorm64(int64_t n, const double* A, int64_t lda, SolveState* st, double* red,
                           hipStream_t s) {
-  const int nb = (int)((n + 255) / 256);
-  hipLaunchKernelGGL(k_rowsum<double>, dim3(nb), dim3(256), 0, s, n, A, lda, red);
-  hipLaunchKernelGGL(k_rowsum_final, dim3(1), dim3(256), 0, s, nb, red, st);
-  return hipGetLastError();
+  return anorm<double>(n, A, lda, st, red, s);
 }
 
 hipError_t launch_ir_residual2(int64_t n, const double* b, const double* Ax, const double* x,

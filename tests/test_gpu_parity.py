@@ -124,18 +124,26 @@ def test_apply_fp64(ctx, name, scene):
 
 
 def _lu_check(A0, LU, perm, scope, nb=64, tol=1e-12):
+    """scope 0: A0[perm] = L U.  scope 1 (static block pivoting): A0 = Lt U,
+    where Lt is L with the rows of each diagonal tile L_mm put back at their
+    original positions perm[64m + r] (tiles left of the diagonal keep the
+    original row order)."""
     n = A0.shape[0]
     L = np.tril(LU, -1) + np.eye(n)
     U = np.triu(LU)
-    PA = A0[perm]
-    err = np.max(np.abs(PA - L @ U)) / np.max(np.abs(A0))
-    assert err <= tol * n, err
     if scope == 0:
+        err = np.max(np.abs(A0[perm] - L @ U)) / np.max(np.abs(A0))
         assert np.max(np.abs(np.tril(LU, -1))) <= 1.0 + 1e-12
     else:
+        Lt = L.copy()
         for k in range(0, n, nb):
-            blk = LU[k:k + nb, k:k + nb]
+            e = min(n, k + nb)
+            assert sorted(perm[k:e]) == list(range(k, e))
+            Lt[perm[k:e], k:e] = L[k:e, k:e]
+            blk = LU[k:e, k:e]
             assert np.max(np.abs(np.tril(blk, -1)), initial=0.0) <= 1.0 + 1e-6
+        err = np.max(np.abs(A0 - Lt @ U)) / np.max(np.abs(A0))
+    assert err <= tol * n, err
 
 
 @pytest.mark.parametrize("n", [1, 7, 63, 64, 65, 130, 300, 515])
@@ -165,13 +173,15 @@ def test_lu_factor_and_solve(ctx, n, precision, scope):
     _lu_check(A0c, LU, p, scope, tol=1e-13 if precision == 64 else 3e-6)
     b = rng.normal(size=n)
     xs = torch.empty(n, dtype=dt, device=DEV)
-    nrs.nrs_lu_solve(ctx, A, lda, perm, T(b, dt), xs)
+    nrs.nrs_lu_solve(ctx, A, lda, perm, T(b, dt), xs, pivot_scope=scope)
     ref = np.linalg.solve(A0c, b)
     err = np.linalg.norm(xs.cpu().numpy() - ref) / np.linalg.norm(ref)
-    assert err <= (1e-10 if precision == 64 else 1e-3 * max(1, n / 100))
+    unit = 2.0 ** -53 if precision == 64 else 2.0 ** -24
+    assert err <= 10 * n * unit * np.linalg.cond(A0c), err
 
 
-def test_lu_singular_flag(ctx):
+@pytest.mark.parametrize("scope", [0, 1])
+def test_lu_singular_flag(ctx, scope):
     n = 70
     A0 = np.random.default_rng(0).normal(size=(n, n))
     A0[:, 5] = 0.0
@@ -179,8 +189,28 @@ def test_lu_singular_flag(ctx):
     ipiv = torch.empty(n, dtype=torch.int32, device=DEV)
     perm = torch.empty(n, dtype=torch.int32, device=DEV)
     sing = torch.zeros(1, dtype=torch.int32, device=DEV)
-    nrs.nrs_lu_factor(ctx, A, n, ipiv, perm, sing)
+    nrs.nrs_lu_factor(ctx, A, n, ipiv, perm, sing, pivot_scope=scope)
     assert sing.item() == 1
+
+
+def test_lu_tiles_repeatable_and_large(ctx):
+    """The tile LU clears its own flags: back-to-back factorisations of
+    different sizes give identical results to fresh ones; n = 3150 spans 50
+    tiles with a ragged last tile."""
+    rng = np.random.default_rng(11)
+    for n in (3150, 200, 3150):
+        A0 = rng.normal(size=(n, n)) + 3 * np.sqrt(n) * np.eye(n)
+        A = torch.from_numpy(A0.T.copy()).to(torch.float32).to(DEV)
+        ipiv = torch.empty(n, dtype=torch.int32, device=DEV)
+        perm = torch.empty(n, dtype=torch.int32, device=DEV)
+        sing = torch.zeros(1, dtype=torch.int32, device=DEV)
+        nrs.nrs_lu_factor(ctx, A, n, ipiv, perm, sing, pivot_scope=1)
+        b = rng.normal(size=n)
+        xs = torch.empty(n, dtype=torch.float32, device=DEV)
+        nrs.nrs_lu_solve(ctx, A, n, perm, T(b, torch.float32), xs, pivot_scope=1)
+        ref = np.linalg.solve(A0, b)
+        err = np.linalg.norm(xs.cpu().numpy() - ref) / np.linalg.norm(ref)
+        assert err < 1e-4, (n, err)
 
 
 SOLVE_CASES = [
