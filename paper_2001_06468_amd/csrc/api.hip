@@ -117,10 +117,10 @@ namespace {
 
 // FP64 LU path: assemble, factor with partial pivoting, solve into x.
 nrs_status run_fp64_lu(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, double* x,
-                       hipStream_t s) {
+                       bool norm, hipStream_t s) {
   const int64_t n = 3 * pb.N + 6 * (int64_t)pb.M;
   NRS_HIP(ctx, launch_assemble<double>(pb, sb.srt, sb.A64, sb.lda, s));
-  NRS_HIP(ctx, launch_anorm64(n, sb.A64, sb.lda, sb.st, sb.red, s));
+  if (norm) NRS_HIP(ctx, launch_anorm64(n, sb.A64, sb.lda, sb.st, sb.red, s));
   NRS_HIP(ctx, lu_factor_any<double>(n, 0, sb.A64, sb.lda, sb.ipiv64, sb.perm64,
                                       &sb.st->singular, sb.lu_done, sb.st->lu_ctl, s));
   NRS_HIP(ctx, launch_lu_solve<double>(n, 0, sb.A64, sb.lda, sb.perm64, sb.b, x, sb.tsync,
@@ -131,10 +131,10 @@ nrs_status run_fp64_lu(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, do
 // FP32 factors + FP64 refinement.  Correction solves use the FP32 factors;
 // residuals use the matrix-free FP64 operator.
 nrs_status run_fp32_ir(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, double* x,
-                       int32_t scope, int32_t max_refine, double tol, hipStream_t s) {
+                       int32_t scope, int32_t max_refine, double tol, bool norm, hipStream_t s) {
   const int64_t n = 3 * pb.N + 6 * (int64_t)pb.M;
   NRS_HIP(ctx, launch_assemble<float>(pb, sb.srt, sb.A32, sb.lda, s));
-  NRS_HIP(ctx, launch_anorm32(n, sb.A32, sb.lda, sb.st, sb.red, s));
+  if (norm) NRS_HIP(ctx, launch_anorm32(n, sb.A32, sb.lda, sb.st, sb.red, s));
   NRS_HIP(ctx, lu_factor_any<float>(n, scope, sb.A32, sb.lda, sb.ipiv, sb.perm,
                                      &sb.st->singular, sb.lu_done, sb.st->lu_ctl, s));
   // x0 = (LU)^-1 b
@@ -176,8 +176,8 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
   hipStream_t s = ctx->stream;
   const int64_t N = pb.N, Q = pb.Q, n = 3 * N + 6 * (int64_t)pb.M;
   const int32_t method = o.method;
-  const int32_t max_refine = o.max_refine > 0 ? o.max_refine : 10;
-  const double tol = o.tol > 0 ? o.tol : 1e-12;
+  const int32_t max_refine = o.max_refine > 0 ? o.max_refine : 6;
+  const double tol = o.tol > 0 ? o.tol : 1e-10;
   NRS_HIP(ctx, launch_state_init(sb.st, method, s));
   NRS_HIP(ctx, launch_fill_i32(sb.tsync, 0, trsv_sync_ints(n), s));
   NRS_HIP(ctx, launch_fill_i32(sb.lu_done, 0, lu_tiles_nt(n) * lu_tiles_nt(n), s));
@@ -187,9 +187,9 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
   NRS_HIP(ctx, launch_rhs(N, pb.M, u, ftext, sb.b, s));
   nrs_status st = NRS_OK;
   if (method == NRS_FP64_LU) {
-    st = run_fp64_lu(ctx, pb, sb, sol, s);
+    st = run_fp64_lu(ctx, pb, sb, sol, sync, s);
   } else if (uses_fp32(method)) {
-    st = run_fp32_ir(ctx, pb, sb, sol, method == NRS_FP32_IR ? 1 : 0, max_refine, tol, s);
+    st = run_fp32_ir(ctx, pb, sb, sol, method == NRS_FP32_IR ? 1 : 0, max_refine, tol, sync, s);
   } else {
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
   }
@@ -202,7 +202,7 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
   bool ok = method == NRS_FP64_LU ? true : (h.converged && !h.failed);
   if (!ok && !o.no_fallback) {
     NRS_HIP(ctx, launch_state_init(sb.st, NRS_FP64_LU, s));
-    if ((st = run_fp64_lu(ctx, pb, sb, sol, s)) != NRS_OK) return st;
+    if ((st = run_fp64_lu(ctx, pb, sb, sol, true, s)) != NRS_OK) return st;
     if ((st = read_state(ctx, sb.st, h)) != NRS_OK) return st;
     h.fell_back = 1;
     ok = true;

@@ -162,37 +162,32 @@ __global__ void k_rigid_cols(int64_t N, int32_t M, const int32_t* __restrict__ b
 }
 
 // Rows 3N .. n-1 (all columns): force rows W_m delta_jk, moment rows
-// W_m (r_m x e_k)_i, zero in the rigid-rigid block.
+// W_m (r_m x e_k)_i, zero in the rigid-rigid block.  One thread per entry,
+// threads of a block run down one column (contiguous stores).
 template <class T>
 __global__ void k_rigid_rows(int64_t N, int32_t M, const int32_t* __restrict__ body,
                              const double* __restrict__ x, const double* __restrict__ Y,
                              const double* __restrict__ W, T* __restrict__ A, int64_t lda) {
-  const int64_t rr = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;  // rigid row
+  const int64_t rr = blockIdx.y * (int64_t)blockDim.x + threadIdx.x;  // rigid row
+  const int64_t col = blockIdx.x;
   const int64_t nrows = 6 * (int64_t)M;
   if (rr >= nrows) return;
   const int s = (int)(rr / 6), c = (int)(rr % 6);
-  const int64_t n = 3 * N + nrows;
-  const int64_t row = 3 * N + rr;
-  const int64_t col0 = blockIdx.y * (int64_t)256;
-  const int64_t col1 = min<int64_t>(n, col0 + 256);
-  for (int64_t col = col0; col < col1; ++col) {
-    double v = 0.0;
-    if (col < 3 * N) {
-      const int k = (int)(col / N);
-      const int64_t m = col - k * N;
-      if (body[m] == s) {
-        if (c < 3) {
-          v = (c == k) ? W[m] : 0.0;
-        } else {
-          const double r[3] = {x[m] - Y[12 * s], x[N + m] - Y[12 * s + 1],
-                               x[2 * N + m] - Y[12 * s + 2]};
-          // (r x e_k)_i = -(e_k x r)_i
-          v = -W[m] * cross_unit(k, c - 3, r);
-        }
+  double v = 0.0;
+  if (col < 3 * N) {
+    const int k = (int)(col / N);
+    const int64_t m = col - k * N;
+    if (body[m] == s) {
+      if (c < 3) {
+        v = (c == k) ? W[m] : 0.0;
+      } else {
+        const double r[3] = {x[m] - Y[12 * s], x[N + m] - Y[12 * s + 1], x[2 * N + m] - Y[12 * s + 2]};
+        // (r x e_k)_i = -(e_k x r)_i
+        v = -W[m] * cross_unit(k, c - 3, r);
       }
     }
-    A[row + col * lda] = (T)v;
   }
+  A[3 * N + rr + col * lda] = (T)v;
 }
 
 __global__ void k_rhs(int64_t N, int32_t M, const double* __restrict__ u,
@@ -323,7 +318,7 @@ hipError_t launch_assemble<float>(const nrs_problem& pb, const Sorted& srt, floa
   if (pb.M > 0) {
     hipLaunchKernelGGL(k_rigid_cols<float>, grid1(3 * N, 256), dim3(256), 0, s, N, pb.M, pb.body,
                        pb.x, pb.Y, A, lda);
-    dim3 g(grid1(6 * (int64_t)pb.M, 64).x, (unsigned)((n + 255) / 256));
+    dim3 g((unsigned)n, grid1(6 * (int64_t)pb.M, 64).x);
     hipLaunchKernelGGL(k_rigid_rows<float>, g, dim3(64), 0, s, N, pb.M, pb.body, pb.x, pb.Y,
                        srt.W, A, lda);
   }
@@ -344,7 +339,7 @@ hipError_t launch_assemble<double>(const nrs_problem& pb, const Sorted& srt, dou
   if (pb.M > 0) {
     hipLaunchKernelGGL(k_rigid_cols<double>, grid1(3 * N, 256), dim3(256), 0, s, N, pb.M,
                        pb.body, pb.x, pb.Y, A, lda);
-    dim3 g(grid1(6 * (int64_t)pb.M, 64).x, (unsigned)((n + 255) / 256));
+    dim3 g((unsigned)n, grid1(6 * (int64_t)pb.M, 64).x);
     hipLaunchKernelGGL(k_rigid_rows<double>, g, dim3(64), 0, s, N, pb.M, pb.body, pb.x, pb.Y,
                        srt.W, A, lda);
   }

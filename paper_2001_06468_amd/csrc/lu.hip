@@ -319,18 +319,37 @@ __device__ inline void st_release(int32_t* p, int32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+template <class T>
+__device__ inline T bcast_lane(T v, int lane);
+template <>
+__device__ inline float bcast_lane<float>(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+template <>
+__device__ inline double bcast_lane<double>(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // LOCALP: the factors come from the tile LU with static block pivoting; the
 // interchanges of block row b (lperm, block-local) are applied to the
 // partial result b_b - sum_k L_bk y_k before the diagonal solve.
+// The diagonal block is read into registers before any wait, and every wait
+// consumes all blocks published so far.
+// The lower pass takes its right-hand side from rhs (gathered through perm for
+// scope 0, read directly for scope 1); the upper pass works in place on x.
 template <class T, bool UPPER, bool LOCALP>
 __global__ __launch_bounds__(kTrsvThreads) void k_trsv(int64_t n, const T* __restrict__ LU,
                                                        int64_t lda, T* __restrict__ x,
                                                        int32_t* __restrict__ sync,
                                                        const int32_t* __restrict__ stop,
                                                        int32_t* __restrict__ err,
-                                                       const int32_t* __restrict__ lperm) {
+                                                       const int32_t* __restrict__ lperm,
+                                                       const T* __restrict__ rhs) {
   if (stop && *stop) return;
-  __shared__ int s_t;
+  __shared__ int s_t, s_jend;
   __shared__ T s_part[kTrsvThreads / 64][kTb];
   __shared__ T s_x[kTb];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -343,10 +362,16 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(int64_t n, const T* __res
   const int rows = (int)min<int64_t>(kTb, n - r0);
   const int64_t row = r0 + lane;
   int32_t* flags = sync + 2;
+  // diagonal block row of this lane (wave 0 only), fetched ahead of the waits
+  T dg[kTb];
+  if (w == 0) {
+#pragma unroll
+    for (int c = 0; c < kTb; ++c) dg[c] = (c < rows && lane < rows) ? LU[row + (r0 + c) * lda] : T(0);
+  }
   T acc = T(0);
-  const int64_t jfirst = UPPER ? nblk - 1 : 0;
   const int64_t jstep = UPPER ? -1 : 1;
-  for (int64_t j = jfirst; j != b; j += jstep) {
+  int64_t j = UPPER ? nblk - 1 : 0;
+  while (j != b) {
     if (tid == 0) {
       int64_t spins = 0;
       while (ld_relaxed(&flags[j]) == 0) {
@@ -355,15 +380,30 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(int64_t n, const T* __res
           atomicExch(err, 1);
           break;
         }
+        if ((spins & 255) == 0 && ld_relaxed(err)) break;
       }
+      int64_t je = j + jstep;
+      while (je != b && ld_relaxed(&flags[je]) != 0) je += jstep;
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      s_jend = (int)je;
     }
     __syncthreads();
-    // wave w covers columns j*64 + w*16 .. +16 of this block row
-    const int64_t c0 = j * kTb + w * 16;
-    const int cn = (int)max<int64_t>(0, min<int64_t>(16, n - c0));
-    if (row < n) {
-      for (int c = 0; c < cn; ++c) acc += LU[row + (c0 + c) * lda] * x[c0 + c];
+    const int64_t jend = s_jend;
+    __syncthreads();
+    for (; j != jend; j += jstep) {
+      // wave w covers columns j*64 + w*16 .. +16 of this block row; all 32
+      // loads are issued before the first product
+      const int64_t c0 = j * kTb + w * 16;
+      const int cn = (int)max<int64_t>(0, min<int64_t>(16, n - c0));
+      T a[16], xv[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        const bool ok = c < cn && row < n;
+        a[c] = ok ? LU[row + (c0 + c) * lda] : T(0);
+        xv[c] = c < cn ? x[c0 + c] : T(0);
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) acc += a[c] * xv[c];
     }
   }
   s_part[w][lane] = acc;
@@ -371,7 +411,7 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(int64_t n, const T* __res
   if (w == 0) {
     T v = T(0);
     if (lane < rows) {
-      v = x[row];
+      v = UPPER ? x[row] : (LOCALP ? rhs[row] : rhs[lperm[row]]);
       for (int q = 0; q < kTrsvThreads / 64; ++q) v -= s_part[q][lane];
     }
     if (LOCALP && !UPPER) {
@@ -381,15 +421,21 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(int64_t n, const T* __res
       __builtin_amdgcn_wave_barrier();
     }
     if (!UPPER) {
-      for (int c = 0; c < rows; ++c) {
-        const T xc = __shfl(v, c);
-        if (lane > c && lane < rows) v -= LU[row + (r0 + c) * lda] * xc;
+#pragma unroll
+      for (int c = 0; c < kTb; ++c) {
+        if (c < rows) {
+          const T xc = bcast_lane<T>(v, c);
+          if (lane > c) v -= dg[c] * xc;
+        }
       }
     } else {
-      for (int c = rows - 1; c >= 0; --c) {
-        if (lane == c) v = v / LU[row + (r0 + c) * lda];
-        const T xc = __shfl(v, c);
-        if (lane < c) v -= LU[row + (r0 + c) * lda] * xc;
+#pragma unroll
+      for (int c = kTb - 1; c >= 0; --c) {
+        if (c < rows) {
+          if (lane == c) v = v / dg[c];
+          const T xc = bcast_lane<T>(v, c);
+          if (lane < c) v -= dg[c] * xc;
+        }
       }
     }
     if (lane < rows) x[row] = v;
@@ -440,16 +486,14 @@ hipError_t launch_lu_solve(int64_t n, int32_t scope, const T* LU, int64_t lda,
                            const int32_t* stop, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const unsigned nblk = (unsigned)((n + kTb - 1) / kTb);
-  hipLaunchKernelGGL(k_gather<T>, grid1(n, 256), dim3(256), 0, s, n, scope ? nullptr : perm, b,
-                     x, stop);
   if (scope)
     hipLaunchKernelGGL((k_trsv<T, false, true>), dim3(nblk), dim3(kTrsvThreads), 0, s, n, LU,
-                       lda, x, sync, stop, err, perm);
+                       lda, x, sync, stop, err, perm, b);
   else
     hipLaunchKernelGGL((k_trsv<T, false, false>), dim3(nblk), dim3(kTrsvThreads), 0, s, n, LU,
-                       lda, x, sync, stop, err, perm);
+                       lda, x, sync, stop, err, perm, b);
   hipLaunchKernelGGL((k_trsv<T, true, false>), dim3(nblk), dim3(kTrsvThreads), 0, s, n, LU, lda,
-                     x, sync, stop, err, perm);
+                     x, sync, stop, err, perm, b);
   return hipGetLastError();
 }
 

@@ -58,6 +58,8 @@ struct Mf<double> {
   static __device__ inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
+// Bounded wait for a completion flag.  After any timeout (err set) every
+// later wait returns at once, so a broken dependency cannot stall the launch.
 __device__ inline void wait_flag(const int32_t* f, int32_t* err) {
   int64_t spins = 0;
   while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
@@ -66,6 +68,8 @@ __device__ inline void wait_flag(const int32_t* f, int32_t* err) {
       atomicExch(err, 1);
       break;
     }
+    if ((spins & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      break;
   }
 }
 
@@ -75,63 +79,83 @@ __device__ inline T ld_pad(const T* A, int64_t lda, int64_t n, int64_t r, int64_
   return r == c ? T(1) : T(0);
 }
 
+// 32-bit pivot key: |v| rounded to FP32, its low 6 mantissa bits replaced by
+// (63 - lane), so the maximum is unique and ties go to the lowest lane.
 template <class T>
-__device__ inline uint64_t pivot_key(T v, int lane) {
-  const double a = fabs((double)v);
-  const uint64_t bits = (uint64_t)__double_as_longlong(a);
-  return (bits & ~uint64_t(127)) | 64u | (uint64_t)(63 - lane);
+__device__ inline uint32_t pivot_key(T v, int lane) {
+  const float a = fabsf((float)v);
+  return (__float_as_uint(a) & ~63u) | (uint32_t)(63 - lane);
 }
 
-// Small and working arrays first so their LDS offsets fit the 16-bit
-// immediate offset of ds instructions.
+// Maximum of a 32-bit value over the 64 lanes of the wave (DPP row
+// operations, then the two row broadcasts); the result is uniform.
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)0, (int)v, 0xB1, 0xF, 0xF, false));  // quad [1,0,3,2]
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)0, (int)v, 0x4E, 0xF, 0xF, false));  // quad [2,3,0,1]
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)0, (int)v, 0x141, 0xF, 0xF, false)); // row_half_mirror
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)0, (int)v, 0x140, 0xF, 0xF, false)); // row_mirror
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)0, (int)v, 0x142, 0xA, 0xF, false)); // row_bcast:15
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp((int)0, (int)v, 0x143, 0xC, 0xF, false)); // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+template <class T>
+__device__ inline T lane_value(T v, int lane);
+template <>
+__device__ inline float lane_value<float>(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+template <>
+__device__ inline double lane_value<double>(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <class T>
 struct Shared {
   T Cs[TB * kCS];
   T row[TB];
-  unsigned long long key[TB];
   int32_t perm[TB];
   int32_t task[4];
   T Ls[TB * kLS];
   T Us[TB * kLS];
 };
 
-// Partial pivoting inside the diagonal tile held in S.Cs (one wavefront).
+// Partial pivoting inside the diagonal tile held in S.Cs (one wavefront, lane
+// = row, the row in registers).  Rows are never moved: the pivot row of step
+// j is relabelled logical row j, its values reach the other lanes through
+// readlane, and eliminated rows are skipped afterwards.
 template <class T>
-__device__ __attribute__((noinline)) void diag_factor(Shared<T>& S, const LuSys<T>& sy, int64_t m, int32_t* sing) {
-  const int lane = threadIdx.x;  // caller: wave 0 only
+__device__ __attribute__((noinline)) void diag_factor(Shared<T>& S, const LuSys<T>& sy, int64_t m,
+                                                      int32_t* sing) {
+  const int lane = threadIdx.x & 63;
   T v[TB];
 #pragma unroll
   for (int c = 0; c < TB; ++c) v[c] = S.Cs[c * kCS + lane];
-  S.key[lane] = 0ull;
-  __builtin_amdgcn_wave_barrier();
   bool used = false;
   int myj = 0;
   bool zero = false;
 #pragma unroll
   for (int j = 0; j < TB; ++j) {
-    const unsigned long long key = used ? 0ull : (unsigned long long)pivot_key(v[j], lane);
-    atomicMax(&S.key[j], key);
-    __builtin_amdgcn_wave_barrier();
-    const unsigned long long best = S.key[j];
-    const int p = 63 - (int)(best & 63ull);
-    const T piv = __shfl(v[j], p);
+    const uint32_t key = used ? 0u : pivot_key(v[j], lane) + 1u;
+    const uint32_t best = wave_max_u32(key);
+    const int p = __builtin_amdgcn_readfirstlane(63 - (int)((best - 1u) & 63u));
+    const T piv = lane_value<T>(v[j], p);
     if (lane == p) {
-#pragma unroll
-      for (int c = j + 1; c < TB; ++c) S.row[c] = v[c];
       used = true;
       myj = j;
     }
-    if (lane == 0) S.perm[j] = p;
-    __builtin_amdgcn_wave_barrier();
     if (piv == T(0)) {
       zero = true;
     } else if (!used) {
       const T l = v[j] / piv;
       v[j] = l;
 #pragma unroll
-      for (int c = j + 1; c < TB; ++c) v[c] -= l * S.row[c];
+      for (int c = j + 1; c < TB; ++c) v[c] -= l * lane_value<T>(v[c], p);
     }
-    __builtin_amdgcn_wave_barrier();
+    if (lane == 0) S.perm[j] = p;
     __builtin_amdgcn_sched_barrier(0);
   }
   if (zero && lane == 0) atomicExch(sing, 1);
@@ -139,6 +163,7 @@ __device__ __attribute__((noinline)) void diag_factor(Shared<T>& S, const LuSys<
 #pragma unroll
   for (int c = 0; c < TB; ++c) S.Cs[c * kCS + myj] = v[c];
   // permutation of this block row: logical row j <- original row perm[j]
+  __builtin_amdgcn_wave_barrier();
   const int64_t r0 = m * TB;
   const int64_t gj = r0 + lane;
   if (gj < sy.n) sy.lperm[gj] = (int32_t)(r0 + S.perm[lane]);
@@ -228,13 +253,20 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
       __syncthreads();
-      {
+      {  // all 32 loads of this thread in flight before the LDS stores
         const int r = tid & 63, c0 = tid >> 6;
-#pragma unroll 4
+        T la[16], ua[16];
+#pragma unroll
         for (int q = 0; q < 16; ++q) {
           const int c = c0 + 4 * q;
-          S.Ls[c * kLS + r] = ld_pad(A, lda, n, i * TB + r, k * TB + c);
-          S.Us[r * kLS + c] = ld_pad(A, lda, n, k * TB + r, j * TB + c);
+          la[q] = ld_pad(A, lda, n, i * TB + r, k * TB + c);
+          ua[q] = ld_pad(A, lda, n, k * TB + r, j * TB + c);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int c = c0 + 4 * q;
+          S.Ls[c * kLS + r] = la[q];
+          S.Us[r * kLS + c] = ua[q];
         }
       }
       __syncthreads();
@@ -271,9 +303,18 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
       if (w == 0) diag_factor<T>(S, sy, m, sy.sing);
     } else if (i < j) {
       // U_mj = L_mm^-1 P_m C; L_mm staged row-major, lane = column
-      for (int e = tid; e < TB * TB; e += kLuThreads) {
-        const int r = e / TB, c = e % TB;
-        S.Ls[r * kLS + c] = ld_pad(A, lda, n, m * TB + r, m * TB + c);
+      {
+        T la[TB * TB / kLuThreads];
+#pragma unroll
+        for (int q = 0; q < TB * TB / kLuThreads; ++q) {
+          const int e = tid + q * kLuThreads, r = e % TB, c = e / TB;
+          la[q] = ld_pad(A, lda, n, m * TB + r, m * TB + c);
+        }
+#pragma unroll
+        for (int q = 0; q < TB * TB / kLuThreads; ++q) {
+          const int e = tid + q * kLuThreads, r = e % TB, c = e / TB;
+          S.Ls[r * kLS + c] = la[q];
+        }
       }
       if (tid < TB) {
         const int64_t g = m * TB + tid;
@@ -284,11 +325,22 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
     } else {
       // L_im = C U_mm^-1; U_mm staged column-major, lane = row
       // Uh = D^-1 U staged column-major, 1 / diag in S.row
-      for (int e = tid; e < TB * TB; e += kLuThreads) {
-        const int c = e / TB, r = e % TB;
-        const T d = ld_pad(A, lda, n, m * TB + r, m * TB + r);
-        S.Us[c * kLS + r] = ld_pad(A, lda, n, m * TB + r, m * TB + c) / d;
-        if (r == c) S.row[c] = T(1) / d;
+      {
+        T ua[TB * TB / kLuThreads];
+#pragma unroll
+        for (int q = 0; q < TB * TB / kLuThreads; ++q) {
+          const int e = tid + q * kLuThreads, r = e % TB, c = e / TB;
+          ua[q] = ld_pad(A, lda, n, m * TB + r, m * TB + c);
+        }
+        if (tid < TB) S.row[tid] = ld_pad(A, lda, n, m * TB + tid, m * TB + tid);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < TB * TB / kLuThreads; ++q) {
+          const int e = tid + q * kLuThreads, r = e % TB, c = e / TB;
+          S.Us[c * kLS + r] = ua[q] / S.row[r];
+        }
+        __syncthreads();
+        if (tid < TB) S.row[tid] = T(1) / S.row[tid];
       }
       __syncthreads();
       if (w == 0) row_solve<T>(S);
