@@ -1,11 +1,17 @@
 """Benchmark of the NEAREST time-step hot path on one MI355X.
 
-Workload: 25 undulating filaments (N = 1000 force points, Q = 10000
-quadrature points, n = 3150 unknowns), classical RK4 with dt = 2 pi / 100.
-One step = four solves, each = geometry + nearest map + fused assembly +
-rigid-body blocks + LU + triangular solves (+ FP64 refinement).  The metric
-is time-step solves per second at <= 1e-8 relative force error against the
-FP64 oracle (checked on the final state).
+Workload (the time-stepping configuration): 25 undulating filaments of unit
+length (N = 1000 force points, Q = 10000 quadrature points, n = 3150
+unknowns), eps = 0.01, classical RK4 with dt = 2 pi / 100 from the seeded
+initial state.  One step = four solves; each solve = geometry + nearest map
++ fused assembly + rigid-body blocks + LU + triangular solves + FP64
+refinement (method fp32_ir).  The metric is time-step solves per second,
+with the solution checked against the FP64 oracle (relative force error <=
+1e-8) on the final state.
+
+Printed as one JSON line; `roofline` describes the dominant kernel (the
+single-launch tile LU), timed here with HIP events around its own launch on
+the benchmark matrix; `cpu_baseline` is the CPU oracle on a bounded sample.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--method fp32_ir|fp64_lu|fp32_gepp_ir]
 """
@@ -22,6 +28,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METHODS = {"fp64_lu": 0, "fp32_ir": 1, "fp32_gepp_ir": 2}
+PEAK_FP32_TFLOPS = 157.3      # MI355X dense FP32 (vector and matrix)
+PEAK_FP64_TFLOPS = 78.6
+# HBM bytes per launch of the tile LU at n = 3150 from the FETCH_SIZE and
+# WRITE_SIZE counter runs (calibrated against a 256 MiB copy), valid only for
+# the kernel source they were taken on (first 16 hex digits of its SHA-256).
+LU_TRAFFIC = {"source_sha256_16": "2daf802283cc8269", "bytes_per_launch": 758455410, "n": 3150}
+
+
+def cpu_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        n = [p.get("num_threads", 0) for p in threadpool_info() if p.get("user_api") == "blas"]
+        if n:
+            return int(max(n))
+    except Exception:
+        pass
+    return os.cpu_count() or 1
 
 
 def main():
@@ -32,9 +55,14 @@ def main():
     ap.add_argument("--method", default="fp32_ir", choices=sorted(METHODS))
     ap.add_argument("--swimmers", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the other solution forms")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="also run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the work would shard); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -46,47 +74,153 @@ def main():
     dev = "cuda:0"
     M = args.swimmers
     scene = synth.filament_scene(M, seed=0)
+    N, Q = scene["N"], scene["Q"]
+    n = 3 * N + 6 * M
     ds = nrs.DeviceScene(scene, dev)
     ctx = nrs.Context(0)
-    method = METHODS[args.method]
-    ws = torch.empty(nrs.nrs_rk4_workspace_size(ctx, ds, method), dtype=torch.uint8, device=dev)
-    Y = torch.from_numpy(scene["Y0"].copy()).to(dev)
     dt = 2 * math.pi / 100
-    t = 0.0
-    for _ in range(args.warmup):
-        nrs.nrs_rk4_step(ctx, ds, Y, t, dt, ws, method=method)
-        t += dt
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    w0 = time.perf_counter()
-    e0.record()
-    for _ in range(args.steps):
-        nrs.nrs_rk4_step(ctx, ds, Y, t, dt, ws, method=method)
-        t += dt
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    ms = e0.elapsed_time(e1)
-    info = nrs.nrs_query_info(ctx, ws)
+
+    def run_steps(method, warmup, steps):
+        ws = torch.empty(nrs.nrs_rk4_workspace_size(ctx, ds, method), dtype=torch.uint8, device=dev)
+        Y = torch.from_numpy(scene["Y0"].copy()).to(dev)
+        t = 0.0
+        for _ in range(warmup):
+            nrs.nrs_rk4_step(ctx, ds, Y, t, dt, ws, method=method)
+            t += dt
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            nrs.nrs_rk4_step(ctx, ds, Y, t, dt, ws, method=method)
+            t += dt
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        info = nrs.nrs_query_info(ctx, ws)
+        return e0.elapsed_time(e1), wall, Y, t, info
+
+    if args.calib_copy > 0:
+        src = torch.ones(args.calib_copy * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    method = METHODS[args.method]
+    ms, wall, Y, t_end, info = run_steps(method, args.warmup, args.steps)
     solves = 4 * args.steps
+    value = solves / (ms / 1e3)
+
+    # --- accuracy of the final state against the FP64 oracle -------------------
+    import oracle
+    Yh = Y.cpu().numpy().reshape(M, 12)
+    x, X, w, u = oracle.geometry(scene, t_end, Yh)
+    nu = oracle.nearest(x, X, scene["group_off"], scene["groupX"])
+    T = lambda a, d=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dtype=d, device=dev)  # noqa: E731
+    pb = nrs.Problem(T(x), T(X), T(w), T(nu, torch.int32), T(scene["body"], torch.int32), T(Yh),
+                     scene["eps"], scene["mu"])
+    ws1 = torch.empty(nrs.nrs_workspace_size(ctx, N, Q, M, method), dtype=torch.uint8, device=dev)
+    sol = torch.empty(n, dtype=torch.float64, device=dev)
+    sinfo = nrs.nrs_solve(ctx, pb, T(u), None, sol, ws1, method=method)
+    f_ref, UW_ref = oracle.solve_scene(scene, t_end, Yh)
+    s = sol.cpu().numpy()
+    err_f = float(np.linalg.norm(s[:3 * N] - f_ref.ravel()) / np.linalg.norm(f_ref))
+    err_uw = float(np.linalg.norm(s[3 * N:] - UW_ref.ravel()) / np.linalg.norm(UW_ref))
+
+    # --- dominant kernel: the tile LU, one launch, timed with events ----------
+    lda = nrs.lda_for(n)
+    A32 = torch.empty((n, lda), dtype=torch.float32, device=dev)
+    nrs.nrs_assemble(ctx, pb, 32, A32, lda, ws1)
+    A0 = A32.clone()
+    ipiv = torch.empty(n, dtype=torch.int32, device=dev)
+    perm = torch.empty(n, dtype=torch.int32, device=dev)
+    sing = torch.zeros(1, dtype=torch.int32, device=dev)
+    lu_ms = []
+    for rep in range(12):
+        A32.copy_(A0)
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record()
+        nrs.nrs_lu_factor(ctx, A32, lda, ipiv, perm, sing, pivot_scope=1)
+        a1.record()
+        torch.cuda.synchronize()
+        if rep >= 2:
+            lu_ms.append(a0.elapsed_time(a1))
+    lu_avg_ms = float(np.mean(lu_ms))
+    lu_flops = 2.0 / 3.0 * n ** 3
+    import hashlib
+    src = os.path.join(ROOT, "paper_2001_06468_amd", "csrc", "lu_tiles.hip")
+    cur = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    traffic = (LU_TRAFFIC["bytes_per_launch"]
+               if cur == LU_TRAFFIC["source_sha256_16"] and n == LU_TRAFFIC["n"] else None)
+    lu_tflops = lu_flops / (lu_avg_ms / 1e3) / 1e12
+
+    # --- assembly rate: nrs_assemble (nu-sorted layout + fused kernel + rigid blocks)
+    as_ms = []
+    for rep in range(12):
+        b0 = torch.cuda.Event(enable_timing=True)
+        b1 = torch.cuda.Event(enable_timing=True)
+        b0.record()
+        nrs.nrs_assemble(ctx, pb, 32, A32, lda, ws1)
+        b1.record()
+        torch.cuda.synchronize()
+        if rep >= 2:
+            as_ms.append(b0.elapsed_time(b1))
+    as_avg_ms = float(np.mean(as_ms))
+    asm_flops = 33.0 * N * Q
+    asm_tflops = asm_flops / (as_avg_ms / 1e3) / 1e12
+
+    forms = {}
+    if not args.no_forms:
+        for name, m in METHODS.items():
+            if m == method:
+                continue
+            k = 2
+            fm, _, _, _, finfo = run_steps(m, 1, k)
+            forms[name] = {"solves_per_s": 4 * k / (fm / 1e3), "steps": k,
+                           "fell_back": finfo["fell_back"]}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        Yc = scene["Y0"].copy()
+        c0 = time.perf_counter()
+        oracle.rk4_step(scene, Yc, 0.0, dt)
+        c_el = time.perf_counter() - c0
+        cpu = {"value": 4.0 / c_el, "unit": "solves/s", "cores": cpu_threads(), "kind": "oracle",
+               "sample": "one RK4 step (4 solves) of the same 25-filament workload from the "
+                         "seeded initial state, NumPy/LAPACK FP64 oracle",
+               "seconds": c_el}
+
     out = {
         "metric": "time-step solves/sec (assemble+solve) at <=1e-8 rel force err",
-        "value": solves / (ms / 1e3),
+        "value": value,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms / args.steps,
-        "wall_s": wall,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64" if method else "f64",
         "data": "synthetic",
-        "config": {"workload": f"filaments_M{M}_rk4", "N": scene["N"], "Q": scene["Q"],
-                   "n": 3 * scene["N"] + 6 * M, "method": args.method, "dt": dt},
-        "last_step_info": info,
+        "config": {"workload": f"filaments_M{M}_rk4", "swimmers": M, "N": N, "Q": Q, "n": n,
+                   "eps": scene["eps"], "dt": dt, "method": args.method},
+        "accuracy": {"rel_force_err": err_f, "rel_velocity_err": err_uw, "target": 1e-8,
+                     "solve_info": sinfo, "step_info": info},
+        "roofline": {"kernel": "k_lu_tiles<float>", "bound": "mfma", "achieved": lu_tflops,
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": lu_tflops / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "flops_per_launch": lu_flops, "avg_launch_ms": lu_avg_ms},
+        "assembly": {"tflops": asm_tflops, "frac_fp32_peak": asm_tflops / PEAK_FP32_TFLOPS,
+                     "flops_per_call": asm_flops, "avg_call_ms": as_avg_ms,
+                     "note": "33 flops per (force point, quadrature point) pair; call includes "
+                             "the nu-sorted layout and rigid-body blocks"},
+        "forms": forms,
+        "cpu_baseline": cpu,
+        "wall_s": wall,
     }
     print(json.dumps(out), flush=True)
 

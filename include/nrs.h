@@ -136,7 +136,7 @@ typedef struct {
   int32_t method;        /* NRS_FP64_LU, NRS_FP32_IR, NRS_FP32_GEPP_IR, NRS_GMRES */
   int32_t max_refine;    /* refinement sweeps (IR) before falling back; <=0: 6   */
   double  tol;           /* IR: stop when |d|_inf <= tol |x|_inf; GMRES: relative
-                            residual |b - A x|_2 <= tol |b|_2.  <=0: 1e-10       */
+                            residual |b - A x|_2 <= tol |b|_2.  <=0: 1e-9        */
   int32_t gmres_restart; /* GMRES(m) restart length, <=0: 40                     */
   int32_t gmres_max_iter;/* total GMRES iterations before LU fallback, <=0: 400  */
   int32_t no_fallback;   /* 1 = report failure instead of falling back to FP64 LU */
