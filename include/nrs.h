@@ -192,6 +192,31 @@ nrs_status nrs_solve(nrs_ctx* ctx, const nrs_problem* pb, const double* u, const
  * that used workspace ws. */
 nrs_status nrs_query_info(nrs_ctx* ctx, void* ws, nrs_info* info);
 
+/* Many independent problems of different orders solved together (the
+ * resistance problems of Sec. 4 for several bodies / parameter values at
+ * once), method NRS_FP32_IR only.  problems, u, ftext, sol and infos are
+ * HOST arrays of B entries; the arrays they point to are on the device as
+ * in nrs_solve (ftext may be NULL, or hold NULL entries).  The FP32
+ * factorisations of all B systems run in one launch of the tile LU, and each
+ * triangular sweep of the refinement in one launch over the batch; the
+ * remaining per-system steps are queued on the context's stream.
+ * Workspace: nrs_solve_batched_workspace_size() bytes for the same problem
+ * list (holds every system's FP32 matrix side by side).  The descriptors are
+ * staged through a pinned host buffer owned by the context.
+ * With infos == NULL the call is asynchronous.  With infos != NULL it
+ * synchronises, fills infos[B], and solves any system whose refinement
+ * failed again alone with FP64 partial pivoting (fell_back = 1) unless
+ * options.no_fallback is set, in which case NRS_E_NOT_CONVERGED is returned.
+ * Errors: NRS_E_ARG (bad sizes, NULL arrays, bad nu/body values),
+ * NRS_E_UNSUPPORTED (method other than NRS_FP32_IR, n > 262144),
+ * NRS_E_WORKSPACE, NRS_E_HIP. */
+nrs_status nrs_solve_batched_workspace_size(nrs_ctx* ctx, int32_t B, const nrs_problem* problems,
+                                            int32_t method, size_t* bytes);
+nrs_status nrs_solve_batched(nrs_ctx* ctx, int32_t B, const nrs_problem* problems,
+                             const double* const* u, const double* const* ftext,
+                             const nrs_options* opt, void* ws, size_t ws_bytes,
+                             double* const* sol, nrs_info* infos);
+
 /* ------------------------------------------------------------------------ */
 /* Dense LU and triangular solves on their own (the linear-algebra part of
  * Sec. 4 step 3), for tests and reuse.                                      */

@@ -22,7 +22,7 @@ from ._lib import (NRS_FP32_GEPP_IR, NRS_FP32_IR, NRS_FP64_LU, NRS_GMRES,  # noq
 __all__ = [
     "NrsError", "Context", "DeviceScene", "Problem", "nrs_create", "nrs_version", "nrs_geometry",
     "nrs_nearest", "nrs_workspace_size", "nrs_assemble", "nrs_apply", "nrs_solve",
-    "nrs_query_info", "nrs_lu_factor", "nrs_lu_solve", "nrs_rk4_workspace_size", "nrs_rk4_step",
+    "nrs_query_info", "nrs_solve_batched_workspace_size", "nrs_solve_batched", "nrs_lu_factor", "nrs_lu_solve", "nrs_rk4_workspace_size", "nrs_rk4_step",
     "NRS_FP64_LU", "NRS_FP32_IR", "NRS_FP32_GEPP_IR", "NRS_GMRES", "lda_for",
 ]
 
@@ -202,6 +202,42 @@ def nrs_solve(ctx, problem, u, ftext, sol, ws, method=NRS_FP64_LU, info=True, **
                                C.byref(inf) if inf is not None else None)
     _check(st, ctx)
     return inf.as_dict() if inf is not None else None
+
+
+def _problem_array(problems):
+    arr = (NrsProblem * len(problems))()
+    for i, p in enumerate(problems):
+        arr[i] = p.struct()
+    return arr
+
+
+def nrs_solve_batched_workspace_size(ctx, problems, method=NRS_FP32_IR):
+    b = C.c_size_t()
+    arr = _problem_array(problems)
+    _check(_lib.load().nrs_solve_batched_workspace_size(ctx.handle, len(problems), arr, method,
+                                                        C.byref(b)), ctx)
+    return b.value
+
+
+def nrs_solve_batched(ctx, problems, us, sols, ws, ftexts=None, method=NRS_FP32_IR, info=True,
+                      **opts):
+    """Returns a list of nrs_info dicts (synchronising) or None (asynchronous)."""
+    B = len(problems)
+    if len(us) != B or len(sols) != B or (ftexts is not None and len(ftexts) != B):
+        raise ValueError("problems, us, sols (and ftexts) need the same length")
+    arr = _problem_array(problems)
+    f64 = torch.float64
+    u_p = (C.c_void_p * B)(*[_ptr(u, f64, "u") for u in us])
+    s_p = (C.c_void_p * B)(*[_ptr(x, f64, "sol") for x in sols])
+    f_p = None
+    if ftexts is not None:
+        f_p = (C.c_void_p * B)(*[_ptr(f, f64, "ftext") for f in ftexts])
+    o = _options(method, **opts)
+    infs = (NrsInfo * B)() if info else None
+    st = _lib.load().nrs_solve_batched(ctx.handle, B, arr, u_p, f_p, C.byref(o),
+                                       _ptr(ws, torch.uint8, "ws"), ws.numel(), s_p, infs)
+    _check(st, ctx)
+    return [i.as_dict() for i in infs] if infs is not None else None
 
 
 def nrs_query_info(ctx, ws):

@@ -69,6 +69,11 @@ PROTOTYPES = {
     "nrs_solve": (_i32, [_p, C.POINTER(NrsProblem), _p, _p, C.POINTER(NrsOptions), _p,
                          C.c_size_t, _p, C.POINTER(NrsInfo)]),
     "nrs_query_info": (_i32, [_p, _p, C.POINTER(NrsInfo)]),
+    "nrs_solve_batched_workspace_size": (_i32, [_p, _i32, C.POINTER(NrsProblem), _i32,
+                                                C.POINTER(C.c_size_t)]),
+    "nrs_solve_batched": (_i32, [_p, _i32, C.POINTER(NrsProblem), C.POINTER(_p), C.POINTER(_p),
+                                 C.POINTER(NrsOptions), _p, C.c_size_t, C.POINTER(_p),
+                                 C.POINTER(NrsInfo)]),
     "nrs_lu_factor": (_i32, [_p, _i64, _i32, _i32, _p, _i64, _p, _p, _p]),
     "nrs_lu_solve": (_i32, [_p, _i64, _i32, _i32, _p, _i64, _p, _p, _p]),
     "nrs_rk4_workspace_size": (_i32, [_p, C.POINTER(NrsScene), _i32, C.POINTER(C.c_size_t)]),

@@ -73,7 +73,8 @@ nrs_status check_problem(nrs_ctx* ctx, const nrs_problem* pb) {
 namespace nrs {
 
 // Workspace layout: [SolveState][Sorted][A32?][A64][vectors][apply partials]
-bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, SolveBuffers& sb) {
+bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, SolveBuffers& sb,
+                 bool with64) {
   const int64_t n = 3 * N + 6 * (int64_t)M;
   sb.st = ar.take<SolveState>(1);
   sb.srt.seg = ar.take<int32_t>(N + 1);
@@ -86,7 +87,7 @@ bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, Sol
   sb.srt.W = ar.take<double>(N);
   sb.lda = lda_for(n);
   sb.A32 = uses_fp32(method) ? ar.take<float>((size_t)sb.lda * n) : nullptr;
-  sb.A64 = ar.take<double>((size_t)sb.lda * n);
+  sb.A64 = with64 ? ar.take<double>((size_t)sb.lda * n) : nullptr;
   sb.ipiv = ar.take<int32_t>(n);
   sb.perm = ar.take<int32_t>(n);
   sb.ipiv64 = ar.take<int32_t>(n);
@@ -263,6 +264,11 @@ nrs_status nrs_destroy(nrs_ctx* ctx) {
   if (ctx) {
     hipSetDevice(ctx->device);
     if (ctx->tsync) hipFree(ctx->tsync);
+    if (ctx->staging_event) {
+      hipEventSynchronize(ctx->staging_event);
+      hipEventDestroy(ctx->staging_event);
+    }
+    if (ctx->staging) hipHostFree(ctx->staging);
   }
   delete ctx;
   return NRS_OK;

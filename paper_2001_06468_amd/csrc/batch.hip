@@ -1,0 +1,288 @@
+// Many independent resistance / swimming problems of different sizes solved
+// together: every factorisation of the batch runs in ONE launch of the tile
+// LU (tasks of all systems interleaved band by band), and every triangular
+// sweep of the batch in one launch per pass.  Assembly and the FP64 residual
+// stay per system (they are short and have no cross-system sharing).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "nrs_internal.h"
+
+using namespace nrs;
+
+namespace {
+
+nrs_status bfail(nrs_ctx* ctx, nrs_status s, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return s;
+}
+
+#define NRS_BHIP(ctx, expr)                                                                     \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return bfail(ctx, NRS_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+struct BatchLayout {
+  int32_t* ctl;            // [0..3] LU ticket/exit/timeout, [4..5] trsv ticket/done, [6] trsv err
+  LuSys<float>* lusys;     // [B]
+  TrsvSys<float>* trsys;   // [B]
+  int32_t* lu_pref;        // [nbands*B + 1]
+  int32_t* tr_pref;        // [nsteps*B + 1]
+  std::vector<SolveBuffers> sb;
+  std::vector<int32_t> lu_pref_h, tr_pref_h;
+  int32_t nbands = 0, nsteps = 0, lu_total = 0, tr_total = 0;
+};
+
+bool carve_batch(Arena& ar, int32_t B, const nrs_problem* pb, BatchLayout& L) {
+  std::vector<int32_t> nts(B), nbs(B);
+  for (int s = 0; s < B; ++s) {
+    const int64_t n = 3 * pb[s].N + 6 * (int64_t)pb[s].M;
+    nts[s] = (int32_t)lu_tiles_nt(n);
+    nbs[s] = (int32_t)((n + 63) / 64);
+  }
+  lu_task_prefix(nts.data(), B, L.lu_pref_h, L.nbands);
+  L.lu_total = L.lu_pref_h.back();
+  // triangular-solve tickets: one per 64-row block, step by step
+  L.nsteps = 0;
+  for (int s = 0; s < B; ++s) L.nsteps = std::max(L.nsteps, nbs[s]);
+  L.tr_pref_h.assign((size_t)L.nsteps * B + 1, 0);
+  int32_t acc = 0;
+  for (int k = 0; k < L.nsteps; ++k)
+    for (int s = 0; s < B; ++s) {
+      L.tr_pref_h[(size_t)k * B + s] = acc;
+      if (k < nbs[s]) acc += 1;
+    }
+  L.tr_pref_h[(size_t)L.nsteps * B] = acc;
+  L.tr_total = acc;
+  L.ctl = ar.take<int32_t>(8);
+  L.lusys = ar.take<LuSys<float>>(B);
+  L.trsys = ar.take<TrsvSys<float>>(B);
+  L.lu_pref = ar.take<int32_t>(L.lu_pref_h.size());
+  L.tr_pref = ar.take<int32_t>(L.tr_pref_h.size());
+  L.sb.resize(B);
+  for (int s = 0; s < B; ++s) carve_solve(ar, pb[s].N, pb[s].Q, pb[s].M, NRS_FP32_IR, L.sb[s], false);
+  return !ar.overflow;
+}
+
+nrs_status check_batch(nrs_ctx* ctx, int32_t B, const nrs_problem* pb) {
+  if (B <= 0 || !pb) return bfail(ctx, NRS_E_ARG, "batch needs B > 0 problems");
+  for (int s = 0; s < B; ++s) {
+    const nrs_problem& p = pb[s];
+    if (p.N <= 0 || p.Q <= 0 || p.M < 0 || !p.x || !p.X || !p.nu || !p.body ||
+        (p.M > 0 && !p.Y) || !(p.eps > 0.0) || !(p.mu > 0.0))
+      return bfail(ctx, NRS_E_ARG, "invalid problem " + std::to_string(s) + " in batch");
+    if (3 * p.N + 6 * (int64_t)p.M > 262144 || p.N > (1 << 20))
+      return bfail(ctx, NRS_E_UNSUPPORTED, "problem " + std::to_string(s) + " too large");
+  }
+  return NRS_OK;
+}
+
+// pinned staging for the batch descriptors; reuse waits for the last copy
+nrs_status stage(nrs_ctx* ctx, size_t bytes, char** host) {
+  if (ctx->staging_event) NRS_BHIP(ctx, hipEventSynchronize(ctx->staging_event));
+  if (ctx->staging_cap < bytes) {
+    if (ctx->staging) NRS_BHIP(ctx, hipHostFree(ctx->staging));
+    ctx->staging = nullptr;
+    ctx->staging_cap = 0;
+    NRS_BHIP(ctx, hipHostMalloc(&ctx->staging, bytes));
+    ctx->staging_cap = bytes;
+  }
+  if (!ctx->staging_event) NRS_BHIP(ctx, hipEventCreateWithFlags(&ctx->staging_event, hipEventDisableTiming));
+  *host = static_cast<char*>(ctx->staging);
+  return NRS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nrs_status nrs_solve_batched_workspace_size(nrs_ctx* ctx, int32_t B, const nrs_problem* problems,
+                                            int32_t method, size_t* bytes) {
+  nrs_status st = check_batch(ctx, B, problems);
+  if (st) return st;
+  if (!bytes) return bfail(ctx, NRS_E_ARG, "bytes is NULL");
+  if (method != NRS_FP32_IR) return bfail(ctx, NRS_E_UNSUPPORTED, "batches use NRS_FP32_IR");
+  Arena ar(nullptr, 0);
+  BatchLayout L;
+  carve_batch(ar, B, problems, L);
+  *bytes = ar.used + 256;
+  return NRS_OK;
+}
+
+nrs_status nrs_solve_batched(nrs_ctx* ctx, int32_t B, const nrs_problem* problems,
+                             const double* const* u, const double* const* ftext,
+                             const nrs_options* opt, void* ws, size_t ws_bytes,
+                             double* const* sol, nrs_info* infos) {
+  if (!ctx) return NRS_E_ARG;
+  NRS_BHIP(ctx, hipSetDevice(ctx->device));
+  nrs_status st = check_batch(ctx, B, problems);
+  if (st) return st;
+  if (!u || !sol) return bfail(ctx, NRS_E_ARG, "u and sol arrays required");
+  for (int s = 0; s < B; ++s)
+    if (!u[s] || !sol[s]) return bfail(ctx, NRS_E_ARG, "u[s] and sol[s] required");
+  nrs_options o = {};
+  o.method = NRS_FP32_IR;
+  if (opt) o = *opt;
+  if (o.method != NRS_FP32_IR) return bfail(ctx, NRS_E_UNSUPPORTED, "batches use NRS_FP32_IR");
+  const int32_t max_refine = o.max_refine > 0 ? o.max_refine : 6;
+  const double tol = o.tol > 0 ? o.tol : 1e-9;
+  Arena ar(ws, ws_bytes);
+  BatchLayout L;
+  if (!carve_batch(ar, B, problems, L)) return bfail(ctx, NRS_E_WORKSPACE, "workspace too small");
+  hipStream_t s = ctx->stream;
+
+  // ---- descriptors -> device (one pinned staging copy) ----
+  std::vector<LuSys<float>> lus(B);
+  std::vector<TrsvSys<float>> trs(B);
+  for (int k = 0; k < B; ++k) {
+    const nrs_problem& p = problems[k];
+    const int64_t n = 3 * p.N + 6 * (int64_t)p.M;
+    SolveBuffers& sb = L.sb[k];
+    lus[k].A = sb.A32;
+    lus[k].lda = sb.lda;
+    lus[k].n = n;
+    lus[k].nt = lu_tiles_nt(n);
+    lus[k].lperm = sb.perm;
+    lus[k].ipiv = sb.ipiv;
+    lus[k].done = sb.lu_done;
+    lus[k].sing = &sb.st->singular;
+    trs[k].LU = sb.A32;
+    trs[k].lda = sb.lda;
+    trs[k].n = n;
+    trs[k].x = sb.d32;
+    trs[k].rhs = reinterpret_cast<const float*>(sb.r);
+    trs[k].perm = sb.perm;
+    trs[k].flags = sb.tsync + 2;
+    trs[k].stop = &sb.st->stop;
+  }
+  const size_t b_lu = sizeof(LuSys<float>) * B, b_tr = sizeof(TrsvSys<float>) * B;
+  const size_t b_lp = sizeof(int32_t) * L.lu_pref_h.size(), b_tp = sizeof(int32_t) * L.tr_pref_h.size();
+  char* h = nullptr;
+  if ((st = stage(ctx, b_lu + b_tr + b_lp + b_tp, &h))) return st;
+  std::memcpy(h, lus.data(), b_lu);
+  std::memcpy(h + b_lu, trs.data(), b_tr);
+  std::memcpy(h + b_lu + b_tr, L.lu_pref_h.data(), b_lp);
+  std::memcpy(h + b_lu + b_tr + b_lp, L.tr_pref_h.data(), b_tp);
+  NRS_BHIP(ctx, hipMemcpyAsync(L.lusys, h, b_lu, hipMemcpyHostToDevice, s));
+  NRS_BHIP(ctx, hipMemcpyAsync(L.trsys, h + b_lu, b_tr, hipMemcpyHostToDevice, s));
+  NRS_BHIP(ctx, hipMemcpyAsync(L.lu_pref, h + b_lu + b_tr, b_lp, hipMemcpyHostToDevice, s));
+  NRS_BHIP(ctx, hipMemcpyAsync(L.tr_pref, h + b_lu + b_tr + b_lp, b_tp, hipMemcpyHostToDevice, s));
+  NRS_BHIP(ctx, hipEventRecord(ctx->staging_event, s));
+  NRS_BHIP(ctx, launch_fill_i32(L.ctl, 0, 8, s));
+
+  // ---- per system: layout, right-hand side, FP32 assembly ----
+  for (int k = 0; k < B; ++k) {
+    const nrs_problem& p = problems[k];
+    SolveBuffers& sb = L.sb[k];
+    const int64_t n = 3 * p.N + 6 * (int64_t)p.M;
+    NRS_BHIP(ctx, launch_state_init(sb.st, NRS_FP32_IR, s));
+    NRS_BHIP(ctx, launch_fill_i32(sb.tsync, 0, trsv_sync_ints(n), s));
+    NRS_BHIP(ctx, launch_fill_i32(sb.lu_done, 0, lu_tiles_nt(n) * lu_tiles_nt(n), s));
+    NRS_BHIP(ctx, launch_build_csr(p.N, p.Q, p.X, p.w, p.nu, sb.srt, s));
+    NRS_BHIP(ctx, launch_check_nu(p.N, sb.srt.cnt, sb.st, s));
+    NRS_BHIP(ctx, launch_check_body(p.N, p.M, p.body, sb.st, s));
+    NRS_BHIP(ctx, launch_rhs(p.N, p.M, u[k], ftext ? ftext[k] : nullptr, sb.b, s));
+    NRS_BHIP(ctx, launch_assemble<float>(p, sb.srt, sb.A32, sb.lda, s));
+    if (infos) NRS_BHIP(ctx, launch_anorm32(n, sb.A32, sb.lda, sb.st, sb.red, s));
+    NRS_BHIP(ctx, launch_convert_f32(n, sb.b, reinterpret_cast<float*>(sb.r), s));
+  }
+
+  // ---- every factorisation in one launch ----
+  LuBatch<float> lb;
+  std::memset(&lb.one, 0, sizeof(lb.one));
+  lb.sys = L.lusys;
+  lb.pref = L.lu_pref;
+  lb.B = B;
+  lb.nbands = L.nbands;
+  lb.total = L.lu_total;
+  NRS_BHIP(ctx, launch_lu_tiles<float>(lb, L.ctl, s));
+
+  TrsvBatch<float> tb;
+  std::memset(&tb.one, 0, sizeof(tb.one));
+  tb.sys = L.trsys;
+  tb.pref = L.tr_pref;
+  tb.B = B;
+  tb.nsteps = L.nsteps;
+  tb.total = L.tr_total;
+
+  // ---- x0 = (LU)^-1 b, then refinement sweeps ----
+  NRS_BHIP(ctx, launch_trsv_batch<float>(tb, 1, L.ctl + 4, L.ctl + 6, s));
+  for (int k = 0; k < B; ++k)
+    NRS_BHIP(ctx, launch_ir_update32(3 * problems[k].N + 6 * (int64_t)problems[k].M, sol[k],
+                                     L.sb[k].d32, tol, 1, L.sb[k].st, s));
+  for (int it = 0; it < max_refine; ++it) {
+    for (int k = 0; k < B; ++k) {
+      const nrs_problem& p = problems[k];
+      SolveBuffers& sb = L.sb[k];
+      const int64_t n = 3 * p.N + 6 * (int64_t)p.M;
+      NRS_BHIP(ctx, launch_apply(p, sb.srt, sol[k], sb.d64, sb.part, sb.chunks, &sb.st->stop, s));
+      NRS_BHIP(ctx, launch_ir_residual2(n, sb.b, sb.d64, sol[k], nullptr,
+                                        reinterpret_cast<float*>(sb.r), nullptr, sb.st, 0, s));
+    }
+    NRS_BHIP(ctx, launch_trsv_batch<float>(tb, 1, L.ctl + 4, L.ctl + 6, s));
+    for (int k = 0; k < B; ++k)
+      NRS_BHIP(ctx, launch_ir_update32(3 * problems[k].N + 6 * (int64_t)problems[k].M, sol[k],
+                                       L.sb[k].d32, tol, 0, L.sb[k].st, s));
+  }
+  if (!infos) return NRS_OK;
+
+  // ---- synchronous report: final FP64 backward error of every system ----
+  for (int k = 0; k < B; ++k) {
+    const nrs_problem& p = problems[k];
+    SolveBuffers& sb = L.sb[k];
+    const int64_t n = 3 * p.N + 6 * (int64_t)p.M;
+    NRS_BHIP(ctx, launch_apply(p, sb.srt, sol[k], sb.d64, sb.part, sb.chunks, nullptr, s));
+    NRS_BHIP(ctx, launch_ir_residual2(n, sb.b, sb.d64, sol[k], sb.r, nullptr, nullptr, sb.st, 1, s));
+  }
+  NRS_BHIP(ctx, hipStreamSynchronize(s));
+  int32_t ctl_h[8];
+  NRS_BHIP(ctx, hipMemcpy(ctl_h, L.ctl, sizeof(ctl_h), hipMemcpyDeviceToHost));
+  std::vector<SolveState> hs(B);
+  for (int k = 0; k < B; ++k)
+    NRS_BHIP(ctx, hipMemcpy(&hs[k], L.sb[k].st, sizeof(SolveState), hipMemcpyDeviceToHost));
+  if (ctl_h[2] || ctl_h[6])
+    return bfail(ctx, NRS_E_HIP, "batched LU / solve: a bounded wait timed out");
+  nrs_status worst = NRS_OK;
+  std::vector<int> redo;
+  for (int k = 0; k < B; ++k) {
+    nrs_info& inf = infos[k];
+    inf.method_used = NRS_FP32_IR;
+    inf.fell_back = 0;
+    inf.iterations = hs[k].iterations;
+    inf.singular = hs[k].singular;
+    inf.backward_error = hs[k].bwd;
+    inf.correction = hs[k].corr;
+    if (hs[k].nonfinite == 2)
+      return bfail(ctx, NRS_E_ARG, "problem " + std::to_string(k) +
+                                       ": nu outside [0, N) or body outside [-1, M)");
+    const bool ok = hs[k].converged && !hs[k].failed && !hs[k].nonfinite;
+    if (!ok) redo.push_back(k);
+  }
+  // Systems that did not converge are solved again one by one in FP64 with
+  // partial pivoting; the workspace is reused from its start (the batched
+  // work is complete).
+  for (int k : redo) {
+    if (o.no_fallback) {
+      worst = NRS_E_NOT_CONVERGED;
+      continue;
+    }
+    const nrs_problem& p = problems[k];
+    if (solve_workspace_bytes(p.N, p.Q, p.M, NRS_FP64_LU) > ws_bytes)
+      return bfail(ctx, NRS_E_WORKSPACE, "workspace too small for the FP64 fallback");
+    nrs_options o64 = o;
+    o64.method = NRS_FP64_LU;
+    nrs_info i64 = {};
+    st = nrs_solve(ctx, &p, u[k], ftext ? ftext[k] : nullptr, &o64, ws, ws_bytes, sol[k], &i64);
+    infos[k] = i64;
+    infos[k].fell_back = 1;
+    if (st != NRS_OK) worst = st;
+  }
+  if (worst == NRS_E_NOT_CONVERGED) bfail(ctx, worst, "refinement did not converge (no fallback)");
+  return worst;
+}
+
+}  // extern "C"

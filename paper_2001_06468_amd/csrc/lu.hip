@@ -340,28 +340,47 @@ __device__ inline double bcast_lane<double>(double v, int lane) {
 // consumes all blocks published so far.
 // The lower pass takes its right-hand side from rhs (gathered through perm for
 // scope 0, read directly for scope 1); the upper pass works in place on x.
+// Batched form: the tickets of one launch are numbered step by step (system by
+// system inside a step, see TrsvBatch); system s owns flags sys[s].flags.
+// ctl[0] = ticket, ctl[1] = finished count of the launch.
 template <class T, bool UPPER, bool LOCALP>
-__global__ __launch_bounds__(kTrsvThreads) void k_trsv(int64_t n, const T* __restrict__ LU,
-                                                       int64_t lda, T* __restrict__ x,
-                                                       int32_t* __restrict__ sync,
-                                                       const int32_t* __restrict__ stop,
-                                                       int32_t* __restrict__ err,
-                                                       const int32_t* __restrict__ lperm,
-                                                       const T* __restrict__ rhs) {
-  if (stop && *stop) return;
+__global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t* __restrict__ ctl,
+                                                       int32_t* __restrict__ err) {
   __shared__ int s_t, s_jend;
   __shared__ T s_part[kTrsvThreads / 64][kTb];
   __shared__ T s_x[kTb];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t nblk = (n + kTb - 1) / kTb;
-  if (tid == 0) s_t = atomicAdd(&sync[0], 1);
+  if (tid == 0) s_t = atomicAdd(&ctl[0], 1);
   __syncthreads();
-  const int64_t t = s_t;
-  const int64_t b = UPPER ? nblk - 1 - t : t;
+  const int32_t tk = s_t;
+  int64_t kstep;
+  int sidx;
+  if (bt.sys == nullptr) {
+    kstep = tk;
+    sidx = 0;
+  } else {
+    int lo = 0, hi = bt.nsteps * bt.B;  // pref[lo] <= tk < pref[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (bt.pref[mid] <= tk) lo = mid; else hi = mid;
+    }
+    kstep = lo / bt.B;
+    sidx = lo % bt.B;
+  }
+  const TrsvSys<T> sy = bt.sys ? bt.sys[sidx] : bt.one;
+  const bool skip = tk >= bt.total || (sy.stop && *sy.stop);
+  const int64_t n = sy.n, lda = sy.lda;
+  const T* __restrict__ LU = sy.LU;
+  T* __restrict__ x = sy.x;
+  const T* __restrict__ rhs = sy.rhs;
+  const int32_t* __restrict__ lperm = sy.perm;
+  int32_t* flags = sy.flags;
+  const int64_t nblk = (n + kTb - 1) / kTb;
+  const int64_t b = UPPER ? nblk - 1 - kstep : kstep;
   const int64_t r0 = b * kTb;
-  const int rows = (int)min<int64_t>(kTb, n - r0);
+  const int rows = skip ? 0 : (int)min<int64_t>(kTb, n - r0);
   const int64_t row = r0 + lane;
-  int32_t* flags = sync + 2;
+  if (!skip) {
   // diagonal block row of this lane (wave 0 only), fetched ahead of the waits
   T dg[kTb];
   if (w == 0) {
@@ -441,13 +460,22 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(int64_t n, const T* __res
     if (lane < rows) x[row] = v;
   }
   __syncthreads();
-  if (tid == 0) {
-    st_release(&flags[b], 1);
-    const int32_t done = atomicAdd(&sync[1], 1);
-    if (done == nblk - 1) {
-      for (int64_t q = 0; q < nblk; ++q) flags[q] = 0;
-      sync[0] = 0;
-      sync[1] = 0;
+  if (tid == 0) st_release(&flags[b], 1);
+  }  // !skip
+  // the last workgroup of the launch clears every flag and the counters
+  if (tid == 0) s_t = atomicAdd(&ctl[1], 1);
+  __syncthreads();
+  if (s_t == (int)gridDim.x - 1) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    for (int q = 0; q < bt.B; ++q) {
+      const TrsvSys<T> sq = bt.sys ? bt.sys[q] : bt.one;
+      const int64_t nb = (sq.n + kTb - 1) / kTb;
+      for (int64_t e = tid; e < nb; e += kTrsvThreads) sq.flags[e] = 0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      ctl[0] = 0;
+      ctl[1] = 0;
     }
   }
 }
@@ -481,19 +509,39 @@ hipError_t launch_lu_factor(int64_t n, T* A, int64_t lda, int32_t* ipiv, int32_t
 }
 
 template <class T>
+hipError_t launch_trsv_batch(const TrsvBatch<T>& bt, int32_t scope, int32_t* ctl, int32_t* err,
+                             hipStream_t s) {
+  if (bt.total <= 0) return hipSuccess;
+  const dim3 g((unsigned)bt.total);
+  if (scope)
+    hipLaunchKernelGGL((k_trsv<T, false, true>), g, dim3(kTrsvThreads), 0, s, bt, ctl, err);
+  else
+    hipLaunchKernelGGL((k_trsv<T, false, false>), g, dim3(kTrsvThreads), 0, s, bt, ctl, err);
+  hipLaunchKernelGGL((k_trsv<T, true, false>), g, dim3(kTrsvThreads), 0, s, bt, ctl, err);
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t launch_lu_solve(int64_t n, int32_t scope, const T* LU, int64_t lda,
                            const int32_t* perm, const T* b, T* x, int32_t* sync, int32_t* err,
                            const int32_t* stop, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const unsigned nblk = (unsigned)((n + kTb - 1) / kTb);
-  if (scope)
-    hipLaunchKernelGGL((k_trsv<T, false, true>), dim3(nblk), dim3(kTrsvThreads), 0, s, n, LU,
-                       lda, x, sync, stop, err, perm, b);
-  else
-    hipLaunchKernelGGL((k_trsv<T, false, false>), dim3(nblk), dim3(kTrsvThreads), 0, s, n, LU,
-                       lda, x, sync, stop, err, perm, b);
-  hipLaunchKernelGGL((k_trsv<T, true, false>), dim3(nblk), dim3(kTrsvThreads), 0, s, n, LU, lda,
-                     x, sync, stop, err, perm, b);
+  TrsvBatch<T> bt;
+  bt.one.LU = LU;
+  bt.one.lda = lda;
+  bt.one.n = n;
+  bt.one.x = x;
+  bt.one.rhs = b;
+  bt.one.perm = perm;
+  bt.one.flags = sync + 2;
+  bt.one.stop = stop;
+  bt.sys = nullptr;
+  bt.pref = nullptr;
+  bt.B = 1;
+  bt.nsteps = (int32_t)((n + kTb - 1) / kTb);
+  bt.total = bt.nsteps;
+  hipError_t e = launch_trsv_batch<T>(bt, scope, sync, err, s);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 
@@ -507,6 +555,10 @@ template hipError_t launch_lu_factor<float>(int64_t, float*, int64_t, int32_t*, 
                                             int32_t*, hipStream_t);
 template hipError_t launch_lu_factor<double>(int64_t, double*, int64_t, int32_t*, int32_t*,
                                              int32_t*, hipStream_t);
+template hipError_t launch_trsv_batch<float>(const TrsvBatch<float>&, int32_t, int32_t*,
+                                             int32_t*, hipStream_t);
+template hipError_t launch_trsv_batch<double>(const TrsvBatch<double>&, int32_t, int32_t*,
+                                              int32_t*, hipStream_t);
 template hipError_t launch_lu_solve<float>(int64_t, int32_t, const float*, int64_t,
                                            const int32_t*, const float*, float*, int32_t*,
                                            int32_t*, const int32_t*, hipStream_t);

@@ -19,6 +19,10 @@ struct nrs_ctx {
   // control words [4] and tile flags [nt*nt]; kept zero by the kernels
   int32_t* tsync = nullptr;
   int64_t tsync_cap = 0;
+  // pinned host staging of batch descriptors; the event marks the last copy
+  void* staging = nullptr;
+  size_t staging_cap = 0;
+  hipEvent_t staging_event = nullptr;
 };
 
 namespace nrs {
@@ -113,7 +117,9 @@ struct SolveBuffers {
 };
 
 size_t solve_workspace_bytes(int64_t N, int64_t Q, int32_t M, int32_t method);
-bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, SolveBuffers& sb);
+// with64 = false leaves out the FP64 matrix (batched FP32 solves)
+bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, SolveBuffers& sb,
+                 bool with64 = true);
 
 // One system of the persistent tile LU (64 x 64 tiles, static block pivoting).
 template <class T>
@@ -141,6 +147,32 @@ struct LuBatch {
 template <class T>
 hipError_t launch_lu_tiles(const LuBatch<T>& bt, int32_t* ctl, hipStream_t s);
 void lu_task_prefix(const int32_t* nts, int32_t B, std::vector<int32_t>& pref, int32_t& nbands);
+
+// One system of the multi-workgroup triangular solves.
+template <class T>
+struct TrsvSys {
+  const T* LU;
+  int64_t lda;
+  int64_t n;
+  T* x;                 // solution (upper pass in place)
+  const T* rhs;         // right-hand side of the lower pass
+  const int32_t* perm;  // scope 0: composite permutation; scope 1: tile-local
+  int32_t* flags;       // [ceil(n/64)] block flags, zero before the launch
+  const int32_t* stop;  // nonzero: skip this system (may be NULL)
+};
+template <class T>
+struct TrsvBatch {
+  TrsvSys<T> one;           // used when sys == NULL (single system)
+  const TrsvSys<T>* sys;    // device array of B systems, or NULL
+  const int32_t* pref;      // device ticket prefix over (step, system), or NULL
+  int32_t B;
+  int32_t nsteps;           // max blocks over systems
+  int32_t total;            // number of tickets (sum of blocks)
+};
+// Lower then upper pass over a batch; ctl[0..1] zero before, kept zero.
+template <class T>
+hipError_t launch_trsv_batch(const TrsvBatch<T>& bt, int32_t scope, int32_t* ctl, int32_t* err,
+                             hipStream_t s);
 
 // ---- kernels / launchers (each returns hipError_t of the launch) ----
 hipError_t launch_geometry(const nrs_scene& sc, double t, const double* Y, double* x, double* X,
