@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the other solution forms")
     ap.add_argument("--batch", type=int, default=512, metavar="B",
                     help="also time the batched rod-over-wall workload with B instances (0: skip)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="time only the batched workload (profiling)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -159,6 +161,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.batch_only:
+        print(json.dumps({"batched": run_batched(ctx, nrs, synth, max(args.batch, 1), dev)}),
+              flush=True)
+        return
 
     method = METHODS[args.method]
     ms, wall, Y, t_end, info = run_steps(method, args.warmup, args.steps)
