@@ -47,6 +47,26 @@ def cpu_threads():
     return os.cpu_count() or 1
 
 
+def train_model(ctx, nrs, solves=2000, steps=8000):
+    """Warm-start network for the GMRES form: training data are solves of the
+    method on seeded filament swimmers (random phases, times, M in {1,5,25}),
+    fitted with the library's own forward/backward/Adam kernels."""
+    import torch
+    from paper_2001_06468_amd import learned
+    t0 = time.perf_counter()
+    states = learned.filament_states(solves, seed0=1000, m_choices=(1, 5, 25),
+                                     m_probs=(0.7, 0.25, 0.05))
+    data = learned.build_targets(ctx, learned.generate(ctx, states, batch=128))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    model, hist = learned.train(ctx, data, steps=steps, batch_bodies=256, lr=5e-3, lr_final=3e-5,
+                                seed=0, log_every=steps)
+    t2 = time.perf_counter()
+    return model, {"solves": solves, "bodies": data.n_bodies, "generate_s": t1 - t0,
+                   "train_s": t2 - t1, "adam_steps": steps, "batch_bodies": 256,
+                   "final_loss": hist[-1]["loss"], "params": int(model.theta.numel())}
+
+
 def run_batched(ctx, nrs, synth, B, dev, reps=3):
     """B independent rod-over-wall resistance problems (orders log-uniform in
     300..6000) in one nrs_solve_batched call: geometry and nearest map on the
@@ -134,12 +154,12 @@ def main():
     ctx = nrs.Context(0)
     dt = 2 * math.pi / 100
 
-    def run_steps(method, warmup, steps):
+    def run_steps(method, warmup, steps, **opts):
         ws = torch.empty(nrs.nrs_rk4_workspace_size(ctx, ds, method), dtype=torch.uint8, device=dev)
         Y = torch.from_numpy(scene["Y0"].copy()).to(dev)
         t = 0.0
         for _ in range(warmup):
-            nrs.nrs_rk4_step(ctx, ds, Y, t, dt, ws, method=method)
+            nrs.nrs_rk4_step(ctx, ds, Y, t, dt, ws, method=method, **opts)
             t += dt
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -147,7 +167,7 @@ def main():
         w0 = time.perf_counter()
         e0.record()
         for _ in range(steps):
-            nrs.nrs_rk4_step(ctx, ds, Y, t, dt, ws, method=method)
+            nrs.nrs_rk4_step(ctx, ds, Y, t, dt, ws, method=method, **opts)
             t += dt
         e1.record()
         torch.cuda.synchronize()
@@ -232,6 +252,7 @@ def main():
     asm_tflops = asm_flops / (as_avg_ms / 1e3) / 1e12
 
     forms = {}
+    learned_info = None
     if not args.no_forms:
         for name, m in METHODS.items():
             if m == method:
@@ -240,6 +261,18 @@ def main():
             fm, _, _, _, finfo = run_steps(m, 1, k)
             forms[name] = {"solves_per_s": 4 * k / (fm / 1e3), "steps": k,
                            "fell_back": finfo["fell_back"]}
+        # GMRES forms: cold, previous-solve warm start, learned warm start
+        model, learned_info = train_model(ctx, nrs)
+        body_off = nrs.nrs_mlp_body_offsets(ctx, ds.t["body"], M)
+        k = 3
+        for name, opts in (("gmres_cold", {}),
+                           ("gmres_previous", {"warm_start": nrs.NRS_WARM_PREVIOUS}),
+                           ("gmres_learned", {"warm_start": nrs.NRS_WARM_MODEL, "model": model,
+                                              "body_off": body_off})):
+            fm, _, Yf, tf, finfo = run_steps(nrs.NRS_GMRES, 1, k, **opts)
+            forms[name] = {"solves_per_s": 4 * k / (fm / 1e3), "steps": k,
+                           "fell_back": finfo["fell_back"],
+                           "max_stage_iterations_last_step": finfo["iterations"]}
 
     batched = None
     if args.batch > 0:
@@ -282,6 +315,7 @@ def main():
                      "note": "33 flops per (force point, quadrature point) pair; call includes "
                              "the nu-sorted layout and rigid-body blocks"},
         "forms": forms,
+        "learned_training": learned_info,
         "batched": batched,
         "cpu_baseline": cpu,
         "wall_s": wall,

@@ -135,12 +135,27 @@ typedef struct {
 typedef struct {
   int32_t method;        /* NRS_FP64_LU, NRS_FP32_IR, NRS_FP32_GEPP_IR, NRS_GMRES */
   int32_t max_refine;    /* refinement sweeps (IR) before falling back; <=0: 6   */
-  double  tol;           /* IR: stop when |d|_inf <= tol |x|_inf; GMRES: relative
-                            residual |b - A x|_2 <= tol |b|_2.  <=0: 1e-9        */
-  int32_t gmres_restart; /* GMRES(m) restart length, <=0: 40                     */
-  int32_t gmres_max_iter;/* total GMRES iterations before LU fallback, <=0: 400  */
+  double  tol;           /* IR: stop when |d|_inf <= tol |x|_inf, <=0: 1e-9.
+                            GMRES: relative residual |b - A x|_2 <= tol |b|_2,
+                            <=0: 1e-11                                          */
+  int32_t gmres_restart; /* GMRES(m) restart length 1..63, <=0: 50              */
+  int32_t gmres_max_iter;/* total GMRES iterations before LU fallback, <=0: 1000 */
   int32_t no_fallback;   /* 1 = report failure instead of falling back to FP64 LU */
-  const double* x_init;  /* [n] device warm start for NRS_GMRES (NULL = zero)    */
+  const double* x_init;  /* [n] device initial guess for NRS_GMRES (NULL = zero); may
+                            equal sol (start from sol's current content)       */
+  /* Warm start of the GMRES solves inside nrs_rk4_step:
+     NRS_WARM_NONE, NRS_WARM_PREVIOUS (the previous solve of the same time
+     stepping workspace on this context) or NRS_WARM_MODEL (the network of the
+     learned warm start, below). */
+  int32_t warm_start;
+  const float* model_theta;     /* device [nrs_mlp_param_count()] (NRS_WARM_MODEL)  */
+  double model_scales[3];       /* force, U and Omega scales of the model outputs   */
+  const int32_t* body_off;      /* device [M+1] from nrs_mlp_body_offsets           */
+  /* NRS_GMRES with x_init and free bodies: before iterating, project the
+     initial forces onto each body's force and torque balance (the constraint
+     rows hold exactly) and refit each body's (U, Omega) to the velocity
+     residual by least squares.  Always applied to NRS_WARM_MODEL starts. */
+  int32_t x_init_complete;
 } nrs_options;
 
 typedef struct {
@@ -247,6 +262,77 @@ nrs_status nrs_lu_factor(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t piv
  * alias b).  Asynchronous. */
 nrs_status nrs_lu_solve(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivot_scope,
                         const void* LU, int64_t lda, const int32_t* perm, const void* b, void* x);
+
+/* ------------------------------------------------------------------------ */
+/* Learned warm start for GMRES (not part of the paper's method: an initial */
+/* guess for the same linear system; the GMRES residual decides).           */
+/* ------------------------------------------------------------------------ */
+/* Network: for each free body b with points m (one contiguous run per body,
+ * bodies in order), features phi_m = (B^T (x_m - x0), B^T u_m, s_m) in the
+ * body frame (x, u lab frame; s the point's arclength parameter), then
+ *   h1 = tanh(W1 phi + b1), c = mean h1, h2 = tanh(W2 h1 + V2 c + b2),
+ *   y_m = W3 h2 + b3 (3 outputs per point), z_b = W4 mean h2 + b4 (6 per body),
+ * hidden width NRS_MLP_HIDDEN.  theta: FP32 [nrs_mlp_param_count()] holding
+ * W1 (64 x 7 row-major), b1, W2 (64 x 64), V2 (64 x 64), b2, W3 (3 x 64), b3,
+ * W4 (6 x 64), b4.  The model predicts y = B^T f / scales[0] and
+ * z = (B^T U / scales[1], B^T Omega / scales[2]). */
+#define NRS_MLP_HIDDEN      64
+#define NRS_MLP_MAX_POINTS  256   /* force points per body */
+#define NRS_WARM_NONE       0
+#define NRS_WARM_PREVIOUS   1
+#define NRS_WARM_MODEL      2
+int64_t nrs_mlp_param_count(void);
+
+/* body_off [M+1] (device) of the point-to-body map body [N]; synchronises and
+ * returns NRS_E_ARG unless every body's points form one contiguous run, the
+ * runs are in body order and adjacent, and no body has more than
+ * NRS_MLP_MAX_POINTS points. */
+nrs_status nrs_mlp_body_offsets(nrs_ctx* ctx, int64_t N, const int32_t* body, int32_t M,
+                                int32_t* body_off);
+/* phi [N][7] FP32; points with body < 0 get zeros.  x, u: [3][N]; s: [N];
+ * Y: [M][12]. */
+nrs_status nrs_mlp_features(nrs_ctx* ctx, int64_t N, const double* x, const double* u,
+                            const double* s, const int32_t* body, int32_t M, const double* Y,
+                            float* phi);
+/* Forward pass over N points in M bodies (phi [N][7]).  sel: device [nsel]
+ * body ids, or NULL for all M bodies.  y: [N][3] written at the points of the
+ * evaluated bodies; z: [M][6].  A body id outside [0, M) or a range outside
+ * [0, N) or longer than NRS_MLP_MAX_POINTS is skipped and raises bit 1 of
+ * nrs_mlp_status. */
+nrs_status nrs_mlp_forward(nrs_ctx* ctx, const float* theta, int64_t N, int32_t M,
+                           const int32_t* body_off, const int32_t* sel, int32_t nsel,
+                           const float* phi, float* y, float* z);
+/* Loss L = mean over the selected bodies of (mean over the body's points and
+ * components of (y - t_pt)^2 + mean over the 6 components of (z - t_body)^2)
+ * and its gradient: grad [nrs_mlp_param_count() + 1], last entry L.  The
+ * per-body contributions are summed in a fixed order (deterministic).
+ * t_pt: [N][3]; t_body: [M][6]; ws: nrs_mlp_grad_workspace_size bytes. */
+nrs_status nrs_mlp_grad_workspace_size(int32_t nsel, size_t* bytes);
+nrs_status nrs_mlp_grad(nrs_ctx* ctx, const float* theta, int64_t N, int32_t M,
+                        const int32_t* body_off, const int32_t* sel, int32_t nsel,
+                        const float* phi, const float* t_pt, const float* t_body, float* grad,
+                        void* ws, size_t ws_bytes);
+/* Adam (Kingma and Ba 2015) step number `step` >= 1 on count parameters:
+ * m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * theta -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps). */
+nrs_status nrs_adam_step(nrs_ctx* ctx, int64_t count, float* theta, const float* grad, float* m,
+                         float* v, int32_t step, float lr, float beta1, float beta2, float eps);
+/* Training targets from a solution sol [3N + 6M]: t_pt = B^T f / scales[0],
+ * t_body = (B^T U / scales[1], B^T Omega / scales[2]); scales: HOST [3]. */
+nrs_status nrs_mlp_targets(nrs_ctx* ctx, int64_t N, int32_t M, const int32_t* body,
+                           const double* Y, const double* sol, const double* scales,
+                           float* t_pt, float* t_body);
+/* Initial guess x0 [3N + 6M] (FP64) from the network: features, forward pass
+ * and the map back to the lab frame (zero force density at points outside
+ * the bodies).  scales: HOST [3]; ws: nrs_mlp_warm_start_workspace_size. */
+nrs_status nrs_mlp_warm_start_workspace_size(int64_t N, int32_t M, size_t* bytes);
+nrs_status nrs_mlp_warm_start(nrs_ctx* ctx, const float* theta, const double* scales, int64_t N,
+                              int32_t M, const int32_t* body, const int32_t* body_off,
+                              const double* x, const double* u, const double* s,
+                              const double* Y, double* x0, void* ws, size_t ws_bytes);
+/* Synchronise, return and clear the sticky error bits of the network kernels
+ * (1: a body id or point range was invalid and the body was skipped). */
+nrs_status nrs_mlp_status(nrs_ctx* ctx, int32_t* flags);
 
 /* ------------------------------------------------------------------------ */
 /* Time stepping (Sec. 4: Y' = F(Y, t), F from the solve).                   */

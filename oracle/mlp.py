@@ -89,26 +89,30 @@ def forward(theta, H, phi, body_off, keep=False):
 
 
 def loss(theta, H, phi, body_off, t_pt, t_body):
-    """Mean squared error over point outputs plus mean squared error over body
-    outputs."""
+    """Mean over bodies of (mean squared error of the body's point outputs +
+    mean squared error of its body outputs)."""
     y, z = forward(theta, H, phi, body_off)
-    return float(np.mean((y - t_pt) ** 2) + np.mean((z - t_body) ** 2))
+    M = len(body_off) - 1
+    L = 0.0
+    for b in range(M):
+        lo, hi = body_off[b], body_off[b + 1]
+        L += np.mean((y[lo:hi] - t_pt[lo:hi]) ** 2) + np.mean((z[b] - t_body[b]) ** 2)
+    return float(L / M)
 
 
 def gradient(theta, H, phi, body_off, t_pt, t_body):
     """(loss, dloss/dtheta) by reverse-mode differentiation of forward()."""
     p = unflatten(theta, H)
     y, z, acts = forward(theta, H, phi, body_off, keep=True)
-    N, M = phi.shape[0], len(body_off) - 1
-    L = float(np.mean((y - t_pt) ** 2) + np.mean((z - t_body) ** 2))
-    dy = 2.0 * (y - t_pt) / (N * O_PT)
+    M = len(body_off) - 1
+    L = loss(theta, H, phi, body_off, t_pt, t_body)
     dz = 2.0 * (z - t_body) / (M * P_BODY)
     g = {name: np.zeros(s) for name, s in shapes(H)}
     for b in range(M):
         lo, hi = body_off[b], body_off[b + 1]
         n_b = hi - lo
         h1, c, h2, d = acts[b]
-        dyb = dy[lo:hi]
+        dyb = 2.0 * (y[lo:hi] - t_pt[lo:hi]) / (M * n_b * O_PT)
         g["W3"] += dyb.T @ h2
         g["b3"] += dyb.sum(axis=0)
         g["W4"] += np.outer(dz[b], d)

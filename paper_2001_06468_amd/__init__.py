@@ -17,13 +17,18 @@ import torch
 
 from . import _lib
 from ._lib import (NRS_FP32_GEPP_IR, NRS_FP32_IR, NRS_FP64_LU, NRS_GMRES,  # noqa: F401
-                   NrsInfo, NrsOptions, NrsProblem, NrsScene)
+                   NRS_MLP_HIDDEN, NRS_MLP_MAX_POINTS, NRS_WARM_MODEL, NRS_WARM_NONE,
+                   NRS_WARM_PREVIOUS, NrsInfo, NrsOptions, NrsProblem, NrsScene)
 
 __all__ = [
     "NrsError", "Context", "DeviceScene", "Problem", "nrs_create", "nrs_version", "nrs_geometry",
     "nrs_nearest", "nrs_workspace_size", "nrs_assemble", "nrs_apply", "nrs_solve",
     "nrs_query_info", "nrs_solve_batched_workspace_size", "nrs_solve_batched", "nrs_lu_factor", "nrs_lu_solve", "nrs_rk4_workspace_size", "nrs_rk4_step",
     "NRS_FP64_LU", "NRS_FP32_IR", "NRS_FP32_GEPP_IR", "NRS_GMRES", "lda_for",
+    "NRS_WARM_NONE", "NRS_WARM_PREVIOUS", "NRS_WARM_MODEL", "Model", "nrs_mlp_param_count",
+    "nrs_mlp_body_offsets", "nrs_mlp_features", "nrs_mlp_forward", "nrs_mlp_grad",
+    "nrs_mlp_grad_workspace_size", "nrs_adam_step", "nrs_mlp_targets",
+    "nrs_mlp_warm_start_workspace_size", "nrs_mlp_warm_start", "nrs_mlp_status",
 ]
 
 
@@ -148,10 +153,25 @@ class Problem:
                           self.eps, self.mu)
 
 
+class Model:
+    """Parameters of the warm-start network (device FP32 [nrs_mlp_param_count()])
+    and the (force, U, Omega) scales of its outputs."""
+
+    def __init__(self, theta, scales):
+        if theta.dtype != torch.float32 or theta.numel() != nrs_mlp_param_count():
+            raise ValueError("theta must be float32 with nrs_mlp_param_count() entries")
+        self.theta = theta
+        self.scales = tuple(float(v) for v in scales)
+
+
 def _options(method=NRS_FP64_LU, max_refine=0, tol=0.0, gmres_restart=0, gmres_max_iter=0,
-             no_fallback=0, x_init=None):
+             no_fallback=0, x_init=None, warm_start=NRS_WARM_NONE, model=None, body_off=None,
+             x_init_complete=0):
+    sc = (C.c_double * 3)(*(model.scales if model is not None else (0.0, 0.0, 0.0)))
     return NrsOptions(method, max_refine, tol, gmres_restart, gmres_max_iter, no_fallback,
-                      _ptr(x_init, torch.float64, "x_init"))
+                      _ptr(x_init, torch.float64, "x_init"), warm_start,
+                      _ptr(model.theta, torch.float32, "theta") if model is not None else None,
+                      sc, _ptr(body_off, torch.int32, "body_off"), int(x_init_complete))
 
 
 def nrs_geometry(ctx, scene, t, Y, x=None, X=None, w=None, u=None):
@@ -279,3 +299,92 @@ def nrs_rk4_step(ctx, scene, Y, t, dt, ws, method=NRS_FP64_LU, ftext=None, **opt
                                     scene.mu, _ptr(ftext, torch.float64, "ftext"),
                                     _ptr(Y, torch.float64, "Y"), float(t), float(dt), C.byref(o),
                                     _ptr(ws, torch.uint8, "ws"), ws.numel()), ctx)
+
+
+# ---------------------------------------------------------------- learned warm start
+
+def nrs_mlp_param_count():
+    return int(_lib.load().nrs_mlp_param_count())
+
+
+def nrs_mlp_body_offsets(ctx, body, M):
+    """Device int32 [M+1] offsets of each body's contiguous run of points."""
+    off = torch.empty(M + 1, dtype=torch.int32, device=body.device)
+    _check(_lib.load().nrs_mlp_body_offsets(ctx.handle, body.numel(), _ptr(body, torch.int32, "body"),
+                                            M, _ptr(off, torch.int32, "body_off")), ctx)
+    return off
+
+
+def nrs_mlp_features(ctx, x, u, s, body, M, Y, phi):
+    f64 = torch.float64
+    _check(_lib.load().nrs_mlp_features(ctx.handle, body.numel(), _ptr(x, f64, "x"), _ptr(u, f64, "u"),
+                                        _ptr(s, f64, "s"), _ptr(body, torch.int32, "body"), M,
+                                        _ptr(Y, f64, "Y"), _ptr(phi, torch.float32, "phi")), ctx)
+
+
+def nrs_mlp_forward(ctx, theta, M, body_off, phi, y, z, sel=None):
+    f32 = torch.float32
+    nsel = 0 if sel is None else sel.numel()
+    _check(_lib.load().nrs_mlp_forward(ctx.handle, _ptr(theta, f32, "theta"), phi.shape[0], M,
+                                       _ptr(body_off, torch.int32, "body_off"),
+                                       _ptr(sel, torch.int32, "sel"), nsel, _ptr(phi, f32, "phi"),
+                                       _ptr(y, f32, "y"), _ptr(z, f32, "z")), ctx)
+
+
+def nrs_mlp_grad_workspace_size(nsel):
+    b = C.c_size_t()
+    _check(_lib.load().nrs_mlp_grad_workspace_size(nsel, C.byref(b)))
+    return b.value
+
+
+def nrs_mlp_grad(ctx, theta, M, body_off, phi, t_pt, t_body, grad, ws, sel=None):
+    """grad: float32 [nrs_mlp_param_count() + 1]; the last entry receives the loss."""
+    f32 = torch.float32
+    nsel = 0 if sel is None else sel.numel()
+    _check(_lib.load().nrs_mlp_grad(ctx.handle, _ptr(theta, f32, "theta"), phi.shape[0], M,
+                                    _ptr(body_off, torch.int32, "body_off"),
+                                    _ptr(sel, torch.int32, "sel"), nsel, _ptr(phi, f32, "phi"),
+                                    _ptr(t_pt, f32, "t_pt"), _ptr(t_body, f32, "t_body"),
+                                    _ptr(grad, f32, "grad"), _ptr(ws, torch.uint8, "ws"),
+                                    ws.numel()), ctx)
+
+
+def nrs_adam_step(ctx, theta, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    f32 = torch.float32
+    _check(_lib.load().nrs_adam_step(ctx.handle, theta.numel(), _ptr(theta, f32, "theta"),
+                                     _ptr(grad, f32, "grad"), _ptr(m, f32, "m"), _ptr(v, f32, "v"),
+                                     int(step), float(lr), float(beta1), float(beta2), float(eps)),
+           ctx)
+
+
+def nrs_mlp_targets(ctx, body, M, Y, sol, scales, t_pt, t_body):
+    f64 = torch.float64
+    sc = (C.c_double * 3)(*scales)
+    _check(_lib.load().nrs_mlp_targets(ctx.handle, body.numel(), M, _ptr(body, torch.int32, "body"),
+                                       _ptr(Y, f64, "Y"), _ptr(sol, f64, "sol"), sc,
+                                       _ptr(t_pt, torch.float32, "t_pt"),
+                                       _ptr(t_body, torch.float32, "t_body")), ctx)
+
+
+def nrs_mlp_warm_start_workspace_size(N, M):
+    b = C.c_size_t()
+    _check(_lib.load().nrs_mlp_warm_start_workspace_size(N, M, C.byref(b)))
+    return b.value
+
+
+def nrs_mlp_warm_start(ctx, model, body, body_off, x, u, s, Y, x0, ws):
+    f64 = torch.float64
+    M = body_off.numel() - 1
+    sc = (C.c_double * 3)(*model.scales)
+    _check(_lib.load().nrs_mlp_warm_start(ctx.handle, _ptr(model.theta, torch.float32, "theta"), sc,
+                                          body.numel(), M, _ptr(body, torch.int32, "body"),
+                                          _ptr(body_off, torch.int32, "body_off"),
+                                          _ptr(x, f64, "x"), _ptr(u, f64, "u"), _ptr(s, f64, "s"),
+                                          _ptr(Y, f64, "Y"), _ptr(x0, f64, "x0"),
+                                          _ptr(ws, torch.uint8, "ws"), ws.numel()), ctx)
+
+
+def nrs_mlp_status(ctx):
+    f = C.c_int32()
+    _check(_lib.load().nrs_mlp_status(ctx.handle, C.byref(f)), ctx)
+    return f.value

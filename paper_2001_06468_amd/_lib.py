@@ -21,6 +21,12 @@ NRS_FP32_IR = 1
 NRS_FP32_GEPP_IR = 2
 NRS_GMRES = 3
 
+NRS_WARM_NONE = 0
+NRS_WARM_PREVIOUS = 1
+NRS_WARM_MODEL = 2
+NRS_MLP_HIDDEN = 64
+NRS_MLP_MAX_POINTS = 256
+
 _p = C.c_void_p
 _i64 = C.c_int64
 _i32 = C.c_int32
@@ -42,7 +48,8 @@ class NrsProblem(C.Structure):
 class NrsOptions(C.Structure):
     _fields_ = [("method", _i32), ("max_refine", _i32), ("tol", C.c_double),
                 ("gmres_restart", _i32), ("gmres_max_iter", _i32), ("no_fallback", _i32),
-                ("x_init", _p)]
+                ("x_init", _p), ("warm_start", _i32), ("model_theta", _p),
+                ("model_scales", C.c_double * 3), ("body_off", _p), ("x_init_complete", _i32)]
 
 
 class NrsInfo(C.Structure):
@@ -76,6 +83,19 @@ PROTOTYPES = {
                                  C.POINTER(NrsInfo)]),
     "nrs_lu_factor": (_i32, [_p, _i64, _i32, _i32, _p, _i64, _p, _p, _p]),
     "nrs_lu_solve": (_i32, [_p, _i64, _i32, _i32, _p, _i64, _p, _p, _p]),
+    "nrs_mlp_param_count": (_i64, []),
+    "nrs_mlp_body_offsets": (_i32, [_p, _i64, _p, _i32, _p]),
+    "nrs_mlp_features": (_i32, [_p, _i64, _p, _p, _p, _p, _i32, _p, _p]),
+    "nrs_mlp_forward": (_i32, [_p, _p, _i64, _i32, _p, _p, _i32, _p, _p, _p]),
+    "nrs_mlp_grad_workspace_size": (_i32, [_i32, C.POINTER(C.c_size_t)]),
+    "nrs_mlp_grad": (_i32, [_p, _p, _i64, _i32, _p, _p, _i32, _p, _p, _p, _p, _p, C.c_size_t]),
+    "nrs_adam_step": (_i32, [_p, _i64, _p, _p, _p, _p, _i32, C.c_float, C.c_float, C.c_float,
+                             C.c_float]),
+    "nrs_mlp_targets": (_i32, [_p, _i64, _i32, _p, _p, _p, C.POINTER(C.c_double), _p, _p]),
+    "nrs_mlp_warm_start_workspace_size": (_i32, [_i64, _i32, C.POINTER(C.c_size_t)]),
+    "nrs_mlp_warm_start": (_i32, [_p, _p, C.POINTER(C.c_double), _i64, _i32, _p, _p, _p, _p, _p,
+                                  _p, _p, _p, C.c_size_t]),
+    "nrs_mlp_status": (_i32, [_p, C.POINTER(_i32)]),
     "nrs_rk4_workspace_size": (_i32, [_p, C.POINTER(NrsScene), _i32, C.POINTER(C.c_size_t)]),
     "nrs_rk4_step": (_i32, [_p, C.POINTER(NrsScene), _i32, _p, _p, C.c_double, C.c_double, _p,
                             _p, C.c_double, C.c_double, C.POINTER(NrsOptions), _p, C.c_size_t]),

@@ -54,6 +54,18 @@ nrs_status ctx_sync_words(nrs_ctx* ctx, int64_t n) {
   return NRS_OK;
 }
 
+}  // namespace
+
+// The context's zeroed device flag words (allocated on first use).
+nrs_status ctx_dev_flags(nrs_ctx* ctx) {
+  if (ctx->dflags) return NRS_OK;
+  NRS_HIP(ctx, hipMalloc(&ctx->dflags, 16 * sizeof(int32_t)));
+  NRS_HIP(ctx, hipMemset(ctx->dflags, 0, 16 * sizeof(int32_t)));
+  return NRS_OK;
+}
+
+namespace {
+
 nrs_status check_problem(nrs_ctx* ctx, const nrs_problem* pb) {
   if (!pb) return fail(ctx, NRS_E_ARG, "problem is NULL");
   if (pb->N <= 0 || pb->Q <= 0 || pb->M < 0) return fail(ctx, NRS_E_ARG, "need N > 0, Q > 0, M >= 0");
@@ -102,6 +114,16 @@ bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, Sol
   sb.red = ar.take<double>(rowsum_scratch(n));
   sb.tsync = ar.take<int32_t>(trsv_sync_ints(n));
   sb.lu_done = ar.take<int32_t>(lu_tiles_nt(n) * lu_tiles_nt(n));
+  sb.AT = sb.V = sb.gw0 = sb.gw1 = sb.gpart = nullptr;
+  sb.gst = nullptr;
+  if (method == NRS_GMRES) {
+    sb.AT = ar.take<double>((size_t)sb.lda * n);
+    sb.V = ar.take<double>((size_t)n * kGmresLd);
+    sb.gw0 = ar.take<double>(n);
+    sb.gw1 = ar.take<double>(n);
+    sb.gpart = ar.take<double>((size_t)gmres_blocks(n) * kGmresLd);
+    sb.gst = ar.take<GmresState>(1);
+  }
   return !ar.overflow;
 }
 
@@ -154,6 +176,58 @@ nrs_status run_fp32_ir(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, do
   return NRS_OK;
 }
 
+// FP64 GMRES on the stored FP64 matrix from x's initial content (x_init
+// copied in by the caller, else zero).  Synchronises once per chunk of
+// Arnoldi steps to decide whether to queue more.
+nrs_status run_gmres(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, double* x,
+                     const nrs_options& o, bool norm, hipStream_t s) {
+  const int64_t n = 3 * pb.N + 6 * (int64_t)pb.M;
+  const int32_t m = o.gmres_restart > 0 ? o.gmres_restart : 50;
+  const int32_t max_iter = o.gmres_max_iter > 0 ? o.gmres_max_iter : 1000;
+  const double tol = o.tol > 0 ? o.tol : 1e-11;
+  NRS_HIP(ctx, launch_assemble<double>(pb, sb.srt, sb.A64, sb.lda, s));
+  if (norm) NRS_HIP(ctx, launch_anorm64(n, sb.A64, sb.lda, sb.st, sb.red, s));
+  NRS_HIP(ctx, launch_transpose64(n, sb.A64, sb.lda, sb.AT, sb.lda, s));
+  if (o.x_init && o.x_init != x)
+    NRS_HIP(ctx, hipMemcpyAsync(x, o.x_init, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  else if (!o.x_init)
+    NRS_HIP(ctx, launch_fill_f64(x, 0.0, n, s));
+  if (o.x_init && o.x_init_complete && pb.M > 0)
+    NRS_HIP(ctx, launch_rigid_completion(pb.N, pb.M, pb.x, pb.Y, pb.body, sb.srt.W, sb.b + 3 * pb.N,
+                                         sb.AT, sb.lda, sb.b, x, sb.gw1, sb.gpart, s));
+  GmresArgs a;
+  a.n = n;
+  a.ld = sb.lda;
+  a.AT = sb.AT;
+  a.b = sb.b;
+  a.x = x;
+  a.V = sb.V;
+  a.w0 = sb.gw0;
+  a.w1 = sb.gw1;
+  a.part = sb.gpart;
+  a.st = sb.gst;
+  NRS_HIP(ctx, launch_gmres_init(sb.gst, tol, m, max_iter, s));
+  NRS_HIP(ctx, launch_gmres_residual(a, s));
+  struct Hdr {
+    int32_t done, stop, fail, k, iters;
+  } h;
+  constexpr int kChunk = 8;
+  for (;;) {
+    NRS_HIP(ctx, launch_gmres_steps(a, kChunk, s));
+    NRS_HIP(ctx, hipMemcpyAsync(&h, sb.gst, sizeof(h), hipMemcpyDeviceToHost, s));
+    NRS_HIP(ctx, hipStreamSynchronize(s));
+    if (h.fail || h.done) break;
+    if (!h.stop) continue;
+    NRS_HIP(ctx, launch_gmres_update(a, s));
+    NRS_HIP(ctx, launch_gmres_residual(a, s));
+    NRS_HIP(ctx, hipMemcpyAsync(&h, sb.gst, sizeof(h), hipMemcpyDeviceToHost, s));
+    NRS_HIP(ctx, hipStreamSynchronize(s));
+    if (h.fail || h.done || h.iters >= max_iter) break;
+  }
+  NRS_HIP(ctx, launch_gmres_report(sb.st, sb.gst, s));
+  return NRS_OK;
+}
+
 nrs_status read_state(nrs_ctx* ctx, const SolveState* dst, SolveState& hst) {
   NRS_HIP(ctx, hipMemcpyAsync(&hst, dst, sizeof(SolveState), hipMemcpyDeviceToHost, ctx->stream));
   NRS_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -191,6 +265,8 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
     st = run_fp64_lu(ctx, pb, sb, sol, sync, s);
   } else if (uses_fp32(method)) {
     st = run_fp32_ir(ctx, pb, sb, sol, method == NRS_FP32_IR ? 1 : 0, max_refine, tol, sync, s);
+  } else if (method == NRS_GMRES) {
+    st = run_gmres(ctx, pb, sb, sol, o, sync, s);
   } else {
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
   }
@@ -269,6 +345,7 @@ nrs_status nrs_destroy(nrs_ctx* ctx) {
       hipEventDestroy(ctx->staging_event);
     }
     if (ctx->staging) hipHostFree(ctx->staging);
+    if (ctx->dflags) hipFree(ctx->dflags);
   }
   delete ctx;
   return NRS_OK;
@@ -319,7 +396,7 @@ nrs_status nrs_nearest(nrs_ctx* ctx, int64_t N, const double* x, int32_t G,
 nrs_status nrs_workspace_size(nrs_ctx* ctx, int64_t N, int64_t Q, int32_t M, int32_t method,
                               size_t* bytes) {
   if (!bytes || N <= 0 || Q <= 0 || M < 0) return fail(ctx, NRS_E_ARG, "bad sizes");
-  if (method < NRS_FP64_LU || method > NRS_FP32_GEPP_IR)
+  if (method < NRS_FP64_LU || method > NRS_GMRES)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
   *bytes = solve_workspace_bytes(N, Q, M, method);
   return NRS_OK;
@@ -376,8 +453,10 @@ nrs_status nrs_solve(nrs_ctx* ctx, const nrs_problem* pb, const double* u, const
   nrs_options o = {};
   o.method = NRS_FP64_LU;
   if (opt) o = *opt;
-  if (o.method < NRS_FP64_LU || o.method > NRS_FP32_GEPP_IR)
+  if (o.method < NRS_FP64_LU || o.method > NRS_GMRES)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
+  if (o.method == NRS_GMRES && o.gmres_restart >= kGmresLd)
+    return fail(ctx, NRS_E_UNSUPPORTED, "GMRES restart length must be below 64");
   Arena ar(ws, ws_bytes);
   SolveBuffers sb;
   if (!carve_solve(ar, pb->N, pb->Q, pb->M, o.method, sb))
@@ -451,6 +530,7 @@ struct RkBuffers {
   SolveState* report;
   double *x, *X, *w, *u, *Ys, *K[4], *sol, *Ysave;
   int32_t* nu;
+  float *phi, *my, *mz;   // network features / outputs (GMRES warm start)
   SolveBuffers sb;
 };
 
@@ -466,13 +546,19 @@ bool carve_rk(Arena& ar, const nrs_scene& sc, int32_t method, RkBuffers& rb) {
   for (int i = 0; i < 4; ++i) rb.K[i] = ar.take<double>(12 * M);
   rb.Ysave = ar.take<double>(12 * M);
   rb.sol = ar.take<double>(n);
+  rb.phi = rb.my = rb.mz = nullptr;
+  if (method == NRS_GMRES) {
+    rb.phi = ar.take<float>(7 * N);
+    rb.my = ar.take<float>(3 * N);
+    rb.mz = ar.take<float>(6 * M);
+  }
   carve_solve(ar, N, Q, sc.M, method, rb.sb);
   return !ar.overflow;
 }
 
 nrs_status rk4_pass(nrs_ctx* ctx, const nrs_scene& sc, const GroupTable& gt,
                     const int32_t* groupX, double eps, double mu, const double* ftext, double* Y,
-                    double t, double dt, const nrs_options& o, RkBuffers& rb) {
+                    double t, double dt, const nrs_options& o, RkBuffers& rb, bool prev_valid) {
   hipStream_t s = ctx->stream;
   const double c[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
   NRS_HIP(ctx, launch_state_init(rb.report, o.method, s));
@@ -492,7 +578,23 @@ nrs_status rk4_pass(nrs_ctx* ctx, const nrs_scene& sc, const GroupTable& gt,
     pb.Y = rb.Ys;
     pb.eps = eps;
     pb.mu = mu;
-    nrs_status st = solve_core(ctx, pb, rb.u, ftext, o, rb.sb, rb.sol, false, nullptr);
+    nrs_options os = o;
+    if (o.method == NRS_GMRES) {
+      // warm start of this stage's GMRES solve
+      os.x_init = nullptr;
+      if (o.warm_start == NRS_WARM_PREVIOUS && (stg > 0 || prev_valid)) {
+        os.x_init = rb.sol;
+      } else if (o.warm_start == NRS_WARM_MODEL) {
+        NRS_HIP(ctx, launch_features(sc.N, rb.x, rb.u, sc.s, sc.body, sc.M, rb.Ys, rb.phi, s));
+        NRS_HIP(ctx, launch_mlp_forward(o.model_theta, sc.M, sc.M, sc.N, o.body_off, nullptr,
+                                        rb.phi, rb.my, rb.mz, ctx->dflags, s));
+        NRS_HIP(ctx, launch_to_lab(sc.N, sc.M, sc.body, rb.Ys, rb.my, rb.mz, o.model_scales,
+                                   rb.sol, s));
+        os.x_init = rb.sol;
+        os.x_init_complete = 1;
+      }
+    }
+    nrs_status st = solve_core(ctx, pb, rb.u, ftext, os, rb.sb, rb.sol, false, nullptr);
     if (st != NRS_OK) return st;
     NRS_HIP(ctx, launch_state_accumulate(rb.report, rb.sb.st, s));
     NRS_HIP(ctx, launch_rk_rates(sc.M, sc.N, rb.Ys, rb.sol, rb.K[stg], s));
@@ -519,7 +621,7 @@ nrs_status nrs_rk4_workspace_size(nrs_ctx* ctx, const nrs_scene* sc, int32_t met
   nrs_status st = check_scene(ctx, sc);
   if (st) return st;
   if (!bytes) return fail(ctx, NRS_E_ARG, "bytes is NULL");
-  if (method < NRS_FP64_LU || method > NRS_FP32_GEPP_IR)
+  if (method < NRS_FP64_LU || method > NRS_GMRES)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
   Arena ar(nullptr, 0);
   RkBuffers rb;
@@ -549,14 +651,27 @@ nrs_status nrs_rk4_step(nrs_ctx* ctx, const nrs_scene* sc, int32_t G, const int3
   nrs_options o = {};
   o.method = NRS_FP64_LU;
   if (opt) o = *opt;
-  if (o.method < NRS_FP64_LU || o.method > NRS_FP32_GEPP_IR)
+  if (o.method < NRS_FP64_LU || o.method > NRS_GMRES)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
+  if (o.method == NRS_GMRES && o.gmres_restart >= kGmresLd)
+    return fail(ctx, NRS_E_UNSUPPORTED, "GMRES restart length must be below 64");
   Arena ar(ws, ws_bytes);
   RkBuffers rb;
   if (!carve_rk(ar, *sc, o.method, rb)) return fail(ctx, NRS_E_WORKSPACE, "workspace too small");
   hipStream_t s = ctx->stream;
   NRS_HIP(ctx, hipMemcpyAsync(rb.Ysave, Y, 12 * sizeof(double) * sc->M, hipMemcpyDeviceToDevice, s));
-  if ((st = rk4_pass(ctx, *sc, gt, groupX, eps, mu, ftext, Y, t, dt, o, rb)) != NRS_OK) return st;
+  if (o.method == NRS_GMRES && o.warm_start == NRS_WARM_MODEL) {
+    if (!o.model_theta || !o.body_off || !sc->s)
+      return fail(ctx, NRS_E_ARG, "model warm start needs model_theta, body_off and scene s");
+    if (!(o.model_scales[0] > 0) || !(o.model_scales[1] > 0) || !(o.model_scales[2] > 0))
+      return fail(ctx, NRS_E_ARG, "model scales must be positive");
+    if ((st = ctx_dev_flags(ctx)) != NRS_OK) return st;
+  }
+  const bool prev_valid = ctx->rk_prev_ws == ws;
+  ctx->rk_prev_ws = nullptr;
+  if ((st = rk4_pass(ctx, *sc, gt, groupX, eps, mu, ftext, Y, t, dt, o, rb, prev_valid)) != NRS_OK)
+    return st;
+  ctx->rk_prev_ws = ws;
   if (o.no_fallback || o.method == NRS_FP64_LU) return NRS_OK;
   SolveState h;
   if ((st = read_state(ctx, rb.report, h)) != NRS_OK) return st;
@@ -565,7 +680,8 @@ nrs_status nrs_rk4_step(nrs_ctx* ctx, const nrs_scene* sc, int32_t G, const int3
   NRS_HIP(ctx, hipMemcpyAsync(Y, rb.Ysave, 12 * sizeof(double) * sc->M, hipMemcpyDeviceToDevice, s));
   nrs_options o64 = o;
   o64.method = NRS_FP64_LU;
-  if ((st = rk4_pass(ctx, *sc, gt, groupX, eps, mu, ftext, Y, t, dt, o64, rb)) != NRS_OK) return st;
+  if ((st = rk4_pass(ctx, *sc, gt, groupX, eps, mu, ftext, Y, t, dt, o64, rb, false)) != NRS_OK)
+    return st;
   SolveState mark = {};
   if ((st = read_state(ctx, rb.report, mark)) != NRS_OK) return st;
   mark.fell_back = 1;

@@ -23,7 +23,19 @@ struct nrs_ctx {
   void* staging = nullptr;
   size_t staging_cap = 0;
   hipEvent_t staging_event = nullptr;
+  // zero-initialised device words for sticky kernel error bits ([0]: network)
+  int32_t* dflags = nullptr;
+  // workspace of the last completed nrs_rk4_step (its solution seeds the next
+  // step's first GMRES solve under NRS_WARM_PREVIOUS)
+  const void* rk_prev_ws = nullptr;
 };
+
+nrs_status ctx_dev_flags(nrs_ctx* ctx);   // allocates ctx->dflags (zeroed) on first use
+
+inline nrs_status set_error(nrs_ctx* ctx, nrs_status s, const std::string& msg) {
+  if (ctx) ctx->last_error = msg;
+  return s;
+}
 
 namespace nrs {
 
@@ -114,6 +126,13 @@ struct SolveBuffers {
   int32_t* lu_done;  // [nt*nt] tile flags of the tile LU
   SolveState* st;
   int32_t chunks;
+  // GMRES (method NRS_GMRES only)
+  double* AT;        // lda x n row-major copy of A64
+  double* V;         // [n][kGmresLd]
+  double* gw0;
+  double* gw1;
+  double* gpart;
+  struct GmresState* gst;
 };
 
 size_t solve_workspace_bytes(int64_t N, int64_t Q, int32_t M, int32_t method);
@@ -173,6 +192,82 @@ struct TrsvBatch {
 template <class T>
 hipError_t launch_trsv_batch(const TrsvBatch<T>& bt, int32_t scope, int32_t* ctl, int32_t* err,
                              hipStream_t s);
+
+// ---- learned warm start (learn.hip) ----
+constexpr int kMlpHidden = 64;     // hidden width: one wavefront
+constexpr int kMlpMaxPts = 256;    // force points per body
+constexpr int kMlpParams = kMlpHidden * 7 + kMlpHidden + 2 * kMlpHidden * kMlpHidden +
+                           kMlpHidden + 3 * kMlpHidden + 3 + 6 * kMlpHidden + 6;
+// nb workgroups (bodies sel[0..nb) or 0..nb); nbodies / npts bound the body ids
+// and point ranges (invalid ones are skipped with err bit 1)
+hipError_t launch_mlp_forward(const float* th, int32_t nb, int32_t nbodies, int64_t npts,
+                              const int32_t* body_off, const int32_t* sel, const float* phi,
+                              float* y, float* z, int32_t* err, hipStream_t s);
+// rows: [nsel][kMlpParams + 1] scratch; grad: [kMlpParams + 1], last = loss
+hipError_t launch_mlp_grad(const float* th, int32_t nbodies, int64_t npts,
+                           const int32_t* body_off, const int32_t* sel, int32_t nsel,
+                           const float* phi, const float* t_pt, const float* t_body, float* rows,
+                           float* grad, int32_t* err, hipStream_t s);
+hipError_t launch_adam(int64_t count, float* th, const float* g, float* m, float* v, int32_t t,
+                       float lr, float beta1, float beta2, float eps, hipStream_t s);
+// off: [M+1] body point offsets; cnt: [2M] scratch; err |= 2 if a body's points
+// are not one contiguous run in body order or exceed kMlpMaxPts
+hipError_t launch_body_off(int64_t N, int32_t M, const int32_t* body, int32_t* off,
+                           int32_t* cnt, int32_t* err, hipStream_t s);
+hipError_t launch_features(int64_t N, const double* x, const double* u, const double* sarc,
+                           const int32_t* body, int32_t M, const double* Y, float* phi,
+                           hipStream_t s);
+hipError_t launch_targets(int64_t N, int32_t M, const int32_t* body, const double* Y,
+                          const double* sol, const double* sc, float* t_pt, float* t_body,
+                          hipStream_t s);
+hipError_t launch_to_lab(int64_t N, int32_t M, const int32_t* body, const double* Y,
+                         const float* y, const float* z, const double* sc, double* x0,
+                         hipStream_t s);
+
+// ---- GMRES (gmres.hip) ----
+constexpr int kGmresLd = 64;       // basis row length; restart m <= kGmresLd - 1
+struct GmresState {
+  int32_t done;       // true residual <= tol |b|
+  int32_t stop;       // current cycle finished (estimate converged, breakdown, m or max_iter)
+  int32_t fail;       // non-finite values
+  int32_t k;          // Arnoldi steps in the current cycle
+  int32_t iters;      // total Arnoldi steps
+  int32_t cur;        // which w buffer holds the next (unnormalised) basis vector
+  int32_t counter;    // last-workgroup ticket (zero between launches)
+  int32_t m, max_iter, pad;
+  double tol, bnorm, beta, nrm;
+  double g[kGmresLd + 1], cs[kGmresLd], sn[kGmresLd], h1[kGmresLd], h2[kGmresLd];
+  double H[(kGmresLd + 1) * kGmresLd];   // column-major, leading dimension kGmresLd + 1
+};
+struct GmresArgs {
+  int64_t n, ld;
+  const double* AT;   // row-major operator, row r at AT + r * ld
+  const double* b;
+  double* x;
+  double* V;          // [n][kGmresLd]
+  double* w0;
+  double* w1;
+  double* part;       // [gmres_blocks(n)][kGmresLd]
+  GmresState* st;
+};
+int64_t gmres_blocks(int64_t n);
+hipError_t launch_transpose64(int64_t n, const double* A, int64_t lda, double* AT, int64_t ld,
+                              hipStream_t s);
+hipError_t launch_gmres_init(GmresState* st, double tol, int32_t m, int32_t max_iter,
+                             hipStream_t s);
+hipError_t launch_gmres_residual(const GmresArgs& a, hipStream_t s);
+hipError_t launch_gmres_steps(const GmresArgs& a, int32_t count, hipStream_t s);
+hipError_t launch_gmres_update(const GmresArgs& a, hipStream_t s);
+// Initial-guess completion for swimming problems: project the forces of x0
+// onto the force / torque balance (weights W, targets ftext or zero), then
+// refit every body's (U, Omega) to the velocity residual by least squares.
+// res: [n] scratch, small: [6M] scratch.
+hipError_t launch_rigid_completion(int64_t N, int32_t M, const double* x, const double* Y,
+                                   const int32_t* body, const double* W, const double* ftext,
+                                   const double* AT, int64_t ld, const double* b, double* x0,
+                                   double* res, double* small, hipStream_t s);
+// converged / failed / iterations of the GMRES state into the solve state
+hipError_t launch_gmres_report(SolveState* st, const GmresState* g, hipStream_t s);
 
 // ---- kernels / launchers (each returns hipError_t of the launch) ----
 hipError_t launch_geometry(const nrs_scene& sc, double t, const double* Y, double* x, double* X,
