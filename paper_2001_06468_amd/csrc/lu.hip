@@ -346,9 +346,15 @@ __device__ inline double bcast_lane<double>(double v, int lane) {
 template <class T, bool UPPER, bool LOCALP>
 __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t* __restrict__ ctl,
                                                        int32_t* __restrict__ err) {
+  // FP32: the diagonal block is applied through its explicit inverse, formed
+  // while the workgroup waits for its dependencies, so the step on the
+  // critical path is a 64 x 64 product instead of a 64-step substitution.
+  constexpr bool kInv = sizeof(T) == 4;
+  constexpr int kLd = kTb + 4;
   __shared__ int s_t, s_jend;
   __shared__ T s_part[kTrsvThreads / 64][kTb];
   __shared__ T s_x[kTb];
+  __shared__ __align__(16) T s_d[kInv ? kTb : 1][kInv ? kLd : 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (tid == 0) s_t = atomicAdd(&ctl[0], 1);
   __syncthreads();
@@ -381,17 +387,85 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t*
   const int rows = skip ? 0 : (int)min<int64_t>(kTb, n - r0);
   const int64_t row = r0 + lane;
   if (!skip) {
-  // diagonal block row of this lane (wave 0 only), fetched ahead of the waits
-  T dg[kTb];
-  if (w == 0) {
+  // this block row's tile of the last dependency (the one on the critical
+  // path), fetched before any wait
+  const int64_t jl = UPPER ? b + 1 : b - 1;
+  const bool has_jl = UPPER ? (b + 1 < nblk) : (b >= 1);
+  T pa[16];
+  {
+    const int64_t c0 = jl * kTb + w * 16;
+    const int cn = has_jl ? (int)max<int64_t>(0, min<int64_t>(16, n - c0)) : 0;
 #pragma unroll
-    for (int c = 0; c < kTb; ++c) dg[c] = (c < rows && lane < rows) ? LU[row + (r0 + c) * lda] : T(0);
+    for (int c = 0; c < 16; ++c) pa[c] = (c < cn && row < n) ? LU[row + (c0 + c) * lda] : T(0);
+  }
+  T dg[kInv ? 1 : kTb];   // FP64: diagonal block row of this lane (wave 0)
+  T xr[kInv ? kTb : 1];   // FP32: row `lane` of the diagonal block's inverse (wave 0)
+  if constexpr (!kInv) {
+    if (w == 0) {
+#pragma unroll
+      for (int c = 0; c < kTb; ++c)
+        dg[c] = (c < rows && lane < rows) ? LU[row + (r0 + c) * lda] : T(0);
+    }
+  } else {
+    // diagonal tile, identity-padded, row-major in LDS
+    for (int e = tid; e < kTb * kTb; e += kTrsvThreads) {
+      const int i = e & (kTb - 1), c = e >> 6;
+      T v = (i == c) ? T(1) : T(0);
+      if (i < rows && c < rows) v = LU[r0 + i + (r0 + c) * lda];
+      s_d[i][c] = v;
+    }
+    __syncthreads();
+    if (w == 0) {
+      T xc[kTb];   // column `lane` of the inverse
+      if (!UPPER) {
+        // unit lower: X[i][c] = [i == c] - sum_{k < i} L[i][k] X[k][c]
+#pragma unroll
+        for (int i = 0; i < kTb; ++i) {
+          T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+#pragma unroll
+          for (int k = 0; k + 3 < i; k += 4) {
+            s0 += s_d[i][k] * xc[k];
+            s1 += s_d[i][k + 1] * xc[k + 1];
+            s2 += s_d[i][k + 2] * xc[k + 2];
+            s3 += s_d[i][k + 3] * xc[k + 3];
+          }
+#pragma unroll
+          for (int k = i & ~3; k < i; ++k) s0 += s_d[i][k] * xc[k];
+          const T sum = (s0 + s1) + (s2 + s3);
+          xc[i] = i < lane ? T(0) : (i == lane ? T(1) : -sum);
+        }
+      } else {
+        // upper: X[i][c] = ([i == c] - sum_{k > i} U[i][k] X[k][c]) / U[i][i]
+#pragma unroll
+        for (int i = kTb - 1; i >= 0; --i) {
+          T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+#pragma unroll
+          for (int k = i + 1; k + 3 < kTb; k += 4) {
+            s0 += s_d[i][k] * xc[k];
+            s1 += s_d[i][k + 1] * xc[k + 1];
+            s2 += s_d[i][k + 2] * xc[k + 2];
+            s3 += s_d[i][k + 3] * xc[k + 3];
+          }
+#pragma unroll
+          for (int k = kTb - ((kTb - 1 - i) & 3); k < kTb; ++k) s0 += s_d[i][k] * xc[k];
+          const T sum = (s0 + s1) + (s2 + s3);
+          xc[i] = i > lane ? T(0) : ((i == lane ? T(1) : T(0)) - sum) / s_d[i][i];
+        }
+      }
+      // transpose through LDS: lane c holds column c, lane i needs row i
+#pragma unroll
+      for (int i = 0; i < kTb; ++i) s_d[i][lane] = xc[i];
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int c = 0; c < kTb; ++c) xr[c] = s_d[lane][c];
+    }
   }
   T acc = T(0);
   const int64_t jstep = UPPER ? -1 : 1;
   int64_t j = UPPER ? nblk - 1 : 0;
+  constexpr int kPoller = 64;   // first lane of wave 1: wave 0 may still be inverting
   while (j != b) {
-    if (tid == 0) {
+    if (tid == kPoller) {
       int64_t spins = 0;
       while (ld_relaxed(&flags[j]) == 0) {
         __builtin_amdgcn_s_sleep(1);
@@ -415,11 +489,19 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t*
       const int64_t c0 = j * kTb + w * 16;
       const int cn = (int)max<int64_t>(0, min<int64_t>(16, n - c0));
       T a[16], xv[16];
+      if (j == jl) {
 #pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        const bool ok = c < cn && row < n;
-        a[c] = ok ? LU[row + (c0 + c) * lda] : T(0);
-        xv[c] = c < cn ? x[c0 + c] : T(0);
+        for (int c = 0; c < 16; ++c) {
+          a[c] = pa[c];
+          xv[c] = c < cn ? x[c0 + c] : T(0);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const bool ok = c < cn && row < n;
+          a[c] = ok ? LU[row + (c0 + c) * lda] : T(0);
+          xv[c] = c < cn ? x[c0 + c] : T(0);
+        }
       }
 #pragma unroll
       for (int c = 0; c < 16; ++c) acc += a[c] * xv[c];
@@ -439,7 +521,19 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t*
       if (lane < rows) v = s_x[lperm[row] - r0];
       __builtin_amdgcn_wave_barrier();
     }
-    if (!UPPER) {
+    if constexpr (kInv) {
+      s_x[lane] = v;
+      __builtin_amdgcn_wave_barrier();
+      T o0 = T(0), o1 = T(0), o2 = T(0), o3 = T(0);
+#pragma unroll
+      for (int c = 0; c < kTb; c += 4) {
+        o0 += xr[c] * s_x[c];
+        o1 += xr[c + 1] * s_x[c + 1];
+        o2 += xr[c + 2] * s_x[c + 2];
+        o3 += xr[c + 3] * s_x[c + 3];
+      }
+      v = (o0 + o1) + (o2 + o3);
+    } else if (!UPPER) {
 #pragma unroll
       for (int c = 0; c < kTb; ++c) {
         if (c < rows) {
