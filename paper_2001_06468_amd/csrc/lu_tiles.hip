@@ -237,6 +237,20 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int64_t nt = sy.nt, n = sy.n, lda = sy.lda;
     T* A = sy.A;
+    const int qi = (w >> 1) * 32, qj = (w & 1) * 32;
+    // this task's tile of A (only this task ever writes it), loaded up front
+    // so that the subtraction after the last update does not wait on memory
+    T a_ij[16];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rr = qi + a * 16 + Mf<T>::row(lane, r);
+          const int cc = qj + b * 16 + (lane & 15);
+          a_ij[(a * 2 + b) * 4 + r] = ld_pad(A, lda, n, i * TB + rr, j * TB + cc);
+        }
     // ---- update: acc = sum_{k<m} L_ik U_kj ----
     acc_t acc[2][2];
 #pragma unroll
@@ -245,7 +259,6 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[a][b][r] = T(0);
-    const int qi = (w >> 1) * 32, qj = (w & 1) * 32;
     for (int64_t k = 0; k < m; ++k) {
       if (tid == 0) {
         wait_flag(&sy.done[i * nt + k], err);
@@ -290,7 +303,7 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
         for (int r = 0; r < 4; ++r) {
           const int rr = qi + a * 16 + Mf<T>::row(lane, r);
           const int cc = qj + b * 16 + (lane & 15);
-          S.Cs[cc * kCS + rr] = ld_pad(A, lda, n, i * TB + rr, j * TB + cc) - acc[a][b][r];
+          S.Cs[cc * kCS + rr] = a_ij[(a * 2 + b) * 4 + r] - acc[a][b][r];
         }
     if (i != j) {
       if (tid == 0) {
