@@ -67,7 +67,7 @@ def train_model(ctx, nrs, solves=2000, steps=8000):
                    "final_loss": hist[-1]["loss"], "params": int(model.theta.numel())}
 
 
-def run_batched(ctx, nrs, synth, B, dev, reps=3):
+def run_batched(ctx, nrs, synth, B, dev, reps=3, tune=True):
     """B independent rod-over-wall resistance problems (orders log-uniform in
     300..6000) in one nrs_solve_batched call: geometry and nearest map on the
     GPU (untimed inputs), then assembly + FP32 tile LU + FP64 refinement of
@@ -92,6 +92,19 @@ def run_batched(ctx, nrs, synth, B, dev, reps=3):
     ns = np.array([p.n for p in probs], dtype=np.float64)
     ws = torch.empty(nrs.nrs_solve_batched_workspace_size(ctx, probs), dtype=torch.uint8,
                      device=dev)
+    tuned = {}
+    tune_s = 0.0
+    if tune:
+        t0 = time.perf_counter()
+        for p in probs:
+            cls = (int(math.log2(p.N)), int(math.log2(max(1, p.Q // p.N))))
+            if cls in tuned:
+                continue
+            wt = torch.empty(nrs.nrs_workspace_size(ctx, p.N, p.Q, p.M, nrs.NRS_FP32_IR),
+                             dtype=torch.uint8, device=dev)
+            r = nrs.nrs_autotune(ctx, p, wt)
+            tuned[cls] = (r["block32"], r["strip32"])
+        tune_s = time.perf_counter() - t0
     sols = [torch.empty(p.n, dtype=torch.float64, device=dev) for p in probs]
     infos = nrs.nrs_solve_batched(ctx, probs, us, sols, ws)
     times = []
@@ -104,10 +117,37 @@ def run_batched(ctx, nrs, synth, B, dev, reps=3):
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1))
     ms = float(np.mean(times))
+    # the same batch captured once into a HIP graph and replayed
+    gstream = torch.cuda.Stream()
+    gctx = nrs.Context(0, stream=gstream.cuda_stream)
+    if tune:
+        for p in probs:
+            cls = (int(math.log2(p.N)), int(math.log2(max(1, p.Q // p.N))))
+            if cls in tuned and tuned[cls] is not None:
+                wt = torch.empty(nrs.nrs_workspace_size(ctx, p.N, p.Q, p.M, nrs.NRS_FP32_IR),
+                                 dtype=torch.uint8, device=dev)
+                nrs.nrs_autotune(gctx, p, wt)
+                tuned[cls] = None
+    torch.cuda.synchronize()
+    nrs.nrs_solve_batched(gctx, probs, us, sols, ws, info=False, graph=1)   # capture + first run
+    gstream.synchronize()
+    gtimes = []
+    for _ in range(reps):
+        g0 = torch.cuda.Event(enable_timing=True)
+        g1 = torch.cuda.Event(enable_timing=True)
+        g0.record(gstream)
+        nrs.nrs_solve_batched(gctx, probs, us, sols, ws, info=False, graph=1)
+        g1.record(gstream)
+        gstream.synchronize()
+        gtimes.append(g0.elapsed_time(g1))
+    gctx.close()
+    gms = float(np.mean(gtimes))
     lu_flops = float((2.0 / 3.0 * ns ** 3).sum())
     return {"workload": f"rodwall_B{B}", "instances": B, "n_min": int(ns.min()),
             "n_max": int(ns.max()), "n_mean": float(ns.mean()),
             "solves_per_s": B / (ms / 1e3), "ms_per_batch": ms, "reps": reps,
+            "graph_solves_per_s": B / (gms / 1e3), "graph_ms_per_batch": gms,
+            "tuned_size_classes": len(tuned), "tune_s": tune_s if tune else 0.0,
             "lu_flops_total": lu_flops,
             "lu_equiv_tflops": lu_flops / (ms / 1e3) / 1e12,
             "max_backward_error": max(i["backward_error"] for i in infos),
@@ -128,6 +168,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip the other solution forms")
     ap.add_argument("--batch", type=int, default=512, metavar="B",
                     help="also time the batched rod-over-wall workload with B instances (0: skip)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--batch-only", action="store_true",
                     help="time only the batched workload (profiling)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
@@ -183,11 +224,25 @@ def main():
         del src, dst
 
     if args.batch_only:
-        print(json.dumps({"batched": run_batched(ctx, nrs, synth, max(args.batch, 1), dev)}),
+        print(json.dumps({"batched": run_batched(ctx, nrs, synth, max(args.batch, 1), dev,
+                                                 tune=not args.no_tune)}),
               flush=True)
         return
 
+    # autotune the assembly launch shape for this size class (never changes results)
     method = METHODS[args.method]
+    tune = None
+    if not args.no_tune:
+        T0 = lambda a, d=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dtype=d, device=dev)  # noqa: E731
+        import oracle as _o
+        xg, Xg, wg, ug = _o.geometry(scene, 0.0, scene["Y0"])
+        nug = _o.nearest(xg, Xg, scene["group_off"], scene["groupX"])
+        pbt = nrs.Problem(T0(xg), T0(Xg), T0(wg), T0(nug, torch.int32), T0(scene["body"], torch.int32),
+                          T0(scene["Y0"]), scene["eps"], scene["mu"])
+        wst = torch.empty(nrs.nrs_workspace_size(ctx, N, Q, M, nrs.NRS_FP32_IR), dtype=torch.uint8,
+                          device=dev)
+        tune = nrs.nrs_autotune(ctx, pbt, wst)
+        del wst
     ms, wall, Y, t_end, info = run_steps(method, args.warmup, args.steps)
     solves = 4 * args.steps
     value = solves / (ms / 1e3)
@@ -276,7 +331,7 @@ def main():
 
     batched = None
     if args.batch > 0:
-        batched = run_batched(ctx, nrs, synth, args.batch, dev)
+        batched = run_batched(ctx, nrs, synth, args.batch, dev, tune=not args.no_tune)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -316,6 +371,7 @@ def main():
                              "the nu-sorted layout and rigid-body blocks"},
         "forms": forms,
         "learned_training": learned_info,
+        "autotune": tune,
         "batched": batched,
         "cpu_baseline": cpu,
         "wall_s": wall,

@@ -156,6 +156,12 @@ typedef struct {
      rows hold exactly) and refit each body's (U, Omega) to the velocity
      residual by least squares.  Always applied to NRS_WARM_MODEL starts. */
   int32_t x_init_complete;
+  /* nrs_solve_batched, asynchronous form only (infos = NULL) on a non-default
+     stream: capture every launch and copy of the batch into a HIP graph on
+     the first call and replay it on later calls with the same arguments
+     (same sizes, pointers, eps, mu, workspace and refinement settings; the
+     array contents may change).  Up to 8 graphs are kept per context. */
+  int32_t graph;
 } nrs_options;
 
 typedef struct {
@@ -262,6 +268,27 @@ nrs_status nrs_lu_factor(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t piv
  * alias b).  Asynchronous. */
 nrs_status nrs_lu_solve(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivot_scope,
                         const void* LU, int64_t lda, const int32_t* perm, const void* b, void* x);
+
+/* Autotuning of launch shapes.  Times every candidate launch shape of the
+ * FP32 and FP64 assembly kernels (rows per workgroup 64 / 128 / 256 x force
+ * points per strip 4 / 8 / 16) on this problem (one warm-up and three timed
+ * runs each, HIP events on the context's stream), and records the fastest
+ * for the problem's size class (floor(log2 N), floor(log2(Q / N))) in the
+ * context; every later assembly of a problem of that class, in any entry
+ * point, uses it.  Every shape computes each matrix entry with the same
+ * operations, so tuning never changes a result.  Synchronises.  ws: at least
+ * nrs_workspace_size(N, Q, M, NRS_FP32_IR) bytes.  out (host, may be NULL):
+ * the choice and its timings. */
+typedef struct {
+  int32_t size_class;
+  int32_t block32, strip32, block64, strip64;
+  float ms32, ms64;                 /* tuned average per assembly, ms        */
+  float default_ms32, default_ms64; /* default shape (128 rows, 8 points)    */
+} nrs_tune_result;
+nrs_status nrs_autotune(nrs_ctx* ctx, const nrs_problem* pb, void* ws, size_t ws_bytes,
+                        nrs_tune_result* out);
+/* Forget every tuned shape of the context (defaults again). */
+nrs_status nrs_autotune_clear(nrs_ctx* ctx);
 
 /* ------------------------------------------------------------------------ */
 /* Learned warm start for GMRES (not part of the paper's method: an initial */

@@ -26,6 +26,7 @@ __all__ = [
     "nrs_query_info", "nrs_solve_batched_workspace_size", "nrs_solve_batched", "nrs_lu_factor", "nrs_lu_solve", "nrs_rk4_workspace_size", "nrs_rk4_step",
     "NRS_FP64_LU", "NRS_FP32_IR", "NRS_FP32_GEPP_IR", "NRS_GMRES", "lda_for",
     "NRS_WARM_NONE", "NRS_WARM_PREVIOUS", "NRS_WARM_MODEL", "Model", "nrs_mlp_param_count",
+    "nrs_autotune", "nrs_autotune_clear",
     "nrs_mlp_body_offsets", "nrs_mlp_features", "nrs_mlp_forward", "nrs_mlp_grad",
     "nrs_mlp_grad_workspace_size", "nrs_adam_step", "nrs_mlp_targets",
     "nrs_mlp_warm_start_workspace_size", "nrs_mlp_warm_start", "nrs_mlp_status",
@@ -166,12 +167,13 @@ class Model:
 
 def _options(method=NRS_FP64_LU, max_refine=0, tol=0.0, gmres_restart=0, gmres_max_iter=0,
              no_fallback=0, x_init=None, warm_start=NRS_WARM_NONE, model=None, body_off=None,
-             x_init_complete=0):
+             x_init_complete=0, graph=0):
     sc = (C.c_double * 3)(*(model.scales if model is not None else (0.0, 0.0, 0.0)))
     return NrsOptions(method, max_refine, tol, gmres_restart, gmres_max_iter, no_fallback,
                       _ptr(x_init, torch.float64, "x_init"), warm_start,
                       _ptr(model.theta, torch.float32, "theta") if model is not None else None,
-                      sc, _ptr(body_off, torch.int32, "body_off"), int(x_init_complete))
+                      sc, _ptr(body_off, torch.int32, "body_off"), int(x_init_complete),
+                      int(graph))
 
 
 def nrs_geometry(ctx, scene, t, Y, x=None, X=None, w=None, u=None):
@@ -388,3 +390,19 @@ def nrs_mlp_status(ctx):
     f = C.c_int32()
     _check(_lib.load().nrs_mlp_status(ctx.handle, C.byref(f)), ctx)
     return f.value
+
+
+# ---------------------------------------------------------------- autotuning
+
+def nrs_autotune(ctx, problem, ws):
+    """Tune the assembly launch shape for the problem's size class; returns the
+    choice and timings (dict)."""
+    pb = problem.struct()
+    out = _lib.NrsTuneResult()
+    _check(_lib.load().nrs_autotune(ctx.handle, C.byref(pb), _ptr(ws, torch.uint8, "ws"),
+                                    ws.numel(), C.byref(out)), ctx)
+    return out.as_dict()
+
+
+def nrs_autotune_clear(ctx):
+    _check(_lib.load().nrs_autotune_clear(ctx.handle), ctx)

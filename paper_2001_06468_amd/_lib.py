@@ -49,12 +49,22 @@ class NrsOptions(C.Structure):
     _fields_ = [("method", _i32), ("max_refine", _i32), ("tol", C.c_double),
                 ("gmres_restart", _i32), ("gmres_max_iter", _i32), ("no_fallback", _i32),
                 ("x_init", _p), ("warm_start", _i32), ("model_theta", _p),
-                ("model_scales", C.c_double * 3), ("body_off", _p), ("x_init_complete", _i32)]
+                ("model_scales", C.c_double * 3), ("body_off", _p), ("x_init_complete", _i32),
+                ("graph", _i32)]
 
 
 class NrsInfo(C.Structure):
     _fields_ = [("method_used", _i32), ("fell_back", _i32), ("iterations", _i32),
                 ("singular", _i32), ("backward_error", C.c_double), ("correction", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class NrsTuneResult(C.Structure):
+    _fields_ = [("size_class", _i32), ("block32", _i32), ("strip32", _i32), ("block64", _i32),
+                ("strip64", _i32), ("ms32", C.c_float), ("ms64", C.c_float),
+                ("default_ms32", C.c_float), ("default_ms64", C.c_float)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -83,6 +93,8 @@ PROTOTYPES = {
                                  C.POINTER(NrsInfo)]),
     "nrs_lu_factor": (_i32, [_p, _i64, _i32, _i32, _p, _i64, _p, _p, _p]),
     "nrs_lu_solve": (_i32, [_p, _i64, _i32, _i32, _p, _i64, _p, _p, _p]),
+    "nrs_autotune": (_i32, [_p, C.POINTER(NrsProblem), _p, C.c_size_t, C.POINTER(NrsTuneResult)]),
+    "nrs_autotune_clear": (_i32, [_p]),
     "nrs_mlp_param_count": (_i64, []),
     "nrs_mlp_body_offsets": (_i32, [_p, _i64, _p, _i32, _p]),
     "nrs_mlp_features": (_i32, [_p, _i64, _p, _p, _p, _p, _i32, _p, _p]),

@@ -142,7 +142,8 @@ namespace {
 nrs_status run_fp64_lu(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, double* x,
                        bool norm, hipStream_t s) {
   const int64_t n = 3 * pb.N + 6 * (int64_t)pb.M;
-  NRS_HIP(ctx, launch_assemble<double>(pb, sb.srt, sb.A64, sb.lda, s));
+  NRS_HIP(ctx, launch_assemble<double>(pb, sb.srt, sb.A64, sb.lda, s,
+                                       asm_shape_for(ctx, pb.N, pb.Q, 64)));
   if (norm) NRS_HIP(ctx, launch_anorm64(n, sb.A64, sb.lda, sb.st, sb.red, s));
   NRS_HIP(ctx, lu_factor_any<double>(n, 0, sb.A64, sb.lda, sb.ipiv64, sb.perm64,
                                       &sb.st->singular, sb.lu_done, sb.st->lu_ctl, s));
@@ -156,7 +157,8 @@ nrs_status run_fp64_lu(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, do
 nrs_status run_fp32_ir(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, double* x,
                        int32_t scope, int32_t max_refine, double tol, bool norm, hipStream_t s) {
   const int64_t n = 3 * pb.N + 6 * (int64_t)pb.M;
-  NRS_HIP(ctx, launch_assemble<float>(pb, sb.srt, sb.A32, sb.lda, s));
+  NRS_HIP(ctx, launch_assemble<float>(pb, sb.srt, sb.A32, sb.lda, s,
+                                      asm_shape_for(ctx, pb.N, pb.Q, 32)));
   if (norm) NRS_HIP(ctx, launch_anorm32(n, sb.A32, sb.lda, sb.st, sb.red, s));
   NRS_HIP(ctx, lu_factor_any<float>(n, scope, sb.A32, sb.lda, sb.ipiv, sb.perm,
                                      &sb.st->singular, sb.lu_done, sb.st->lu_ctl, s));
@@ -185,7 +187,8 @@ nrs_status run_gmres(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, doub
   const int32_t m = o.gmres_restart > 0 ? o.gmres_restart : 50;
   const int32_t max_iter = o.gmres_max_iter > 0 ? o.gmres_max_iter : 1000;
   const double tol = o.tol > 0 ? o.tol : 1e-11;
-  NRS_HIP(ctx, launch_assemble<double>(pb, sb.srt, sb.A64, sb.lda, s));
+  NRS_HIP(ctx, launch_assemble<double>(pb, sb.srt, sb.A64, sb.lda, s,
+                                       asm_shape_for(ctx, pb.N, pb.Q, 64)));
   if (norm) NRS_HIP(ctx, launch_anorm64(n, sb.A64, sb.lda, sb.st, sb.red, s));
   NRS_HIP(ctx, launch_transpose64(n, sb.A64, sb.lda, sb.AT, sb.lda, s));
   if (o.x_init && o.x_init != x)
@@ -346,6 +349,13 @@ nrs_status nrs_destroy(nrs_ctx* ctx) {
     }
     if (ctx->staging) hipHostFree(ctx->staging);
     if (ctx->dflags) hipFree(ctx->dflags);
+    if (!ctx->graphs.empty()) {
+      if (ctx->stream) hipStreamSynchronize(ctx->stream);
+      for (auto& g : ctx->graphs) {
+        hipGraphExecDestroy(g.exec);
+        hipHostFree(g.host_desc);
+      }
+    }
   }
   delete ctx;
   return NRS_OK;
@@ -419,9 +429,11 @@ nrs_status nrs_assemble(nrs_ctx* ctx, const nrs_problem* pb, int32_t precision, 
   NRS_HIP(ctx, launch_build_csr(pb->N, pb->Q, pb->X, pb->w, pb->nu, sb.srt, s));
   NRS_HIP(ctx, launch_check_nu(pb->N, sb.srt.cnt, sb.st, s));
   if (precision == 32)
-    NRS_HIP(ctx, launch_assemble<float>(*pb, sb.srt, static_cast<float*>(A), lda, s));
+    NRS_HIP(ctx, launch_assemble<float>(*pb, sb.srt, static_cast<float*>(A), lda, s,
+                                        asm_shape_for(ctx, pb->N, pb->Q, 32)));
   else
-    NRS_HIP(ctx, launch_assemble<double>(*pb, sb.srt, static_cast<double*>(A), lda, s));
+    NRS_HIP(ctx, launch_assemble<double>(*pb, sb.srt, static_cast<double*>(A), lda, s,
+                                         asm_shape_for(ctx, pb->N, pb->Q, 64)));
   return NRS_OK;
 }
 
@@ -519,6 +531,105 @@ nrs_status nrs_lu_solve(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivo
                                          nullptr, ctx->stream));
   else
     return fail(ctx, NRS_E_ARG, "precision must be 32 or 64");
+  return NRS_OK;
+}
+
+}  // extern "C"
+
+namespace nrs {
+
+int32_t size_class(int64_t N, int64_t Q) {
+  auto lg = [](int64_t v) {
+    int r = 0;
+    while (v > 1) {
+      v >>= 1;
+      ++r;
+    }
+    return r;
+  };
+  return 64 * lg(N) + lg(Q / (N > 0 ? N : 1));
+}
+
+int32_t asm_shape_for(const nrs_ctx* ctx, int64_t N, int64_t Q, int bits) {
+  if (!ctx) return -1;
+  const int32_t c = size_class(N, Q);
+  for (const auto& e : ctx->tune)
+    if (e.cls == c) return bits == 32 ? e.shape32 : e.shape64;
+  return -1;
+}
+
+}  // namespace nrs
+
+extern "C" {
+
+nrs_status nrs_autotune(nrs_ctx* ctx, const nrs_problem* pb, void* ws, size_t ws_bytes,
+                        nrs_tune_result* out) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if ((st = check_problem(ctx, pb))) return st;
+  Arena ar(ws, ws_bytes);
+  SolveBuffers sb;
+  if (!carve_solve(ar, pb->N, pb->Q, pb->M, NRS_FP32_IR, sb))
+    return fail(ctx, NRS_E_WORKSPACE, "workspace too small (size it for NRS_FP32_IR)");
+  hipStream_t s = ctx->stream;
+  NRS_HIP(ctx, launch_state_init(sb.st, NRS_FP64_LU, s));
+  NRS_HIP(ctx, launch_build_csr(pb->N, pb->Q, pb->X, pb->w, pb->nu, sb.srt, s));
+  NRS_HIP(ctx, launch_check_nu(pb->N, sb.srt.cnt, sb.st, s));
+  hipEvent_t e0, e1;
+  NRS_HIP(ctx, hipEventCreate(&e0));
+  NRS_HIP(ctx, hipEventCreate(&e1));
+  int32_t best[2] = {kAsmDefaultShape, kAsmDefaultShape};
+  float best_ms[2] = {0.f, 0.f}, def_ms[2] = {0.f, 0.f};
+  hipError_t err = hipSuccess;
+  for (int prec = 0; prec < 2 && err == hipSuccess; ++prec) {
+    for (int shape = 0; shape < kAsmShapes && err == hipSuccess; ++shape) {
+      float tot = 0.f;
+      for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
+        err = hipEventRecord(e0, s);
+        if (err == hipSuccess)
+          err = prec == 0 ? launch_assemble<float>(*pb, sb.srt, sb.A32, sb.lda, s, shape)
+                          : launch_assemble<double>(*pb, sb.srt, sb.A64, sb.lda, s, shape);
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) tot += ms;   // first run warms up
+      }
+      const float avg = tot / 3.f;
+      if (shape == kAsmDefaultShape) def_ms[prec] = avg;
+      if (shape == 0 || avg < best_ms[prec]) {
+        best_ms[prec] = avg;
+        best[prec] = shape;
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(ctx, NRS_E_HIP, std::string("autotune: ") + hipGetErrorString(err));
+  const int32_t c = size_class(pb->N, pb->Q);
+  bool found = false;
+  for (auto& e : ctx->tune)
+    if (e.cls == c) {
+      e.shape32 = best[0];
+      e.shape64 = best[1];
+      found = true;
+    }
+  if (!found) ctx->tune.push_back({c, best[0], best[1]});
+  if (out) {
+    out->size_class = c;
+    asm_shape_dims(best[0], &out->block32, &out->strip32);
+    asm_shape_dims(best[1], &out->block64, &out->strip64);
+    out->ms32 = best_ms[0];
+    out->ms64 = best_ms[1];
+    out->default_ms32 = def_ms[0];
+    out->default_ms64 = def_ms[1];
+  }
+  return NRS_OK;
+}
+
+nrs_status nrs_autotune_clear(nrs_ctx* ctx) {
+  if (!ctx) return NRS_E_ARG;
+  ctx->tune.clear();
   return NRS_OK;
 }
 

@@ -15,11 +15,15 @@ namespace nrs {
 
 namespace {
 
-constexpr int kAsmBlock = 128;
-constexpr int kTN = 8;
+// Launch shapes (rows per workgroup, force points per strip); every shape
+// computes each entry with the same operations, so the choice (made by the
+// autotuner) never changes a result.
+constexpr int kShapeBlk[kAsmShapes] = {64, 64, 64, 128, 128, 128, 256, 256, 256};
+constexpr int kShapeTN[kAsmShapes] = {4, 8, 16, 4, 8, 16, 4, 8, 16};
 
 // FP32 form: coordinates carried as hi + lo floats so that r = x_m - X_q keeps
 // FP32 relative accuracy even when |r| << |x|.
+template <int kAsmBlock, int kTN>
 __global__ __launch_bounds__(kAsmBlock) void k_assemble32(
     int64_t N, const double* __restrict__ x, const int32_t* __restrict__ seg,
     const float4* __restrict__ Xhi, const float4* __restrict__ Xlo, float eps2, float scale,
@@ -76,6 +80,7 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble32(
   }
 }
 
+template <int kAsmBlock, int kTN>
 __global__ __launch_bounds__(kAsmBlock) void k_assemble64(
     int64_t N, const double* __restrict__ x, const int32_t* __restrict__ seg,
     const double4* __restrict__ X64, double eps2, double scale, double* __restrict__ A,
@@ -302,49 +307,78 @@ __global__ __launch_bounds__(kBodyBlock) void k_apply_body(
 
 inline dim3 grid1(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)); }
 
+template <int BLK, int TN>
+void asm32(const nrs_problem& pb, const Sorted& srt, float* A, int64_t lda, float scale,
+           hipStream_t s) {
+  const int64_t N = pb.N;
+  dim3 g((unsigned)((N + BLK - 1) / BLK), (unsigned)((N + TN - 1) / TN));
+  hipLaunchKernelGGL((k_assemble32<BLK, TN>), g, dim3(BLK), 0, s, N, pb.x, srt.seg, srt.X32hi,
+                     srt.X32lo, (float)(pb.eps * pb.eps), scale, A, lda);
+}
+template <int BLK, int TN>
+void asm64(const nrs_problem& pb, const Sorted& srt, double* A, int64_t lda, double scale,
+           hipStream_t s) {
+  const int64_t N = pb.N;
+  dim3 g((unsigned)((N + BLK - 1) / BLK), (unsigned)((N + TN - 1) / TN));
+  hipLaunchKernelGGL((k_assemble64<BLK, TN>), g, dim3(BLK), 0, s, N, pb.x, srt.seg, srt.X64,
+                     pb.eps * pb.eps, scale, A, lda);
+}
+
+template <class T>
+void asm_dispatch(int shape, const nrs_problem& pb, const Sorted& srt, T* A, int64_t lda, T scale,
+                  hipStream_t s);
+#define NRS_ASM_CASES(F)                                                                        \
+  switch (shape) {                                                                             \
+    case 0: F<64, 4>(pb, srt, A, lda, scale, s); break;                                        \
+    case 1: F<64, 8>(pb, srt, A, lda, scale, s); break;                                        \
+    case 2: F<64, 16>(pb, srt, A, lda, scale, s); break;                                       \
+    case 3: F<128, 4>(pb, srt, A, lda, scale, s); break;                                       \
+    case 5: F<128, 16>(pb, srt, A, lda, scale, s); break;                                      \
+    case 6: F<256, 4>(pb, srt, A, lda, scale, s); break;                                       \
+    case 7: F<256, 8>(pb, srt, A, lda, scale, s); break;                                       \
+    case 8: F<256, 16>(pb, srt, A, lda, scale, s); break;                                      \
+    default: F<128, 8>(pb, srt, A, lda, scale, s); break;                                      \
+  }
+template <>
+void asm_dispatch<float>(int shape, const nrs_problem& pb, const Sorted& srt, float* A,
+                         int64_t lda, float scale, hipStream_t s) {
+  NRS_ASM_CASES(asm32)
+}
+template <>
+void asm_dispatch<double>(int shape, const nrs_problem& pb, const Sorted& srt, double* A,
+                          int64_t lda, double scale, hipStream_t s) {
+  NRS_ASM_CASES(asm64)
+}
+#undef NRS_ASM_CASES
+
 }  // namespace
 
-template <>
-hipError_t launch_assemble<float>(const nrs_problem& pb, const Sorted& srt, float* A,
-                                  int64_t lda, hipStream_t s) {
-  const int64_t N = pb.N;
-  const int64_t n = 3 * N + 6 * (int64_t)pb.M;
-  const float scale = (float)(1.0 / (8.0 * kPi * pb.mu));
-  if (N > 0) {
-    dim3 g((unsigned)((N + kAsmBlock - 1) / kAsmBlock), (unsigned)((N + kTN - 1) / kTN));
-    hipLaunchKernelGGL(k_assemble32, g, dim3(kAsmBlock), 0, s, N, pb.x, srt.seg, srt.X32hi,
-                       srt.X32lo, (float)(pb.eps * pb.eps), scale, A, lda);
-  }
-  if (pb.M > 0) {
-    hipLaunchKernelGGL(k_rigid_cols<float>, grid1(3 * N, 256), dim3(256), 0, s, N, pb.M, pb.body,
-                       pb.x, pb.Y, A, lda);
-    dim3 g((unsigned)n, grid1(6 * (int64_t)pb.M, 64).x);
-    hipLaunchKernelGGL(k_rigid_rows<float>, g, dim3(64), 0, s, N, pb.M, pb.body, pb.x, pb.Y,
-                       srt.W, A, lda);
-  }
-  return hipGetLastError();
+void asm_shape_dims(int32_t shape, int32_t* blk, int32_t* tn) {
+  if (shape < 0 || shape >= kAsmShapes) shape = kAsmDefaultShape;
+  *blk = kShapeBlk[shape];
+  *tn = kShapeTN[shape];
 }
 
-template <>
-hipError_t launch_assemble<double>(const nrs_problem& pb, const Sorted& srt, double* A,
-                                   int64_t lda, hipStream_t s) {
+template <class T>
+hipError_t launch_assemble(const nrs_problem& pb, const Sorted& srt, T* A, int64_t lda,
+                           hipStream_t s, int32_t shape) {
   const int64_t N = pb.N;
   const int64_t n = 3 * N + 6 * (int64_t)pb.M;
-  const double scale = 1.0 / (8.0 * kPi * pb.mu);
-  if (N > 0) {
-    dim3 g((unsigned)((N + kAsmBlock - 1) / kAsmBlock), (unsigned)((N + kTN - 1) / kTN));
-    hipLaunchKernelGGL(k_assemble64, g, dim3(kAsmBlock), 0, s, N, pb.x, srt.seg, srt.X64,
-                       pb.eps * pb.eps, scale, A, lda);
-  }
+  const T scale = (T)(1.0 / (8.0 * kPi * pb.mu));
+  if (N > 0) asm_dispatch<T>(shape, pb, srt, A, lda, scale, s);
   if (pb.M > 0) {
-    hipLaunchKernelGGL(k_rigid_cols<double>, grid1(3 * N, 256), dim3(256), 0, s, N, pb.M,
-                       pb.body, pb.x, pb.Y, A, lda);
+    hipLaunchKernelGGL(k_rigid_cols<T>, grid1(3 * N, 256), dim3(256), 0, s, N, pb.M, pb.body,
+                       pb.x, pb.Y, A, lda);
     dim3 g((unsigned)n, grid1(6 * (int64_t)pb.M, 64).x);
-    hipLaunchKernelGGL(k_rigid_rows<double>, g, dim3(64), 0, s, N, pb.M, pb.body, pb.x, pb.Y,
-                       srt.W, A, lda);
+    hipLaunchKernelGGL(k_rigid_rows<T>, g, dim3(64), 0, s, N, pb.M, pb.body, pb.x, pb.Y, srt.W,
+                       A, lda);
   }
   return hipGetLastError();
 }
+template hipError_t launch_assemble<float>(const nrs_problem&, const Sorted&, float*, int64_t,
+                                           hipStream_t, int32_t);
+template hipError_t launch_assemble<double>(const nrs_problem&, const Sorted&, double*, int64_t,
+                                            hipStream_t, int32_t);
 
 hipError_t launch_rhs(int64_t N, int32_t M, const double* u, const double* ftext, double* b,
                       hipStream_t s) {

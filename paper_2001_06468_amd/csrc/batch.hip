@@ -96,45 +96,21 @@ nrs_status stage(nrs_ctx* ctx, size_t bytes, char** host) {
   return NRS_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-nrs_status nrs_solve_batched_workspace_size(nrs_ctx* ctx, int32_t B, const nrs_problem* problems,
-                                            int32_t method, size_t* bytes) {
-  nrs_status st = check_batch(ctx, B, problems);
-  if (st) return st;
-  if (!bytes) return bfail(ctx, NRS_E_ARG, "bytes is NULL");
-  if (method != NRS_FP32_IR) return bfail(ctx, NRS_E_UNSUPPORTED, "batches use NRS_FP32_IR");
-  Arena ar(nullptr, 0);
-  BatchLayout L;
-  carve_batch(ar, B, problems, L);
-  *bytes = ar.used + 256;
-  return NRS_OK;
+// Host descriptors (systems, ticket prefixes) of a batch layout, in bytes.
+size_t desc_bytes(const BatchLayout& L, int32_t B) {
+  return sizeof(LuSys<float>) * B + sizeof(TrsvSys<float>) * B +
+         sizeof(int32_t) * (L.lu_pref_h.size() + L.tr_pref_h.size());
 }
 
-nrs_status nrs_solve_batched(nrs_ctx* ctx, int32_t B, const nrs_problem* problems,
-                             const double* const* u, const double* const* ftext,
-                             const nrs_options* opt, void* ws, size_t ws_bytes,
-                             double* const* sol, nrs_info* infos) {
-  if (!ctx) return NRS_E_ARG;
-  NRS_BHIP(ctx, hipSetDevice(ctx->device));
-  nrs_status st = check_batch(ctx, B, problems);
-  if (st) return st;
-  if (!u || !sol) return bfail(ctx, NRS_E_ARG, "u and sol arrays required");
-  for (int s = 0; s < B; ++s)
-    if (!u[s] || !sol[s]) return bfail(ctx, NRS_E_ARG, "u[s] and sol[s] required");
-  nrs_options o = {};
-  o.method = NRS_FP32_IR;
-  if (opt) o = *opt;
-  if (o.method != NRS_FP32_IR) return bfail(ctx, NRS_E_UNSUPPORTED, "batches use NRS_FP32_IR");
-  const int32_t max_refine = o.max_refine > 0 ? o.max_refine : 6;
-  const double tol = o.tol > 0 ? o.tol : 1e-9;
-  Arena ar(ws, ws_bytes);
-  BatchLayout L;
-  if (!carve_batch(ar, B, problems, L)) return bfail(ctx, NRS_E_WORKSPACE, "workspace too small");
+// Enqueue the whole batched solve on the context's stream.  h: pinned host
+// buffer for the descriptors (NULL: the context's staging buffer, reuse
+// fenced by an event); nothing here synchronises, so it can be captured.
+nrs_status enqueue_batch(nrs_ctx* ctx, int32_t B, const nrs_problem* problems,
+                         const double* const* u, const double* const* ftext, int32_t max_refine,
+                         double tol, bool norm, BatchLayout& L, char* h, bool record_event,
+                         double* const* sol) {
+  nrs_status st = NRS_OK;
   hipStream_t s = ctx->stream;
-
   // ---- descriptors -> device (one pinned staging copy) ----
   std::vector<LuSys<float>> lus(B);
   std::vector<TrsvSys<float>> trs(B);
@@ -161,8 +137,9 @@ nrs_status nrs_solve_batched(nrs_ctx* ctx, int32_t B, const nrs_problem* problem
   }
   const size_t b_lu = sizeof(LuSys<float>) * B, b_tr = sizeof(TrsvSys<float>) * B;
   const size_t b_lp = sizeof(int32_t) * L.lu_pref_h.size(), b_tp = sizeof(int32_t) * L.tr_pref_h.size();
-  char* h = nullptr;
-  if ((st = stage(ctx, b_lu + b_tr + b_lp + b_tp, &h))) return st;
+  if (!h) {
+    if ((st = stage(ctx, b_lu + b_tr + b_lp + b_tp, &h))) return st;
+  }
   std::memcpy(h, lus.data(), b_lu);
   std::memcpy(h + b_lu, trs.data(), b_tr);
   std::memcpy(h + b_lu + b_tr, L.lu_pref_h.data(), b_lp);
@@ -171,7 +148,7 @@ nrs_status nrs_solve_batched(nrs_ctx* ctx, int32_t B, const nrs_problem* problem
   NRS_BHIP(ctx, hipMemcpyAsync(L.trsys, h + b_lu, b_tr, hipMemcpyHostToDevice, s));
   NRS_BHIP(ctx, hipMemcpyAsync(L.lu_pref, h + b_lu + b_tr, b_lp, hipMemcpyHostToDevice, s));
   NRS_BHIP(ctx, hipMemcpyAsync(L.tr_pref, h + b_lu + b_tr + b_lp, b_tp, hipMemcpyHostToDevice, s));
-  NRS_BHIP(ctx, hipEventRecord(ctx->staging_event, s));
+  if (record_event) NRS_BHIP(ctx, hipEventRecord(ctx->staging_event, s));
   NRS_BHIP(ctx, launch_fill_i32(L.ctl, 0, 8, s));
 
   // ---- per system: layout, right-hand side, FP32 assembly ----
@@ -186,8 +163,9 @@ nrs_status nrs_solve_batched(nrs_ctx* ctx, int32_t B, const nrs_problem* problem
     NRS_BHIP(ctx, launch_check_nu(p.N, sb.srt.cnt, sb.st, s));
     NRS_BHIP(ctx, launch_check_body(p.N, p.M, p.body, sb.st, s));
     NRS_BHIP(ctx, launch_rhs(p.N, p.M, u[k], ftext ? ftext[k] : nullptr, sb.b, s));
-    NRS_BHIP(ctx, launch_assemble<float>(p, sb.srt, sb.A32, sb.lda, s));
-    if (infos) NRS_BHIP(ctx, launch_anorm32(n, sb.A32, sb.lda, sb.st, sb.red, s));
+    NRS_BHIP(ctx, launch_assemble<float>(p, sb.srt, sb.A32, sb.lda, s,
+                                         asm_shape_for(ctx, p.N, p.Q, 32)));
+    if (norm) NRS_BHIP(ctx, launch_anorm32(n, sb.A32, sb.lda, sb.st, sb.red, s));
     NRS_BHIP(ctx, launch_convert_f32(n, sb.b, reinterpret_cast<float*>(sb.r), s));
   }
 
@@ -228,6 +206,137 @@ nrs_status nrs_solve_batched(nrs_ctx* ctx, int32_t B, const nrs_problem* problem
       NRS_BHIP(ctx, launch_ir_update32(3 * problems[k].N + 6 * (int64_t)problems[k].M, sol[k],
                                        L.sb[k].d32, tol, 0, L.sb[k].st, s));
   }
+  return NRS_OK;
+}
+
+constexpr size_t kMaxGraphs = 8;
+
+uint64_t fnv(uint64_t h, const void* p, size_t n) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= c[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// Hash of everything a captured batch depends on: sizes, every pointer,
+// eps / mu, the workspace and the refinement settings.
+uint64_t batch_key(int32_t B, const nrs_problem* pb, const double* const* u,
+                   const double* const* ftext, double* const* sol, const void* ws,
+                   size_t ws_bytes, int32_t max_refine, double tol) {
+  uint64_t h = 1469598103934665603ull;
+  h = fnv(h, &B, sizeof(B));
+  for (int k = 0; k < B; ++k) {
+    h = fnv(h, &pb[k], sizeof(nrs_problem));
+    h = fnv(h, &u[k], sizeof(u[k]));
+    const double* f = ftext ? ftext[k] : nullptr;
+    h = fnv(h, &f, sizeof(f));
+    h = fnv(h, &sol[k], sizeof(sol[k]));
+  }
+  h = fnv(h, &ws, sizeof(ws));
+  h = fnv(h, &ws_bytes, sizeof(ws_bytes));
+  h = fnv(h, &max_refine, sizeof(max_refine));
+  h = fnv(h, &tol, sizeof(tol));
+  return h;
+}
+
+// Replay the graph captured for these arguments, capturing it first if it
+// is new.  Every launch and copy of the asynchronous batched solve is in the
+// graph; the descriptors come from a pinned buffer owned by the entry.
+nrs_status graph_batch(nrs_ctx* ctx, int32_t B, const nrs_problem* problems,
+                       const double* const* u, const double* const* ftext, int32_t max_refine,
+                       double tol, void* ws, size_t ws_bytes, BatchLayout& L,
+                       double* const* sol) {
+  hipStream_t s = ctx->stream;
+  const uint64_t key = batch_key(B, problems, u, ftext, sol, ws, ws_bytes, max_refine, tol);
+  for (auto& g : ctx->graphs)
+    if (g.key == key) {
+      NRS_BHIP(ctx, hipGraphLaunch(g.exec, s));
+      return NRS_OK;
+    }
+  void* hd = nullptr;
+  NRS_BHIP(ctx, hipHostMalloc(&hd, desc_bytes(L, B)));
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) {
+    hipHostFree(hd);
+    return bfail(ctx, NRS_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  }
+  const nrs_status st = enqueue_batch(ctx, B, problems, u, ftext, max_refine, tol, false, L,
+                                      static_cast<char*>(hd), false, sol);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(s, &graph);
+  if (st != NRS_OK || e != hipSuccess) {
+    if (graph) hipGraphDestroy(graph);
+    hipHostFree(hd);
+    if (st != NRS_OK) return st;
+    return bfail(ctx, NRS_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  }
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    hipHostFree(hd);
+    return bfail(ctx, NRS_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  if (ctx->graphs.size() >= kMaxGraphs) {
+    NRS_BHIP(ctx, hipStreamSynchronize(s));
+    hipGraphExecDestroy(ctx->graphs.front().exec);
+    hipHostFree(ctx->graphs.front().host_desc);
+    ctx->graphs.erase(ctx->graphs.begin());
+  }
+  ctx->graphs.push_back({key, exec, hd});
+  NRS_BHIP(ctx, hipGraphLaunch(exec, s));
+  return NRS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nrs_status nrs_solve_batched_workspace_size(nrs_ctx* ctx, int32_t B, const nrs_problem* problems,
+                                            int32_t method, size_t* bytes) {
+  nrs_status st = check_batch(ctx, B, problems);
+  if (st) return st;
+  if (!bytes) return bfail(ctx, NRS_E_ARG, "bytes is NULL");
+  if (method != NRS_FP32_IR) return bfail(ctx, NRS_E_UNSUPPORTED, "batches use NRS_FP32_IR");
+  Arena ar(nullptr, 0);
+  BatchLayout L;
+  carve_batch(ar, B, problems, L);
+  *bytes = ar.used + 256;
+  return NRS_OK;
+}
+
+nrs_status nrs_solve_batched(nrs_ctx* ctx, int32_t B, const nrs_problem* problems,
+                             const double* const* u, const double* const* ftext,
+                             const nrs_options* opt, void* ws, size_t ws_bytes,
+                             double* const* sol, nrs_info* infos) {
+  if (!ctx) return NRS_E_ARG;
+  NRS_BHIP(ctx, hipSetDevice(ctx->device));
+  nrs_status st = check_batch(ctx, B, problems);
+  if (st) return st;
+  if (!u || !sol) return bfail(ctx, NRS_E_ARG, "u and sol arrays required");
+  for (int s = 0; s < B; ++s)
+    if (!u[s] || !sol[s]) return bfail(ctx, NRS_E_ARG, "u[s] and sol[s] required");
+  nrs_options o = {};
+  o.method = NRS_FP32_IR;
+  if (opt) o = *opt;
+  if (o.method != NRS_FP32_IR) return bfail(ctx, NRS_E_UNSUPPORTED, "batches use NRS_FP32_IR");
+  const int32_t max_refine = o.max_refine > 0 ? o.max_refine : 6;
+  const double tol = o.tol > 0 ? o.tol : 1e-9;
+  Arena ar(ws, ws_bytes);
+  BatchLayout L;
+  if (!carve_batch(ar, B, problems, L)) return bfail(ctx, NRS_E_WORKSPACE, "workspace too small");
+  hipStream_t s = ctx->stream;
+
+  if (o.graph) {
+    if (infos) return bfail(ctx, NRS_E_ARG, "graph replay is asynchronous: pass infos = NULL");
+    if (!s) return bfail(ctx, NRS_E_UNSUPPORTED, "graph capture needs a non-default stream");
+    return graph_batch(ctx, B, problems, u, ftext, max_refine, tol, ws, ws_bytes, L, sol);
+  }
+  if ((st = enqueue_batch(ctx, B, problems, u, ftext, max_refine, tol, infos != nullptr, L,
+                          nullptr, true, sol)))
+    return st;
   if (!infos) return NRS_OK;
 
   // ---- synchronous report: final FP64 backward error of every system ----

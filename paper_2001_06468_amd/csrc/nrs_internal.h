@@ -10,6 +10,22 @@
 
 #include "../../include/nrs.h"
 
+// A captured batched solve (nrs_solve_batched with options.graph): the
+// executable graph, the argument hash it was captured for, and the pinned
+// host copy of the batch descriptors its copy nodes read.
+struct nrs_graph_entry {
+  uint64_t key;
+  hipGraphExec_t exec;
+  void* host_desc;
+};
+
+// Autotuned assembly launch shape of one size class (see nrs_autotune).
+struct nrs_tune_entry {
+  int32_t cls;       // size class: 64 * floor(log2 N) + floor(log2(Q / N))
+  int32_t shape32;   // assembly shape index, FP32 (-1: not tuned)
+  int32_t shape64;   // FP64
+};
+
 struct nrs_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -28,7 +44,18 @@ struct nrs_ctx {
   // workspace of the last completed nrs_rk4_step (its solution seeds the next
   // step's first GMRES solve under NRS_WARM_PREVIOUS)
   const void* rk_prev_ws = nullptr;
+  // captured batched solves, oldest first (at most kMaxGraphs)
+  std::vector<nrs_graph_entry> graphs;
+  // autotuned assembly shapes by size class
+  std::vector<nrs_tune_entry> tune;
 };
+
+namespace nrs {
+// Tuned assembly shape for a problem of N force and Q quadrature points in
+// precision bits (32 / 64), or -1 (default shape) if its class is not tuned.
+int32_t asm_shape_for(const nrs_ctx* ctx, int64_t N, int64_t Q, int bits);
+int32_t size_class(int64_t N, int64_t Q);
+}  // namespace nrs
 
 nrs_status ctx_dev_flags(nrs_ctx* ctx);   // allocates ctx->dflags (zeroed) on first use
 
@@ -276,9 +303,14 @@ hipError_t launch_nearest(int64_t N, const double* x, const GroupTable& gt, int6
                           const double* X, const int32_t* groupX, int32_t* nu, hipStream_t s);
 hipError_t launch_build_csr(int64_t N, int64_t Q, const double* X, const double* w,
                             const int32_t* nu, Sorted& srt, hipStream_t s);
+// Assembly launch shapes: shape index -> (rows per workgroup, force points
+// per strip); -1 = default.  Results do not depend on the shape.
+constexpr int kAsmShapes = 9;
+constexpr int kAsmDefaultShape = 4;   // 128 rows, 8 force points
+void asm_shape_dims(int32_t shape, int32_t* blk, int32_t* tn);
 template <class T>
 hipError_t launch_assemble(const nrs_problem& pb, const Sorted& srt, T* A, int64_t lda,
-                           hipStream_t s);
+                           hipStream_t s, int32_t shape = -1);
 hipError_t launch_rhs(int64_t N, int32_t M, const double* u, const double* ftext, double* b,
                       hipStream_t s);
 hipError_t launch_apply(const nrs_problem& pb, const Sorted& srt, const double* v, double* y,

@@ -219,3 +219,49 @@ def test_c4_full_batch_sampled_parity(ctx):
         f = sols[k].cpu().numpy()[:3 * N]
         ef = np.linalg.norm(f - f_ref.ravel()) / np.linalg.norm(f_ref)
         assert ef <= 1e-8, (k, ns[k], ef, infos[k])
+
+
+def test_batched_graph_replay():
+    """The asynchronous batched solve captured into a HIP graph: every replay
+    (with other GPU work and synchronisations in between) equals the eager
+    solve bit for bit, and replays read the current contents of the inputs."""
+    stream = torch.cuda.Stream()
+    c = nrs.Context(0, stream=stream.cuda_stream)
+    scenes = synth.rod_wall_batch(6, seed=21, lo=300, hi=1500)
+    preps = [prepare(s) for s in scenes]
+    pbs = [p for p, _ in preps]
+    us = [T(h["u"]) for _, h in preps]
+    ws = torch.empty(nrs.nrs_solve_batched_workspace_size(c, pbs), dtype=torch.uint8, device=DEV)
+    sols_e = [torch.empty(p.n, dtype=torch.float64, device=DEV) for p in pbs]
+    sols_g = [torch.empty(p.n, dtype=torch.float64, device=DEV) for p in pbs]
+    torch.cuda.synchronize()
+    nrs.nrs_solve_batched(c, pbs, us, sols_e, ws, info=False)
+    stream.synchronize()
+    ref = [x.clone() for x in sols_e]
+    other = torch.randn(512, 512, device=DEV)
+    for rep in range(3):
+        for x in sols_g:
+            x.zero_()
+        (other @ other).sum().item()          # unrelated eager work between replays
+        torch.cuda.synchronize()
+        nrs.nrs_solve_batched(c, pbs, us, sols_g, ws, info=False, graph=1)
+        stream.synchronize()
+        for k in range(len(pbs)):
+            assert torch.equal(sols_g[k], ref[k]), (rep, k)
+    # new right-hand sides (same pointers): the replay solves for them; scaling
+    # by two is exact through every step, so the result is exactly 2 x
+    for u in us:
+        u.mul_(2.0)
+    torch.cuda.synchronize()
+    nrs.nrs_solve_batched(c, pbs, us, sols_g, ws, info=False, graph=1)
+    stream.synchronize()
+    for k in range(len(pbs)):
+        assert torch.equal(sols_g[k], 2.0 * ref[k]), k
+    with pytest.raises(nrs.NrsError, match="asynchronous"):
+        nrs.nrs_solve_batched(c, pbs, us, sols_g, ws, info=True, graph=1)
+    c.close()
+    # the default (null) stream cannot be captured
+    c0 = nrs.Context(0, stream=0)
+    with pytest.raises(nrs.NrsError, match="non-default stream"):
+        nrs.nrs_solve_batched(c0, pbs, us, sols_g, ws, info=False, graph=1)
+    c0.close()

@@ -320,3 +320,34 @@ def test_minimal_problem(ctx):
     nrs.nrs_solve(ctx, pb, T(u), None, sol, ws, method=nrs.NRS_FP32_IR)
     a = 0.5 * (2.0 / 0.1) / (8 * math.pi * 2.0)
     np.testing.assert_allclose(sol.cpu().numpy(), u / a, rtol=1e-12)
+
+
+@pytest.mark.parametrize("name,mk", [("filaments_M5", lambda: synth.filament_scene(5, seed=0)),
+                                     ("rodwall_1500", lambda: synth.rod_wall_batch(1, seed=5, lo=1500, hi=1500)[0])])
+def test_autotune_never_changes_results(ctx, name, mk):
+    """The assembly launch shape chosen by the autotuner is recorded for the
+    size class and used afterwards; matrices and solutions are bit-identical
+    to those of the default shape."""
+    scene = mk()
+    pb, host = prepare(scene, 0.1)
+    ws = workspace(ctx, pb, nrs.NRS_FP32_IR)
+    lda = nrs.lda_for(pb.n)
+    nrs.nrs_autotune_clear(ctx)
+
+    def run():
+        A32 = torch.zeros((pb.n, lda), dtype=torch.float32, device=DEV)
+        A64 = torch.zeros((pb.n, lda), dtype=torch.float64, device=DEV)
+        nrs.nrs_assemble(ctx, pb, 32, A32, lda, ws)
+        nrs.nrs_assemble(ctx, pb, 64, A64, lda, ws)
+        sol, info = gpu_solve(ctx, scene, pb, host, nrs.NRS_FP32_IR)
+        return A32, A64, sol
+
+    A32, A64, sol = run()
+    res = nrs.nrs_autotune(ctx, pb, ws)
+    assert res["block32"] in (64, 128, 256) and res["strip32"] in (4, 8, 16)
+    assert res["block64"] in (64, 128, 256) and res["strip64"] in (4, 8, 16)
+    assert 0 < res["ms32"] <= res["default_ms32"] and 0 < res["ms64"] <= res["default_ms64"]
+    B32, B64, sol2 = run()
+    assert torch.equal(A32, B32) and torch.equal(A64, B64)
+    np.testing.assert_array_equal(sol, sol2)
+    nrs.nrs_autotune_clear(ctx)
