@@ -128,6 +128,15 @@ struct Shared {
 // j is relabelled logical row j, its values reach the other lanes through
 // readlane, and eliminated rows are skipped afterwards.
 template <class T>
+__device__ inline T pivot_inverse(T piv) {
+  return T(1) / piv;
+}
+template <>
+__device__ inline float pivot_inverse<float>(float piv) {
+  return __builtin_amdgcn_rcpf(piv);   // hardware reciprocal (1 ulp)
+}
+
+template <class T>
 __device__ __attribute__((noinline)) void diag_factor(Shared<T>& S, const LuSys<T>& sy, int64_t m,
                                                       int32_t* sing) {
   const int lane = threadIdx.x & 63;
@@ -137,9 +146,9 @@ __device__ __attribute__((noinline)) void diag_factor(Shared<T>& S, const LuSys<
   bool used = false;
   int myj = 0;
   bool zero = false;
+  uint32_t key = pivot_key(v[0], lane) + 1u;
 #pragma unroll
   for (int j = 0; j < TB; ++j) {
-    const uint32_t key = used ? 0u : pivot_key(v[j], lane) + 1u;
     const uint32_t best = wave_max_u32(key);
     const int p = __builtin_amdgcn_readfirstlane(63 - (int)((best - 1u) & 63u));
     const T piv = lane_value<T>(v[j], p);
@@ -147,16 +156,21 @@ __device__ __attribute__((noinline)) void diag_factor(Shared<T>& S, const LuSys<
       used = true;
       myj = j;
     }
-    if (piv == T(0)) {
-      zero = true;
-    } else if (!used) {
-      const T l = v[j] / piv;
-      v[j] = l;
-#pragma unroll
-      for (int c = j + 1; c < TB; ++c) v[c] -= l * lane_value<T>(v[c], p);
+    // branch-free: rows already used (and the pivot row) get l = 0 and stay
+    // unchanged
+    const bool upd = !used && piv != T(0);
+    zero = zero || piv == T(0);
+    const T l = upd ? v[j] * pivot_inverse<T>(piv) : T(0);
+    v[j] = upd ? l : v[j];
+    if (j + 1 < TB) {
+      v[j + 1] -= l * lane_value<T>(v[j + 1], p);
+      // the next column is final: its pivot search can start while the
+      // rest of the rank-1 update proceeds
+      key = used ? 0u : pivot_key(v[j + 1], lane) + 1u;
     }
+#pragma unroll
+    for (int c = j + 2; c < TB; ++c) v[c] -= l * lane_value<T>(v[c], p);
     if (lane == 0) S.perm[j] = p;
-    __builtin_amdgcn_sched_barrier(0);
   }
   if (zero && lane == 0) atomicExch(sing, 1);
   // this lane holds logical row myj of the factors
@@ -376,8 +390,11 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
 
 // One workgroup per task.  The ticket, not blockIdx, decides the task, so a
 // workgroup only waits for tasks taken by workgroups that already run.
-template <class T>
-__global__ __launch_bounds__(kLuThreads) void k_lu_tiles(LuBatch<T> bt, int32_t* ctl) {
+// MINB = workgroups per CU the register budget must allow: 1 for a single
+// system (the diagonal chain runs alone on its CU), 2 for batches (more
+// independent tasks in flight).
+template <class T, int MINB>
+__global__ __launch_bounds__(kLuThreads, MINB) void k_lu_tiles(LuBatch<T> bt, int32_t* ctl) {
   __shared__ Shared<T> S;
   const int tid = threadIdx.x;
   const int32_t B = bt.B;
@@ -462,7 +479,12 @@ void lu_task_prefix(const int32_t* nts, int32_t B, std::vector<int32_t>& pref, i
 template <class T>
 hipError_t launch_lu_tiles(const LuBatch<T>& bt, int32_t* ctl, hipStream_t s) {
   if (bt.total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_lu_tiles<T>, dim3((unsigned)bt.total), dim3(kLuThreads), 0, s, bt, ctl);
+  if (bt.sys)
+    hipLaunchKernelGGL((k_lu_tiles<T, 2>), dim3((unsigned)bt.total), dim3(kLuThreads), 0, s, bt,
+                       ctl);
+  else
+    hipLaunchKernelGGL((k_lu_tiles<T, 1>), dim3((unsigned)bt.total), dim3(kLuThreads), 0, s, bt,
+                       ctl);
   return hipGetLastError();
 }
 
