@@ -107,8 +107,9 @@ __global__ __launch_bounds__(kRedThreads) void k_ir_residual(int64_t n,
   }
 }
 
-// x += d; convergence when |d|_inf <= tol |x|_inf; failure when the
-// correction stops contracting or turns non-finite.
+// x += d; convergence when |d|_inf <= tol |x|_inf or when the predicted next
+// correction is (see below); failure when the correction stops contracting
+// or turns non-finite.
 template <class T>
 __global__ __launch_bounds__(kRedThreads) void k_ir_update(int64_t n, double* __restrict__ x,
                                                            const T* __restrict__ d, double tol,
@@ -135,7 +136,12 @@ __global__ __launch_bounds__(kRedThreads) void k_ir_update(int64_t n, double* __
       st->nonfinite = 1;
       st->failed = 1;
     } else if (!first) {
-      if (c <= tol) {
+      // Converged when this correction, or the next one predicted from the
+      // contraction rho = c / c_prev (the initial solve counts as a
+      // correction of relative size 1), is below tol: with geometric
+      // convergence the error left after this update is about c * rho.
+      const double rho = c / st->prev_corr;
+      if (c <= tol || (rho <= 0.5 && c * rho <= tol)) {
         st->converged = 1;
       } else if (st->iterations > 2 && c > 0.9 * st->prev_corr) {
         st->failed = 1;

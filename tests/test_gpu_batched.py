@@ -80,7 +80,7 @@ def test_batched_matches_single_and_oracle(ctx):
         ef, eg = rel_force_errors(sols[k], ref, scene["N"])
         assert ef <= 1e-8 and eg <= 1e-8, (k, pb.n, ef, eg, infos[k])
         assert infos[k]["iterations"] == sinfo["iterations"]
-        assert infos[k]["backward_error"] <= 1e-14
+        assert infos[k]["backward_error"] <= 1e-12
 
 
 def _scatter_problem(N, seed, eps=0.05):
@@ -211,7 +211,7 @@ def test_c4_full_batch_sampled_parity(ctx):
     infos = nrs.nrs_solve_batched(ctx, probs, us, sols, ws)
     bwd = np.array([i["backward_error"] for i in infos])
     assert all(i["fell_back"] == 0 for i in infos)
-    assert bwd.max() <= 1e-14, bwd.max()
+    assert bwd.max() <= 1e-12, bwd.max()
     order = np.argsort(ns)
     for k in (order[0], order[len(order) // 2], order[-1]):
         f_ref, _ = oracle.solve_scene(scenes[k], 0.0)
