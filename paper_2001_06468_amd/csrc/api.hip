@@ -39,19 +39,27 @@ int32_t apply_chunks(int64_t N, int64_t Q) {
 
 bool uses_fp32(int32_t method) { return method == NRS_FP32_IR || method == NRS_FP32_GEPP_IR; }
 
-// Grow the context's zero-initialised synchronisation words to fit order n.
-nrs_status ctx_sync_words(nrs_ctx* ctx, int64_t n) {
-  const int64_t nt = lu_tiles_nt(n);
-  const int64_t need = 1 + trsv_sync_ints(n) + 4 + nt * nt;
-  if (ctx->tsync_cap >= need) return NRS_OK;
+// Grow the context's zero-initialised synchronisation words to fit order n:
+// the triangular-solve words and, separately, the tile-LU words.
+nrs_status grow_words(nrs_ctx* ctx, int32_t*& p, int64_t& cap, int64_t need) {
+  if (cap >= need) return NRS_OK;
   NRS_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  if (ctx->tsync) NRS_HIP(ctx, hipFree(ctx->tsync));
-  ctx->tsync = nullptr;
-  ctx->tsync_cap = 0;
-  NRS_HIP(ctx, hipMalloc(&ctx->tsync, need * sizeof(int32_t)));
-  NRS_HIP(ctx, hipMemset(ctx->tsync, 0, need * sizeof(int32_t)));
-  ctx->tsync_cap = need;
+  if (p) NRS_HIP(ctx, hipFree(p));
+  p = nullptr;
+  cap = 0;
+  NRS_HIP(ctx, hipMalloc(&p, need * sizeof(int32_t)));
+  NRS_HIP(ctx, hipMemset(p, 0, need * sizeof(int32_t)));
+  cap = need;
   return NRS_OK;
+}
+
+nrs_status ctx_sync_words(nrs_ctx* ctx, int64_t n) {
+  return grow_words(ctx, ctx->tsync, ctx->tsync_cap, 1 + trsv_sync_ints(n));
+}
+
+nrs_status ctx_lu_words(nrs_ctx* ctx, int64_t n) {
+  const int64_t nt = lu_tiles_nt(n);
+  return grow_words(ctx, ctx->lusync, ctx->lusync_cap, 4 + nt * nt);
 }
 
 }  // namespace
@@ -343,6 +351,7 @@ nrs_status nrs_destroy(nrs_ctx* ctx) {
   if (ctx) {
     hipSetDevice(ctx->device);
     if (ctx->tsync) hipFree(ctx->tsync);
+    if (ctx->lusync) hipFree(ctx->lusync);
     if (ctx->staging_event) {
       hipEventSynchronize(ctx->staging_event);
       hipEventDestroy(ctx->staging_event);
@@ -497,8 +506,8 @@ nrs_status nrs_lu_factor(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t piv
     return fail(ctx, NRS_E_ARG, "bad LU arguments");
   if (pivot_scope != 0 && pivot_scope != 1) return fail(ctx, NRS_E_ARG, "pivot_scope is 0 or 1");
   if (n > 262144) return fail(ctx, NRS_E_UNSUPPORTED, "n too large");
-  if ((st = ctx_sync_words(ctx, n))) return st;
-  int32_t* ctl = ctx->tsync + 1 + trsv_sync_ints(n);
+  if ((st = ctx_lu_words(ctx, n))) return st;
+  int32_t* ctl = ctx->lusync;
   int32_t* done = ctl + 4;
   if (precision == 32)
     NRS_HIP(ctx, lu_factor_any<float>(n, pivot_scope, static_cast<float*>(A), lda, ipiv, perm,
@@ -520,6 +529,8 @@ nrs_status nrs_lu_solve(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivo
   if (pivot_scope != 0 && pivot_scope != 1) return fail(ctx, NRS_E_ARG, "pivot_scope is 0 or 1");
   if (n > 262144) return fail(ctx, NRS_E_UNSUPPORTED, "n too large");
   if ((st = ctx_sync_words(ctx, n))) return st;
+  // the sweep words depend on n: start every call from a clean slate
+  NRS_HIP(ctx, launch_fill_i32(ctx->tsync + 1, 0, trsv_sync_ints(n), ctx->stream));
   if (precision == 32)
     NRS_HIP(ctx, launch_lu_solve<float>(n, pivot_scope, static_cast<const float*>(LU), lda, perm,
                                         static_cast<const float*>(b), static_cast<float*>(x),

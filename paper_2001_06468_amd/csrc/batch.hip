@@ -133,6 +133,8 @@ nrs_status enqueue_batch(nrs_ctx* ctx, int32_t B, const nrs_problem* problems,
     trs[k].rhs = reinterpret_cast<const float*>(sb.r);
     trs[k].perm = sb.perm;
     trs[k].flags = sb.tsync + 2;
+    trs[k].epoch = trsv_epoch(sb.tsync, n);
+    trs[k].xp = trsv_xp(sb.tsync, n);
     trs[k].stop = &sb.st->stop;
   }
   const size_t b_lu = sizeof(LuSys<float>) * B, b_tr = sizeof(TrsvSys<float>) * B;

@@ -381,6 +381,10 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t*
   const T* __restrict__ rhs = sy.rhs;
   const int32_t* __restrict__ lperm = sy.perm;
   int32_t* flags = sy.flags;
+  // FP32: solved blocks are published as (tag, value) 64-bit words, so a
+  // consumer's poll also delivers the data (no separate flag and fence);
+  // the tag is this launch's epoch, bumped by the last workgroup
+  const uint32_t tag = kInv && !skip ? ((uint32_t)*sy.epoch & 0x7fffffffu) + 1u : 0u;
   const int64_t nblk = (n + kTb - 1) / kTb;
   const int64_t b = UPPER ? nblk - 1 - kstep : kstep;
   const int64_t r0 = b * kTb;
@@ -463,7 +467,44 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t*
   T acc = T(0);
   const int64_t jstep = UPPER ? -1 : 1;
   int64_t j = UPPER ? nblk - 1 : 0;
-  constexpr int kPoller = 64;   // first lane of wave 1: wave 0 may still be inverting
+  constexpr int kPoller = 64;   // first lane of wave 1 (FP64 path)
+  if constexpr (kInv) {
+    // each wavefront polls the 16 tagged words it needs, independently
+    for (; j != b; j += jstep) {
+      const int64_t c0 = j * kTb + w * 16;
+      const int cn = (int)max<int64_t>(0, min<int64_t>(16, n - c0));
+      T a[16];
+      if (j == jl) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) a[c] = pa[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          a[c] = (c < cn && row < n) ? LU[row + (c0 + c) * lda] : T(0);
+      }
+      uint64_t wd[16];
+      int64_t spins = 0;
+      for (;;) {
+        bool ok = true;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          wd[c] = c < cn ? __hip_atomic_load(&sy.xp[c0 + c], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT)
+                         : ((uint64_t)tag << 32);
+          ok = ok && (uint32_t)(wd[c] >> 32) == tag;
+        }
+        if (ok) break;
+        if (++spins > kSpinLimit) {
+          if (lane == 0) atomicExch(err, 1);
+          break;
+        }
+        if ((spins & 255) == 0 && ld_relaxed(err)) break;
+        __builtin_amdgcn_s_sleep(1);
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) acc += a[c] * __uint_as_float((uint32_t)wd[c]);
+    }
+  } else {
   while (j != b) {
     if (tid == kPoller) {
       int64_t spins = 0;
@@ -506,6 +547,7 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t*
 #pragma unroll
       for (int c = 0; c < 16; ++c) acc += a[c] * xv[c];
     }
+  }
   }
   s_part[w][lane] = acc;
   __syncthreads();
@@ -551,10 +593,18 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t*
         }
       }
     }
-    if (lane < rows) x[row] = v;
+    if (lane < rows) {
+      x[row] = v;
+      if constexpr (kInv) {
+        const uint64_t word = ((uint64_t)tag << 32) | (uint64_t)__float_as_uint((float)v);
+        __hip_atomic_store(&sy.xp[row], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
   }
-  __syncthreads();
-  if (tid == 0) st_release(&flags[b], 1);
+  if constexpr (!kInv) {
+    __syncthreads();
+    if (tid == 0) st_release(&flags[b], 1);
+  }
   }  // !skip
   // the last workgroup of the launch clears every flag and the counters
   if (tid == 0) s_t = atomicAdd(&ctl[1], 1);
@@ -563,8 +613,12 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t*
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     for (int q = 0; q < bt.B; ++q) {
       const TrsvSys<T> sq = bt.sys ? bt.sys[q] : bt.one;
-      const int64_t nb = (sq.n + kTb - 1) / kTb;
-      for (int64_t e = tid; e < nb; e += kTrsvThreads) sq.flags[e] = 0;
+      if constexpr (kInv) {
+        if (tid == 0) *sq.epoch = (int32_t)(((uint32_t)*sq.epoch + 1u) & 0x7fffffffu);
+      } else {
+        const int64_t nb = (sq.n + kTb - 1) / kTb;
+        for (int64_t e = tid; e < nb; e += kTrsvThreads) sq.flags[e] = 0;
+      }
     }
     __syncthreads();
     if (tid == 0) {
@@ -628,6 +682,8 @@ hipError_t launch_lu_solve(int64_t n, int32_t scope, const T* LU, int64_t lda,
   bt.one.rhs = b;
   bt.one.perm = perm;
   bt.one.flags = sync + 2;
+  bt.one.epoch = trsv_epoch(sync, n);
+  bt.one.xp = trsv_xp(sync, n);
   bt.one.stop = stop;
   bt.sys = nullptr;
   bt.pref = nullptr;

@@ -30,11 +30,14 @@ struct nrs_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string last_error;
-  // zero-initialised synchronisation words for nrs_lu_factor / nrs_lu_solve:
-  // [0] solve timeout flag, [1..] triangular-solve words, then the tile-LU
-  // control words [4] and tile flags [nt*nt]; kept zero by the kernels
+  // synchronisation words of nrs_lu_solve: [0] timeout flag, [1..] the
+  // triangular-solve words (cleared before every call)
   int32_t* tsync = nullptr;
   int64_t tsync_cap = 0;
+  // zero-initialised tile-LU words of nrs_lu_factor: control [4], tile flags
+  // [nt*nt]; kept zero by the kernel
+  int32_t* lusync = nullptr;
+  int64_t lusync_cap = 0;
   // pinned host staging of batch descriptors; the event marks the last copy
   void* staging = nullptr;
   size_t staging_cap = 0;
@@ -203,8 +206,10 @@ struct TrsvSys {
   T* x;                 // solution (upper pass in place)
   const T* rhs;         // right-hand side of the lower pass
   const int32_t* perm;  // scope 0: composite permutation; scope 1: tile-local
-  int32_t* flags;       // [ceil(n/64)] block flags, zero before the launch
+  int32_t* flags;       // [ceil(n/64)] block flags, zero before the launch (FP64)
   const int32_t* stop;  // nonzero: skip this system (may be NULL)
+  int32_t* epoch;       // launch counter of this system's sweeps (FP32)
+  uint64_t* xp;         // [n] tagged solution words (epoch tag, value bits) (FP32)
 };
 template <class T>
 struct TrsvBatch {
@@ -329,8 +334,15 @@ template <class T>
 hipError_t launch_lu_solve(int64_t n, int32_t scope, const T* LU, int64_t lda,
                            const int32_t* perm, const T* b, T* x, int32_t* sync, int32_t* err,
                            const int32_t* stop, hipStream_t s);
-// ints of the zero-initialised synchronisation buffer launch_lu_solve needs
-inline int64_t trsv_sync_ints(int64_t n) { return 2 + (n + 63) / 64; }
+// ints of the zero-initialised synchronisation buffer launch_lu_solve needs.
+// Layout (int32 units): [0] ticket, [1] exit count, [2, 2 + nblk) block flags,
+// [2 + nblk] epoch, then n 64-bit tagged solution words (8-byte aligned).
+inline int64_t trsv_sync_ints(int64_t n) { return 2 + (n + 63) / 64 + 2 + 2 * n; }
+inline int32_t* trsv_epoch(int32_t* sync, int64_t n) { return sync + 2 + (n + 63) / 64; }
+inline uint64_t* trsv_xp(int32_t* sync, int64_t n) {
+  const uintptr_t a = reinterpret_cast<uintptr_t>(trsv_epoch(sync, n) + 1);
+  return reinterpret_cast<uint64_t*>((a + 7) & ~uintptr_t(7));
+}
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s);
 hipError_t launch_ipiv_to_perm(int64_t n, const int32_t* ipiv, int32_t* perm, hipStream_t s);
