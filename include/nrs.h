@@ -224,6 +224,7 @@ nrs_status nrs_query_info(nrs_ctx* ctx, void* ws, nrs_info* info);
  * Workspace: nrs_solve_batched_workspace_size() bytes for the same problem
  * list (holds every system's FP32 matrix side by side).  The descriptors are
  * staged through a pinned host buffer owned by the context.
+ * Refinement runs at most options.max_refine sweeps (<= 0: 3 for batches).
  * With infos == NULL the call is asynchronous.  With infos != NULL it
  * synchronises, fills infos[B], and solves any system whose refinement
  * failed again alone with FP64 partial pivoting (fell_back = 1) unless

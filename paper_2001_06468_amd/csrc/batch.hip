@@ -324,7 +324,10 @@ nrs_status nrs_solve_batched(nrs_ctx* ctx, int32_t B, const nrs_problem* problem
   o.method = NRS_FP32_IR;
   if (opt) o = *opt;
   if (o.method != NRS_FP32_IR) return bfail(ctx, NRS_E_UNSUPPORTED, "batches use NRS_FP32_IR");
-  const int32_t max_refine = o.max_refine > 0 ? o.max_refine : 6;
+  // refinement converges in one or two sweeps on these systems; the default
+  // cap keeps the asynchronous form from queueing sweeps that would only
+  // find every system converged
+  const int32_t max_refine = o.max_refine > 0 ? o.max_refine : 3;
   const double tol = o.tol > 0 ? o.tol : 1e-9;
   Arena ar(ws, ws_bytes);
   BatchLayout L;
