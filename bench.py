@@ -360,7 +360,10 @@ def main():
         "config": {"workload": f"filaments_M{M}_rk4", "swimmers": M, "N": N, "Q": Q, "n": n,
                    "eps": scene["eps"], "dt": dt, "method": args.method},
         "accuracy": {"rel_force_err": err_f, "rel_velocity_err": err_uw, "target": 1e-8,
-                     "solve_info": sinfo, "step_info": info},
+                     "solve_info": sinfo, "step_info": info,
+                     "note": "solve_info: synchronous solve of the final state, backward_error at "
+                             "the returned solution; step_info: worst of the last step's four "
+                             "stages, backward_error at the iterate before the last correction"},
         "roofline": {"kernel": "k_lu_tiles<float>", "bound": "mfma", "achieved": lu_tflops,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": lu_tflops / PEAK_FP32_TFLOPS, "traffic": traffic,

@@ -172,6 +172,11 @@ typedef struct {
   double  backward_error;/* |b - A x|_inf / (|A|_inf |x|_inf + |b|_inf), FP64 A  */
   double  correction;    /* last |d|_inf / |x|_inf of the refinement             */
 } nrs_info;
+/* backward_error: the synchronous forms (info / infos != NULL) evaluate it
+ * at the returned sol.  The asynchronous forms (nrs_query_info, the RK4
+ * stages) report the last residual the refinement took, i.e. at the iterate
+ * before its last correction; after that correction the error is about
+ * correction times smaller. */
 
 /* Bytes of device workspace that nrs_solve / nrs_assemble / nrs_apply need
  * for this size and method. */

@@ -113,20 +113,26 @@ __device__ inline double lane_value<double>(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Orders the LDS accesses of a wavefront's lanes around a hand-over between
+// lanes (one lane stores what another loads): without it the compiler may
+// move a load above a store that, per thread, did not happen.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <class T>
 struct Shared {
   T Cs[TB * kCS];
   T row[TB];
   int32_t perm[TB];
+  int32_t pos[TB];
   int32_t task[4];
+  uint64_t live[2];  // diagonal tile, per panel parity: bit r set while row r is no pivot
   T Ls[TB * kLS];
   T Us[TB * kLS];
 };
 
-// Partial pivoting inside the diagonal tile held in S.Cs (one wavefront, lane
-// = row, the row in registers).  Rows are never moved: the pivot row of step
-// j is relabelled logical row j, its values reach the other lanes through
-// readlane, and eliminated rows are skipped afterwards.
 template <class T>
 __device__ inline T pivot_inverse(T piv) {
   return T(1) / piv;
@@ -136,92 +142,222 @@ __device__ inline float pivot_inverse<float>(float piv) {
   return __builtin_amdgcn_rcpf(piv);   // hardware reciprocal (1 ulp)
 }
 
+// Partial pivoting inside the diagonal tile held in S.Cs, blocked by panels of
+// kPW columns; called by all four waves.  Rows stay at their physical place
+// (S.pos[r] = logical index of physical row r once it has been the pivot, TB
+// before).  Per panel:
+//   wave 0 factors the panel (lane = row, the panel row in registers, DPP
+//          wave maximum for the pivot, pivot values by readlane);
+//   then each wave takes one column tile right of the panel: the panel's
+//          pivot rows are finished there by a unit-lower substitution
+//          (U12 = L11^-1 C, one lane per column) and every row that is not
+//          yet a pivot gets C -= L21 U12 on the matrix cores (the live-row
+//          mask comes from a ballot of wave 0).
+// Wave 0 owns the column tile next to the panel, so the next panel's
+// factorisation starts as soon as that tile is done; the other waves finish
+// the remaining tiles meanwhile (one barrier per panel).  Afterwards the rows
+// stay in physical order; the caller stores physical row r at logical row
+// S.pos[r].
+constexpr int kPW = 16;
+
 template <class T>
 __device__ __attribute__((noinline)) void diag_factor(Shared<T>& S, const LuSys<T>& sy, int64_t m,
                                                       int32_t* sing) {
-  const int lane = threadIdx.x & 63;
-  T v[TB];
-#pragma unroll
-  for (int c = 0; c < TB; ++c) v[c] = S.Cs[c * kCS + lane];
-  bool used = false;
+  typedef typename Mf<T>::acc_t acc_t;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  bool used = false, zero = false;  // wave 0 only
   int myj = 0;
-  bool zero = false;
-  uint32_t key = pivot_key(v[0], lane) + 1u;
 #pragma unroll
-  for (int j = 0; j < TB; ++j) {
-    const uint32_t best = wave_max_u32(key);
-    const int p = __builtin_amdgcn_readfirstlane(63 - (int)((best - 1u) & 63u));
-    const T piv = lane_value<T>(v[j], p);
-    if (lane == p) {
-      used = true;
-      myj = j;
-    }
-    // branch-free: rows already used (and the pivot row) get l = 0 and stay
-    // unchanged
-    const bool upd = !used && piv != T(0);
-    zero = zero || piv == T(0);
-    const T l = upd ? v[j] * pivot_inverse<T>(piv) : T(0);
-    v[j] = upd ? l : v[j];
-    if (j + 1 < TB) {
-      v[j + 1] -= l * lane_value<T>(v[j + 1], p);
-      // the next column is final: its pivot search can start while the
-      // rest of the rank-1 update proceeds
-      key = used ? 0u : pivot_key(v[j + 1], lane) + 1u;
-    }
+  for (int b = 0; b < TB / kPW; ++b) {
+    const int c0 = b * kPW;
+    T* Lp = S.Ls + (b & 1) * kPW * kPW;  // [k][k2]: multiplier of pivot k2 at panel column k
+    if (w == 0) {
+      wave_sync();  // this panel's columns were last written in MFMA layout
+      T v[kPW];
 #pragma unroll
-    for (int c = j + 2; c < TB; ++c) v[c] -= l * lane_value<T>(v[c], p);
-    if (lane == 0) S.perm[j] = p;
+      for (int k = 0; k < kPW; ++k) v[k] = S.Cs[(c0 + k) * kCS + lane];
+      uint32_t key = used ? 0u : pivot_key(v[0], lane) + 1u;
+#pragma unroll
+      for (int k = 0; k < kPW; ++k) {
+        const uint32_t best = wave_max_u32(key);
+        const int p = __builtin_amdgcn_readfirstlane(63 - (int)((best - 1u) & 63u));
+        const T piv = lane_value<T>(v[k], p);
+        if (lane == p) {
+          used = true;
+          myj = c0 + k;
+        }
+        // rows already used (and the pivot row) get l = 0 and stay unchanged
+        const bool upd = !used && piv != T(0);
+        zero = zero || piv == T(0);
+        const T l = upd ? v[k] * pivot_inverse<T>(piv) : T(0);
+        v[k] = upd ? l : v[k];
+        if (k + 1 < kPW) {
+          v[k + 1] -= l * lane_value<T>(v[k + 1], p);
+          key = used ? 0u : pivot_key(v[k + 1], lane) + 1u;
+        }
+#pragma unroll
+        for (int c = k + 2; c < kPW; ++c) v[c] -= l * lane_value<T>(v[c], p);
+        if (lane == 0) S.perm[c0 + k] = p;
+      }
+#pragma unroll
+      for (int k = 0; k < kPW; ++k) S.Cs[(c0 + k) * kCS + lane] = v[k];
+      S.pos[lane] = used ? myj : TB;
+      const uint64_t um = __ballot(used);
+      if (lane == 0) S.live[b & 1] = ~um;
+      if (used && myj >= c0) {
+        const int kp = myj - c0;
+#pragma unroll
+        for (int k = 0; k < kPW; ++k) Lp[k * kPW + kp] = k < kp ? v[k] : T(0);
+      }
+    }
+    __syncthreads();
+    const int ct = b + 1 + w;  // this wave's column tile
+    if (ct < TB / kPW) {
+      const int c = ct * kPW + (lane & 15), g = lane >> 4;
+      if (lane < kPW) {  // U12 = L11^-1 C on the panel's pivot rows, column c
+        T x[kPW];
+#pragma unroll
+        for (int k = 0; k < kPW; ++k) x[k] = S.Cs[c * kCS + S.perm[c0 + k]];
+#pragma unroll
+        for (int k = 0; k < kPW; ++k)
+#pragma unroll
+          for (int k2 = k + 1; k2 < kPW; ++k2) x[k2] -= Lp[k * kPW + k2] * x[k];
+#pragma unroll
+        for (int k = 0; k < kPW; ++k) S.Cs[c * kCS + S.perm[c0 + k]] = x[k];
+      }
+      wave_sync();
+      // C -= L21 U12 on rows that are not yet pivots (others: L = 0)
+      const uint64_t live = S.live[b & 1];
+      acc_t acc[TB / 16];
+#pragma unroll
+      for (int rt = 0; rt < TB / 16; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[rt][r] = S.Cs[c * kCS + rt * 16 + Mf<T>::row(lane, r)];
+#pragma unroll
+      for (int ks = 0; ks < kPW / 4; ++ks) {
+        const int kk = c0 + ks * 4 + g;
+        const T bu = S.Cs[c * kCS + S.perm[kk]];
+#pragma unroll
+        for (int rt = 0; rt < TB / 16; ++rt) {
+          const int row = rt * 16 + (lane & 15);
+          const T a = (live >> row) & 1 ? -S.Cs[kk * kCS + row] : T(0);
+          acc[rt] = Mf<T>::run(a, bu, acc[rt]);
+        }
+      }
+#pragma unroll
+      for (int rt = 0; rt < TB / 16; ++rt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) S.Cs[c * kCS + rt * 16 + Mf<T>::row(lane, r)] = acc[rt][r];
+    }
   }
-  if (zero && lane == 0) atomicExch(sing, 1);
-  // this lane holds logical row myj of the factors
-#pragma unroll
-  for (int c = 0; c < TB; ++c) S.Cs[c * kCS + myj] = v[c];
+  if (w == 0 && zero && lane == 0) atomicExch(sing, 1);
   // permutation of this block row: logical row j <- original row perm[j]
-  __builtin_amdgcn_wave_barrier();
-  const int64_t r0 = m * TB;
-  const int64_t gj = r0 + lane;
-  if (gj < sy.n) sy.lperm[gj] = (int32_t)(r0 + S.perm[lane]);
+  if (tid < TB) {
+    const int64_t r0 = m * TB;
+    const int64_t gj = r0 + tid;
+    if (gj < sy.n) sy.lperm[gj] = (int32_t)(r0 + S.perm[tid]);
+  }
 }
 
-// U_mj = L_mm^-1 P_m C, in place in the working tile S.Cs (one wavefront,
-// lane = column); L_mm is staged row-major in S.Ls, the permutation in S.perm.
+// U_mj = L_mm^-1 P_m C, in place in the working tile S.Cs; L_mm (unit lower)
+// is staged column-major in S.Ls, the permutation in S.perm.  Called by all
+// four waves; wave w owns columns 16w..16w+15 and needs no other wave: per
+// block of 16 rows, a substitution with the diagonal block (one lane per
+// column) and then the rows below on the matrix cores.
 template <class T>
 __device__ __attribute__((noinline)) void col_solve(Shared<T>& S) {
-  const int lane = threadIdx.x & 63;
-  T x[TB];
+  typedef typename Mf<T>::acc_t acc_t;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4;
+  T* col = S.Cs + (w * 16 + (lane & 15)) * kCS;
+  {  // rows to logical order in this wave's columns (all loads before stores)
+    T t[TB / 4];
 #pragma unroll
-  for (int r = 0; r < TB; ++r) x[r] = S.Cs[lane * kCS + S.perm[r]];
+    for (int q = 0; q < TB / 4; ++q) t[q] = col[S.perm[g + 4 * q]];
+    wave_sync();
 #pragma unroll
-  for (int r = 1; r < TB; ++r) {
-    T sum = x[r];
-#pragma unroll
-    for (int q = 0; q < r; ++q) sum -= S.Ls[r * kLS + q] * x[q];
-    x[r] = sum;
-    __builtin_amdgcn_sched_barrier(0);
+    for (int q = 0; q < TB / 4; ++q) col[g + 4 * q] = t[q];
   }
 #pragma unroll
-  for (int r = 0; r < TB; ++r) S.Cs[lane * kCS + r] = x[r];
+  for (int b = 0; b < TB / 16; ++b) {
+    const int rb = b * 16;
+    wave_sync();
+    if (lane < 16) {
+      T x[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) x[k] = col[rb + k];
+#pragma unroll
+      for (int k = 0; k < 16; ++k)
+#pragma unroll
+        for (int k2 = k + 1; k2 < 16; ++k2) x[k2] -= S.Ls[(rb + k) * kLS + rb + k2] * x[k];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) col[rb + k] = x[k];
+    }
+    wave_sync();
+#pragma unroll
+    for (int rt = b + 1; rt < TB / 16; ++rt) {
+      acc_t acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = col[rt * 16 + Mf<T>::row(lane, r)];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int k = rb + ks * 4 + g;
+        acc = Mf<T>::run(-S.Ls[k * kLS + rt * 16 + (lane & 15)], col[k], acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) col[rt * 16 + Mf<T>::row(lane, r)] = acc[r];
+    }
+  }
 }
 
-// L_im = C U_mm^-1, in place in S.Cs (one wavefront, lane = row).  With
-// U = D Uh (D its diagonal, Uh unit upper), Y = C Uh^-1 by substitution and
-// L = Y D^-1.  S.Us holds Uh column-major, S.row the reciprocals of D.
+// L_im = C U_mm^-1, in place in S.Cs.  With U = D Uh (D its diagonal, Uh unit
+// upper), Y = C Uh^-1 and L = Y D^-1.  S.Us holds Uh row-major, S.row the
+// reciprocals of D.  Called by all four waves; wave w owns rows 16w..16w+15:
+// per block of 16 columns, a substitution with the diagonal block (one lane
+// per row) and then the columns to the right on the matrix cores.
 template <class T>
 __device__ __attribute__((noinline)) void row_solve(Shared<T>& S) {
-  const int lane = threadIdx.x & 63;
-  T x[TB];
+  typedef typename Mf<T>::acc_t acc_t;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4;
+  const int r0 = w * 16;
 #pragma unroll
-  for (int c = 0; c < TB; ++c) x[c] = S.Cs[c * kCS + lane];
+  for (int b = 0; b < TB / 16; ++b) {
+    const int cb = b * 16;
+    wave_sync();
+    if (lane < 16) {
+      T y[16];
 #pragma unroll
-  for (int c = 1; c < TB; ++c) {
-    T sum = x[c];
+      for (int k = 0; k < 16; ++k) y[k] = S.Cs[(cb + k) * kCS + r0 + lane];
 #pragma unroll
-    for (int q = 0; q < c; ++q) sum -= x[q] * S.Us[c * kLS + q];
-    x[c] = sum;
-    __builtin_amdgcn_sched_barrier(0);
+      for (int k = 0; k < 16; ++k)
+#pragma unroll
+        for (int k2 = k + 1; k2 < 16; ++k2) y[k2] -= y[k] * S.Us[(cb + k) * kLS + cb + k2];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) S.Cs[(cb + k) * kCS + r0 + lane] = y[k];
+    }
+    wave_sync();
+#pragma unroll
+    for (int ct = b + 1; ct < TB / 16; ++ct) {
+      T* cc = S.Cs + (ct * 16 + (lane & 15)) * kCS + r0;
+      acc_t acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = cc[Mf<T>::row(lane, r)];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int k = cb + ks * 4 + g;
+        acc = Mf<T>::run(-S.Cs[k * kCS + r0 + (lane & 15)], S.Us[k * kLS + ct * 16 + (lane & 15)],
+                         acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cc[Mf<T>::row(lane, r)] = acc[r];
+    }
   }
+  wave_sync();
 #pragma unroll
-  for (int c = 0; c < TB; ++c) S.Cs[c * kCS + lane] = x[c] * S.row[c];
+  for (int q = 0; q < TB / 4; ++q) {
+    const int c = g + 4 * q;
+    T* e = &S.Cs[c * kCS + r0 + (lane & 15)];
+    *e = *e * S.row[c];
+  }
 }
 
 // LAPACK-style interchange sequence of one diagonal tile (lane 0).
@@ -249,6 +385,9 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
                                                    int64_t j, int64_t m, int32_t* err) {
   typedef typename Mf<T>::acc_t acc_t;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // tasks on the diagonal chain issue ahead of other waves on their SIMDs
+    const bool chain = i == j || i == j + 1 || j == i + 1;
+    if (chain) __builtin_amdgcn_s_setprio(2);
     const int64_t nt = sy.nt, n = sy.n, lda = sy.lda;
     T* A = sy.A;
     const int qi = (w >> 1) * 32, qj = (w & 1) * 32;
@@ -327,9 +466,9 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
     }
     __syncthreads();
     if (i == j) {
-      if (w == 0) diag_factor<T>(S, sy, m, sy.sing);
+      diag_factor<T>(S, sy, m, sy.sing);
     } else if (i < j) {
-      // U_mj = L_mm^-1 P_m C; L_mm staged row-major, lane = column
+      // U_mj = L_mm^-1 P_m C; L_mm staged column-major
       {
         T la[TB * TB / kLuThreads];
 #pragma unroll
@@ -340,7 +479,7 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
 #pragma unroll
         for (int q = 0; q < TB * TB / kLuThreads; ++q) {
           const int e = tid + q * kLuThreads, r = e % TB, c = e / TB;
-          S.Ls[r * kLS + c] = la[q];
+          S.Ls[c * kLS + r] = la[q];
         }
       }
       if (tid < TB) {
@@ -348,10 +487,9 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
         S.perm[tid] = g < n ? (int)(sy.lperm[g] - m * TB) : tid;
       }
       __syncthreads();
-      if (w == 0) col_solve<T>(S);
+      col_solve<T>(S);
     } else {
-      // L_im = C U_mm^-1; U_mm staged column-major, lane = row
-      // Uh = D^-1 U staged column-major, 1 / diag in S.row
+      // L_im = C U_mm^-1; Uh = D^-1 U staged row-major, 1 / diag in S.row
       {
         T ua[TB * TB / kLuThreads];
 #pragma unroll
@@ -364,17 +502,18 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
 #pragma unroll
         for (int q = 0; q < TB * TB / kLuThreads; ++q) {
           const int e = tid + q * kLuThreads, r = e % TB, c = e / TB;
-          S.Us[c * kLS + r] = ua[q] / S.row[r];
+          S.Us[r * kLS + c] = ua[q] / S.row[r];
         }
         __syncthreads();
         if (tid < TB) S.row[tid] = T(1) / S.row[tid];
       }
       __syncthreads();
-      if (w == 0) row_solve<T>(S);
+      row_solve<T>(S);
     }
     __syncthreads();
-    {  // store the finished tile, one column per 64 threads (coalesced)
-      const int64_t rr = i * TB + lane;
+    {  // store the finished tile, one column per 64 threads (coalesced); the
+       // diagonal tile's rows go to their logical places
+      const int64_t rr = i * TB + (i == j ? S.pos[lane] : lane);
       if (rr < n) {
         for (int c = w; c < TB; c += kLuThreads / TB) {
           const int64_t cc = j * TB + c;
@@ -386,6 +525,7 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
     if (tid == 0) {
       __hip_atomic_store(&sy.done[i * nt + j], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     }
+    if (chain) __builtin_amdgcn_s_setprio(0);
 }
 
 // One workgroup per task.  The ticket, not blockIdx, decides the task, so a
