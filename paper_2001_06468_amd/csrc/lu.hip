@@ -299,7 +299,8 @@ __global__ void k_ipiv_to_perm(int64_t n, const int32_t* __restrict__ ipiv, int3
   }
 }
 
-// Multi-workgroup triangular solves.  Row block b (64 rows) is owned by one
+// Multi-workgroup triangular solves (the FP64 form; FP32 uses k_trsv32
+// below).  Row block b (64 rows) is owned by one
 // workgroup; blocks are handed out by an atomic ticket in dispatch order, so
 // a workgroup only ever waits for blocks whose owners are already running.
 // It folds in the contribution of each solved block as its flag appears,
@@ -311,6 +312,12 @@ __global__ void k_ipiv_to_perm(int64_t n, const int32_t* __restrict__ ipiv, int3
 constexpr int kTb = 64;
 constexpr int kTrsvThreads = 256;
 constexpr int64_t kSpinLimit = 1 << 22;
+
+// Orders a wavefront's LDS accesses around a hand-over between its lanes.
+__device__ inline void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
 
 __device__ inline int32_t ld_relaxed(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -346,15 +353,9 @@ __device__ inline double bcast_lane<double>(double v, int lane) {
 template <class T, bool UPPER, bool LOCALP>
 __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t* __restrict__ ctl,
                                                        int32_t* __restrict__ err) {
-  // FP32: the diagonal block is applied through its explicit inverse, formed
-  // while the workgroup waits for its dependencies, so the step on the
-  // critical path is a 64 x 64 product instead of a 64-step substitution.
-  constexpr bool kInv = sizeof(T) == 4;
-  constexpr int kLd = kTb + 4;
   __shared__ int s_t, s_jend;
   __shared__ T s_part[kTrsvThreads / 64][kTb];
   __shared__ T s_x[kTb];
-  __shared__ __align__(16) T s_d[kInv ? kTb : 1][kInv ? kLd : 1];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (tid == 0) s_t = atomicAdd(&ctl[0], 1);
   __syncthreads();
@@ -381,10 +382,6 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t*
   const T* __restrict__ rhs = sy.rhs;
   const int32_t* __restrict__ lperm = sy.perm;
   int32_t* flags = sy.flags;
-  // FP32: solved blocks are published as (tag, value) 64-bit words, so a
-  // consumer's poll also delivers the data (no separate flag and fence);
-  // the tag is this launch's epoch, bumped by the last workgroup
-  const uint32_t tag = kInv && !skip ? ((uint32_t)*sy.epoch & 0x7fffffffu) + 1u : 0u;
   const int64_t nblk = (n + kTb - 1) / kTb;
   const int64_t b = UPPER ? nblk - 1 - kstep : kstep;
   const int64_t r0 = b * kTb;
@@ -402,109 +399,16 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t*
 #pragma unroll
     for (int c = 0; c < 16; ++c) pa[c] = (c < cn && row < n) ? LU[row + (c0 + c) * lda] : T(0);
   }
-  T dg[kInv ? 1 : kTb];   // FP64: diagonal block row of this lane (wave 0)
-  T xr[kInv ? kTb : 1];   // FP32: row `lane` of the diagonal block's inverse (wave 0)
-  if constexpr (!kInv) {
-    if (w == 0) {
+  T dg[kTb];   // diagonal block row of this lane (wave 0)
+  if (w == 0) {
 #pragma unroll
-      for (int c = 0; c < kTb; ++c)
-        dg[c] = (c < rows && lane < rows) ? LU[row + (r0 + c) * lda] : T(0);
-    }
-  } else {
-    // diagonal tile, identity-padded, row-major in LDS
-    for (int e = tid; e < kTb * kTb; e += kTrsvThreads) {
-      const int i = e & (kTb - 1), c = e >> 6;
-      T v = (i == c) ? T(1) : T(0);
-      if (i < rows && c < rows) v = LU[r0 + i + (r0 + c) * lda];
-      s_d[i][c] = v;
-    }
-    __syncthreads();
-    if (w == 0) {
-      T xc[kTb];   // column `lane` of the inverse
-      if (!UPPER) {
-        // unit lower: X[i][c] = [i == c] - sum_{k < i} L[i][k] X[k][c]
-#pragma unroll
-        for (int i = 0; i < kTb; ++i) {
-          T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
-#pragma unroll
-          for (int k = 0; k + 3 < i; k += 4) {
-            s0 += s_d[i][k] * xc[k];
-            s1 += s_d[i][k + 1] * xc[k + 1];
-            s2 += s_d[i][k + 2] * xc[k + 2];
-            s3 += s_d[i][k + 3] * xc[k + 3];
-          }
-#pragma unroll
-          for (int k = i & ~3; k < i; ++k) s0 += s_d[i][k] * xc[k];
-          const T sum = (s0 + s1) + (s2 + s3);
-          xc[i] = i < lane ? T(0) : (i == lane ? T(1) : -sum);
-        }
-      } else {
-        // upper: X[i][c] = ([i == c] - sum_{k > i} U[i][k] X[k][c]) / U[i][i]
-#pragma unroll
-        for (int i = kTb - 1; i >= 0; --i) {
-          T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
-#pragma unroll
-          for (int k = i + 1; k + 3 < kTb; k += 4) {
-            s0 += s_d[i][k] * xc[k];
-            s1 += s_d[i][k + 1] * xc[k + 1];
-            s2 += s_d[i][k + 2] * xc[k + 2];
-            s3 += s_d[i][k + 3] * xc[k + 3];
-          }
-#pragma unroll
-          for (int k = kTb - ((kTb - 1 - i) & 3); k < kTb; ++k) s0 += s_d[i][k] * xc[k];
-          const T sum = (s0 + s1) + (s2 + s3);
-          xc[i] = i > lane ? T(0) : ((i == lane ? T(1) : T(0)) - sum) / s_d[i][i];
-        }
-      }
-      // transpose through LDS: lane c holds column c, lane i needs row i
-#pragma unroll
-      for (int i = 0; i < kTb; ++i) s_d[i][lane] = xc[i];
-      __builtin_amdgcn_wave_barrier();
-#pragma unroll
-      for (int c = 0; c < kTb; ++c) xr[c] = s_d[lane][c];
-    }
+    for (int c = 0; c < kTb; ++c)
+      dg[c] = (c < rows && lane < rows) ? LU[row + (r0 + c) * lda] : T(0);
   }
   T acc = T(0);
   const int64_t jstep = UPPER ? -1 : 1;
   int64_t j = UPPER ? nblk - 1 : 0;
-  constexpr int kPoller = 64;   // first lane of wave 1 (FP64 path)
-  if constexpr (kInv) {
-    // each wavefront polls the 16 tagged words it needs, independently
-    for (; j != b; j += jstep) {
-      const int64_t c0 = j * kTb + w * 16;
-      const int cn = (int)max<int64_t>(0, min<int64_t>(16, n - c0));
-      T a[16];
-      if (j == jl) {
-#pragma unroll
-        for (int c = 0; c < 16; ++c) a[c] = pa[c];
-      } else {
-#pragma unroll
-        for (int c = 0; c < 16; ++c)
-          a[c] = (c < cn && row < n) ? LU[row + (c0 + c) * lda] : T(0);
-      }
-      uint64_t wd[16];
-      int64_t spins = 0;
-      for (;;) {
-        bool ok = true;
-#pragma unroll
-        for (int c = 0; c < 16; ++c) {
-          wd[c] = c < cn ? __hip_atomic_load(&sy.xp[c0 + c], __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT)
-                         : ((uint64_t)tag << 32);
-          ok = ok && (uint32_t)(wd[c] >> 32) == tag;
-        }
-        if (ok) break;
-        if (++spins > kSpinLimit) {
-          if (lane == 0) atomicExch(err, 1);
-          break;
-        }
-        if ((spins & 255) == 0 && ld_relaxed(err)) break;
-        __builtin_amdgcn_s_sleep(1);
-      }
-#pragma unroll
-      for (int c = 0; c < 16; ++c) acc += a[c] * __uint_as_float((uint32_t)wd[c]);
-    }
-  } else {
+  constexpr int kPoller = 64;   // first lane of wave 1
   while (j != b) {
     if (tid == kPoller) {
       int64_t spins = 0;
@@ -548,7 +452,6 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t*
       for (int c = 0; c < 16; ++c) acc += a[c] * xv[c];
     }
   }
-  }
   s_part[w][lane] = acc;
   __syncthreads();
   if (w == 0) {
@@ -563,19 +466,7 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t*
       if (lane < rows) v = s_x[lperm[row] - r0];
       __builtin_amdgcn_wave_barrier();
     }
-    if constexpr (kInv) {
-      s_x[lane] = v;
-      __builtin_amdgcn_wave_barrier();
-      T o0 = T(0), o1 = T(0), o2 = T(0), o3 = T(0);
-#pragma unroll
-      for (int c = 0; c < kTb; c += 4) {
-        o0 += xr[c] * s_x[c];
-        o1 += xr[c + 1] * s_x[c + 1];
-        o2 += xr[c + 2] * s_x[c + 2];
-        o3 += xr[c + 3] * s_x[c + 3];
-      }
-      v = (o0 + o1) + (o2 + o3);
-    } else if (!UPPER) {
+    if (!UPPER) {
 #pragma unroll
       for (int c = 0; c < kTb; ++c) {
         if (c < rows) {
@@ -593,18 +484,10 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t*
         }
       }
     }
-    if (lane < rows) {
-      x[row] = v;
-      if constexpr (kInv) {
-        const uint64_t word = ((uint64_t)tag << 32) | (uint64_t)__float_as_uint((float)v);
-        __hip_atomic_store(&sy.xp[row], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
+    if (lane < rows) x[row] = v;
   }
-  if constexpr (!kInv) {
-    __syncthreads();
-    if (tid == 0) st_release(&flags[b], 1);
-  }
+  __syncthreads();
+  if (tid == 0) st_release(&flags[b], 1);
   }  // !skip
   // the last workgroup of the launch clears every flag and the counters
   if (tid == 0) s_t = atomicAdd(&ctl[1], 1);
@@ -613,15 +496,258 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t*
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     for (int q = 0; q < bt.B; ++q) {
       const TrsvSys<T> sq = bt.sys ? bt.sys[q] : bt.one;
-      if constexpr (kInv) {
-        if (tid == 0) *sq.epoch = (int32_t)(((uint32_t)*sq.epoch + 1u) & 0x7fffffffu);
-      } else {
-        const int64_t nb = (sq.n + kTb - 1) / kTb;
-        for (int64_t e = tid; e < nb; e += kTrsvThreads) sq.flags[e] = 0;
-      }
+      const int64_t nb = (sq.n + kTb - 1) / kTb;
+      for (int64_t e = tid; e < nb; e += kTrsvThreads) sq.flags[e] = 0;
     }
     __syncthreads();
     if (tid == 0) {
+      ctl[0] = 0;
+      ctl[1] = 0;
+    }
+  }
+}
+
+// FP32 triangular solves.  Block row b (64 rows) is solved by one workgroup
+// as x_b = c_b - M_b x_l, where l is the block solved just before it (b - 1
+// for the lower pass, b + 1 for the upper), D_b the diagonal block (unit
+// lower for the lower pass, with the block-local interchanges folded into its
+// inverse as columns), and
+//   M_b = D_b^-1 A_bl          (matrix cores, formed before any wait),
+//   c_b = D_b^-1 (r_b - sum_{j other than l} A_bj x_j)   (folded in as the
+//         solved blocks appear).
+// The step on the critical path is therefore one 64 x 64 product by a single
+// wavefront: poll the 64 words of x_l, multiply, publish.  Solved blocks are
+// published as tagged 64-bit words (this launch's epoch, value bits), so a
+// consumer's poll also delivers the data; the last workgroup bumps the epoch.
+template <bool UPPER, bool LOCALP>
+__global__ __launch_bounds__(kTrsvThreads) void k_trsv32(TrsvBatch<float> bt,
+                                                         int32_t* __restrict__ ctl,
+                                                         int32_t* __restrict__ err) {
+  typedef float floatx4 __attribute__((ext_vector_type(4)));
+  constexpr int kLd = kTb + 1;
+  __shared__ int s_t;
+  __shared__ float s_part[kTrsvThreads / 64][kTb];
+  __shared__ float s_x[kTb];
+  __shared__ float s_d[kTb][kLd];  // diagonal block, then D^-1 (row-major)
+  __shared__ float s_l[kTb][kLd];  // A_bl (row-major), then M
+  __shared__ float s_w[kTrsvThreads / 64][16];  // per-wave copy of the polled values
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) s_t = atomicAdd(&ctl[0], 1);
+  __syncthreads();
+  const int32_t tk = s_t;
+  int64_t kstep;
+  int sidx;
+  if (bt.sys == nullptr) {
+    kstep = tk;
+    sidx = 0;
+  } else {
+    int lo = 0, hi = bt.nsteps * bt.B;  // pref[lo] <= tk < pref[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (bt.pref[mid] <= tk) lo = mid; else hi = mid;
+    }
+    kstep = lo / bt.B;
+    sidx = lo % bt.B;
+  }
+  const TrsvSys<float> sy = bt.sys ? bt.sys[sidx] : bt.one;
+  const bool skip = tk >= bt.total || (sy.stop && *sy.stop);
+  if (!skip) {
+    const int64_t n = sy.n, lda = sy.lda;
+    const float* __restrict__ LU = sy.LU;
+    const uint32_t tag = ((uint32_t)*sy.epoch & 0x7fffffffu) + 1u;
+    const int64_t nblk = (n + kTb - 1) / kTb;
+    const int64_t b = UPPER ? nblk - 1 - kstep : kstep;
+    const int64_t r0 = b * kTb;
+    const int rows = (int)min<int64_t>(kTb, n - r0);
+    const int64_t row = r0 + lane;
+    const int64_t jl = UPPER ? b + 1 : b - 1;
+    const bool has_jl = UPPER ? (b + 1 < nblk) : (b >= 1);
+    // A_bl (16 columns per wave) and the identity-padded diagonal block
+    {
+      const int64_t c0 = jl * kTb + w * 16;
+      const int cn = has_jl ? (int)max<int64_t>(0, min<int64_t>(16, n - c0)) : 0;
+      float pa[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) pa[c] = (c < cn && row < n) ? LU[row + (c0 + c) * lda] : 0.f;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) s_l[lane][w * 16 + c] = pa[c];
+    }
+    for (int e = tid; e < kTb * kTb; e += kTrsvThreads) {
+      const int i = e & (kTb - 1), c = e >> 6;
+      float v = (i == c) ? 1.f : 0.f;
+      if (i < rows && c < rows) v = LU[r0 + i + (r0 + c) * lda];
+      s_d[i][c] = v;
+    }
+    __syncthreads();
+    if (w == 0) {
+      // the lower pass of the tile LU's factors applies the block row's
+      // interchanges first: (D^-1 P)[i][p(c)] = D^-1[i][c]
+      const int pc = (LOCALP && !UPPER && lane < rows) ? sy.perm[row] - (int)r0 : lane;
+      float xc[kTb];  // column `lane` of D^-1
+      if (!UPPER) {
+        // unit lower: X[i][c] = [i == c] - sum_{k < i} L[i][k] X[k][c]
+#pragma unroll
+        for (int i = 0; i < kTb; ++i) {
+          float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+#pragma unroll
+          for (int k = 0; k + 3 < i; k += 4) {
+            s0 += s_d[i][k] * xc[k];
+            s1 += s_d[i][k + 1] * xc[k + 1];
+            s2 += s_d[i][k + 2] * xc[k + 2];
+            s3 += s_d[i][k + 3] * xc[k + 3];
+          }
+#pragma unroll
+          for (int k = i & ~3; k < i; ++k) s0 += s_d[i][k] * xc[k];
+          const float sum = (s0 + s1) + (s2 + s3);
+          xc[i] = i < lane ? 0.f : (i == lane ? 1.f : -sum);
+        }
+      } else {
+        // upper: X[i][c] = ([i == c] - sum_{k > i} U[i][k] X[k][c]) / U[i][i]
+#pragma unroll
+        for (int i = kTb - 1; i >= 0; --i) {
+          float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+#pragma unroll
+          for (int k = i + 1; k + 3 < kTb; k += 4) {
+            s0 += s_d[i][k] * xc[k];
+            s1 += s_d[i][k + 1] * xc[k + 1];
+            s2 += s_d[i][k + 2] * xc[k + 2];
+            s3 += s_d[i][k + 3] * xc[k + 3];
+          }
+#pragma unroll
+          for (int k = kTb - ((kTb - 1 - i) & 3); k < kTb; ++k) s0 += s_d[i][k] * xc[k];
+          const float sum = (s0 + s1) + (s2 + s3);
+          xc[i] = i > lane ? 0.f : ((i == lane ? 1.f : 0.f) - sum) / s_d[i][i];
+        }
+      }
+      wave_sync_lds();
+      float* dcol = &s_d[0][pc];
+#pragma unroll
+      for (int i = 0; i < kTb; ++i) dcol[i * kLd] = xc[i];
+    }
+    __syncthreads();
+    // M = D^-1 A_bl: wave w forms rows 16w..16w+15
+    if (has_jl) {
+      floatx4 acc[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < kTb / 4; ++ks) {
+        const int k = ks * 4 + (lane >> 4);
+        const float a = s_d[w * 16 + (lane & 15)][k];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, s_l[k][t * 16 + (lane & 15)], acc[t], 0,
+                                                       0, 0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) s_l[w * 16 + 4 * (lane >> 4) + r][t * 16 + (lane & 15)] = acc[t][r];
+    }
+    // r_b - sum_{j other than l} A_bj x_j: each wavefront polls the 16 tagged
+    // words it needs, block by block
+    float part = 0.f;
+    {
+      const int64_t jstep = UPPER ? -1 : 1;
+      for (int64_t j = UPPER ? nblk - 1 : 0; j != b && j != jl; j += jstep) {
+        const int64_t c0 = j * kTb + w * 16;
+        const int cn = (int)max<int64_t>(0, min<int64_t>(16, n - c0));
+        float a[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) a[c] = (c < cn && row < n) ? LU[row + (c0 + c) * lda] : 0.f;
+        // lanes 0..15 poll one word each; the values reach the wave through LDS
+        uint64_t wd = (uint64_t)tag << 32;
+        int64_t spins = 0;
+        for (;;) {
+          if (lane < cn)
+            wd = __hip_atomic_load(&sy.xp[c0 + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (__all((uint32_t)(wd >> 32) == tag)) break;
+          if (++spins > kSpinLimit) {
+            if (lane == 0) atomicExch(err, 1);
+            break;
+          }
+          if ((spins & 255) == 0 && ld_relaxed(err)) break;
+          __builtin_amdgcn_s_sleep(1);
+        }
+        wave_sync_lds();
+        if (lane < 16) s_w[w][lane] = __uint_as_float((uint32_t)wd);
+        wave_sync_lds();
+#pragma unroll
+        for (int c = 0; c < 16; ++c) part += a[c] * s_w[w][c];
+      }
+    }
+    s_part[w][lane] = part;
+    __syncthreads();
+    if (w == 0) {
+      float v = 0.f;
+      if (lane < rows) {
+        v = UPPER ? sy.x[row] : (LOCALP ? sy.rhs[row] : sy.rhs[sy.perm[row]]);
+#pragma unroll
+        for (int q = 0; q < kTrsvThreads / 64; ++q) v -= s_part[q][lane];
+      }
+      s_x[lane] = v;
+      wave_sync_lds();
+      // c = D^-1 r (row `lane`)
+      float o0 = 0.f, o1 = 0.f, o2 = 0.f, o3 = 0.f;
+#pragma unroll
+      for (int c = 0; c < kTb; c += 4) {
+        o0 += s_d[lane][c] * s_x[c];
+        o1 += s_d[lane][c + 1] * s_x[c + 1];
+        o2 += s_d[lane][c + 2] * s_x[c + 2];
+        o3 += s_d[lane][c + 3] * s_x[c + 3];
+      }
+      v = (o0 + o1) + (o2 + o3);
+      if (has_jl) {
+        float mr[kTb];
+#pragma unroll
+        for (int c = 0; c < kTb; ++c) mr[c] = s_l[lane][c];
+        // lane k polls word k of x_l; the values reach every lane through LDS
+        const int64_t c0 = jl * kTb;
+        const int cn = (int)min<int64_t>(kTb, n - c0);
+        uint64_t wd = (uint64_t)tag << 32;
+        int64_t spins = 0;
+        for (;;) {
+          if (lane < cn)
+            wd = __hip_atomic_load(&sy.xp[c0 + lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (__all((uint32_t)(wd >> 32) == tag)) break;
+          if (++spins > kSpinLimit) {
+            if (lane == 0) atomicExch(err, 1);
+            break;
+          }
+          if ((spins & 255) == 0 && ld_relaxed(err)) break;
+          __builtin_amdgcn_s_sleep(1);
+        }
+        wave_sync_lds();
+        s_x[lane] = __uint_as_float((uint32_t)wd);
+        wave_sync_lds();
+        float q0 = 0.f, q1 = 0.f, q2 = 0.f, q3 = 0.f;
+#pragma unroll
+        for (int c = 0; c < kTb; c += 4) {
+          q0 += mr[c] * s_x[c];
+          q1 += mr[c + 1] * s_x[c + 1];
+          q2 += mr[c + 2] * s_x[c + 2];
+          q3 += mr[c + 3] * s_x[c + 3];
+        }
+        v -= (q0 + q1) + (q2 + q3);
+      }
+      if (lane < rows) {
+        sy.x[row] = v;
+        const uint64_t word = ((uint64_t)tag << 32) | (uint64_t)__float_as_uint(v);
+        __hip_atomic_store(&sy.xp[row], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }  // !skip
+  // the last workgroup of the launch bumps every epoch and clears the counters
+  if (tid == 0) s_t = atomicAdd(&ctl[1], 1);
+  __syncthreads();
+  if (s_t == (int)gridDim.x - 1) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (tid == 0) {
+      for (int q = 0; q < bt.B; ++q) {
+        const TrsvSys<float> sq = bt.sys ? bt.sys[q] : bt.one;
+        *sq.epoch = (int32_t)(((uint32_t)*sq.epoch + 1u) & 0x7fffffffu);
+      }
       ctl[0] = 0;
       ctl[1] = 0;
     }
@@ -661,11 +787,19 @@ hipError_t launch_trsv_batch(const TrsvBatch<T>& bt, int32_t scope, int32_t* ctl
                              hipStream_t s) {
   if (bt.total <= 0) return hipSuccess;
   const dim3 g((unsigned)bt.total);
-  if (scope)
-    hipLaunchKernelGGL((k_trsv<T, false, true>), g, dim3(kTrsvThreads), 0, s, bt, ctl, err);
-  else
-    hipLaunchKernelGGL((k_trsv<T, false, false>), g, dim3(kTrsvThreads), 0, s, bt, ctl, err);
-  hipLaunchKernelGGL((k_trsv<T, true, false>), g, dim3(kTrsvThreads), 0, s, bt, ctl, err);
+  if constexpr (sizeof(T) == 4) {
+    if (scope)
+      hipLaunchKernelGGL((k_trsv32<false, true>), g, dim3(kTrsvThreads), 0, s, bt, ctl, err);
+    else
+      hipLaunchKernelGGL((k_trsv32<false, false>), g, dim3(kTrsvThreads), 0, s, bt, ctl, err);
+    hipLaunchKernelGGL((k_trsv32<true, false>), g, dim3(kTrsvThreads), 0, s, bt, ctl, err);
+  } else {
+    if (scope)
+      hipLaunchKernelGGL((k_trsv<T, false, true>), g, dim3(kTrsvThreads), 0, s, bt, ctl, err);
+    else
+      hipLaunchKernelGGL((k_trsv<T, false, false>), g, dim3(kTrsvThreads), 0, s, bt, ctl, err);
+    hipLaunchKernelGGL((k_trsv<T, true, false>), g, dim3(kTrsvThreads), 0, s, bt, ctl, err);
+  }
   return hipGetLastError();
 }
 
