@@ -29,8 +29,10 @@ nrs_status use_device(nrs_ctx* ctx) {
   return NRS_OK;
 }
 
+// chunks of the nu-sorted points per row block of the matrix-free product
+// (about 2048 workgroups; one chunk per 64 points at least)
 int32_t apply_chunks(int64_t N, int64_t Q) {
-  const int64_t mblocks = (N + 127) / 128;
+  const int64_t mblocks = (N + 63) / 64;
   int64_t c = (2048 + mblocks - 1) / std::max<int64_t>(mblocks, 1);
   c = std::min<int64_t>(c, std::max<int64_t>(1, Q / 64));
   c = std::max<int64_t>(1, std::min<int64_t>(c, 256));

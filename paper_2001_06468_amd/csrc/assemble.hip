@@ -206,16 +206,24 @@ __global__ void k_rhs(int64_t N, int32_t M, const double* __restrict__ u,
     b[i] = ft ? ft[i - 3 * N] : 0.0;
 }
 
-// Matrix-free FP64 NEAREST product, stage 1: lane m sums
-// S^eps(x_m - X_p) w_p f[nu_p] over one chunk of the nu-sorted points.
-constexpr int kApplyBlock = 128;
-__global__ __launch_bounds__(kApplyBlock) void k_apply_part(
+// Matrix-free FP64 NEAREST product, stage 1.  Workgroup (row block, chunk)
+// stages its chunk of the nu-sorted points in LDS (position and the gathered
+// w_p f[nu_p], loaded in parallel), then lane m of wave w sums
+// S^eps(x_m - X_p) w_p f[nu_p] over every fourth staged point; the four wave
+// sums are added in a fixed order.
+constexpr int kApplyRows = 64;
+constexpr int kApplyThreads = 256;
+constexpr int kApplyPts = 256;  // staged points per round
+__global__ __launch_bounds__(kApplyThreads) void k_apply_part(
     int64_t N, int64_t chunk, const int32_t* __restrict__ seg, const double* __restrict__ x,
     const double4* __restrict__ X64, const int32_t* __restrict__ nus,
     const double* __restrict__ v, double eps2, double* __restrict__ part,
     const int32_t* __restrict__ stop) {
   if (stop && *stop) return;
-  const int64_t m = blockIdx.x * (int64_t)kApplyBlock + threadIdx.x;
+  __shared__ double sp[6][kApplyPts];  // X, Y, Z, w f_x, w f_y, w f_z
+  __shared__ double red[3][kApplyThreads / 64][kApplyRows];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t m = blockIdx.x * (int64_t)kApplyRows + lane;
   const int64_t Qv = seg[N];  // points with a valid nearest index
   const int64_t p0 = blockIdx.y * chunk;
   const int64_t p1 = min<int64_t>(Qv, p0 + chunk);
@@ -226,40 +234,76 @@ __global__ __launch_bounds__(kApplyBlock) void k_apply_part(
     pz = x[2 * N + m];
   }
   double ux = 0, uy = 0, uz = 0;
-  for (int64_t p = p0; p < p1; ++p) {
-    const double4 q = X64[p];
-    const int nn = nus[p];
-    const double fx = q.w * v[nn], fy = q.w * v[N + nn], fz = q.w * v[2 * N + nn];
-    const double rx = px - q.x, ry = py - q.y, rz = pz - q.z;
-    const double d = rx * rx + ry * ry + rz * rz + eps2;
-    const double rho = 1.0 / sqrt(d);
-    const double t = rho * rho * rho;
-    const double rf = rx * fx + ry * fy + rz * fz;
-    const double s = d + eps2;
-    ux += t * (s * fx + rx * rf);
-    uy += t * (s * fy + ry * rf);
-    uz += t * (s * fz + rz * rf);
+  for (int64_t base = p0; base < p1; base += kApplyPts) {
+    const int cnt = (int)min<int64_t>(kApplyPts, p1 - base);
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+      const double4 q = X64[base + threadIdx.x];
+      const int nn = nus[base + threadIdx.x];
+      sp[0][threadIdx.x] = q.x;
+      sp[1][threadIdx.x] = q.y;
+      sp[2][threadIdx.x] = q.z;
+      sp[3][threadIdx.x] = q.w * v[nn];
+      sp[4][threadIdx.x] = q.w * v[N + nn];
+      sp[5][threadIdx.x] = q.w * v[2 * N + nn];
+    }
+    __syncthreads();
+    for (int k = w; k < cnt; k += kApplyThreads / 64) {
+      const double fx = sp[3][k], fy = sp[4][k], fz = sp[5][k];
+      const double rx = px - sp[0][k], ry = py - sp[1][k], rz = pz - sp[2][k];
+      const double d = rx * rx + ry * ry + rz * rz + eps2;
+      const double rho = 1.0 / sqrt(d);
+      const double t = rho * rho * rho;
+      const double rf = rx * fx + ry * fy + rz * fz;
+      const double s = d + eps2;
+      ux += t * (s * fx + rx * rf);
+      uy += t * (s * fy + ry * rf);
+      uz += t * (s * fz + rz * rf);
+    }
   }
-  if (m < N) {
-    double* out = part + blockIdx.y * 3 * N;
-    out[m] = ux;
-    out[N + m] = uy;
-    out[2 * N + m] = uz;
+  red[0][w][lane] = ux;
+  red[1][w][lane] = uy;
+  red[2][w][lane] = uz;
+  __syncthreads();
+  if (w < 3 && m < N) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < kApplyThreads / 64; ++q) acc += red[w][q][lane];
+    part[blockIdx.y * 3 * N + w * N + m] = acc;
   }
 }
 
-// Stage 2 for the 3N velocity rows: sum the chunks in order, scale, subtract
-// the rigid-body motion U + Omega x r_m of free-body points.
-__global__ void k_apply_rows(int64_t N, int32_t M, int32_t chunks, const double* __restrict__ part,
-                             double scale, const double* __restrict__ x,
-                             const int32_t* __restrict__ body, const double* __restrict__ Y,
-                             const double* __restrict__ v, double* __restrict__ y,
-                             const int32_t* __restrict__ stop) {
+// Stage 2 for the 3N velocity rows: sum the chunks in a fixed order (wave w
+// takes a contiguous quarter of them with four running sums), scale,
+// subtract the rigid-body motion U + Omega x r_m of free-body points.
+__global__ __launch_bounds__(kApplyThreads) void k_apply_rows(
+    int64_t N, int32_t M, int32_t chunks, const double* __restrict__ part, double scale,
+    const double* __restrict__ x, const int32_t* __restrict__ body,
+    const double* __restrict__ Y, const double* __restrict__ v, double* __restrict__ y,
+    const int32_t* __restrict__ stop) {
   if (stop && *stop) return;
-  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (row >= 3 * N) return;
+  __shared__ double red[kApplyThreads / 64][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t row = blockIdx.x * (int64_t)64 + lane;
+  const int per = (chunks + kApplyThreads / 64 - 1) / (kApplyThreads / 64);
+  const int c0 = w * per, c1 = min(chunks, c0 + per);
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  if (row < 3 * N) {
+    int c = c0;
+    for (; c + 3 < c1; c += 4) {
+      a0 += part[(int64_t)c * 3 * N + row];
+      a1 += part[(int64_t)(c + 1) * 3 * N + row];
+      a2 += part[(int64_t)(c + 2) * 3 * N + row];
+      a3 += part[(int64_t)(c + 3) * 3 * N + row];
+    }
+    for (; c < c1; ++c) a0 += part[(int64_t)c * 3 * N + row];
+  }
+  red[w][lane] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (w != 0 || row >= 3 * N) return;
   double acc = 0.0;
-  for (int c = 0; c < chunks; ++c) acc += part[c * 3 * N + row];
+#pragma unroll
+  for (int q = 0; q < kApplyThreads / 64; ++q) acc += red[q][lane];
   acc *= scale;
   const int j = (int)(row / N);
   const int64_t m = row - j * N;
@@ -392,11 +436,11 @@ hipError_t launch_apply(const nrs_problem& pb, const Sorted& srt, const double* 
   const int64_t N = pb.N, Q = pb.Q;
   const int64_t chunk = (Q + chunks - 1) / chunks;
   if (N > 0) {
-    dim3 g((unsigned)((N + kApplyBlock - 1) / kApplyBlock), (unsigned)chunks);
-    hipLaunchKernelGGL(k_apply_part, g, dim3(kApplyBlock), 0, s, N, chunk, srt.seg, pb.x, srt.X64,
-                       srt.nus, v, pb.eps * pb.eps, part, stop);
-    hipLaunchKernelGGL(k_apply_rows, grid1(3 * N, 256), dim3(256), 0, s, N, pb.M, chunks, part,
-                       1.0 / (8.0 * kPi * pb.mu), pb.x, pb.body, pb.Y, v, y, stop);
+    dim3 g((unsigned)((N + kApplyRows - 1) / kApplyRows), (unsigned)chunks);
+    hipLaunchKernelGGL(k_apply_part, g, dim3(kApplyThreads), 0, s, N, chunk, srt.seg, pb.x,
+                       srt.X64, srt.nus, v, pb.eps * pb.eps, part, stop);
+    hipLaunchKernelGGL(k_apply_rows, grid1(3 * N, 64), dim3(kApplyThreads), 0, s, N, pb.M, chunks,
+                       part, 1.0 / (8.0 * kPi * pb.mu), pb.x, pb.body, pb.Y, v, y, stop);
   }
   if (pb.M > 0) {
     hipLaunchKernelGGL(k_apply_body, dim3(pb.M), dim3(kBodyBlock), 0, s, N, pb.body, pb.x, pb.Y,
