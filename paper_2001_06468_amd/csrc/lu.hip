@@ -562,6 +562,9 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv32(TrsvBatch<float> bt,
     const int64_t row = r0 + lane;
     const int64_t jl = UPPER ? b + 1 : b - 1;
     const bool has_jl = UPPER ? (b + 1 < nblk) : (b >= 1);
+    // this block's right-hand side, fetched before any wait
+    float rv = 0.f;
+    if (w == 0 && lane < rows) rv = UPPER ? sy.x[row] : (LOCALP ? sy.rhs[row] : sy.rhs[sy.perm[row]]);
     // A_bl (16 columns per wave) and the identity-padded diagonal block
     {
       const int64_t c0 = jl * kTb + w * 16;
@@ -682,7 +685,7 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv32(TrsvBatch<float> bt,
     if (w == 0) {
       float v = 0.f;
       if (lane < rows) {
-        v = UPPER ? sy.x[row] : (LOCALP ? sy.rhs[row] : sy.rhs[sy.perm[row]]);
+        v = rv;
 #pragma unroll
         for (int q = 0; q < kTrsvThreads / 64; ++q) v -= s_part[q][lane];
       }
