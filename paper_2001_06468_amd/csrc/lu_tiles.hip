@@ -412,30 +412,51 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[a][b][r] = T(0);
+    // The rank-64 terms are folded in as their tiles appear: one wait covers
+    // every term whose two tiles are already published ([k, kend)), and inside
+    // such a run the tiles of term k+1 are loaded while term k runs on the
+    // matrix cores.
+    const int r = tid & 63, c0 = tid >> 6;
+    T la[16], ua[16];
+    int64_t kend = 0;
     for (int64_t k = 0; k < m; ++k) {
-      if (tid == 0) {
-        wait_flag(&sy.done[i * nt + k], err);
-        wait_flag(&sy.done[k * nt + j], err);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      }
-      __syncthreads();
-      {  // all 32 loads of this thread in flight before the LDS stores
-        const int r = tid & 63, c0 = tid >> 6;
-        T la[16], ua[16];
+      if (k >= kend) {
+        if (tid == 0) {
+          wait_flag(&sy.done[i * nt + k], err);
+          wait_flag(&sy.done[k * nt + j], err);
+          int64_t e = k + 1;
+          while (e < m &&
+                 __hip_atomic_load(&sy.done[i * nt + e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &&
+                 __hip_atomic_load(&sy.done[e * nt + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            ++e;
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          S.task[2] = (int32_t)e;
+        }
+        __syncthreads();
+        kend = S.task[2];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
           const int c = c0 + 4 * q;
           la[q] = ld_pad(A, lda, n, i * TB + r, k * TB + c);
           ua[q] = ld_pad(A, lda, n, k * TB + r, j * TB + c);
         }
+      }
+      __syncthreads();  // the previous term's reads of S.Ls / S.Us are done
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int c = c0 + 4 * q;
+        S.Ls[c * kLS + r] = la[q];
+        S.Us[r * kLS + c] = ua[q];
+      }
+      __syncthreads();
+      if (k + 1 < kend) {  // next term's tiles, in flight during this one
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
           const int c = c0 + 4 * q;
-          S.Ls[c * kLS + r] = la[q];
-          S.Us[r * kLS + c] = ua[q];
+          la[q] = ld_pad(A, lda, n, i * TB + r, (k + 1) * TB + c);
+          ua[q] = ld_pad(A, lda, n, (k + 1) * TB + r, j * TB + c);
         }
       }
-      __syncthreads();
 #pragma unroll 4
       for (int kk = 0; kk < TB; kk += 4) {
         const int kr = kk + (lane >> 4), li = lane & 15;
