@@ -517,9 +517,12 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t*
 //         solved blocks appear).
 // The step on the critical path is therefore one 64 x 64 product by a single
 // wavefront: poll the 64 words of x_l, multiply, publish.  Solved blocks are
-// published as tagged 64-bit words (this launch's epoch, value bits), so a
-// consumer's poll also delivers the data; the last workgroup bumps the epoch.
-template <bool UPPER, bool LOCALP>
+// published as tagged 64-bit words (a tag per pass and launch, value bits), so
+// a consumer's poll also delivers the data; the last workgroup bumps the
+// epoch.  One launch runs both passes: tickets [0, total) are the lower pass,
+// [total, 2 total) the upper one, whose workgroups form D^-1 and M while the
+// lower pass runs and take their right-hand side from its tagged words.
+template <bool LOCALP>
 __global__ __launch_bounds__(kTrsvThreads) void k_trsv32(TrsvBatch<float> bt,
                                                          int32_t* __restrict__ ctl,
                                                          int32_t* __restrict__ err) {
@@ -528,13 +531,18 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv32(TrsvBatch<float> bt,
   __shared__ int s_t;
   __shared__ float s_part[kTrsvThreads / 64][kTb];
   __shared__ float s_x[kTb];
-  __shared__ float s_d[kTb][kLd];  // diagonal block, then D^-1 (row-major)
+  // diagonal block (rows 16-byte aligned for the broadcast reads of the
+  // inversion) and D^-1 (odd stride for the column reads that follow)
+  __shared__ __align__(16) float s_d[kTb][kTb + 4];
+  __shared__ float s_di[kTb][kLd];
   __shared__ float s_l[kTb][kLd];  // A_bl (row-major), then M
   __shared__ float s_w[kTrsvThreads / 64][16];  // per-wave copy of the polled values
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (tid == 0) s_t = atomicAdd(&ctl[0], 1);
   __syncthreads();
-  const int32_t tk = s_t;
+  const int32_t tk0 = s_t;
+  const bool UPPER = tk0 >= bt.total;
+  const int32_t tk = UPPER ? tk0 - bt.total : tk0;
   int64_t kstep;
   int sidx;
   if (bt.sys == nullptr) {
@@ -549,12 +557,13 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv32(TrsvBatch<float> bt,
     kstep = lo / bt.B;
     sidx = lo % bt.B;
   }
-  const TrsvSys<float> sy = bt.sys ? bt.sys[sidx] : bt.one;
+  const TrsvSys<float> sy = bt.sys ? bt.sys[min(sidx, bt.B - 1)] : bt.one;
   const bool skip = tk >= bt.total || (sy.stop && *sy.stop);
   if (!skip) {
     const int64_t n = sy.n, lda = sy.lda;
     const float* __restrict__ LU = sy.LU;
-    const uint32_t tag = ((uint32_t)*sy.epoch & 0x7fffffffu) + 1u;
+    const uint32_t tagl = 2u * ((uint32_t)*sy.epoch & 0x3fffffffu) + 1u;  // lower pass
+    const uint32_t tag = UPPER ? tagl + 1u : tagl;
     const int64_t nblk = (n + kTb - 1) / kTb;
     const int64_t b = UPPER ? nblk - 1 - kstep : kstep;
     const int64_t r0 = b * kTb;
@@ -562,9 +571,10 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv32(TrsvBatch<float> bt,
     const int64_t row = r0 + lane;
     const int64_t jl = UPPER ? b + 1 : b - 1;
     const bool has_jl = UPPER ? (b + 1 < nblk) : (b >= 1);
-    // this block's right-hand side, fetched before any wait
+    // the lower pass's right-hand side, fetched before any wait (the upper
+    // pass takes its own from the lower pass's words below)
     float rv = 0.f;
-    if (w == 0 && lane < rows) rv = UPPER ? sy.x[row] : (LOCALP ? sy.rhs[row] : sy.rhs[sy.perm[row]]);
+    if (!UPPER && w == 0 && lane < rows) rv = LOCALP ? sy.rhs[row] : sy.rhs[sy.perm[row]];
     // A_bl (16 columns per wave) and the identity-padded diagonal block
     {
       const int64_t c0 = jl * kTb + w * 16;
@@ -623,7 +633,7 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv32(TrsvBatch<float> bt,
         }
       }
       wave_sync_lds();
-      float* dcol = &s_d[0][pc];
+      float* dcol = &s_di[0][pc];
 #pragma unroll
       for (int i = 0; i < kTb; ++i) dcol[i * kLd] = xc[i];
     }
@@ -636,7 +646,7 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv32(TrsvBatch<float> bt,
 #pragma unroll
       for (int ks = 0; ks < kTb / 4; ++ks) {
         const int k = ks * 4 + (lane >> 4);
-        const float a = s_d[w * 16 + (lane & 15)][k];
+        const float a = s_di[w * 16 + (lane & 15)][k];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
           acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, s_l[k][t * 16 + (lane & 15)], acc[t], 0,
@@ -683,6 +693,22 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv32(TrsvBatch<float> bt,
     s_part[w][lane] = part;
     __syncthreads();
     if (w == 0) {
+      if (UPPER) {  // this block of the lower pass's solution
+        uint64_t wd = (uint64_t)tagl << 32;
+        int64_t spins = 0;
+        for (;;) {
+          if (lane < rows)
+            wd = __hip_atomic_load(&sy.xp[row], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (__all((uint32_t)(wd >> 32) == tagl)) break;
+          if (++spins > kSpinLimit) {
+            if (lane == 0) atomicExch(err, 1);
+            break;
+          }
+          if ((spins & 255) == 0 && ld_relaxed(err)) break;
+          __builtin_amdgcn_s_sleep(1);
+        }
+        rv = __uint_as_float((uint32_t)wd);
+      }
       float v = 0.f;
       if (lane < rows) {
         v = rv;
@@ -695,10 +721,10 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv32(TrsvBatch<float> bt,
       float o0 = 0.f, o1 = 0.f, o2 = 0.f, o3 = 0.f;
 #pragma unroll
       for (int c = 0; c < kTb; c += 4) {
-        o0 += s_d[lane][c] * s_x[c];
-        o1 += s_d[lane][c + 1] * s_x[c + 1];
-        o2 += s_d[lane][c + 2] * s_x[c + 2];
-        o3 += s_d[lane][c + 3] * s_x[c + 3];
+        o0 += s_di[lane][c] * s_x[c];
+        o1 += s_di[lane][c + 1] * s_x[c + 1];
+        o2 += s_di[lane][c + 2] * s_x[c + 2];
+        o3 += s_di[lane][c + 3] * s_x[c + 3];
       }
       v = (o0 + o1) + (o2 + o3);
       if (has_jl) {
@@ -735,7 +761,7 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv32(TrsvBatch<float> bt,
         v -= (q0 + q1) + (q2 + q3);
       }
       if (lane < rows) {
-        sy.x[row] = v;
+        if (UPPER) sy.x[row] = v;  // the lower pass's result lives in its words only
         const uint64_t word = ((uint64_t)tag << 32) | (uint64_t)__float_as_uint(v);
         __hip_atomic_store(&sy.xp[row], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
@@ -789,14 +815,14 @@ template <class T>
 hipError_t launch_trsv_batch(const TrsvBatch<T>& bt, int32_t scope, int32_t* ctl, int32_t* err,
                              hipStream_t s) {
   if (bt.total <= 0) return hipSuccess;
-  const dim3 g((unsigned)bt.total);
   if constexpr (sizeof(T) == 4) {
+    const dim3 g2(2u * (unsigned)bt.total);  // lower and upper pass in one launch
     if (scope)
-      hipLaunchKernelGGL((k_trsv32<false, true>), g, dim3(kTrsvThreads), 0, s, bt, ctl, err);
+      hipLaunchKernelGGL((k_trsv32<true>), g2, dim3(kTrsvThreads), 0, s, bt, ctl, err);
     else
-      hipLaunchKernelGGL((k_trsv32<false, false>), g, dim3(kTrsvThreads), 0, s, bt, ctl, err);
-    hipLaunchKernelGGL((k_trsv32<true, false>), g, dim3(kTrsvThreads), 0, s, bt, ctl, err);
+      hipLaunchKernelGGL((k_trsv32<false>), g2, dim3(kTrsvThreads), 0, s, bt, ctl, err);
   } else {
+    const dim3 g((unsigned)bt.total);
     if (scope)
       hipLaunchKernelGGL((k_trsv<T, false, true>), g, dim3(kTrsvThreads), 0, s, bt, ctl, err);
     else
