@@ -23,4 +23,7 @@ from .core import (  # noqa: F401
     solve_system, solve_scene, split_solution, doolittle_solve,
     rates, rk4_step, orthonormalise, rk4_generic, gmres, condition_1,
 )
+from .field import (  # noqa: F401
+    field_velocity, tracer_rk4_step, rk4_step_tracers,
+)
 
