@@ -5,13 +5,16 @@ length (N = 1000 force points, Q = 10000 quadrature points, n = 3150
 unknowns), eps = 0.01, classical RK4 with dt = 2 pi / 100 from the seeded
 initial state.  One step = four solves; each solve = geometry + nearest map
 + fused assembly + rigid-body blocks + LU + triangular solves + FP64
-refinement (method fp32_ir).  The metric is time-step solves per second,
-with the solution checked against the FP64 oracle (relative force error <=
-1e-8) on the final state.
+refinement (method fp32_ir).  The metric is time-step solves per second;
+a synchronous solve of the seeded initial state is checked against the FP64
+oracle (relative force error <= 1e-8) in the CPU leg.
 
 Printed as one JSON line; `roofline` describes the dominant kernel (the
 single-launch tile LU), timed here with HIP events around its own launch on
-the benchmark matrix; `cpu_baseline` is the CPU oracle on a bounded sample.
+the benchmark matrix; `cpu_baseline` is the CPU oracle on a bounded sample
+(the only part of this script that runs the oracle).  `field` is the flow at
+806 tracers of a 10-swimmer channel (nrs_field_velocity) and the tracer RK4
+step, with its own roofline and oracle sample.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--method fp32_ir|fp64_lu|fp32_gepp_ir]
 """
@@ -65,6 +68,121 @@ def train_model(ctx, nrs, solves=2000, steps=8000):
     return model, {"solves": solves, "bodies": data.n_bodies, "generate_s": t1 - t0,
                    "train_s": t2 - t1, "adam_steps": steps, "batch_bodies": 256,
                    "final_loss": hist[-1]["loss"], "params": int(model.theta.numel())}
+
+
+def device_problem(ctx, nrs, ds, scene, t, Y, dev):
+    """Geometry and nearest map of a scene state on the GPU (nrs_geometry,
+    nrs_nearest): the Problem and the prescribed velocities u [3N]."""
+    import torch
+    N, Q = scene["N"], scene["Q"]
+    x = torch.empty((3, N), dtype=torch.float64, device=dev)
+    X = torch.empty((3, Q), dtype=torch.float64, device=dev)
+    w = torch.empty(Q, dtype=torch.float64, device=dev)
+    u = torch.empty(3 * N, dtype=torch.float64, device=dev)
+    nrs.nrs_geometry(ctx, ds, t, Y, x, X, w, u)
+    nu = torch.empty(Q, dtype=torch.int32, device=dev)
+    nrs.nrs_nearest(ctx, x, scene["group_off"], X, ds.t["groupX"], nu)
+    return nrs.Problem(x, X, w, nu, ds.t["body"], Y, scene["eps"], scene["mu"]), u
+
+
+FIELD_FLOPS_PER_PAIR = 32.0
+
+
+def field_workload(synth):
+    """Tracer workload: 10 sperm-like swimmers in the 4 x 1 x 0.5 channel
+    (wall spacing 1/16: N = 4728 force and Q = 73248 quadrature points) and
+    806 tracers on a 26 x 31 grid in the channel mid-plane."""
+    scene = synth.sperm_channel_scene(10, h=1.0 / 16, seed=0)
+    y = synth.tracer_grid(26, 31, (-1.9, 1.9), (-0.45, 0.45), 0.0)
+    return scene, y
+
+
+def run_field(ctx, nrs, synth, dev, reps=40):
+    """Flow at the tracers (nrs_field_velocity: source gather, pair sum,
+    chunk sum) with seeded force densities, timed with HIP events on the
+    context's stream; then RK4 steps of the tracers through three
+    precomputed flows (geometry at t, t + dt/2, t + dt)."""
+    import numpy as np
+    import torch
+    scene, yh = field_workload(synth)
+    N, Q, P = scene["N"], scene["Q"], yh.shape[1]
+    ds = nrs.DeviceScene(scene, dev)
+    Y = torch.from_numpy(scene["Y0"].copy()).to(dev)
+    rng = np.random.default_rng(7)
+    flows, fs = [], []
+    dt = 2 * math.pi / 100
+    for k, t in enumerate((0.0, 0.5 * dt, dt)):
+        pb, _ = device_problem(ctx, nrs, ds, scene, t, Y, dev)
+        flows.append(pb)
+        fs.append(torch.from_numpy(rng.normal(size=(3, N))).to(dev))
+    y = torch.from_numpy(yh).to(dev)
+    u = torch.empty((3, P), dtype=torch.float64, device=dev)
+    ws = torch.empty(nrs.nrs_field_workspace_size(ctx, P, Q), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        nrs.nrs_field_velocity(ctx, flows[0], fs[0], y, u, ws)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        nrs.nrs_field_velocity(ctx, flows[0], fs[0], y, u, ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    call_ms = e0.elapsed_time(e1) / reps
+    pairs = float(P) * Q
+    tflops = FIELD_FLOPS_PER_PAIR * pairs / (call_ms / 1e3) / 1e12
+    yt = y.clone()
+    nrs.nrs_tracer_rk4_step(ctx, flows, fs, yt, dt, ws)
+    torch.cuda.synchronize()
+    ksteps = 10
+    e0.record(stream)
+    for _ in range(ksteps):
+        nrs.nrs_tracer_rk4_step(ctx, flows, fs, yt, dt, ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / ksteps
+    return {"workload": f"sperm_K10_h16_tracers{P}", "tracers": P, "N": N, "Q": Q,
+            "pairs_per_call": pairs, "ms_per_call": call_ms, "pairs_per_s": pairs / (call_ms / 1e3),
+            "roofline": {"kernel": "nrs_field_velocity (k_field_sources + k_field_part + "
+                                   "k_field_sum)", "bound": "alu", "achieved": tflops,
+                         "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tflops / PEAK_FP64_TFLOPS, "traffic": None,
+                         "flops_per_pair": FIELD_FLOPS_PER_PAIR},
+            "tracer_rk4_ms_per_step": step_ms, "tracer_rk4_steps_per_s": 1e3 / step_ms,
+            "note": "FP64; flops counted as 32 per (tracer, quadrature point) pair with the "
+                    "reciprocal square root as one; the call time includes the gather of "
+                    "w_q f[nu(q)] and the fixed-order chunk sum"}
+
+
+def cpu_oracle_leg(scene, dt, field_pairs_sample=200):
+    """The CPU FP64 oracle on bounded samples of the same workloads (timed),
+    and its solve of the seeded initial state (the accuracy reference)."""
+    import numpy as np
+    import oracle
+    import synth
+    Yc = scene["Y0"].copy()
+    c0 = time.perf_counter()
+    oracle.rk4_step(scene, Yc, 0.0, dt)
+    c_el = time.perf_counter() - c0
+    f_ref, UW_ref = oracle.solve_scene(scene, 0.0, scene["Y0"])
+    fscene, yh = field_workload(synth)
+    x, X, w, _ = oracle.geometry(fscene, 0.0, fscene["Y0"])
+    nu = oracle.nearest(x, X, fscene["group_off"], fscene["groupX"])
+    f = np.random.default_rng(7).normal(size=(3, fscene["N"]))
+    ys = np.ascontiguousarray(yh[:, :field_pairs_sample])
+    c1 = time.perf_counter()
+    oracle.field_velocity(ys, X, w, nu, f, fscene["eps"], fscene["mu"])
+    f_el = time.perf_counter() - c1
+    cpu = {"value": 4.0 / c_el, "unit": "solves/s", "cores": cpu_threads(), "kind": "oracle",
+           "sample": "one RK4 step (4 solves) of the same 25-filament workload from the "
+                     "seeded initial state, NumPy/LAPACK FP64 oracle",
+           "seconds": c_el}
+    field_cpu = {"value": ys.shape[1] * float(fscene["Q"]) / f_el, "unit": "pairs/s",
+                 "cores": cpu_threads(), "kind": "oracle",
+                 "sample": f"flow at the first {ys.shape[1]} tracers of the tracer workload",
+                 "seconds": f_el}
+    return cpu, field_cpu, f_ref, UW_ref
 
 
 def run_batched(ctx, nrs, synth, B, dev, reps=3, tune=True):
@@ -171,6 +289,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--batch-only", action="store_true",
                     help="time only the batched workload (profiling)")
+    ap.add_argument("--no-field", action="store_true",
+                    help="skip the flow-at-tracers workload")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -232,13 +352,9 @@ def main():
     # autotune the assembly launch shape for this size class (never changes results)
     method = METHODS[args.method]
     tune = None
+    Y0d = torch.from_numpy(scene["Y0"].copy()).to(dev)
     if not args.no_tune:
-        T0 = lambda a, d=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dtype=d, device=dev)  # noqa: E731
-        import oracle as _o
-        xg, Xg, wg, ug = _o.geometry(scene, 0.0, scene["Y0"])
-        nug = _o.nearest(xg, Xg, scene["group_off"], scene["groupX"])
-        pbt = nrs.Problem(T0(xg), T0(Xg), T0(wg), T0(nug, torch.int32), T0(scene["body"], torch.int32),
-                          T0(scene["Y0"]), scene["eps"], scene["mu"])
+        pbt, _ = device_problem(ctx, nrs, ds, scene, 0.0, Y0d, dev)
         wst = torch.empty(nrs.nrs_workspace_size(ctx, N, Q, M, nrs.NRS_FP32_IR), dtype=torch.uint8,
                           device=dev)
         tune = nrs.nrs_autotune(ctx, pbt, wst)
@@ -247,21 +363,13 @@ def main():
     solves = 4 * args.steps
     value = solves / (ms / 1e3)
 
-    # --- accuracy of the final state against the FP64 oracle -------------------
-    import oracle
-    Yh = Y.cpu().numpy().reshape(M, 12)
-    x, X, w, u = oracle.geometry(scene, t_end, Yh)
-    nu = oracle.nearest(x, X, scene["group_off"], scene["groupX"])
-    T = lambda a, d=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dtype=d, device=dev)  # noqa: E731
-    pb = nrs.Problem(T(x), T(X), T(w), T(nu, torch.int32), T(scene["body"], torch.int32), T(Yh),
-                     scene["eps"], scene["mu"])
+    # --- one synchronous solve of the seeded initial state (accuracy check
+    # against the oracle in the CPU leg) on the product's own geometry -------
+    pb, u = device_problem(ctx, nrs, ds, scene, 0.0, Y0d, dev)
     ws1 = torch.empty(nrs.nrs_workspace_size(ctx, N, Q, M, method), dtype=torch.uint8, device=dev)
     sol = torch.empty(n, dtype=torch.float64, device=dev)
-    sinfo = nrs.nrs_solve(ctx, pb, T(u), None, sol, ws1, method=method)
-    f_ref, UW_ref = oracle.solve_scene(scene, t_end, Yh)
+    sinfo = nrs.nrs_solve(ctx, pb, u, None, sol, ws1, method=method)
     s = sol.cpu().numpy()
-    err_f = float(np.linalg.norm(s[:3 * N] - f_ref.ravel()) / np.linalg.norm(f_ref))
-    err_uw = float(np.linalg.norm(s[3 * N:] - UW_ref.ravel()) / np.linalg.norm(UW_ref))
 
     # --- dominant kernel: the tile LU, one launch, timed with events ----------
     lda = nrs.lda_for(n)
@@ -333,16 +441,24 @@ def main():
     if args.batch > 0:
         batched = run_batched(ctx, nrs, synth, args.batch, dev, tune=not args.no_tune)
 
+    field = None
+    if not args.no_field:
+        field = run_field(ctx, nrs, synth, dev)
+
     cpu = None
+    accuracy = None
     if not args.no_cpu_baseline:
-        Yc = scene["Y0"].copy()
-        c0 = time.perf_counter()
-        oracle.rk4_step(scene, Yc, 0.0, dt)
-        c_el = time.perf_counter() - c0
-        cpu = {"value": 4.0 / c_el, "unit": "solves/s", "cores": cpu_threads(), "kind": "oracle",
-               "sample": "one RK4 step (4 solves) of the same 25-filament workload from the "
-                         "seeded initial state, NumPy/LAPACK FP64 oracle",
-               "seconds": c_el}
+        cpu, field_cpu, f_ref, UW_ref = cpu_oracle_leg(scene, dt)
+        if field is not None:
+            field["cpu_baseline"] = field_cpu
+        err_f = float(np.linalg.norm(s[:3 * N] - f_ref.ravel()) / np.linalg.norm(f_ref))
+        err_uw = float(np.linalg.norm(s[3 * N:] - UW_ref.ravel()) / np.linalg.norm(UW_ref))
+        accuracy = {"rel_force_err": err_f, "rel_velocity_err": err_uw, "target": 1e-8,
+                    "solve_info": sinfo, "step_info": info,
+                    "note": "solve_info: synchronous solve of the seeded initial state "
+                            "(compared with the oracle), backward_error at the returned "
+                            "solution; step_info: worst of the last timed step's four stages, "
+                            "backward_error at the iterate before the last correction"}
 
     out = {
         "metric": "time-step solves/sec (assemble+solve) at <=1e-8 rel force err",
@@ -359,11 +475,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"filaments_M{M}_rk4", "swimmers": M, "N": N, "Q": Q, "n": n,
                    "eps": scene["eps"], "dt": dt, "method": args.method},
-        "accuracy": {"rel_force_err": err_f, "rel_velocity_err": err_uw, "target": 1e-8,
-                     "solve_info": sinfo, "step_info": info,
-                     "note": "solve_info: synchronous solve of the final state, backward_error at "
-                             "the returned solution; step_info: worst of the last step's four "
-                             "stages, backward_error at the iterate before the last correction"},
+        "accuracy": accuracy,
         "roofline": {"kernel": "k_lu_tiles<float>", "bound": "mfma", "achieved": lu_tflops,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": lu_tflops / PEAK_FP32_TFLOPS, "traffic": traffic,
@@ -376,6 +488,7 @@ def main():
         "learned_training": learned_info,
         "autotune": tune,
         "batched": batched,
+        "field": field,
         "cpu_baseline": cpu,
         "wall_s": wall,
     }

@@ -384,6 +384,57 @@ nrs_status nrs_rk4_step(nrs_ctx* ctx, const nrs_scene* sc, int32_t G, const int3
                         double* Y, double t, double dt, const nrs_options* opt,
                         void* ws, size_t ws_bytes);
 
+/* ------------------------------------------------------------------------ */
+/* Flow at field points and passive tracers.  The regularized single-layer  */
+/* equation (Sec. 3, eq. 19) holds anywhere in the fluid, so the nearest-   */
+/* neighbour sum of eq. 23 evaluated at a field point y gives the velocity  */
+/* there; the particle-tracking experiments (Sec. 4.3, Sec. 5.2) carry      */
+/* tracers with it.  Tracers do not act on the fluid.                       */
+/* ------------------------------------------------------------------------ */
+/* Bytes of device workspace nrs_field_velocity and nrs_tracer_rk4_step need
+ * for P field points and up to Q quadrature points (0 <= P <= 2^28). */
+nrs_status nrs_field_workspace_size(nrs_ctx* ctx, int64_t P, int64_t Q, size_t* bytes);
+
+/* u_j(y_p) = (8 pi mu)^-1 sum_q S^eps_jk(y_p - X_q) w_q f_k[nu(q)]
+ * for P field points y [3][P] (component-major, device, FP64).  Reads
+ * pb->N, Q, X, w (NULL = all 1), nu, eps and mu only; f [3][N] (device) are
+ * the force densities, i.e. the first 3N entries of a solution of
+ * nrs_solve.  Quadrature points whose nu is outside [0, N) contribute
+ * nothing.  u [3][P] (device) may alias y.  P = 0 does nothing.  The result
+ * does not depend on the order of the quadrature points beyond rounding, and
+ * repeated calls with the same sizes give identical bits.  Asynchronous.
+ * Errors: NRS_E_ARG (NULL arrays, sizes, eps or mu), NRS_E_UNSUPPORTED
+ * (N > 2^20 or Q > 2^30), NRS_E_WORKSPACE, NRS_E_HIP. */
+nrs_status nrs_field_velocity(nrs_ctx* ctx, const nrs_problem* pb, const double* f, int64_t P,
+                              const double* y, double* u, void* ws, size_t ws_bytes);
+
+/* One classical RK4 step of P tracers y [3][P] (device, in place) through
+ * flows known in advance (forces precomputed, as in the node experiment):
+ * flows[0..2] (HOST array of three problems, fields as in nrs_field_velocity)
+ * with force densities f[0..2] (HOST array of three device pointers) are the
+ * flow at t, t + dt/2 and t + dt; both middle stages use flows[1]:
+ *   k1 = u0(y), k2 = u1(y + dt/2 k1), k3 = u1(y + dt/2 k2), k4 = u2(y + dt k3),
+ *   y <- y + dt/6 (k1 + 2 k2 + 2 k3 + k4).
+ * ws: nrs_field_workspace_size(P, largest Q of the three) bytes.
+ * Asynchronous; errors as nrs_field_velocity. */
+nrs_status nrs_tracer_rk4_step(nrs_ctx* ctx, const nrs_problem* flows, const double* const* f,
+                               int64_t P, double* y, double dt, void* ws, size_t ws_bytes);
+
+/* nrs_rk4_step with P passive tracers ytr [3][P] (device, in place) carried
+ * by the same step: every stage evaluates its own flow (that stage's
+ * geometry and solved forces) at the tracers' stage positions, and the
+ * tracers take the RK4 combination of the four rates (not orthonormalised).
+ * If the step is redone with FP64 LU, the tracers are redone with it.
+ * P = 0 is nrs_rk4_step.  ws: nrs_rk4_tracers_workspace_size bytes
+ * (P = 0 gives nrs_rk4_workspace_size). */
+nrs_status nrs_rk4_tracers_workspace_size(nrs_ctx* ctx, const nrs_scene* sc, int32_t method,
+                                          int64_t P, size_t* bytes);
+nrs_status nrs_rk4_step_tracers(nrs_ctx* ctx, const nrs_scene* sc, int32_t G,
+                                const int32_t* group_off_host, const int32_t* groupX, double eps,
+                                double mu, const double* ftext, double* Y, double t, double dt,
+                                const nrs_options* opt, int64_t P, double* ytr, void* ws,
+                                size_t ws_bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -303,6 +303,59 @@ def nrs_rk4_step(ctx, scene, Y, t, dt, ws, method=NRS_FP64_LU, ftext=None, **opt
                                     _ptr(ws, torch.uint8, "ws"), ws.numel()), ctx)
 
 
+def nrs_rk4_tracers_workspace_size(ctx, scene, method, P):
+    b = C.c_size_t()
+    sc = scene.struct()
+    _check(_lib.load().nrs_rk4_tracers_workspace_size(ctx.handle, C.byref(sc), method, int(P),
+                                                      C.byref(b)), ctx)
+    return b.value
+
+
+def nrs_rk4_step_tracers(ctx, scene, Y, ytr, t, dt, ws, method=NRS_FP64_LU, ftext=None, **opts):
+    """ytr: device float64 [3, P] tracer positions, advanced in place."""
+    sc = scene.struct()
+    o = _options(method, **opts)
+    go = scene.group_off
+    P = 0 if ytr is None else int(ytr.numel() // 3)
+    _check(_lib.load().nrs_rk4_step_tracers(
+        ctx.handle, C.byref(sc), len(go) - 1, go.ctypes.data_as(C.c_void_p),
+        _ptr(scene.t["groupX"], torch.int32, "groupX"), scene.eps, scene.mu,
+        _ptr(ftext, torch.float64, "ftext"), _ptr(Y, torch.float64, "Y"), float(t), float(dt),
+        C.byref(o), P, _ptr(ytr, torch.float64, "ytr"), _ptr(ws, torch.uint8, "ws"),
+        ws.numel()), ctx)
+
+
+# ---------------------------------------------------------------- field points and tracers
+
+def nrs_field_workspace_size(ctx, P, Q):
+    b = C.c_size_t()
+    _check(_lib.load().nrs_field_workspace_size(ctx.handle, int(P), int(Q), C.byref(b)), ctx)
+    return b.value
+
+
+def nrs_field_velocity(ctx, problem, f, y, u, ws):
+    """u [3, P] = flow of force densities f [3, N] at field points y [3, P]."""
+    pb = problem.struct()
+    P = int(y.numel() // 3)
+    _check(_lib.load().nrs_field_velocity(ctx.handle, C.byref(pb), _ptr(f, torch.float64, "f"), P,
+                                          _ptr(y, torch.float64, "y"),
+                                          _ptr(u, torch.float64, "u"),
+                                          _ptr(ws, torch.uint8, "ws"), ws.numel()), ctx)
+
+
+def nrs_tracer_rk4_step(ctx, problems, fs, y, dt, ws):
+    """problems, fs: the flows (Problem) and force densities at t, t + dt/2,
+    t + dt; y [3, P] advanced in place."""
+    if len(problems) != 3 or len(fs) != 3:
+        raise ValueError("three flows (t, t + dt/2, t + dt) required")
+    arr = (NrsProblem * 3)(*[p.struct() for p in problems])
+    fp = (C.c_void_p * 3)(*[_ptr(f, torch.float64, "f") for f in fs])
+    P = int(y.numel() // 3)
+    _check(_lib.load().nrs_tracer_rk4_step(ctx.handle, arr, fp, P, _ptr(y, torch.float64, "y"),
+                                           float(dt), _ptr(ws, torch.uint8, "ws"), ws.numel()),
+           ctx)
+
+
 # ---------------------------------------------------------------- learned warm start
 
 def nrs_mlp_param_count():

@@ -111,6 +111,15 @@ PROTOTYPES = {
     "nrs_rk4_workspace_size": (_i32, [_p, C.POINTER(NrsScene), _i32, C.POINTER(C.c_size_t)]),
     "nrs_rk4_step": (_i32, [_p, C.POINTER(NrsScene), _i32, _p, _p, C.c_double, C.c_double, _p,
                             _p, C.c_double, C.c_double, C.POINTER(NrsOptions), _p, C.c_size_t]),
+    "nrs_field_workspace_size": (_i32, [_p, _i64, _i64, C.POINTER(C.c_size_t)]),
+    "nrs_field_velocity": (_i32, [_p, C.POINTER(NrsProblem), _p, _i64, _p, _p, _p, C.c_size_t]),
+    "nrs_tracer_rk4_step": (_i32, [_p, C.POINTER(NrsProblem), C.POINTER(_p), _i64, _p,
+                                   C.c_double, _p, C.c_size_t]),
+    "nrs_rk4_tracers_workspace_size": (_i32, [_p, C.POINTER(NrsScene), _i32, _i64,
+                                              C.POINTER(C.c_size_t)]),
+    "nrs_rk4_step_tracers": (_i32, [_p, C.POINTER(NrsScene), _i32, _p, _p, C.c_double,
+                                    C.c_double, _p, _p, C.c_double, C.c_double,
+                                    C.POINTER(NrsOptions), _i64, _p, _p, C.c_size_t]),
 }
 
 _LIB = None

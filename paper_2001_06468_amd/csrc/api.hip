@@ -656,9 +656,14 @@ struct RkBuffers {
   int32_t* nu;
   float *phi, *my, *mz;   // network features / outputs (GMRES warm start)
   SolveBuffers sb;
+  // passive tracers: stage rates, saved positions, field sources and sums
+  int64_t P;
+  FieldPlan fplan;
+  double *TK[4], *ysave, *fpart;
+  FieldSrc* src;
 };
 
-bool carve_rk(Arena& ar, const nrs_scene& sc, int32_t method, RkBuffers& rb) {
+bool carve_rk(Arena& ar, const nrs_scene& sc, int32_t method, int64_t P, RkBuffers& rb) {
   const int64_t N = sc.N, Q = sc.Q, M = sc.M, n = 3 * N + 6 * M;
   rb.report = ar.take<SolveState>(1);
   rb.x = ar.take<double>(3 * N);
@@ -677,12 +682,20 @@ bool carve_rk(Arena& ar, const nrs_scene& sc, int32_t method, RkBuffers& rb) {
     rb.mz = ar.take<float>(6 * M);
   }
   carve_solve(ar, N, Q, sc.M, method, rb.sb);
+  // tracers last: the report stays at the start of the workspace (nrs_query_info)
+  rb.P = P;
+  rb.fplan = field_plan(P, Q);
+  for (int i = 0; i < 4; ++i) rb.TK[i] = P > 0 ? ar.take<double>(3 * P) : nullptr;
+  rb.ysave = P > 0 ? ar.take<double>(3 * P) : nullptr;
+  rb.fpart = P > 0 ? ar.take<double>((size_t)rb.fplan.cap * 3 * P) : nullptr;
+  rb.src = P > 0 ? ar.take<FieldSrc>(Q) : nullptr;
   return !ar.overflow;
 }
 
 nrs_status rk4_pass(nrs_ctx* ctx, const nrs_scene& sc, const GroupTable& gt,
                     const int32_t* groupX, double eps, double mu, const double* ftext, double* Y,
-                    double t, double dt, const nrs_options& o, RkBuffers& rb, bool prev_valid) {
+                    double* ytr, double t, double dt, const nrs_options& o, RkBuffers& rb,
+                    bool prev_valid) {
   hipStream_t s = ctx->stream;
   const double c[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
   NRS_HIP(ctx, launch_state_init(rb.report, o.method, s));
@@ -722,8 +735,44 @@ nrs_status rk4_pass(nrs_ctx* ctx, const nrs_scene& sc, const GroupTable& gt,
     if (st != NRS_OK) return st;
     NRS_HIP(ctx, launch_state_accumulate(rb.report, rb.sb.st, s));
     NRS_HIP(ctx, launch_rk_rates(sc.M, sc.N, rb.Ys, rb.sol, rb.K[stg], s));
+    if (rb.P > 0) {
+      // this stage's flow (its geometry and forces) at the tracers' stage positions
+      NRS_HIP(ctx, launch_field_sources(sc.N, sc.Q, rb.X, rb.w, rb.nu, rb.sol, rb.src, s));
+      NRS_HIP(ctx, launch_field(rb.fplan, rb.P, sc.Q, ytr, stg ? rb.TK[stg - 1] : nullptr, c[stg],
+                                rb.src, eps, mu, rb.fpart, rb.TK[stg], s));
+    }
   }
   NRS_HIP(ctx, launch_rk_combine(sc.M, Y, rb.K[0], rb.K[1], rb.K[2], rb.K[3], dt, s));
+  NRS_HIP(ctx, launch_tracer_combine(rb.P, ytr, rb.TK[0], rb.TK[1], rb.TK[2], rb.TK[3], dt, s));
+  return NRS_OK;
+}
+
+// Field points per call: the grid of the pair kernel stays below 2^31 workgroups.
+constexpr int64_t kMaxFieldPoints = (int64_t)1 << 28;
+
+struct FieldBuffers {
+  FieldSrc* src;   // [Q] gathered sources
+  double* part;    // [chunks][3P] chunk sums
+  double* K[4];    // [3P] RK stage rates (tracer steps)
+};
+
+bool carve_field(Arena& ar, int64_t P, int64_t Q, FieldBuffers& fb) {
+  const FieldPlan fp = field_plan(P, Q);
+  fb.src = ar.take<FieldSrc>(Q);
+  fb.part = ar.take<double>((size_t)fp.cap * 3 * std::max<int64_t>(P, 1));
+  for (int i = 0; i < 4; ++i) fb.K[i] = ar.take<double>(3 * std::max<int64_t>(P, 1));
+  return !ar.overflow;
+}
+
+// A flow for the field sum: sources X, w, nu of N force points, densities f.
+nrs_status check_flow(nrs_ctx* ctx, const nrs_problem* pb, const double* f) {
+  if (!pb) return fail(ctx, NRS_E_ARG, "problem is NULL");
+  if (pb->N <= 0 || pb->Q <= 0) return fail(ctx, NRS_E_ARG, "need N > 0, Q > 0");
+  if (pb->N > (int64_t)1 << 20 || pb->Q > (int64_t)1 << 30)
+    return fail(ctx, NRS_E_UNSUPPORTED, "N or Q too large");
+  if (!pb->X || !pb->nu || !f) return fail(ctx, NRS_E_ARG, "X, nu and f required");
+  if (!(pb->eps > 0.0) || !(pb->mu > 0.0) || !std::isfinite(pb->eps) || !std::isfinite(pb->mu))
+    return fail(ctx, NRS_E_ARG, "eps and mu must be positive and finite");
   return NRS_OK;
 }
 
@@ -740,28 +789,37 @@ nrs_status check_scene(nrs_ctx* ctx, const nrs_scene* sc) {
 
 extern "C" {
 
-nrs_status nrs_rk4_workspace_size(nrs_ctx* ctx, const nrs_scene* sc, int32_t method,
-                                  size_t* bytes) {
+nrs_status nrs_rk4_tracers_workspace_size(nrs_ctx* ctx, const nrs_scene* sc, int32_t method,
+                                          int64_t P, size_t* bytes) {
   nrs_status st = check_scene(ctx, sc);
   if (st) return st;
   if (!bytes) return fail(ctx, NRS_E_ARG, "bytes is NULL");
+  if (P < 0 || P > kMaxFieldPoints) return fail(ctx, NRS_E_ARG, "tracer count out of range");
   if (method < NRS_FP64_LU || method > NRS_GMRES)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
   Arena ar(nullptr, 0);
   RkBuffers rb;
-  carve_rk(ar, *sc, method, rb);
+  carve_rk(ar, *sc, method, P, rb);
   *bytes = ar.used + 256;
   return NRS_OK;
 }
 
-nrs_status nrs_rk4_step(nrs_ctx* ctx, const nrs_scene* sc, int32_t G, const int32_t* group_off_host,
-                        const int32_t* groupX, double eps, double mu, const double* ftext,
-                        double* Y, double t, double dt, const nrs_options* opt, void* ws,
-                        size_t ws_bytes) {
+nrs_status nrs_rk4_workspace_size(nrs_ctx* ctx, const nrs_scene* sc, int32_t method,
+                                  size_t* bytes) {
+  return nrs_rk4_tracers_workspace_size(ctx, sc, method, 0, bytes);
+}
+
+nrs_status nrs_rk4_step_tracers(nrs_ctx* ctx, const nrs_scene* sc, int32_t G,
+                                const int32_t* group_off_host, const int32_t* groupX, double eps,
+                                double mu, const double* ftext, double* Y, double t, double dt,
+                                const nrs_options* opt, int64_t P, double* ytr, void* ws,
+                                size_t ws_bytes) {
   nrs_status st = use_device(ctx);
   if (st) return st;
   if ((st = check_scene(ctx, sc))) return st;
   if (sc->M <= 0 || !Y) return fail(ctx, NRS_E_ARG, "time stepping needs free bodies and Y");
+  if (P < 0 || P > kMaxFieldPoints) return fail(ctx, NRS_E_ARG, "tracer count out of range");
+  if (P > 0 && !ytr) return fail(ctx, NRS_E_ARG, "tracer positions required");
   if (!group_off_host || !groupX || G <= 0) return fail(ctx, NRS_E_ARG, "groups required");
   if (G > kMaxGroups) return fail(ctx, NRS_E_UNSUPPORTED, "too many groups");
   if (!(eps > 0.0) || !(mu > 0.0) || !std::isfinite(t) || !std::isfinite(dt))
@@ -781,9 +839,11 @@ nrs_status nrs_rk4_step(nrs_ctx* ctx, const nrs_scene* sc, int32_t G, const int3
     return fail(ctx, NRS_E_UNSUPPORTED, "GMRES restart length must be below 64");
   Arena ar(ws, ws_bytes);
   RkBuffers rb;
-  if (!carve_rk(ar, *sc, o.method, rb)) return fail(ctx, NRS_E_WORKSPACE, "workspace too small");
+  if (!carve_rk(ar, *sc, o.method, P, rb)) return fail(ctx, NRS_E_WORKSPACE, "workspace too small");
   hipStream_t s = ctx->stream;
   NRS_HIP(ctx, hipMemcpyAsync(rb.Ysave, Y, 12 * sizeof(double) * sc->M, hipMemcpyDeviceToDevice, s));
+  if (P > 0)
+    NRS_HIP(ctx, hipMemcpyAsync(rb.ysave, ytr, 3 * sizeof(double) * P, hipMemcpyDeviceToDevice, s));
   if (o.method == NRS_GMRES && o.warm_start == NRS_WARM_MODEL) {
     if (!o.model_theta || !o.body_off || !sc->s)
       return fail(ctx, NRS_E_ARG, "model warm start needs model_theta, body_off and scene s");
@@ -793,7 +853,8 @@ nrs_status nrs_rk4_step(nrs_ctx* ctx, const nrs_scene* sc, int32_t G, const int3
   }
   const bool prev_valid = ctx->rk_prev_ws == ws;
   ctx->rk_prev_ws = nullptr;
-  if ((st = rk4_pass(ctx, *sc, gt, groupX, eps, mu, ftext, Y, t, dt, o, rb, prev_valid)) != NRS_OK)
+  if ((st = rk4_pass(ctx, *sc, gt, groupX, eps, mu, ftext, Y, ytr, t, dt, o, rb, prev_valid)) !=
+      NRS_OK)
     return st;
   ctx->rk_prev_ws = ws;
   if (o.no_fallback || o.method == NRS_FP64_LU) return NRS_OK;
@@ -802,15 +863,86 @@ nrs_status nrs_rk4_step(nrs_ctx* ctx, const nrs_scene* sc, int32_t G, const int3
   if (!h.failed) return NRS_OK;
   // a stage missed its tolerance: redo the whole step with FP64 LU
   NRS_HIP(ctx, hipMemcpyAsync(Y, rb.Ysave, 12 * sizeof(double) * sc->M, hipMemcpyDeviceToDevice, s));
+  if (P > 0)
+    NRS_HIP(ctx, hipMemcpyAsync(ytr, rb.ysave, 3 * sizeof(double) * P, hipMemcpyDeviceToDevice, s));
   nrs_options o64 = o;
   o64.method = NRS_FP64_LU;
-  if ((st = rk4_pass(ctx, *sc, gt, groupX, eps, mu, ftext, Y, t, dt, o64, rb, false)) != NRS_OK)
+  if ((st = rk4_pass(ctx, *sc, gt, groupX, eps, mu, ftext, Y, ytr, t, dt, o64, rb, false)) != NRS_OK)
     return st;
   SolveState mark = {};
   if ((st = read_state(ctx, rb.report, mark)) != NRS_OK) return st;
   mark.fell_back = 1;
   NRS_HIP(ctx, hipMemcpyAsync(rb.report, &mark, sizeof(SolveState), hipMemcpyHostToDevice, s));
   NRS_HIP(ctx, hipStreamSynchronize(s));
+  return NRS_OK;
+}
+
+nrs_status nrs_rk4_step(nrs_ctx* ctx, const nrs_scene* sc, int32_t G, const int32_t* group_off_host,
+                        const int32_t* groupX, double eps, double mu, const double* ftext,
+                        double* Y, double t, double dt, const nrs_options* opt, void* ws,
+                        size_t ws_bytes) {
+  return nrs_rk4_step_tracers(ctx, sc, G, group_off_host, groupX, eps, mu, ftext, Y, t, dt, opt, 0,
+                              nullptr, ws, ws_bytes);
+}
+
+// ---- flow at field points and tracers through precomputed flows ----
+
+nrs_status nrs_field_workspace_size(nrs_ctx* ctx, int64_t P, int64_t Q, size_t* bytes) {
+  if (!bytes) return fail(ctx, NRS_E_ARG, "bytes is NULL");
+  if (P < 0 || P > kMaxFieldPoints || Q <= 0 || Q > ((int64_t)1 << 30))
+    return fail(ctx, NRS_E_ARG, "P or Q out of range");
+  Arena ar(nullptr, 0);
+  FieldBuffers fb;
+  carve_field(ar, P, Q, fb);
+  *bytes = ar.used + 256;
+  return NRS_OK;
+}
+
+nrs_status nrs_field_velocity(nrs_ctx* ctx, const nrs_problem* pb, const double* f, int64_t P,
+                              const double* y, double* u, void* ws, size_t ws_bytes) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if ((st = check_flow(ctx, pb, f))) return st;
+  if (P < 0 || P > kMaxFieldPoints) return fail(ctx, NRS_E_ARG, "field point count out of range");
+  if (P == 0) return NRS_OK;
+  if (!y || !u) return fail(ctx, NRS_E_ARG, "y and u required");
+  Arena ar(ws, ws_bytes);
+  FieldBuffers fb;
+  if (!carve_field(ar, P, pb->Q, fb)) return fail(ctx, NRS_E_WORKSPACE, "workspace too small");
+  hipStream_t s = ctx->stream;
+  NRS_HIP(ctx, launch_field_sources(pb->N, pb->Q, pb->X, pb->w, pb->nu, f, fb.src, s));
+  NRS_HIP(ctx, launch_field(field_plan(P, pb->Q), P, pb->Q, y, nullptr, 0.0, fb.src, pb->eps,
+                            pb->mu, fb.part, u, s));
+  return NRS_OK;
+}
+
+nrs_status nrs_tracer_rk4_step(nrs_ctx* ctx, const nrs_problem* flows, const double* const* f,
+                               int64_t P, double* y, double dt, void* ws, size_t ws_bytes) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if (!flows || !f) return fail(ctx, NRS_E_ARG, "flows and f required");
+  for (int k = 0; k < 3; ++k)
+    if ((st = check_flow(ctx, &flows[k], f[k]))) return st;
+  if (P < 0 || P > kMaxFieldPoints) return fail(ctx, NRS_E_ARG, "tracer count out of range");
+  if (!std::isfinite(dt)) return fail(ctx, NRS_E_ARG, "dt must be finite");
+  if (P == 0) return NRS_OK;
+  if (!y) return fail(ctx, NRS_E_ARG, "tracer positions required");
+  const int64_t Qmax = std::max(flows[0].Q, std::max(flows[1].Q, flows[2].Q));
+  Arena ar(ws, ws_bytes);
+  FieldBuffers fb;
+  if (!carve_field(ar, P, Qmax, fb)) return fail(ctx, NRS_E_WORKSPACE, "workspace too small");
+  hipStream_t s = ctx->stream;
+  // stages: flow at t, t + dt/2 (twice), t + dt
+  const int which[4] = {0, 1, 1, 2};
+  const double c[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
+  for (int stg = 0; stg < 4; ++stg) {
+    const nrs_problem& fl = flows[which[stg]];
+    if (stg != 2)
+      NRS_HIP(ctx, launch_field_sources(fl.N, fl.Q, fl.X, fl.w, fl.nu, f[which[stg]], fb.src, s));
+    NRS_HIP(ctx, launch_field(field_plan(P, fl.Q), P, fl.Q, y, stg ? fb.K[stg - 1] : nullptr,
+                              c[stg], fb.src, fl.eps, fl.mu, fb.part, fb.K[stg], s));
+  }
+  NRS_HIP(ctx, launch_tracer_combine(P, y, fb.K[0], fb.K[1], fb.K[2], fb.K[3], dt, s));
   return NRS_OK;
 }
 

@@ -372,4 +372,29 @@ hipError_t launch_rk_rates(int32_t M, int64_t N, const double* Ys, const double*
 hipError_t launch_rk_combine(int32_t M, double* Y, const double* K1, const double* K2,
                              const double* K3, const double* K4, double dt, hipStream_t s);
 
+// flow at field points and tracers
+// One quadrature point as a source of the field sum: position and
+// g = w_q f[nu(q)] (zero when nu(q) is outside [0, N)); 64 bytes so that a
+// wave reads a record with one scalar load.
+struct alignas(64) FieldSrc {
+  double X, Y, Z, gx, gy, gz, pad0, pad1;
+};
+// Field points in blocks of 64 (one per lane), sources cut into `chunks`
+// ranges of `chunk` records; partial sums need chunks * 3P doubles.
+// cap >= chunks never decreases with Q, so a buffer of cap * 3P doubles
+// planned for some Q serves every smaller Q.
+struct FieldPlan {
+  int64_t pblocks, chunk;
+  int32_t chunks, cap;
+};
+FieldPlan field_plan(int64_t P, int64_t Q);
+hipError_t launch_field_sources(int64_t N, int64_t Q, const double* X, const double* w,
+                                const int32_t* nu, const double* f, FieldSrc* src, hipStream_t s);
+// u [3][P] = flow of the sources at y + c K (K may be NULL: at y)
+hipError_t launch_field(const FieldPlan& fp, int64_t P, int64_t Q, const double* y,
+                        const double* K, double c, const FieldSrc* src, double eps, double mu,
+                        double* part, double* u, hipStream_t s);
+hipError_t launch_tracer_combine(int64_t P, double* y, const double* K1, const double* K2,
+                                 const double* K3, const double* K4, double dt, hipStream_t s);
+
 }  // namespace nrs

@@ -373,6 +373,15 @@ def rod_wall_batch(B=512, seed=0, lo=300, hi=6000):
     return [rod_wall_scene(int(round(t)), rng) for t in targets]
 
 
+def tracer_grid(nx, ny, xr, yr, z):
+    """nx x ny tracers on a rectangular grid (end points included) spanning
+    xr x yr in the plane z = const; returns (3, nx*ny), x fastest."""
+    gx = np.linspace(xr[0], xr[1], nx)
+    gy = np.linspace(yr[0], yr[1], ny)
+    X, Y = np.meshgrid(gx, gy, indexing="xy")
+    return np.ascontiguousarray(np.stack([X.ravel(), Y.ravel(), np.full(nx * ny, float(z))]))
+
+
 def scene_sizes(sc):
     """(N, Q, M, n) with n = 3N + 6M unknowns."""
     return sc["N"], sc["Q"], sc["M"], 3 * sc["N"] + 6 * sc["M"]
