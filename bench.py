@@ -36,7 +36,11 @@ PEAK_FP64_TFLOPS = 78.6
 # HBM bytes per launch of the tile LU at n = 3150 from the FETCH_SIZE and
 # WRITE_SIZE counter runs (calibrated against a 256 MiB copy), valid only for
 # the kernel source they were taken on (first 16 hex digits of its SHA-256).
-LU_TRAFFIC = {"source_sha256_16": "5898a348aa994156", "bytes_per_launch": 775932420, "n": 3150}
+LU_TRAFFIC = {"source_sha256_16": "5898a348aa994156", "bytes_per_launch": 779262102, "n": 3150}
+# HBM bytes per nrs_field_velocity call (sources + pair sum + chunk sum) on the
+# tracer workload, from the same two counter runs, valid for that field.hip.
+FIELD_TRAFFIC = {"source_sha256_16": "0e07e3708f3a6a69", "bytes_per_call": 24466341, "Q": 73248,
+                 "tracers": 806}
 
 
 def cpu_threads():
@@ -132,6 +136,12 @@ def run_field(ctx, nrs, synth, dev, reps=40):
     call_ms = e0.elapsed_time(e1) / reps
     pairs = float(P) * Q
     tflops = FIELD_FLOPS_PER_PAIR * pairs / (call_ms / 1e3) / 1e12
+    import hashlib
+    fsrc = os.path.join(ROOT, "paper_2001_06468_amd", "csrc", "field.hip")
+    fh = hashlib.sha256(open(fsrc, "rb").read()).hexdigest()[:16]
+    traffic = (FIELD_TRAFFIC["bytes_per_call"]
+               if fh == FIELD_TRAFFIC["source_sha256_16"] and Q == FIELD_TRAFFIC["Q"]
+               and P == FIELD_TRAFFIC["tracers"] else None)
     yt = y.clone()
     nrs.nrs_tracer_rk4_step(ctx, flows, fs, yt, dt, ws)
     torch.cuda.synchronize()
@@ -147,7 +157,7 @@ def run_field(ctx, nrs, synth, dev, reps=40):
             "roofline": {"kernel": "nrs_field_velocity (k_field_sources + k_field_part + "
                                    "k_field_sum)", "bound": "alu", "achieved": tflops,
                          "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                         "frac": tflops / PEAK_FP64_TFLOPS, "traffic": None,
+                         "frac": tflops / PEAK_FP64_TFLOPS, "traffic": traffic,
                          "flops_per_pair": FIELD_FLOPS_PER_PAIR},
             "tracer_rk4_ms_per_step": step_ms, "tracer_rk4_steps_per_s": 1e3 / step_ms,
             "note": "FP64; flops counted as 32 per (tracer, quadrature point) pair with the "
@@ -291,6 +301,8 @@ def main():
                     help="time only the batched workload (profiling)")
     ap.add_argument("--no-field", action="store_true",
                     help="skip the flow-at-tracers workload")
+    ap.add_argument("--field-only", action="store_true",
+                    help="time only the flow-at-tracers workload (profiling)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -342,6 +354,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.field_only:
+        print(json.dumps({"field": run_field(ctx, nrs, synth, dev)}), flush=True)
+        return
 
     if args.batch_only:
         print(json.dumps({"batched": run_batched(ctx, nrs, synth, max(args.batch, 1), dev,

@@ -30,6 +30,8 @@ __all__ = [
     "nrs_mlp_body_offsets", "nrs_mlp_features", "nrs_mlp_forward", "nrs_mlp_grad",
     "nrs_mlp_grad_workspace_size", "nrs_adam_step", "nrs_mlp_targets",
     "nrs_mlp_warm_start_workspace_size", "nrs_mlp_warm_start", "nrs_mlp_status",
+    "nrs_field_workspace_size", "nrs_field_velocity", "nrs_tracer_rk4_step",
+    "nrs_rk4_tracers_workspace_size", "nrs_rk4_step_tracers",
 ]
 
 

@@ -23,16 +23,14 @@ namespace {
 constexpr int kFieldThreads = 256;  // four waves, one field point per lane
 constexpr int kFieldWaves = kFieldThreads / 64;
 
-// 1/sqrt(d) for d > 0: the hardware estimate refined by two Newton steps on
-// r^-2 = d, r <- r + r (1/2 - (d/2) r^2), each of which roughly doubles the
-// number of correct bits; the result is within rounding of the correctly
-// rounded value.
-__device__ inline double rsqrt_newton(double d) {
-  double r = __builtin_amdgcn_rsq(d);
-  const double hd = 0.5 * d;
-#pragma unroll
-  for (int it = 0; it < 2; ++it) r = fma(r, fma(-(hd * r), r, 0.5), r);
-  return r;
+// 1/sqrt(d) for d > 0: the hardware estimate r0 (relative error about
+// 2^-23) corrected by the series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + O(e^3)
+// with e = 1 - d r0^2, i.e. one third-order step; the neglected terms are
+// about 2^-69, so the result is within rounding of the correctly rounded value.
+__device__ inline double rsqrt_refined(double d) {
+  const double r0 = __builtin_amdgcn_rsq(d);
+  const double e = fma(-(d * r0), r0, 1.0);
+  return fma(r0 * e, fma(e, 0.375, 0.5), r0);
 }
 
 // Eight lanes per record, one double each, so that consecutive lanes store
@@ -54,21 +52,33 @@ __global__ void k_field_sources(int64_t N, int64_t Q, const double* __restrict__
   src[i] = v;
 }
 
-// Workgroup b takes chunk (b mod chunks) of the sources and field-point block
-// (b div chunks): consecutive workgroups land on different XCDs and read
-// disjoint chunks, so each XCD's L2 holds only its share of the records.
-// Wave w sums a contiguous quarter of the chunk; the four wave sums are added
-// in a fixed order.  With K != NULL the field points are the RK stage
-// positions y + c K.
+// Workgroups are dealt to the eight XCDs in turn (XCD = b mod 8).  With at
+// least eight chunks, workgroup b = 8 (pb + pblocks k) + x takes field-point
+// block pb and chunk 8k + x, so every workgroup that reads chunk ch runs on
+// XCD ch mod 8 and each XCD's L2 holds only its eighth of the records
+// (workgroups past the last chunk exit at once).  With fewer chunks,
+// workgroup b takes chunk b mod chunks of block b div chunks.  Wave w sums a
+// contiguous quarter of the chunk; the four wave sums are added in a fixed
+// order.  With K != NULL the field points are the RK stage positions y + c K.
 __global__ __launch_bounds__(kFieldThreads) void k_field_part(
-    int64_t P, int64_t Q, int32_t chunks, int64_t chunk, const double* __restrict__ y,
-    const double* __restrict__ K, double c, const FieldSrc* __restrict__ src, double eps2,
-    double* __restrict__ part) {
+    int64_t P, int64_t Q, int64_t pblocks, int32_t chunks, int64_t chunk,
+    const double* __restrict__ y, const double* __restrict__ K, double c,
+    const FieldSrc* __restrict__ src, double eps2, double* __restrict__ part) {
   __shared__ double red[3][kFieldWaves][64];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int32_t ch = blockIdx.x % chunks;
-  const int64_t p = (int64_t)(blockIdx.x / chunks) * 64 + lane;
+  int32_t ch;
+  int64_t pb;
+  if (chunks >= 8) {
+    const int64_t j = blockIdx.x >> 3;
+    pb = j % pblocks;
+    ch = 8 * (int32_t)(j / pblocks) + (int32_t)(blockIdx.x & 7);
+    if (ch >= chunks) return;
+  } else {
+    ch = blockIdx.x % chunks;
+    pb = blockIdx.x / chunks;
+  }
+  const int64_t p = pb * 64 + lane;
   double px = 0.0, py = 0.0, pz = 0.0;
   if (p < P) {
     px = y[p];
@@ -80,18 +90,21 @@ __global__ __launch_bounds__(kFieldThreads) void k_field_part(
       pz += c * K[2 * P + p];
     }
   }
+  // this wave's records [a, a + cnt) (Q < 2^31), kept wave-uniform
   const int64_t q0 = (int64_t)ch * chunk;
   const int64_t q1 = min<int64_t>(Q, q0 + chunk);
   const int64_t per = (q1 - q0 + kFieldWaves - 1) / kFieldWaves;
-  const int64_t a = min<int64_t>(q1, q0 + w * per);
-  const int64_t b = min<int64_t>(q1, a + per);
+  const int64_t a64 = min<int64_t>(q1, q0 + w * per);
+  const int a = __builtin_amdgcn_readfirstlane((int)a64);
+  const int cnt = __builtin_amdgcn_readfirstlane((int)(min<int64_t>(q1, a64 + per) - a64));
+  const FieldSrc* __restrict__ sw = src + a;
   double ux = 0.0, uy = 0.0, uz = 0.0;
 #pragma unroll 2
-  for (int64_t q = a; q < b; ++q) {
-    const FieldSrc s = src[q];
+  for (int k = 0; k < cnt; ++k) {
+    const FieldSrc s = sw[k];
     const double rx = px - s.X, ry = py - s.Y, rz = pz - s.Z;
     const double d = fma(rz, rz, fma(ry, ry, fma(rx, rx, eps2)));
-    const double r = rsqrt_newton(d);                            // (|r|^2 + eps^2)^(-1/2)
+    const double r = rsqrt_refined(d);                           // (|r|^2 + eps^2)^(-1/2)
     const double t = r * r * r;                                  // (|r|^2 + eps^2)^(-3/2)
     const double rg = fma(rz, s.gz, fma(ry, s.gy, rx * s.gx));  // r . g
     const double al = fma(t, eps2, r);                           // (|r|^2 + 2 eps^2) t
@@ -164,6 +177,7 @@ FieldPlan field_plan(int64_t P, int64_t Q) {
   int64_t c = 2048 / std::max<int64_t>(fp.pblocks, 1);
   c = std::min<int64_t>(c, std::max<int64_t>(1, Q / 256));
   c = std::max<int64_t>(1, std::min<int64_t>(c, 1024));
+  if (c >= 8) c -= c % 8;  // whole rounds of the eight XCDs
   fp.cap = (int32_t)c;
   fp.chunk = (Q + c - 1) / c;
   fp.chunks = (int32_t)((Q + fp.chunk - 1) / fp.chunk);
@@ -182,9 +196,10 @@ hipError_t launch_field(const FieldPlan& fp, int64_t P, int64_t Q, const double*
                         const double* K, double c, const FieldSrc* src, double eps, double mu,
                         double* part, double* u, hipStream_t s) {
   if (P <= 0) return hipSuccess;
-  const unsigned grid = (unsigned)(fp.pblocks * fp.chunks);
-  hipLaunchKernelGGL(k_field_part, dim3(grid), dim3(kFieldThreads), 0, s, P, Q, fp.chunks,
-                     fp.chunk, y, K, c, src, eps * eps, part);
+  const int64_t slots = fp.chunks >= 8 ? 8 * ((fp.chunks + 7) / 8) : fp.chunks;
+  const unsigned grid = (unsigned)(fp.pblocks * slots);
+  hipLaunchKernelGGL(k_field_part, dim3(grid), dim3(kFieldThreads), 0, s, P, Q, fp.pblocks,
+                     fp.chunks, fp.chunk, y, K, c, src, eps * eps, part);
   hipLaunchKernelGGL(k_field_sum, dim3((unsigned)((3 * P + 63) / 64)), dim3(kSumWaves * 64), 0, s,
                      3 * P, fp.chunks, part, 1.0 / (8.0 * kPi * mu), u);
   return hipGetLastError();
