@@ -59,6 +59,9 @@ typedef int32_t nrs_status;
 #define NRS_FP32_IR        1  /* FP32 assembly + FP32 block-pivoted LU, FP64 refinement */
 #define NRS_FP32_GEPP_IR   2  /* as NRS_FP32_IR but with full partial pivoting          */
 #define NRS_GMRES          3  /* FP64 GMRES(m) on the stored FP64 matrix, from x_init   */
+#define NRS_FP32_GMRES_IR  4  /* FP32 assembly + FP32 tile LU (static block pivoting),
+                                 then flexible GMRES(m) in FP64 on the matrix-free
+                                 operator with the LU as right preconditioner        */
 
 typedef struct nrs_ctx nrs_ctx;
 
@@ -133,13 +136,16 @@ typedef struct {
 } nrs_problem;
 
 typedef struct {
-  int32_t method;        /* NRS_FP64_LU, NRS_FP32_IR, NRS_FP32_GEPP_IR, NRS_GMRES */
+  int32_t method;        /* NRS_FP64_LU, NRS_FP32_IR, NRS_FP32_GEPP_IR, NRS_GMRES,
+                            NRS_FP32_GMRES_IR                                    */
   int32_t max_refine;    /* refinement sweeps (IR) before falling back; <=0: 6   */
   double  tol;           /* IR: stop when |d|_inf <= tol |x|_inf, <=0: 1e-9.
                             GMRES: relative residual |b - A x|_2 <= tol |b|_2,
-                            <=0: 1e-11                                          */
-  int32_t gmres_restart; /* GMRES(m) restart length 1..63, <=0: 50              */
-  int32_t gmres_max_iter;/* total GMRES iterations before LU fallback, <=0: 1000 */
+                            <=0: 1e-11 (NRS_GMRES), 1e-12 (NRS_FP32_GMRES_IR)  */
+  int32_t gmres_restart; /* GMRES(m) restart length 1..63, <=0: 50 (NRS_GMRES),
+                            30 (NRS_FP32_GMRES_IR)                              */
+  int32_t gmres_max_iter;/* total GMRES iterations before LU fallback, <=0: 1000
+                            (NRS_GMRES), 300 (NRS_FP32_GMRES_IR)               */
   int32_t no_fallback;   /* 1 = report failure instead of falling back to FP64 LU */
   const double* x_init;  /* [n] device initial guess for NRS_GMRES (NULL = zero); may
                             equal sol (start from sol's current content)       */
@@ -203,6 +209,14 @@ nrs_status nrs_apply(nrs_ctx* ctx, const nrs_problem* pb, const double* v, doubl
 
 /* Solve A sol = b, b = [u_x; u_y; u_z; (F_ext, T_ext) per body], for the
  * force densities and rigid-body velocities (Sec. 4, step 3).
+ * NRS_FP32_IR refines the FP32 solution with FP64 residuals; in the
+ * synchronous form (info != NULL), if the refinement stalls (the static
+ * block pivots can leave the FP32 factors too inexact for plain refinement
+ * on large wall-bounded systems), it continues from its iterate with the
+ * flexible GMRES of NRS_FP32_GMRES_IR on the same factors (relative residual
+ * 1e-12) before any FP64 fallback; info->iterations then counts both.
+ * NRS_FP32_GMRES_IR synchronises with the host once every few GMRES steps
+ * even in the asynchronous form.
  * u: [3][N] prescribed velocities; ftext: [M][6] external force and torque
  * (NULL = force- and torque-free); sol: [n] output.
  * With info == NULL the call is fully asynchronous; numerical status then

@@ -147,11 +147,16 @@ def nearest(x, X, group_off, groupX):
             continue
         if hi <= lo:
             raise ValueError(f"group {g} has quadrature points but no force points")
-        dx = x[0, lo:hi][None, :] - X[0, qs][:, None]
-        dy = x[1, lo:hi][None, :] - X[1, qs][:, None]
-        dz = x[2, lo:hi][None, :] - X[2, qs][:, None]
-        d2 = dx * dx + dy * dy + dz * dz
-        nu[qs] = lo + np.argmin(d2, axis=1)
+        # quadrature points taken in blocks only to bound memory; each q's
+        # argmin is computed on its own
+        step = max(1, (1 << 24) // (hi - lo))
+        for a in range(0, qs.size, step):
+            qb = qs[a:a + step]
+            dx = x[0, lo:hi][None, :] - X[0, qb][:, None]
+            dy = x[1, lo:hi][None, :] - X[1, qb][:, None]
+            dz = x[2, lo:hi][None, :] - X[2, qb][:, None]
+            d2 = dx * dx + dy * dy + dz * dz
+            nu[qb] = lo + np.argmin(d2, axis=1)
     return nu
 
 

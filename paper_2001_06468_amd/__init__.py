@@ -16,7 +16,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (NRS_FP32_GEPP_IR, NRS_FP32_IR, NRS_FP64_LU, NRS_GMRES,  # noqa: F401
+from ._lib import (NRS_FP32_GEPP_IR, NRS_FP32_GMRES_IR, NRS_FP32_IR, NRS_FP64_LU,  # noqa: F401
+                   NRS_GMRES,
                    NRS_MLP_HIDDEN, NRS_MLP_MAX_POINTS, NRS_WARM_MODEL, NRS_WARM_NONE,
                    NRS_WARM_PREVIOUS, NrsInfo, NrsOptions, NrsProblem, NrsScene)
 
@@ -24,7 +25,7 @@ __all__ = [
     "NrsError", "Context", "DeviceScene", "Problem", "nrs_create", "nrs_version", "nrs_geometry",
     "nrs_nearest", "nrs_workspace_size", "nrs_assemble", "nrs_apply", "nrs_solve",
     "nrs_query_info", "nrs_solve_batched_workspace_size", "nrs_solve_batched", "nrs_lu_factor", "nrs_lu_solve", "nrs_rk4_workspace_size", "nrs_rk4_step",
-    "NRS_FP64_LU", "NRS_FP32_IR", "NRS_FP32_GEPP_IR", "NRS_GMRES", "lda_for",
+    "NRS_FP64_LU", "NRS_FP32_IR", "NRS_FP32_GEPP_IR", "NRS_GMRES", "NRS_FP32_GMRES_IR", "lda_for",
     "NRS_WARM_NONE", "NRS_WARM_PREVIOUS", "NRS_WARM_MODEL", "Model", "nrs_mlp_param_count",
     "nrs_autotune", "nrs_autotune_clear",
     "nrs_mlp_body_offsets", "nrs_mlp_features", "nrs_mlp_forward", "nrs_mlp_grad",

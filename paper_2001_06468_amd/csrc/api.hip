@@ -39,7 +39,12 @@ int32_t apply_chunks(int64_t N, int64_t Q) {
   return (int32_t)c;
 }
 
-bool uses_fp32(int32_t method) { return method == NRS_FP32_IR || method == NRS_FP32_GEPP_IR; }
+bool uses_fp32(int32_t method) {
+  return method == NRS_FP32_IR || method == NRS_FP32_GEPP_IR || method == NRS_FP32_GMRES_IR;
+}
+// methods whose single-system solves can run the flexible GMRES on the FP32 factors
+bool uses_fgmres(int32_t method) { return method == NRS_FP32_IR || method == NRS_FP32_GMRES_IR; }
+constexpr double kFgmresTol = 1e-12;
 
 // Grow the context's zero-initialised synchronisation words to fit order n:
 // the triangular-solve words and, separately, the tile-LU words.
@@ -126,8 +131,15 @@ bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, Sol
   sb.lu_done = ar.take<int32_t>(lu_tiles_nt(n) * lu_tiles_nt(n));
   sb.AT = sb.V = sb.gw0 = sb.gw1 = sb.gpart = nullptr;
   sb.gst = nullptr;
-  if (method == NRS_GMRES) {
-    sb.AT = ar.take<double>((size_t)sb.lda * n);
+  sb.Z = sb.fzv = sb.fax = nullptr;
+  const bool fg = with64 && uses_fgmres(method);
+  if (fg) {
+    sb.Z = ar.take<double>((size_t)n * kGmresLd);
+    sb.fzv = ar.take<double>(n);
+    sb.fax = ar.take<double>(n);
+  }
+  if (method == NRS_GMRES || fg) {
+    if (method == NRS_GMRES) sb.AT = ar.take<double>((size_t)sb.lda * n);
     sb.V = ar.take<double>((size_t)n * kGmresLd);
     sb.gw0 = ar.take<double>(n);
     sb.gw1 = ar.take<double>(n);
@@ -241,6 +253,62 @@ nrs_status run_gmres(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, doub
   return NRS_OK;
 }
 
+// Flexible GMRES(m) in FP64 from the iterate in x (GMRES-IR): the operator is
+// the matrix-free FP64 product, the right preconditioner the FP32 tile-LU
+// factors in sb.A32 (two triangular passes per step).  Queues kChunk steps
+// between host checks; every launch queued behind a finished cycle skips
+// (the state's halt word).  Reports into sb.st (iterations are added).
+nrs_status run_fgmres(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, double* x,
+                      const nrs_options& o, hipStream_t s) {
+  const int64_t n = 3 * pb.N + 6 * (int64_t)pb.M;
+  const int32_t m = (o.gmres_restart > 0 && o.gmres_restart < kGmresLd) ? o.gmres_restart : 30;
+  const int32_t max_iter = o.gmres_max_iter > 0 ? o.gmres_max_iter : 300;
+  const double tol = (o.method == NRS_FP32_GMRES_IR && o.tol > 0) ? o.tol : kFgmresTol;
+  float* v32 = reinterpret_cast<float*>(sb.r);
+  GmresArgs a;
+  a.n = n;
+  a.ld = kGmresLd;
+  a.AT = nullptr;
+  a.b = sb.b;
+  a.x = x;
+  a.V = sb.V;
+  a.Z = sb.Z;
+  a.w0 = sb.gw0;
+  a.w1 = sb.gw1;
+  a.part = sb.gpart;
+  a.st = sb.gst;
+  const int32_t* halt = &sb.gst->halt;
+  NRS_HIP(ctx, launch_gmres_init(sb.gst, tol, m, max_iter, s));
+  NRS_HIP(ctx, launch_apply(pb, sb.srt, x, sb.fax, sb.part, sb.chunks, nullptr, s));
+  NRS_HIP(ctx, launch_fgmres_residual(a, sb.fax, s));
+  struct Hdr {
+    int32_t done, stop, fail, k, iters;
+  } h;
+  constexpr int kChunk = 4;
+  for (;;) {
+    for (int i = 0; i < kChunk; ++i) {
+      NRS_HIP(ctx, launch_fgmres_begin(a, v32, s));
+      NRS_HIP(ctx, launch_lu_solve<float>(n, 1, sb.A32, sb.lda, sb.perm, v32, sb.d32, sb.tsync,
+                                          &sb.st->sync_err, halt, s));
+      NRS_HIP(ctx, launch_fgmres_zstore(a, sb.d32, sb.fzv, s));
+      NRS_HIP(ctx, launch_apply(pb, sb.srt, sb.fzv, sb.d64, sb.part, sb.chunks, halt, s));
+      NRS_HIP(ctx, launch_fgmres_orth(a, sb.d64, s));
+    }
+    NRS_HIP(ctx, hipMemcpyAsync(&h, sb.gst, sizeof(h), hipMemcpyDeviceToHost, s));
+    NRS_HIP(ctx, hipStreamSynchronize(s));
+    if (h.fail || h.done) break;
+    if (!h.stop) continue;
+    NRS_HIP(ctx, launch_gmres_update(a, s));
+    NRS_HIP(ctx, launch_apply(pb, sb.srt, x, sb.fax, sb.part, sb.chunks, nullptr, s));
+    NRS_HIP(ctx, launch_fgmres_residual(a, sb.fax, s));
+    NRS_HIP(ctx, hipMemcpyAsync(&h, sb.gst, sizeof(h), hipMemcpyDeviceToHost, s));
+    NRS_HIP(ctx, hipStreamSynchronize(s));
+    if (h.fail || h.done || h.iters >= max_iter) break;
+  }
+  NRS_HIP(ctx, launch_fgmres_report(sb.st, sb.gst, s));
+  return NRS_OK;
+}
+
 nrs_status read_state(nrs_ctx* ctx, const SolveState* dst, SolveState& hst) {
   NRS_HIP(ctx, hipMemcpyAsync(&hst, dst, sizeof(SolveState), hipMemcpyDeviceToHost, ctx->stream));
   NRS_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -277,7 +345,10 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
   if (method == NRS_FP64_LU) {
     st = run_fp64_lu(ctx, pb, sb, sol, sync, s);
   } else if (uses_fp32(method)) {
-    st = run_fp32_ir(ctx, pb, sb, sol, method == NRS_FP32_IR ? 1 : 0, max_refine, tol, sync, s);
+    const bool fgm = method == NRS_FP32_GMRES_IR;
+    st = run_fp32_ir(ctx, pb, sb, sol, method == NRS_FP32_GEPP_IR ? 0 : 1, fgm ? 0 : max_refine,
+                     tol, sync, s);
+    if (st == NRS_OK && fgm) st = run_fgmres(ctx, pb, sb, sol, o, s);
   } else if (method == NRS_GMRES) {
     st = run_gmres(ctx, pb, sb, sol, o, sync, s);
   } else {
@@ -290,6 +361,12 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
   if (h.nonfinite == 2)
     return fail(ctx, NRS_E_ARG, "nu outside [0, N) or body outside [-1, M)");
   bool ok = method == NRS_FP64_LU ? true : (h.converged && !h.failed);
+  if (!ok && method == NRS_FP32_IR && sb.Z && !h.nonfinite && !h.sync_err && !h.lu_ctl[2]) {
+    // the refinement stalled: GMRES-IR from its iterate on the same factors
+    if ((st = run_fgmres(ctx, pb, sb, sol, o, s)) != NRS_OK) return st;
+    if ((st = read_state(ctx, sb.st, h)) != NRS_OK) return st;
+    ok = h.converged && !h.failed;
+  }
   if (!ok && !o.no_fallback) {
     NRS_HIP(ctx, launch_state_init(sb.st, NRS_FP64_LU, s));
     if ((st = run_fp64_lu(ctx, pb, sb, sol, true, s)) != NRS_OK) return st;
@@ -417,7 +494,7 @@ nrs_status nrs_nearest(nrs_ctx* ctx, int64_t N, const double* x, int32_t G,
 nrs_status nrs_workspace_size(nrs_ctx* ctx, int64_t N, int64_t Q, int32_t M, int32_t method,
                               size_t* bytes) {
   if (!bytes || N <= 0 || Q <= 0 || M < 0) return fail(ctx, NRS_E_ARG, "bad sizes");
-  if (method < NRS_FP64_LU || method > NRS_GMRES)
+  if (method < NRS_FP64_LU || method > NRS_FP32_GMRES_IR)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
   *bytes = solve_workspace_bytes(N, Q, M, method);
   return NRS_OK;
@@ -476,9 +553,9 @@ nrs_status nrs_solve(nrs_ctx* ctx, const nrs_problem* pb, const double* u, const
   nrs_options o = {};
   o.method = NRS_FP64_LU;
   if (opt) o = *opt;
-  if (o.method < NRS_FP64_LU || o.method > NRS_GMRES)
+  if (o.method < NRS_FP64_LU || o.method > NRS_FP32_GMRES_IR)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
-  if (o.method == NRS_GMRES && o.gmres_restart >= kGmresLd)
+  if ((o.method == NRS_GMRES || o.method == NRS_FP32_GMRES_IR) && o.gmres_restart >= kGmresLd)
     return fail(ctx, NRS_E_UNSUPPORTED, "GMRES restart length must be below 64");
   Arena ar(ws, ws_bytes);
   SolveBuffers sb;
@@ -795,7 +872,7 @@ nrs_status nrs_rk4_tracers_workspace_size(nrs_ctx* ctx, const nrs_scene* sc, int
   if (st) return st;
   if (!bytes) return fail(ctx, NRS_E_ARG, "bytes is NULL");
   if (P < 0 || P > kMaxFieldPoints) return fail(ctx, NRS_E_ARG, "tracer count out of range");
-  if (method < NRS_FP64_LU || method > NRS_GMRES)
+  if (method < NRS_FP64_LU || method > NRS_FP32_GMRES_IR)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
   Arena ar(nullptr, 0);
   RkBuffers rb;
@@ -833,9 +910,9 @@ nrs_status nrs_rk4_step_tracers(nrs_ctx* ctx, const nrs_scene* sc, int32_t G,
   nrs_options o = {};
   o.method = NRS_FP64_LU;
   if (opt) o = *opt;
-  if (o.method < NRS_FP64_LU || o.method > NRS_GMRES)
+  if (o.method < NRS_FP64_LU || o.method > NRS_FP32_GMRES_IR)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
-  if (o.method == NRS_GMRES && o.gmres_restart >= kGmresLd)
+  if ((o.method == NRS_GMRES || o.method == NRS_FP32_GMRES_IR) && o.gmres_restart >= kGmresLd)
     return fail(ctx, NRS_E_UNSUPPORTED, "GMRES restart length must be below 64");
   Arena ar(ws, ws_bytes);
   RkBuffers rb;

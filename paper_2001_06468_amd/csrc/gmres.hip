@@ -146,6 +146,7 @@ __global__ __launch_bounds__(kThreads) void k_gm_residual(GmresArgs a) {
       st->stop = 0;
       st->cur = 0;   // w0 holds the unnormalised first basis vector
     }
+    st->halt = st->done | st->stop | st->fail;
   }
 }
 
@@ -261,6 +262,7 @@ __global__ __launch_bounds__(kThreads) void k_gm_orth(GmresArgs a) {
              st->iters >= st->max_iter) {
     st->stop = 1;
   }
+  st->halt = st->done | st->stop | st->fail;
 }
 
 // End of a cycle: y = R^-1 g (upper triangular, k x k, solved redundantly in
@@ -286,13 +288,141 @@ __global__ __launch_bounds__(kThreads) void k_gm_update(GmresArgs a) {
   }
   __syncthreads();
   const double yl = s_y[lane];
+  const double* __restrict__ basis = a.Z ? a.Z : a.V;   // x += Z y (flexible) or V y
   for (int64_t r = (int64_t)blockIdx.x * kWavesG + w; r < a.n;
        r += (int64_t)gridDim.x * kWavesG) {
     {
-      const double vi = lane < k ? a.V[r * kGmresLd + lane] : 0.0;
+      const double vi = lane < k ? basis[r * kGmresLd + lane] : 0.0;
       const double d = wave_sum_d(vi * yl);
       if (lane == 0) a.x[r] += d;
     }
+  }
+}
+
+// ---- flexible GMRES (Saad, 1993) with the low-precision LU as right
+// preconditioner: x = x0 + Z y with z_k = M^-1 v_k; the operator products
+// A x and A z_k come from the matrix-free FP64 product, so no FP64 matrix is
+// stored.  The Arnoldi bookkeeping (CGS2, Givens rotations, stop rules) is the
+// same as above. ----
+
+// r = b - Ax into w0, |r|^2 and |b|^2 partials (one row per thread); the last
+// block decides convergence or starts a cycle, as k_gm_residual.
+__global__ __launch_bounds__(kThreads) void k_fg_residual(GmresArgs a,
+                                                         const double* __restrict__ Ax) {
+  GmresState* st = a.st;
+  if (st->done | st->fail) return;
+  __shared__ double s_p[kWavesG][2];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double acc = 0.0, accb = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < a.n;
+       r += (int64_t)gridDim.x * kThreads) {
+    const double br = a.b[r];
+    const double rr = br - Ax[r];
+    a.w0[r] = rr;
+    acc = fma(rr, rr, acc);
+    accb = fma(br, br, accb);
+  }
+  acc = wave_sum_d(acc);
+  accb = wave_sum_d(accb);
+  if (lane == 0) {
+    s_p[w][0] = acc;
+    s_p[w][1] = accb;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    double t = 0.0;
+    for (int q = 0; q < kWavesG; ++q) t += s_p[q][threadIdx.x];
+    a.part[(int64_t)blockIdx.x * kGmresLd + threadIdx.x] = t;
+  }
+  if (!last_block(&st->counter)) return;
+  __shared__ double s_r[2];
+  reduce_partials(a.part, gridDim.x, 2, s_r);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st->counter = 0;
+    const double beta = sqrt(s_r[0]);
+    if (st->bnorm < 0.0) st->bnorm = sqrt(s_r[1]);
+    st->beta = beta;
+    if (!isfinite(beta)) {
+      st->fail = 1;
+    } else if (beta <= st->tol * st->bnorm) {
+      st->done = 1;
+    } else {
+      st->nrm = beta;
+      st->g[0] = beta;
+      st->k = 0;
+      st->stop = 0;
+      st->cur = 0;
+    }
+    st->halt = st->done | st->stop | st->fail;
+  }
+}
+
+// v_k = w_cur / nrm into V[:, k], and its FP32 copy for the preconditioner.
+__global__ void k_fg_begin(GmresArgs a, float* __restrict__ v32) {
+  const GmresState* st = a.st;
+  if (st->halt) return;
+  const int k = st->k;
+  const double* __restrict__ vin = st->cur ? a.w1 : a.w0;
+  const double s = 1.0 / st->nrm;
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r < a.n) {
+    const double v = vin[r] * s;
+    a.V[r * kGmresLd + k] = v;
+    v32[r] = (float)v;
+  }
+}
+
+// z_k = M^-1 v_k (FP32 result of the triangular solves) into Z[:, k] and zv.
+__global__ void k_fg_zstore(GmresArgs a, const float* __restrict__ d32, double* __restrict__ zv) {
+  const GmresState* st = a.st;
+  if (st->halt) return;
+  const int k = st->k;
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r < a.n) {
+    const double z = (double)d32[r];
+    a.Z[r * kGmresLd + k] = z;
+    zv[r] = z;
+  }
+}
+
+// w = A z_k (given) into the next basis buffer; partial dots V[:, 0..k]^T w,
+// reduced by the last block into h1 (the first Gram-Schmidt pass).
+__global__ __launch_bounds__(kThreads) void k_fg_dots(GmresArgs a, const double* __restrict__ Aw) {
+  GmresState* st = a.st;
+  if (st->halt) return;
+  const int k = st->k;
+  double* __restrict__ wout = st->cur ? a.w0 : a.w1;
+  __shared__ double s_p[kWavesG][kGmresLd];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double acc = 0.0;
+  for (int64_t r = (int64_t)blockIdx.x * kWavesG + w; r < a.n;
+       r += (int64_t)gridDim.x * kWavesG) {
+    const double y = Aw[r];
+    if (lane == 0) wout[r] = y;
+    const double vi = lane <= k ? a.V[r * kGmresLd + lane] : 0.0;
+    acc = fma(vi, y, acc);
+  }
+  s_p[w][lane] = acc;
+  __syncthreads();
+  if (w == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kWavesG; ++q) t += s_p[q][lane];
+    a.part[(int64_t)blockIdx.x * kGmresLd + lane] = t;
+  }
+  if (!last_block(&st->counter)) return;
+  reduce_partials(a.part, gridDim.x, k + 1, st->h1);
+  __syncthreads();
+  if (threadIdx.x == 0) st->counter = 0;
+}
+
+__global__ void k_fg_report(SolveState* st, const GmresState* g) {
+  if (threadIdx.x == 0) {
+    st->converged = g->done;
+    st->failed = !g->done;
+    st->iterations += g->iters;
+    if (g->fail) st->nonfinite |= 1;
+    st->corr = g->bnorm > 0.0 ? g->beta / g->bnorm : 0.0;
   }
 }
 
@@ -464,6 +594,7 @@ __global__ void k_gm_init(GmresState* st, double tol, int32_t m, int32_t max_ite
     st->bnorm = -1.0;
     st->beta = 0.0;
     st->nrm = 1.0;
+    st->halt = 0;
   }
 }
 
@@ -536,6 +667,35 @@ hipError_t launch_gmres_steps(const GmresArgs& a, int32_t count, hipStream_t s) 
     hipLaunchKernelGGL(k_gm_orth<false>, g, dim3(kThreads), 0, s, a);
     hipLaunchKernelGGL(k_gm_orth<true>, g, dim3(kThreads), 0, s, a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_fgmres_residual(const GmresArgs& a, const double* Ax, hipStream_t s) {
+  hipLaunchKernelGGL(k_fg_residual, dim3((unsigned)gmres_blocks(a.n)), dim3(kThreads), 0, s, a, Ax);
+  return hipGetLastError();
+}
+
+hipError_t launch_fgmres_begin(const GmresArgs& a, float* v32, hipStream_t s) {
+  hipLaunchKernelGGL(k_fg_begin, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, v32);
+  return hipGetLastError();
+}
+
+hipError_t launch_fgmres_zstore(const GmresArgs& a, const float* d32, double* zv, hipStream_t s) {
+  hipLaunchKernelGGL(k_fg_zstore, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, d32,
+                     zv);
+  return hipGetLastError();
+}
+
+hipError_t launch_fgmres_orth(const GmresArgs& a, const double* Aw, hipStream_t s) {
+  const dim3 g((unsigned)gmres_blocks(a.n));
+  hipLaunchKernelGGL(k_fg_dots, g, dim3(kThreads), 0, s, a, Aw);
+  hipLaunchKernelGGL(k_gm_orth<false>, g, dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(k_gm_orth<true>, g, dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fgmres_report(SolveState* st, const GmresState* g, hipStream_t s) {
+  hipLaunchKernelGGL(k_fg_report, dim3(1), dim3(64), 0, s, st, g);
   return hipGetLastError();
 }
 

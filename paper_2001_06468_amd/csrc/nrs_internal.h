@@ -163,6 +163,9 @@ struct SolveBuffers {
   double* gw1;
   double* gpart;
   struct GmresState* gst;
+  double* Z;         // flexible GMRES: preconditioned basis [n][kGmresLd]
+  double* fzv;       // [n] z_k, the operator's input
+  double* fax;       // [n] A x for the true residual
 };
 
 size_t solve_workspace_bytes(int64_t N, int64_t Q, int32_t M, int32_t method);
@@ -266,7 +269,8 @@ struct GmresState {
   int32_t iters;      // total Arnoldi steps
   int32_t cur;        // which w buffer holds the next (unnormalised) basis vector
   int32_t counter;    // last-workgroup ticket (zero between launches)
-  int32_t m, max_iter, pad;
+  int32_t m, max_iter;
+  int32_t halt;       // done | stop | fail: launches queued behind a finished cycle skip
   double tol, bnorm, beta, nrm;
   double g[kGmresLd + 1], cs[kGmresLd], sn[kGmresLd], h1[kGmresLd], h2[kGmresLd];
   double H[(kGmresLd + 1) * kGmresLd];   // column-major, leading dimension kGmresLd + 1
@@ -277,6 +281,7 @@ struct GmresArgs {
   const double* b;
   double* x;
   double* V;          // [n][kGmresLd]
+  double* Z;          // [n][kGmresLd] preconditioned basis (flexible GMRES), else NULL
   double* w0;
   double* w1;
   double* part;       // [gmres_blocks(n)][kGmresLd]
@@ -290,6 +295,16 @@ hipError_t launch_gmres_init(GmresState* st, double tol, int32_t m, int32_t max_
 hipError_t launch_gmres_residual(const GmresArgs& a, hipStream_t s);
 hipError_t launch_gmres_steps(const GmresArgs& a, int32_t count, hipStream_t s);
 hipError_t launch_gmres_update(const GmresArgs& a, hipStream_t s);
+// Flexible GMRES with a preconditioner between the Arnoldi steps (GMRES-IR):
+// the operator products are computed outside (Ax, Aw given), the preconditioner
+// input is v32 (FP32 copy of the new basis vector) and its output d32.
+hipError_t launch_fgmres_residual(const GmresArgs& a, const double* Ax, hipStream_t s);
+hipError_t launch_fgmres_begin(const GmresArgs& a, float* v32, hipStream_t s);
+hipError_t launch_fgmres_zstore(const GmresArgs& a, const float* d32, double* zv, hipStream_t s);
+// Aw = A z_k: into the next basis buffer, dots with V, then the two CGS passes
+hipError_t launch_fgmres_orth(const GmresArgs& a, const double* Aw, hipStream_t s);
+// adds the GMRES iterations to the solve state and reports convergence
+hipError_t launch_fgmres_report(SolveState* st, const GmresState* g, hipStream_t s);
 // Initial-guess completion for swimming problems: project the forces of x0
 // onto the force / torque balance (weights W, targets ftext or zero), then
 // refit every body's (U, Omega) to the velocity residual by least squares.

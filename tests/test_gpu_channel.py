@@ -1,0 +1,111 @@
+"""Channel-with-swimmers configuration at full size: 10 and 40 sperm-like
+swimmers in the 4 x 1 x 0.5 channel (wall spacing 1/16 and 1/24), n = 14,244
+and 39,504 unknowns, solved with FP32 assembly, FP32 tile LU and FP64
+refinement.
+
+A dense FP64 oracle solve at these orders is out of reach of a test, so the
+solution is checked equation by equation: the velocity rows at a seeded
+sample of force points through the oracle's own field sum at those points
+(row m of A_s f is the flow of f at x_m), and every force and torque row.
+Tolerance: each residual within 1e-10 of the sum of the absolute values of
+its terms (the refinement's backward-error target is 1e-12 of |A| |x|, and
+the oracle adds the row's terms in FP64 in a different order).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2001_06468_amd as nrs
+    from gpu_util import T, prepare, gpu_solve
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = nrs.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _row_abs(xs, X, w, nu, f, eps, mu):
+    """(8 pi mu)^-1 sum_q |S^eps(x - X_q)| |w_q f[nu_q]| per point (bound of
+    the absolute terms of a velocity row)."""
+    g = np.linalg.norm(f[:, nu] * w[None, :], axis=0)
+    out = np.zeros(xs.shape[1])
+    for p in range(xs.shape[1]):
+        r2 = np.sum((xs[:, p:p + 1] - X) ** 2, axis=0)
+        out[p] = np.sum((2 * r2 + 2 * eps * eps) / (r2 + eps * eps) ** 1.5 * g)
+    return out / (8 * math.pi * mu)
+
+
+def _check_equations(scene, host, sol, nsample, seed):
+    N, M = scene["N"], scene["M"]
+    f = sol[:3 * N].reshape(3, N)
+    UW = sol[3 * N:].reshape(M, 6)
+    Y = scene["Y0"]
+    rng = np.random.default_rng(seed)
+    pick = np.sort(rng.choice(N, nsample, replace=False))
+    xs = np.ascontiguousarray(host["x"][:, pick])
+    Af = oracle.field_velocity(xs, host["X"], host["w"], host["nu"], f, scene["eps"], scene["mu"])
+    absrow = _row_abs(xs, host["X"], host["w"], host["nu"], f, scene["eps"], scene["mu"])
+    u = host["u"].reshape(3, N)
+    worst = 0.0
+    for k, m in enumerate(pick):
+        b = scene["body"][m]
+        rigid = np.zeros(3)
+        if b >= 0:
+            r = host["x"][:, m] - Y[b, :3]
+            rigid = UW[b, :3] + np.cross(UW[b, 3:], r)
+        res = Af[:, k] - rigid - u[:, m]
+        scale = absrow[k] + np.abs(rigid).max() + np.abs(u[:, m]).max()
+        worst = max(worst, np.abs(res).max() / scale)
+    W = oracle.patch_weights(host["w"], host["nu"], N)
+    for b in range(M):
+        sel = scene["body"] == b
+        Wf = W[sel][None, :] * f[:, sel]
+        r = host["x"][:, sel] - Y[b, :3][:, None]
+        F = Wf.sum(axis=1) - scene["ftext"][b, :3]
+        Tq = np.cross(r.T, Wf.T).sum(axis=0) - scene["ftext"][b, 3:]
+        worst = max(worst, np.abs(F).max() / np.abs(Wf).sum(),
+                    np.abs(Tq).max() / np.abs(np.cross(r.T, Wf.T)).sum())
+    return worst
+
+
+_PREP = {}
+
+
+def _prepared(K, h):
+    """Oracle geometry and nearest map of the channel scene (kept for the
+    second method of the same size)."""
+    if (K, h) not in _PREP:
+        _PREP.clear()
+        scene = synth.sperm_channel_scene(K, h=1.0 / h, seed=0)
+        print(f"channel K={K}: oracle geometry and nearest map", flush=True)
+        pb, host = prepare(scene, 0.0)
+        _PREP[(K, h)] = (scene, pb, host)
+    return _PREP[(K, h)]
+
+
+@pytest.mark.parametrize("K,h,n", [(10, 16, 14244), (40, 24, 39504)], ids=["K10", "K40"])
+@pytest.mark.parametrize("method", ["FP32_GMRES_IR", "FP32_IR"])
+def test_channel_full_size_equations(ctx, K, h, n, method):
+    """FP32_GMRES_IR directly, and FP32_IR, whose refinement stalls at these
+    sizes (contraction about 1/3 per sweep with the static block pivots) and
+    continues with the flexible GMRES on the same factors: no FP64 fallback."""
+    scene, pb, host = _prepared(K, h)
+    N, M = scene["N"], scene["M"]
+    assert 3 * N + 6 * M == n
+    print(f"channel K={K} n={n}: GPU solve {method}", flush=True)
+    sol, info = gpu_solve(ctx, scene, pb, host, getattr(nrs, "NRS_" + method))
+    print(f"channel K={K} n={n}: info {info}", flush=True)
+    assert info["fell_back"] == 0 and info["backward_error"] <= 1e-12, info
+    worst = _check_equations(scene, host, sol, 96 if K == 10 else 48, seed=K)
+    assert worst <= 1e-10, worst

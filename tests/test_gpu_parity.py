@@ -223,7 +223,7 @@ SOLVE_CASES = [
 
 
 @pytest.mark.parametrize("name,mk", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
-@pytest.mark.parametrize("method", ["FP64_LU", "FP32_IR", "FP32_GEPP_IR"])
+@pytest.mark.parametrize("method", ["FP64_LU", "FP32_IR", "FP32_GEPP_IR", "FP32_GMRES_IR"])
 def test_solve_matches_oracle(ctx, name, mk, method):
     scene = mk()
     pb, host = prepare(scene, 0.3)
@@ -237,6 +237,8 @@ def test_solve_matches_oracle(ctx, name, mk, method):
     assert info["backward_error"] <= 1e-12
     if method != "FP64_LU":
         assert info["iterations"] >= 2
+    if method == "FP32_GMRES_IR":
+        assert info["method_used"] == nrs.NRS_FP32_GMRES_IR
 
 
 def test_sphere_drag_on_gpu(ctx):
