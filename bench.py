@@ -165,6 +165,63 @@ def run_field(ctx, nrs, synth, dev, reps=40):
                     "w_q f[nu(q)] and the fixed-order chunk sum"}
 
 
+def run_channel(ctx, nrs, synth, dev):
+    """Channel configuration (10 and 40 sperm-like swimmers in the 4 x 1 x 0.5
+    channel, wall spacing 1/16 and 1/24, n = 14,244 and 39,504): one
+    synchronous solve each with the GMRES-IR forms after a warm-up solve, and
+    the tile LU alone (FP32 updates, and BF16-input updates) timed with HIP
+    events.  Geometry and nearest map on the GPU."""
+    import torch
+    out = []
+    for K, h in ((10, 16), (40, 24)):
+        sc = synth.sperm_channel_scene(K, h=1.0 / h, seed=0)
+        ds = nrs.DeviceScene(sc, dev)
+        Y = torch.from_numpy(sc["Y0"].copy()).to(dev)
+        pb, u = device_problem(ctx, nrs, ds, sc, 0.0, Y, dev)
+        n = pb.n
+        rec = {"workload": f"sperm_K{K}_h{h}", "N": pb.N, "Q": pb.Q, "n": n, "solves": {}}
+        methods = [("fp32_gmres_ir", nrs.NRS_FP32_GMRES_IR)]
+        if K == 10:
+            methods.append(("bf16_gmres_ir", nrs.NRS_BF16_GMRES_IR))
+        wsz = max(nrs.nrs_workspace_size(ctx, pb.N, pb.Q, pb.M, m) for _, m in methods)
+        ws = torch.empty(wsz, dtype=torch.uint8, device=dev)
+        sol = torch.empty(n, dtype=torch.float64, device=dev)
+        for name, m in methods:
+            nrs.nrs_solve(ctx, pb, u, None, sol, ws, method=m)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = nrs.nrs_solve(ctx, pb, u, None, sol, ws, method=m)
+            wall = time.perf_counter() - t0
+            rec["solves"][name] = {"ms": 1e3 * wall, "iterations": info["iterations"],
+                                   "fell_back": info["fell_back"],
+                                   "backward_error": info["backward_error"]}
+        del ws
+        lda = nrs.lda_for(n)
+        A32 = torch.empty((n, lda), dtype=torch.float32, device=dev)
+        wa = torch.empty(nrs.nrs_workspace_size(ctx, pb.N, pb.Q, pb.M, nrs.NRS_FP32_IR),
+                         dtype=torch.uint8, device=dev)
+        nrs.nrs_assemble(ctx, pb, 32, A32, lda, wa)
+        del wa
+        A0 = A32.clone()
+        ipiv = torch.empty(n, dtype=torch.int32, device=dev)
+        perm = torch.empty(n, dtype=torch.int32, device=dev)
+        sing = torch.zeros(1, dtype=torch.int32, device=dev)
+        for name, bf in (("lu_fp32", False), ("lu_bf16_updates", True)):
+            A32.copy_(A0)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            nrs.nrs_lu_factor(ctx, A32, lda, ipiv, perm, sing, pivot_scope=1, bf16_updates=bf)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            rec[name] = {"ms": ms, "tflops": 2.0 / 3.0 * n ** 3 / (ms / 1e3) / 1e12}
+        del A32, A0
+        torch.cuda.empty_cache()
+        out.append(rec)
+    return out
+
+
 def cpu_oracle_leg(scene, dt, field_pairs_sample=200):
     """The CPU FP64 oracle on bounded samples of the same workloads (timed),
     and its solve of the seeded initial state (the accuracy reference)."""
@@ -301,6 +358,8 @@ def main():
                     help="time only the batched workload (profiling)")
     ap.add_argument("--no-field", action="store_true",
                     help="skip the flow-at-tracers workload")
+    ap.add_argument("--no-channel", action="store_true",
+                    help="skip the channel configuration (n = 14,244 and 39,504)")
     ap.add_argument("--field-only", action="store_true",
                     help="time only the flow-at-tracers workload (profiling)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
@@ -461,6 +520,10 @@ def main():
     if not args.no_field:
         field = run_field(ctx, nrs, synth, dev)
 
+    channel = None
+    if not args.no_channel:
+        channel = run_channel(ctx, nrs, synth, dev)
+
     cpu = None
     accuracy = None
     if not args.no_cpu_baseline:
@@ -505,6 +568,7 @@ def main():
         "autotune": tune,
         "batched": batched,
         "field": field,
+        "channel": channel,
         "cpu_baseline": cpu,
         "wall_s": wall,
     }

@@ -62,6 +62,10 @@ typedef int32_t nrs_status;
 #define NRS_FP32_GMRES_IR  4  /* FP32 assembly + FP32 tile LU (static block pivoting),
                                  then flexible GMRES(m) in FP64 on the matrix-free
                                  operator with the LU as right preconditioner        */
+#define NRS_BF16_GMRES_IR  5  /* as NRS_FP32_GMRES_IR, but the tile LU's trailing
+                                 updates take BF16 copies of the finished tiles on
+                                 the matrix cores (FP32 accumulation, FP32 pivots and
+                                 tile solves); the workspace also holds those copies */
 
 typedef struct nrs_ctx nrs_ctx;
 
@@ -137,15 +141,15 @@ typedef struct {
 
 typedef struct {
   int32_t method;        /* NRS_FP64_LU, NRS_FP32_IR, NRS_FP32_GEPP_IR, NRS_GMRES,
-                            NRS_FP32_GMRES_IR                                    */
+                            NRS_FP32_GMRES_IR, NRS_BF16_GMRES_IR                 */
   int32_t max_refine;    /* refinement sweeps (IR) before falling back; <=0: 6   */
   double  tol;           /* IR: stop when |d|_inf <= tol |x|_inf, <=0: 1e-9.
                             GMRES: relative residual |b - A x|_2 <= tol |b|_2,
-                            <=0: 1e-11 (NRS_GMRES), 1e-12 (NRS_FP32_GMRES_IR)  */
+                            <=0: 1e-11 (NRS_GMRES), 1e-12 (the GMRES-IR forms) */
   int32_t gmres_restart; /* GMRES(m) restart length 1..63, <=0: 50 (NRS_GMRES),
-                            30 (NRS_FP32_GMRES_IR)                              */
+                            60 (the GMRES-IR forms)                             */
   int32_t gmres_max_iter;/* total GMRES iterations before LU fallback, <=0: 1000
-                            (NRS_GMRES), 300 (NRS_FP32_GMRES_IR)               */
+                            (NRS_GMRES), 300 (the GMRES-IR forms)              */
   int32_t no_fallback;   /* 1 = report failure instead of falling back to FP64 LU */
   const double* x_init;  /* [n] device initial guess for NRS_GMRES (NULL = zero); may
                             equal sol (start from sol's current content)       */
@@ -215,7 +219,7 @@ nrs_status nrs_apply(nrs_ctx* ctx, const nrs_problem* pb, const double* v, doubl
  * on large wall-bounded systems), it continues from its iterate with the
  * flexible GMRES of NRS_FP32_GMRES_IR on the same factors (relative residual
  * 1e-12) before any FP64 fallback; info->iterations then counts both.
- * NRS_FP32_GMRES_IR synchronises with the host once every few GMRES steps
+ * The GMRES-IR forms synchronise with the host once every few GMRES steps
  * even in the asynchronous form.
  * u: [3][N] prescribed velocities; ftext: [M][6] external force and torque
  * (NULL = force- and torque-free); sol: [n] output.
@@ -263,7 +267,9 @@ nrs_status nrs_solve_batched(nrs_ctx* ctx, int32_t B, const nrs_problem* problem
  * Sec. 4 step 3), for tests and reuse.                                      */
 /* ------------------------------------------------------------------------ */
 /* In-place LU factorisation of the n x n column-major matrix A (precision 32
- * or 64), n <= 262144.
+ * or 64; 16 = FP32 matrix and factors whose trailing updates take BF16
+ * copies of the finished tiles on the matrix cores with FP32 accumulation,
+ * pivot_scope 1 only, the copies held by the context), n <= 262144.
  * pivot_scope = 0: partial pivoting over the whole column, P A = L U.
  * pivot_scope = 1: static block pivoting for use with iterative refinement:
  *   pivots are searched only inside each 64 x 64 diagonal tile, and those

@@ -16,7 +16,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (NRS_FP32_GEPP_IR, NRS_FP32_GMRES_IR, NRS_FP32_IR, NRS_FP64_LU,  # noqa: F401
+from ._lib import (NRS_BF16_GMRES_IR, NRS_FP32_GEPP_IR, NRS_FP32_GMRES_IR, NRS_FP32_IR,  # noqa: F401
+                   NRS_FP64_LU,
                    NRS_GMRES,
                    NRS_MLP_HIDDEN, NRS_MLP_MAX_POINTS, NRS_WARM_MODEL, NRS_WARM_NONE,
                    NRS_WARM_PREVIOUS, NrsInfo, NrsOptions, NrsProblem, NrsScene)
@@ -25,7 +26,8 @@ __all__ = [
     "NrsError", "Context", "DeviceScene", "Problem", "nrs_create", "nrs_version", "nrs_geometry",
     "nrs_nearest", "nrs_workspace_size", "nrs_assemble", "nrs_apply", "nrs_solve",
     "nrs_query_info", "nrs_solve_batched_workspace_size", "nrs_solve_batched", "nrs_lu_factor", "nrs_lu_solve", "nrs_rk4_workspace_size", "nrs_rk4_step",
-    "NRS_FP64_LU", "NRS_FP32_IR", "NRS_FP32_GEPP_IR", "NRS_GMRES", "NRS_FP32_GMRES_IR", "lda_for",
+    "NRS_FP64_LU", "NRS_FP32_IR", "NRS_FP32_GEPP_IR", "NRS_GMRES", "NRS_FP32_GMRES_IR", "NRS_BF16_GMRES_IR",
+    "lda_for",
     "NRS_WARM_NONE", "NRS_WARM_PREVIOUS", "NRS_WARM_MODEL", "Model", "nrs_mlp_param_count",
     "nrs_autotune", "nrs_autotune_clear",
     "nrs_mlp_body_offsets", "nrs_mlp_features", "nrs_mlp_forward", "nrs_mlp_grad",
@@ -271,8 +273,13 @@ def nrs_query_info(ctx, ws):
     return inf.as_dict()
 
 
-def nrs_lu_factor(ctx, A, lda, ipiv, perm, singular, pivot_scope=0):
+def nrs_lu_factor(ctx, A, lda, ipiv, perm, singular, pivot_scope=0, bf16_updates=False):
+    """bf16_updates (FP32 A, pivot_scope 1): trailing updates on BF16 tile copies."""
     prec = 32 if A.dtype == torch.float32 else 64
+    if bf16_updates:
+        if prec != 32:
+            raise TypeError("BF16 updates need an FP32 matrix")
+        prec = 16
     n = int(ipiv.numel())
     _check(_lib.load().nrs_lu_factor(ctx.handle, n, prec, pivot_scope, _ptr(A, A.dtype, "A"), lda,
                                      _ptr(ipiv, torch.int32, "ipiv"), _ptr(perm, torch.int32, "perm"),

@@ -21,6 +21,7 @@ NRS_FP32_IR = 1
 NRS_FP32_GEPP_IR = 2
 NRS_GMRES = 3
 NRS_FP32_GMRES_IR = 4
+NRS_BF16_GMRES_IR = 5
 
 NRS_WARM_NONE = 0
 NRS_WARM_PREVIOUS = 1

@@ -40,10 +40,13 @@ int32_t apply_chunks(int64_t N, int64_t Q) {
 }
 
 bool uses_fp32(int32_t method) {
-  return method == NRS_FP32_IR || method == NRS_FP32_GEPP_IR || method == NRS_FP32_GMRES_IR;
+  return method == NRS_FP32_IR || method == NRS_FP32_GEPP_IR || method == NRS_FP32_GMRES_IR ||
+         method == NRS_BF16_GMRES_IR;
 }
+// the GMRES-IR forms (flexible GMRES straight after the tile LU)
+bool gmres_ir(int32_t method) { return method == NRS_FP32_GMRES_IR || method == NRS_BF16_GMRES_IR; }
 // methods whose single-system solves can run the flexible GMRES on the FP32 factors
-bool uses_fgmres(int32_t method) { return method == NRS_FP32_IR || method == NRS_FP32_GMRES_IR; }
+bool uses_fgmres(int32_t method) { return method == NRS_FP32_IR || gmres_ir(method); }
 constexpr double kFgmresTol = 1e-12;
 
 // Grow the context's zero-initialised synchronisation words to fit order n:
@@ -132,6 +135,7 @@ bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, Sol
   sb.AT = sb.V = sb.gw0 = sb.gw1 = sb.gpart = nullptr;
   sb.gst = nullptr;
   sb.Z = sb.fzv = sb.fax = nullptr;
+  sb.sh = (with64 && method == NRS_BF16_GMRES_IR) ? ar.take<uint16_t>(lu_shadow_elems(n)) : nullptr;
   const bool fg = with64 && uses_fgmres(method);
   if (fg) {
     sb.Z = ar.take<double>((size_t)n * kGmresLd);
@@ -183,7 +187,8 @@ nrs_status run_fp32_ir(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, do
                                       asm_shape_for(ctx, pb.N, pb.Q, 32)));
   if (norm) NRS_HIP(ctx, launch_anorm32(n, sb.A32, sb.lda, sb.st, sb.red, s));
   NRS_HIP(ctx, lu_factor_any<float>(n, scope, sb.A32, sb.lda, sb.ipiv, sb.perm,
-                                     &sb.st->singular, sb.lu_done, sb.st->lu_ctl, s));
+                                     &sb.st->singular, sb.lu_done, sb.st->lu_ctl, s,
+                                     scope == 1 ? sb.sh : nullptr));
   // x0 = (LU)^-1 b
   float* b32 = reinterpret_cast<float*>(sb.r);  // r is free until the first residual
   NRS_HIP(ctx, launch_convert_f32(n, sb.b, b32, s));
@@ -261,9 +266,9 @@ nrs_status run_gmres(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, doub
 nrs_status run_fgmres(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, double* x,
                       const nrs_options& o, hipStream_t s) {
   const int64_t n = 3 * pb.N + 6 * (int64_t)pb.M;
-  const int32_t m = (o.gmres_restart > 0 && o.gmres_restart < kGmresLd) ? o.gmres_restart : 30;
+  const int32_t m = (o.gmres_restart > 0 && o.gmres_restart < kGmresLd) ? o.gmres_restart : 60;
   const int32_t max_iter = o.gmres_max_iter > 0 ? o.gmres_max_iter : 300;
-  const double tol = (o.method == NRS_FP32_GMRES_IR && o.tol > 0) ? o.tol : kFgmresTol;
+  const double tol = (gmres_ir(o.method) && o.tol > 0) ? o.tol : kFgmresTol;
   float* v32 = reinterpret_cast<float*>(sb.r);
   GmresArgs a;
   a.n = n;
@@ -345,7 +350,7 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
   if (method == NRS_FP64_LU) {
     st = run_fp64_lu(ctx, pb, sb, sol, sync, s);
   } else if (uses_fp32(method)) {
-    const bool fgm = method == NRS_FP32_GMRES_IR;
+    const bool fgm = gmres_ir(method);
     st = run_fp32_ir(ctx, pb, sb, sol, method == NRS_FP32_GEPP_IR ? 0 : 1, fgm ? 0 : max_refine,
                      tol, sync, s);
     if (st == NRS_OK && fgm) st = run_fgmres(ctx, pb, sb, sol, o, s);
@@ -431,6 +436,7 @@ nrs_status nrs_destroy(nrs_ctx* ctx) {
     hipSetDevice(ctx->device);
     if (ctx->tsync) hipFree(ctx->tsync);
     if (ctx->lusync) hipFree(ctx->lusync);
+    if (ctx->lush) hipFree(ctx->lush);
     if (ctx->staging_event) {
       hipEventSynchronize(ctx->staging_event);
       hipEventDestroy(ctx->staging_event);
@@ -494,7 +500,7 @@ nrs_status nrs_nearest(nrs_ctx* ctx, int64_t N, const double* x, int32_t G,
 nrs_status nrs_workspace_size(nrs_ctx* ctx, int64_t N, int64_t Q, int32_t M, int32_t method,
                               size_t* bytes) {
   if (!bytes || N <= 0 || Q <= 0 || M < 0) return fail(ctx, NRS_E_ARG, "bad sizes");
-  if (method < NRS_FP64_LU || method > NRS_FP32_GMRES_IR)
+  if (method < NRS_FP64_LU || method > NRS_BF16_GMRES_IR)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
   *bytes = solve_workspace_bytes(N, Q, M, method);
   return NRS_OK;
@@ -553,9 +559,9 @@ nrs_status nrs_solve(nrs_ctx* ctx, const nrs_problem* pb, const double* u, const
   nrs_options o = {};
   o.method = NRS_FP64_LU;
   if (opt) o = *opt;
-  if (o.method < NRS_FP64_LU || o.method > NRS_FP32_GMRES_IR)
+  if (o.method < NRS_FP64_LU || o.method > NRS_BF16_GMRES_IR)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
-  if ((o.method == NRS_GMRES || o.method == NRS_FP32_GMRES_IR) && o.gmres_restart >= kGmresLd)
+  if ((o.method == NRS_GMRES || gmres_ir(o.method)) && o.gmres_restart >= kGmresLd)
     return fail(ctx, NRS_E_UNSUPPORTED, "GMRES restart length must be below 64");
   Arena ar(ws, ws_bytes);
   SolveBuffers sb;
@@ -588,14 +594,27 @@ nrs_status nrs_lu_factor(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t piv
   if ((st = ctx_lu_words(ctx, n))) return st;
   int32_t* ctl = ctx->lusync;
   int32_t* done = ctl + 4;
-  if (precision == 32)
+  if (precision == 16) {
+    if (pivot_scope != 1) return fail(ctx, NRS_E_ARG, "precision 16 needs pivot_scope 1");
+    const int64_t need = lu_shadow_elems(n);
+    if (ctx->lush_cap < need) {
+      NRS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      if (ctx->lush) NRS_HIP(ctx, hipFree(ctx->lush));
+      ctx->lush = nullptr;
+      ctx->lush_cap = 0;
+      NRS_HIP(ctx, hipMalloc(&ctx->lush, need * sizeof(uint16_t)));
+      ctx->lush_cap = need;
+    }
+    NRS_HIP(ctx, lu_factor_any<float>(n, 1, static_cast<float*>(A), lda, ipiv, perm, singular_flag,
+                                      done, ctl, ctx->stream, ctx->lush));
+  } else if (precision == 32)
     NRS_HIP(ctx, lu_factor_any<float>(n, pivot_scope, static_cast<float*>(A), lda, ipiv, perm,
                                       singular_flag, done, ctl, ctx->stream));
   else if (precision == 64)
     NRS_HIP(ctx, lu_factor_any<double>(n, pivot_scope, static_cast<double*>(A), lda, ipiv, perm,
                                        singular_flag, done, ctl, ctx->stream));
   else
-    return fail(ctx, NRS_E_ARG, "precision must be 32 or 64");
+    return fail(ctx, NRS_E_ARG, "precision must be 16, 32 or 64");
   return NRS_OK;
 }
 
@@ -872,7 +891,7 @@ nrs_status nrs_rk4_tracers_workspace_size(nrs_ctx* ctx, const nrs_scene* sc, int
   if (st) return st;
   if (!bytes) return fail(ctx, NRS_E_ARG, "bytes is NULL");
   if (P < 0 || P > kMaxFieldPoints) return fail(ctx, NRS_E_ARG, "tracer count out of range");
-  if (method < NRS_FP64_LU || method > NRS_FP32_GMRES_IR)
+  if (method < NRS_FP64_LU || method > NRS_BF16_GMRES_IR)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
   Arena ar(nullptr, 0);
   RkBuffers rb;
@@ -910,9 +929,9 @@ nrs_status nrs_rk4_step_tracers(nrs_ctx* ctx, const nrs_scene* sc, int32_t G,
   nrs_options o = {};
   o.method = NRS_FP64_LU;
   if (opt) o = *opt;
-  if (o.method < NRS_FP64_LU || o.method > NRS_FP32_GMRES_IR)
+  if (o.method < NRS_FP64_LU || o.method > NRS_BF16_GMRES_IR)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
-  if ((o.method == NRS_GMRES || o.method == NRS_FP32_GMRES_IR) && o.gmres_restart >= kGmresLd)
+  if ((o.method == NRS_GMRES || gmres_ir(o.method)) && o.gmres_restart >= kGmresLd)
     return fail(ctx, NRS_E_UNSUPPORTED, "GMRES restart length must be below 64");
   Arena ar(ws, ws_bytes);
   RkBuffers rb;

@@ -22,6 +22,7 @@
 //   P_m (A_m - sum_{k<m} L_mk U_k) = L_mm U_m   (columns >= m),
 // and the forward substitution applies P_m after the block-row update.
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "nrs_internal.h"
@@ -38,6 +39,8 @@ constexpr int64_t kLuSpin = 1 << 22;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int kL16 = 72;  // LDS row stride (bf16) of the BF16 staging tiles
 
 template <class T>
 struct Mf;
@@ -380,7 +383,7 @@ __device__ void diag_ipiv(Shared<T>& S, const LuSys<T>& sy, int64_t m) {
 }
 
 // One tile task: update, then factor / solve, store, publish.
-template <class T>
+template <class T, bool B16>
 __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
                                                    int64_t j, int64_t m, int32_t* err) {
   typedef typename Mf<T>::acc_t acc_t;
@@ -416,6 +419,69 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
     // every term whose two tiles are already published ([k, kend)), and inside
     // such a run the tiles of term k+1 are loaded while term k runs on the
     // matrix cores.
+    if constexpr (B16) {
+      // BF16 inputs: the tiles' BF16 copies (L_ik as [row][k], U_kj as
+      // [column][k]) staged in LDS with k contiguous, so that each lane reads
+      // its eight k values of a 16x16x32 matrix-core step with one load.
+      __bf16* L16 = reinterpret_cast<__bf16*>(S.Ls);
+      __bf16* U16 = reinterpret_cast<__bf16*>(S.Us);
+      const __bf16* sh = reinterpret_cast<const __bf16*>(sy.sh);
+      uint4 lq[2], uq[2];
+      int64_t kend = 0;
+      for (int64_t k = 0; k < m; ++k) {
+        if (k >= kend) {
+          if (tid == 0) {
+            wait_flag(&sy.done[i * nt + k], err);
+            wait_flag(&sy.done[k * nt + j], err);
+            int64_t e = k + 1;
+            while (e < m &&
+                   __hip_atomic_load(&sy.done[i * nt + e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &&
+                   __hip_atomic_load(&sy.done[e * nt + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+              ++e;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            S.task[2] = (int32_t)e;
+          }
+          __syncthreads();
+          kend = S.task[2];
+          const uint4* Lt = reinterpret_cast<const uint4*>(sh + (i * nt + k) * (TB * TB));
+          const uint4* Ut = reinterpret_cast<const uint4*>(sh + (k * nt + j) * (TB * TB));
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            lq[h] = Lt[tid + h * kLuThreads];
+            uq[h] = Ut[tid + h * kLuThreads];
+          }
+        }
+        __syncthreads();  // the previous term's reads of the staging tiles are done
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int q = tid + h * kLuThreads, row = q >> 3, k0 = (q & 7) * 8;
+          *reinterpret_cast<uint4*>(L16 + row * kL16 + k0) = lq[h];
+          *reinterpret_cast<uint4*>(U16 + row * kL16 + k0) = uq[h];
+        }
+        __syncthreads();
+        if (k + 1 < kend) {  // next term's tiles, in flight during this one
+          const uint4* Lt = reinterpret_cast<const uint4*>(sh + (i * nt + k + 1) * (TB * TB));
+          const uint4* Ut = reinterpret_cast<const uint4*>(sh + ((k + 1) * nt + j) * (TB * TB));
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            lq[h] = Lt[tid + h * kLuThreads];
+            uq[h] = Ut[tid + h * kLuThreads];
+          }
+        }
+#pragma unroll
+        for (int kk = 0; kk < TB; kk += 32) {
+          const int li = lane & 15, kg = kk + 8 * (lane >> 4);
+          const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(L16 + (qi + li) * kL16 + kg);
+          const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(L16 + (qi + 16 + li) * kL16 + kg);
+          const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(U16 + (qj + li) * kL16 + kg);
+          const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(U16 + (qj + 16 + li) * kL16 + kg);
+          acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+        }
+      }
+    } else {
     const int r = tid & 63, c0 = tid >> 6;
     T la[16], ua[16];
     int64_t kend = 0;
@@ -467,6 +533,7 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
         acc[1][0] = Mf<T>::run(a1, b0, acc[1][0]);
         acc[1][1] = Mf<T>::run(a1, b1, acc[1][1]);
       }
+    }
     }
     // ---- C = A_ij - acc into the working tile ----
 #pragma unroll
@@ -542,6 +609,23 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
         }
       }
     }
+    if constexpr (B16) {
+      // the BF16 copy of an off-diagonal tile for the updates that read it:
+      // L tile [row][k] = C(row, k), U tile [column][k] = C(k, column); entries
+      // past the order are zero, as ld_pad reads them
+      if (i != j) {
+        __bf16* dst = reinterpret_cast<__bf16*>(sy.sh) + (i * nt + j) * (TB * TB);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int q = tid + h * kLuThreads, a = q >> 3, b0 = (q & 7) * 8;
+          bf16x8 v;
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            v[e] = (__bf16)(i > j ? S.Cs[(b0 + e) * kCS + a] : S.Cs[a * kCS + b0 + e]);
+          *reinterpret_cast<bf16x8*>(dst + a * TB + b0) = v;
+        }
+      }
+    }
     __syncthreads();
     if (tid == 0) {
       __hip_atomic_store(&sy.done[i * nt + j], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -554,7 +638,7 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
 // MINB = workgroups per CU the register budget must allow: 1 for a single
 // system (the diagonal chain runs alone on its CU), 2 for batches (more
 // independent tasks in flight).
-template <class T, int MINB>
+template <class T, int MINB, bool B16>
 __global__ __launch_bounds__(kLuThreads, MINB) void k_lu_tiles(LuBatch<T> bt, int32_t* ctl) {
   __shared__ Shared<T> S;
   const int tid = threadIdx.x;
@@ -598,7 +682,7 @@ __global__ __launch_bounds__(kLuThreads, MINB) void k_lu_tiles(LuBatch<T> bt, in
       j = m;
     }
     const LuSys<T> sy = bt.sys ? bt.sys[s] : bt.one;
-    run_task<T>(S, sy, i, j, m, err);
+    run_task<T, B16>(S, sy, i, j, m, err);
     if (i == j) diag_ipiv<T>(S, sy, m);
   }
   // the last workgroup to finish clears the ticket and every flag
@@ -640,19 +724,27 @@ void lu_task_prefix(const int32_t* nts, int32_t B, std::vector<int32_t>& pref, i
 template <class T>
 hipError_t launch_lu_tiles(const LuBatch<T>& bt, int32_t* ctl, hipStream_t s) {
   if (bt.total <= 0) return hipSuccess;
-  if (bt.sys)
-    hipLaunchKernelGGL((k_lu_tiles<T, 2>), dim3((unsigned)bt.total), dim3(kLuThreads), 0, s, bt,
-                       ctl);
-  else
-    hipLaunchKernelGGL((k_lu_tiles<T, 1>), dim3((unsigned)bt.total), dim3(kLuThreads), 0, s, bt,
-                       ctl);
+  if (bt.sys) {
+    hipLaunchKernelGGL((k_lu_tiles<T, 2, false>), dim3((unsigned)bt.total), dim3(kLuThreads), 0, s,
+                       bt, ctl);
+    return hipGetLastError();
+  }
+  if constexpr (std::is_same<T, float>::value) {
+    if (bt.one.sh) {
+      hipLaunchKernelGGL((k_lu_tiles<float, 1, true>), dim3((unsigned)bt.total), dim3(kLuThreads),
+                         0, s, bt, ctl);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((k_lu_tiles<T, 1, false>), dim3((unsigned)bt.total), dim3(kLuThreads), 0, s,
+                     bt, ctl);
   return hipGetLastError();
 }
 
 template <class T>
 hipError_t lu_factor_any(int64_t n, int32_t scope, T* A, int64_t lda, int32_t* ipiv,
                          int32_t* perm, int32_t* sing, int32_t* done, int32_t* ctl,
-                         hipStream_t s) {
+                         hipStream_t s, uint16_t* sh) {
   if (scope == 0) return launch_lu_factor<T>(n, A, lda, ipiv, perm, sing, s);
   LuBatch<T> bt;
   const int64_t nt = lu_tiles_nt(n);
@@ -664,6 +756,7 @@ hipError_t lu_factor_any(int64_t n, int32_t scope, T* A, int64_t lda, int32_t* i
   bt.one.ipiv = ipiv;
   bt.one.done = done;
   bt.one.sing = sing;
+  bt.one.sh = std::is_same<T, float>::value ? sh : nullptr;
   bt.sys = nullptr;
   bt.pref = nullptr;
   bt.B = 1;
@@ -673,9 +766,9 @@ hipError_t lu_factor_any(int64_t n, int32_t scope, T* A, int64_t lda, int32_t* i
 }
 
 template hipError_t lu_factor_any<float>(int64_t, int32_t, float*, int64_t, int32_t*, int32_t*,
-                                         int32_t*, int32_t*, int32_t*, hipStream_t);
+                                         int32_t*, int32_t*, int32_t*, hipStream_t, uint16_t*);
 template hipError_t lu_factor_any<double>(int64_t, int32_t, double*, int64_t, int32_t*, int32_t*,
-                                          int32_t*, int32_t*, int32_t*, hipStream_t);
+                                          int32_t*, int32_t*, int32_t*, hipStream_t, uint16_t*);
 template hipError_t launch_lu_tiles<float>(const LuBatch<float>&, int32_t*, hipStream_t);
 template hipError_t launch_lu_tiles<double>(const LuBatch<double>&, int32_t*, hipStream_t);
 

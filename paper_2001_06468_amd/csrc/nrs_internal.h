@@ -38,6 +38,9 @@ struct nrs_ctx {
   // [nt*nt]; kept zero by the kernel
   int32_t* lusync = nullptr;
   int64_t lusync_cap = 0;
+  // BF16 tile copies of nrs_lu_factor with precision 16 (grown on demand)
+  uint16_t* lush = nullptr;
+  int64_t lush_cap = 0;
   // pinned host staging of batch descriptors; the event marks the last copy
   void* staging = nullptr;
   size_t staging_cap = 0;
@@ -166,6 +169,7 @@ struct SolveBuffers {
   double* Z;         // flexible GMRES: preconditioned basis [n][kGmresLd]
   double* fzv;       // [n] z_k, the operator's input
   double* fax;       // [n] A x for the true residual
+  uint16_t* sh;      // BF16 tile copies of the tile LU (NRS_BF16_GMRES_IR)
 };
 
 size_t solve_workspace_bytes(int64_t N, int64_t Q, int32_t M, int32_t method);
@@ -184,6 +188,11 @@ struct LuSys {
   int32_t* ipiv;    // [n] LAPACK-style interchanges (may be NULL)
   int32_t* done;    // [nt * nt] tile completion flags, zero before the launch
   int32_t* sing;    // set to 1 on an exact zero pivot
+  // BF16 copies of the finished off-diagonal tiles, 64 x 64 each at
+  // (i nt + j) * 4096, k index contiguous (L tiles [row][k], U tiles
+  // [column][k]); when set (FP32 only), the trailing updates take these as
+  // matrix-core inputs (BF16 in, FP32 accumulate).  NULL: FP32 updates.
+  uint16_t* sh = nullptr;
 };
 template <class T>
 struct LuBatch {
@@ -343,7 +352,12 @@ hipError_t launch_lu_factor(int64_t n, T* A, int64_t lda, int32_t* ipiv, int32_t
 template <class T>
 hipError_t lu_factor_any(int64_t n, int32_t scope, T* A, int64_t lda, int32_t* ipiv,
                          int32_t* perm, int32_t* sing, int32_t* done, int32_t* ctl,
-                         hipStream_t s);
+                         hipStream_t s, uint16_t* sh = nullptr);
+// elements of the BF16 tile copies of an order-n tile LU
+inline int64_t lu_shadow_elems(int64_t n) {
+  const int64_t nt = (n + 63) / 64;
+  return nt * nt * 4096;
+}
 inline int64_t lu_tiles_nt(int64_t n) { return (n + 63) / 64; }
 template <class T>
 hipError_t launch_lu_solve(int64_t n, int32_t scope, const T* LU, int64_t lda,

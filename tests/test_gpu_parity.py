@@ -213,6 +213,33 @@ def test_lu_tiles_repeatable_and_large(ctx):
         assert err < 1e-4, (n, err)
 
 
+def test_lu_tiles_bf16_updates(ctx):
+    """Tile LU whose trailing updates take BF16 copies of the tiles (FP32
+    accumulation): a usable preconditioner (solve error at the level of BF16
+    rounding, above the FP32 factorisation's), repeatable bit for bit, and the
+    flags clear between sizes (ragged last tile at 3150 and 1000)."""
+    rng = np.random.default_rng(12)
+    for n in (3150, 200, 1000):
+        A0 = rng.normal(size=(n, n)) + 3 * np.sqrt(n) * np.eye(n)
+        b = rng.normal(size=n)
+        ref = np.linalg.solve(A0, b)
+        errs, outs = [], []
+        for bf in (True, True, False):
+            A = torch.from_numpy(A0.T.copy()).to(torch.float32).to(DEV)
+            ipiv = torch.empty(n, dtype=torch.int32, device=DEV)
+            perm = torch.empty(n, dtype=torch.int32, device=DEV)
+            sing = torch.zeros(1, dtype=torch.int32, device=DEV)
+            nrs.nrs_lu_factor(ctx, A, n, ipiv, perm, sing, pivot_scope=1, bf16_updates=bf)
+            xs = torch.empty(n, dtype=torch.float32, device=DEV)
+            nrs.nrs_lu_solve(ctx, A, n, perm, T(b, torch.float32), xs, pivot_scope=1)
+            x = xs.cpu().numpy()
+            outs.append(A.cpu().numpy())
+            errs.append(np.linalg.norm(x - ref) / np.linalg.norm(ref))
+        assert np.array_equal(outs[0], outs[1]), n
+        assert errs[0] < 2e-2 and errs[2] < 1e-4, (n, errs)
+        assert errs[2] < errs[0], (n, errs)
+
+
 SOLVE_CASES = [
     ("sphere_c1", lambda: synth.sphere_scene(4, 16)),
     ("filaments_M1", lambda: synth.filament_scene(1, seed=0)),
@@ -223,7 +250,8 @@ SOLVE_CASES = [
 
 
 @pytest.mark.parametrize("name,mk", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
-@pytest.mark.parametrize("method", ["FP64_LU", "FP32_IR", "FP32_GEPP_IR", "FP32_GMRES_IR"])
+@pytest.mark.parametrize("method", ["FP64_LU", "FP32_IR", "FP32_GEPP_IR", "FP32_GMRES_IR",
+                                    "BF16_GMRES_IR"])
 def test_solve_matches_oracle(ctx, name, mk, method):
     scene = mk()
     pb, host = prepare(scene, 0.3)
@@ -237,8 +265,8 @@ def test_solve_matches_oracle(ctx, name, mk, method):
     assert info["backward_error"] <= 1e-12
     if method != "FP64_LU":
         assert info["iterations"] >= 2
-    if method == "FP32_GMRES_IR":
-        assert info["method_used"] == nrs.NRS_FP32_GMRES_IR
+    if method.endswith("GMRES_IR"):
+        assert info["method_used"] == getattr(nrs, "NRS_" + method)
 
 
 def test_sphere_drag_on_gpu(ctx):
