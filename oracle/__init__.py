@@ -26,4 +26,7 @@ from .core import (  # noqa: F401
 from .field import (  # noqa: F401
     field_velocity, tracer_rk4_step, rk4_step_tracers,
 )
+from .dopri import (  # noqa: F401
+    dopri_attempt, dopri_integrate, dopri_swimmers, error_norm,
+)
 
