@@ -404,6 +404,34 @@ nrs_status nrs_rk4_step(nrs_ctx* ctx, const nrs_scene* sc, int32_t G, const int3
                         double* Y, double t, double dt, const nrs_options* opt,
                         void* ws, size_t ws_bytes);
 
+/* Adaptive time stepping with the Dormand-Prince 5(4) pair (Dormand and
+ * Prince, 1980; the kind of integrator the paper's MATLAB ode45 is): Y [M][12]
+ * (in place) from t0 to t1.  Every attempt evaluates six new stages (the
+ * geometry, nearest map, solve with opt->method and rates of nrs_rk4_step);
+ * its first stage is the last stage of the previous accepted step.  Error
+ * estimate e = h sum_i (b5_i - b4_i) k_i, norm ||e / (atol + rtol max(|y|,
+ * |y_new|))||_rms; accepted when <= 1; next step h * min(10, 0.9 norm^-1/5)
+ * after an acceptance (at most h right after a rejection), h * max(0.2,
+ * 0.9 norm^-1/5) after a rejection; the last step is cut to end at t1.  Body
+ * frames are not re-orthonormalised between steps.  *h_io: first step in,
+ * proposed next step out.  At most max_steps attempts.  Synchronises with
+ * the host once per attempt (one scalar and the solve status); if a stage
+ * solve misses its tolerance the attempt is redone with NRS_FP64_LU (unless
+ * opt->no_fallback).  stats (host, may be NULL): attempts and solves. */
+typedef struct {
+  int32_t accepted, rejected, solves, fell_back;
+  double t;   /* time reached */
+  double h;   /* proposed next step */
+} nrs_dopri5_stats;
+nrs_status nrs_dopri5_workspace_size(nrs_ctx* ctx, const nrs_scene* sc, int32_t method,
+                                     size_t* bytes);
+nrs_status nrs_dopri5_integrate(nrs_ctx* ctx, const nrs_scene* sc, int32_t G,
+                                const int32_t* group_off_host, const int32_t* groupX, double eps,
+                                double mu, const double* ftext, double* Y, double t0, double t1,
+                                double* h_io, double rtol, double atol, const nrs_options* opt,
+                                int32_t max_steps, nrs_dopri5_stats* stats, void* ws,
+                                size_t ws_bytes);
+
 /* ------------------------------------------------------------------------ */
 /* Flow at field points and passive tracers.  The regularized single-layer  */
 /* equation (Sec. 3, eq. 19) holds anywhere in the fluid, so the nearest-   */

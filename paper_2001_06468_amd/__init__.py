@@ -35,6 +35,7 @@ __all__ = [
     "nrs_mlp_warm_start_workspace_size", "nrs_mlp_warm_start", "nrs_mlp_status",
     "nrs_field_workspace_size", "nrs_field_velocity", "nrs_tracer_rk4_step",
     "nrs_rk4_tracers_workspace_size", "nrs_rk4_step_tracers",
+    "nrs_dopri5_workspace_size", "nrs_dopri5_integrate",
 ]
 
 
@@ -333,6 +334,31 @@ def nrs_rk4_step_tracers(ctx, scene, Y, ytr, t, dt, ws, method=NRS_FP64_LU, ftex
         _ptr(ftext, torch.float64, "ftext"), _ptr(Y, torch.float64, "Y"), float(t), float(dt),
         C.byref(o), P, _ptr(ytr, torch.float64, "ytr"), _ptr(ws, torch.uint8, "ws"),
         ws.numel()), ctx)
+
+
+def nrs_dopri5_workspace_size(ctx, scene, method):
+    b = C.c_size_t()
+    sc = scene.struct()
+    _check(_lib.load().nrs_dopri5_workspace_size(ctx.handle, C.byref(sc), method, C.byref(b)), ctx)
+    return b.value
+
+
+def nrs_dopri5_integrate(ctx, scene, Y, t0, t1, h, rtol, atol, ws, method=NRS_FP64_LU,
+                         ftext=None, max_steps=100000, **opts):
+    """Adaptive Dormand-Prince 5(4) from t0 to t1 (Y advanced in place);
+    returns the stats dict (accepted, rejected, solves, fell_back, t, h)."""
+    sc = scene.struct()
+    o = _options(method, **opts)
+    go = scene.group_off
+    hh = C.c_double(float(h))
+    st = _lib.NrsDopriStats()
+    _check(_lib.load().nrs_dopri5_integrate(
+        ctx.handle, C.byref(sc), len(go) - 1, go.ctypes.data_as(C.c_void_p),
+        _ptr(scene.t["groupX"], torch.int32, "groupX"), scene.eps, scene.mu,
+        _ptr(ftext, torch.float64, "ftext"), _ptr(Y, torch.float64, "Y"), float(t0), float(t1),
+        C.byref(hh), float(rtol), float(atol), C.byref(o), int(max_steps), C.byref(st),
+        _ptr(ws, torch.uint8, "ws"), ws.numel()), ctx)
+    return st.as_dict()
 
 
 # ---------------------------------------------------------------- field points and tracers

@@ -63,6 +63,14 @@ class NrsInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class NrsDopriStats(C.Structure):
+    _fields_ = [("accepted", _i32), ("rejected", _i32), ("solves", _i32), ("fell_back", _i32),
+                ("t", C.c_double), ("h", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class NrsTuneResult(C.Structure):
     _fields_ = [("size_class", _i32), ("block32", _i32), ("strip32", _i32), ("block64", _i32),
                 ("strip64", _i32), ("ms32", C.c_float), ("ms64", C.c_float),
@@ -113,6 +121,11 @@ PROTOTYPES = {
     "nrs_rk4_workspace_size": (_i32, [_p, C.POINTER(NrsScene), _i32, C.POINTER(C.c_size_t)]),
     "nrs_rk4_step": (_i32, [_p, C.POINTER(NrsScene), _i32, _p, _p, C.c_double, C.c_double, _p,
                             _p, C.c_double, C.c_double, C.POINTER(NrsOptions), _p, C.c_size_t]),
+    "nrs_dopri5_workspace_size": (_i32, [_p, C.POINTER(NrsScene), _i32, C.POINTER(C.c_size_t)]),
+    "nrs_dopri5_integrate": (_i32, [_p, C.POINTER(NrsScene), _i32, _p, _p, C.c_double, C.c_double,
+                                    _p, _p, C.c_double, C.c_double, C.POINTER(C.c_double),
+                                    C.c_double, C.c_double, C.POINTER(NrsOptions), _i32,
+                                    C.POINTER(NrsDopriStats), _p, C.c_size_t]),
     "nrs_field_workspace_size": (_i32, [_p, _i64, _i64, C.POINTER(C.c_size_t)]),
     "nrs_field_velocity": (_i32, [_p, C.POINTER(NrsProblem), _p, _i64, _p, _p, _p, C.c_size_t]),
     "nrs_tracer_rk4_step": (_i32, [_p, C.POINTER(NrsProblem), C.POINTER(_p), _i64, _p,

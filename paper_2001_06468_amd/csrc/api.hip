@@ -29,15 +29,9 @@ nrs_status use_device(nrs_ctx* ctx) {
   return NRS_OK;
 }
 
-// chunks of the nu-sorted points per row block of the matrix-free product
-// (about 2048 workgroups; one chunk per 64 points at least)
-int32_t apply_chunks(int64_t N, int64_t Q) {
-  const int64_t mblocks = (N + 63) / 64;
-  int64_t c = (2048 + mblocks - 1) / std::max<int64_t>(mblocks, 1);
-  c = std::min<int64_t>(c, std::max<int64_t>(1, Q / 64));
-  c = std::max<int64_t>(1, std::min<int64_t>(c, 256));
-  return (int32_t)c;
-}
+// chunk partial sums the matrix-free product may need: it runs the field
+// pair sum at the N force points
+int32_t apply_chunks(int64_t N, int64_t Q) { return field_plan(N, Q).cap; }
 
 bool uses_fp32(int32_t method) {
   return method == NRS_FP32_IR || method == NRS_FP32_GEPP_IR || method == NRS_FP32_GMRES_IR ||
@@ -115,6 +109,7 @@ bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, Sol
   sb.srt.X32hi = ar.take<float4>(Q);
   sb.srt.X32lo = ar.take<float4>(Q);
   sb.srt.W = ar.take<double>(N);
+  sb.srt.fsrc = ar.take<FieldSrc>(Q);
   sb.lda = lda_for(n);
   sb.A32 = uses_fp32(method) ? ar.take<float>((size_t)sb.lda * n) : nullptr;
   sb.A64 = with64 ? ar.take<double>((size_t)sb.lda * n) : nullptr;
@@ -752,6 +747,9 @@ struct RkBuffers {
   int32_t* nu;
   float *phi, *my, *mz;   // network features / outputs (GMRES warm start)
   SolveBuffers sb;
+  // adaptive Dormand-Prince: seven stage rates, the candidate state, its
+  // error norm (device scalar)
+  double *DK[7], *Ynew, *enorm;
   // passive tracers: stage rates, saved positions, field sources and sums
   int64_t P;
   FieldPlan fplan;
@@ -759,7 +757,8 @@ struct RkBuffers {
   FieldSrc* src;
 };
 
-bool carve_rk(Arena& ar, const nrs_scene& sc, int32_t method, int64_t P, RkBuffers& rb) {
+bool carve_rk(Arena& ar, const nrs_scene& sc, int32_t method, int64_t P, RkBuffers& rb,
+              bool dopri = false) {
   const int64_t N = sc.N, Q = sc.Q, M = sc.M, n = 3 * N + 6 * M;
   rb.report = ar.take<SolveState>(1);
   rb.x = ar.take<double>(3 * N);
@@ -785,7 +784,54 @@ bool carve_rk(Arena& ar, const nrs_scene& sc, int32_t method, int64_t P, RkBuffe
   rb.ysave = P > 0 ? ar.take<double>(3 * P) : nullptr;
   rb.fpart = P > 0 ? ar.take<double>((size_t)rb.fplan.cap * 3 * P) : nullptr;
   rb.src = P > 0 ? ar.take<FieldSrc>(Q) : nullptr;
+  for (int i = 0; i < 7; ++i) rb.DK[i] = dopri ? ar.take<double>(12 * M) : nullptr;
+  rb.Ynew = dopri ? ar.take<double>(12 * M) : nullptr;
+  rb.enorm = dopri ? ar.take<double>(8) : nullptr;
   return !ar.overflow;
+}
+
+// One stage: geometry, nearest map and solve at the state rb.Ys and time tt,
+// then the rates of the bodies into Kout.  warm: the previous solve of this
+// workspace may seed a GMRES warm start.
+nrs_status stage_solve(nrs_ctx* ctx, const nrs_scene& sc, const GroupTable& gt,
+                       const int32_t* groupX, double eps, double mu, const double* ftext,
+                       double tt, const nrs_options& o, RkBuffers& rb, bool warm, double* Kout) {
+  hipStream_t s = ctx->stream;
+  NRS_HIP(ctx, launch_geometry(sc, tt, rb.Ys, rb.x, rb.X, rb.w, rb.u, s));
+  NRS_HIP(ctx, launch_nearest(sc.N, rb.x, gt, sc.Q, rb.X, groupX, rb.nu, s));
+  nrs_problem pb;
+  pb.N = sc.N;
+  pb.Q = sc.Q;
+  pb.M = sc.M;
+  pb.x = rb.x;
+  pb.X = rb.X;
+  pb.w = rb.w;
+  pb.nu = rb.nu;
+  pb.body = sc.body;
+  pb.Y = rb.Ys;
+  pb.eps = eps;
+  pb.mu = mu;
+  nrs_options os = o;
+  if (o.method == NRS_GMRES) {
+    // warm start of this stage's GMRES solve
+    os.x_init = nullptr;
+    if (o.warm_start == NRS_WARM_PREVIOUS && warm) {
+      os.x_init = rb.sol;
+    } else if (o.warm_start == NRS_WARM_MODEL) {
+      NRS_HIP(ctx, launch_features(sc.N, rb.x, rb.u, sc.s, sc.body, sc.M, rb.Ys, rb.phi, s));
+      NRS_HIP(ctx, launch_mlp_forward(o.model_theta, sc.M, sc.M, sc.N, o.body_off, nullptr,
+                                      rb.phi, rb.my, rb.mz, ctx->dflags, s));
+      NRS_HIP(ctx, launch_to_lab(sc.N, sc.M, sc.body, rb.Ys, rb.my, rb.mz, o.model_scales,
+                                 rb.sol, s));
+      os.x_init = rb.sol;
+      os.x_init_complete = 1;
+    }
+  }
+  nrs_status st = solve_core(ctx, pb, rb.u, ftext, os, rb.sb, rb.sol, false, nullptr);
+  if (st != NRS_OK) return st;
+  NRS_HIP(ctx, launch_state_accumulate(rb.report, rb.sb.st, s));
+  NRS_HIP(ctx, launch_rk_rates(sc.M, sc.N, rb.Ys, rb.sol, Kout, s));
+  return NRS_OK;
 }
 
 nrs_status rk4_pass(nrs_ctx* ctx, const nrs_scene& sc, const GroupTable& gt,
@@ -797,40 +843,9 @@ nrs_status rk4_pass(nrs_ctx* ctx, const nrs_scene& sc, const GroupTable& gt,
   NRS_HIP(ctx, launch_state_init(rb.report, o.method, s));
   for (int stg = 0; stg < 4; ++stg) {
     NRS_HIP(ctx, launch_rk_stage_state(sc.M, Y, stg ? rb.K[stg - 1] : nullptr, c[stg], rb.Ys, s));
-    NRS_HIP(ctx, launch_geometry(sc, t + c[stg], rb.Ys, rb.x, rb.X, rb.w, rb.u, s));
-    NRS_HIP(ctx, launch_nearest(sc.N, rb.x, gt, sc.Q, rb.X, groupX, rb.nu, s));
-    nrs_problem pb;
-    pb.N = sc.N;
-    pb.Q = sc.Q;
-    pb.M = sc.M;
-    pb.x = rb.x;
-    pb.X = rb.X;
-    pb.w = rb.w;
-    pb.nu = rb.nu;
-    pb.body = sc.body;
-    pb.Y = rb.Ys;
-    pb.eps = eps;
-    pb.mu = mu;
-    nrs_options os = o;
-    if (o.method == NRS_GMRES) {
-      // warm start of this stage's GMRES solve
-      os.x_init = nullptr;
-      if (o.warm_start == NRS_WARM_PREVIOUS && (stg > 0 || prev_valid)) {
-        os.x_init = rb.sol;
-      } else if (o.warm_start == NRS_WARM_MODEL) {
-        NRS_HIP(ctx, launch_features(sc.N, rb.x, rb.u, sc.s, sc.body, sc.M, rb.Ys, rb.phi, s));
-        NRS_HIP(ctx, launch_mlp_forward(o.model_theta, sc.M, sc.M, sc.N, o.body_off, nullptr,
-                                        rb.phi, rb.my, rb.mz, ctx->dflags, s));
-        NRS_HIP(ctx, launch_to_lab(sc.N, sc.M, sc.body, rb.Ys, rb.my, rb.mz, o.model_scales,
-                                   rb.sol, s));
-        os.x_init = rb.sol;
-        os.x_init_complete = 1;
-      }
-    }
-    nrs_status st = solve_core(ctx, pb, rb.u, ftext, os, rb.sb, rb.sol, false, nullptr);
+    nrs_status st = stage_solve(ctx, sc, gt, groupX, eps, mu, ftext, t + c[stg], o, rb,
+                                stg > 0 || prev_valid, rb.K[stg]);
     if (st != NRS_OK) return st;
-    NRS_HIP(ctx, launch_state_accumulate(rb.report, rb.sb.st, s));
-    NRS_HIP(ctx, launch_rk_rates(sc.M, sc.N, rb.Ys, rb.sol, rb.K[stg], s));
     if (rb.P > 0) {
       // this stage's flow (its geometry and forces) at the tracers' stage positions
       NRS_HIP(ctx, launch_field_sources(sc.N, sc.Q, rb.X, rb.w, rb.nu, rb.sol, rb.src, s));
@@ -979,6 +994,157 @@ nrs_status nrs_rk4_step(nrs_ctx* ctx, const nrs_scene* sc, int32_t G, const int3
                         size_t ws_bytes) {
   return nrs_rk4_step_tracers(ctx, sc, G, group_off_host, groupX, eps, mu, ftext, Y, t, dt, opt, 0,
                               nullptr, ws, ws_bytes);
+}
+
+// ---- adaptive Dormand-Prince 5(4) time stepping ----
+
+nrs_status nrs_dopri5_workspace_size(nrs_ctx* ctx, const nrs_scene* sc, int32_t method,
+                                     size_t* bytes) {
+  nrs_status st = check_scene(ctx, sc);
+  if (st) return st;
+  if (!bytes) return fail(ctx, NRS_E_ARG, "bytes is NULL");
+  if (method < NRS_FP64_LU || method > NRS_BF16_GMRES_IR)
+    return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
+  Arena ar(nullptr, 0);
+  RkBuffers rb;
+  carve_rk(ar, *sc, method, 0, rb, true);
+  *bytes = ar.used + 256;
+  return NRS_OK;
+}
+
+nrs_status nrs_dopri5_integrate(nrs_ctx* ctx, const nrs_scene* sc, int32_t G,
+                                const int32_t* group_off_host, const int32_t* groupX, double eps,
+                                double mu, const double* ftext, double* Y, double t0, double t1,
+                                double* h_io, double rtol, double atol, const nrs_options* opt,
+                                int32_t max_steps, nrs_dopri5_stats* stats, void* ws,
+                                size_t ws_bytes) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if ((st = check_scene(ctx, sc))) return st;
+  if (sc->M <= 0 || !Y) return fail(ctx, NRS_E_ARG, "time stepping needs free bodies and Y");
+  if (!group_off_host || !groupX || G <= 0) return fail(ctx, NRS_E_ARG, "groups required");
+  if (G > kMaxGroups) return fail(ctx, NRS_E_UNSUPPORTED, "too many groups");
+  if (!(eps > 0.0) || !(mu > 0.0) || !std::isfinite(t0) || !std::isfinite(t1) || !(t1 >= t0))
+    return fail(ctx, NRS_E_ARG, "eps, mu > 0 and finite t0 <= t1 required");
+  if (!h_io || !(*h_io > 0.0) || !std::isfinite(*h_io) || !(rtol > 0.0) || !(atol >= 0.0))
+    return fail(ctx, NRS_E_ARG, "first step > 0, rtol > 0 and atol >= 0 required");
+  GroupTable gt;
+  gt.G = G;
+  for (int g = 0; g <= G; ++g) gt.off[g] = group_off_host[g];
+  if (gt.off[0] != 0 || gt.off[G] != sc->N) return fail(ctx, NRS_E_ARG, "group_off must span [0, N]");
+  for (int g = 0; g < G; ++g)
+    if (gt.off[g + 1] <= gt.off[g]) return fail(ctx, NRS_E_ARG, "every group needs a force point");
+  nrs_options o = {};
+  o.method = NRS_FP64_LU;
+  if (opt) o = *opt;
+  if (o.method < NRS_FP64_LU || o.method > NRS_BF16_GMRES_IR)
+    return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
+  if ((o.method == NRS_GMRES || gmres_ir(o.method)) && o.gmres_restart >= kGmresLd)
+    return fail(ctx, NRS_E_UNSUPPORTED, "GMRES restart length must be below 64");
+  if (o.method == NRS_GMRES && o.warm_start == NRS_WARM_MODEL) {
+    if (!o.model_theta || !o.body_off || !sc->s)
+      return fail(ctx, NRS_E_ARG, "model warm start needs model_theta, body_off and scene s");
+    if ((st = ctx_dev_flags(ctx)) != NRS_OK) return st;
+  }
+  Arena ar(ws, ws_bytes);
+  RkBuffers rb;
+  if (!carve_rk(ar, *sc, o.method, 0, rb, true))
+    return fail(ctx, NRS_E_WORKSPACE, "workspace too small");
+  hipStream_t s = ctx->stream;
+  const int64_t n12 = 12 * (int64_t)sc->M;
+  const size_t bytes12 = n12 * sizeof(double);
+  ctx->rk_prev_ws = nullptr;
+  // Dormand-Prince 5(4): nodes, stage rows, error weights (5th minus 4th order)
+  static const double kC[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
+  static const double kA[7][6] = {
+      {0, 0, 0, 0, 0, 0},
+      {1.0 / 5, 0, 0, 0, 0, 0},
+      {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+      {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+      {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+      {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+      {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+  static const double kB4[7] = {5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640,
+                                -92097.0 / 339200, 187.0 / 2100, 1.0 / 40};
+  double kE[7];
+  for (int j = 0; j < 7; ++j) kE[j] = (j < 6 ? kA[6][j] : 0.0) - kB4[j];
+  nrs_dopri5_stats sts = {};
+  double t = t0, h = *h_io;
+  bool rejected = false;
+  // k1 = F(Y, t0)
+  NRS_HIP(ctx, launch_state_init(rb.report, o.method, s));
+  NRS_HIP(ctx, hipMemcpyAsync(rb.Ys, Y, bytes12, hipMemcpyDeviceToDevice, s));
+  if ((st = stage_solve(ctx, *sc, gt, groupX, eps, mu, ftext, t, o, rb, false, rb.DK[0])) != NRS_OK)
+    return st;
+  sts.solves = 1;
+  double* K[7];
+  for (int i = 0; i < 7; ++i) K[i] = rb.DK[i];
+  while (t < t1 && sts.accepted + sts.rejected < max_steps) {
+    h = std::min(h, t1 - t);
+    nrs_options oa = o;
+    for (int pass = 0; pass < 2; ++pass) {
+      // stages 2..7 (stage 7 at the candidate state y_new = Y + h sum a7j k_j)
+      for (int stg = 1; stg < 7; ++stg) {
+        RkComb cb;
+        cb.count = stg;
+        for (int j = 0; j < 7; ++j) {
+          cb.K[j] = K[j];
+          cb.c[j] = j < stg ? kA[stg][j] : 0.0;
+        }
+        double* dst = stg == 6 ? rb.Ynew : rb.Ys;
+        NRS_HIP(ctx, launch_rk_lincomb(n12, Y, cb, h, dst, s));
+        if (stg == 6) NRS_HIP(ctx, hipMemcpyAsync(rb.Ys, rb.Ynew, bytes12, hipMemcpyDeviceToDevice, s));
+        if ((st = stage_solve(ctx, *sc, gt, groupX, eps, mu, ftext, t + kC[stg] * h, oa, rb, true,
+                              K[stg])) != NRS_OK)
+          return st;
+        sts.solves += 1;
+      }
+      RkComb ce;
+      ce.count = 7;
+      for (int j = 0; j < 7; ++j) {
+        ce.K[j] = K[j];
+        ce.c[j] = kE[j];
+      }
+      NRS_HIP(ctx, launch_dp_error(n12, Y, rb.Ynew, ce, h, rtol, atol, rb.enorm, s));
+      SolveState rep;
+      NRS_HIP(ctx, hipMemcpyAsync(&rep, rb.report, sizeof(rep), hipMemcpyDeviceToHost, s));
+      double nrm = 0.0;
+      NRS_HIP(ctx, hipMemcpyAsync(&nrm, rb.enorm, sizeof(double), hipMemcpyDeviceToHost, s));
+      NRS_HIP(ctx, hipStreamSynchronize(s));
+      if (rep.nonfinite == 2) return fail(ctx, NRS_E_ARG, "nu outside [0, N) or body outside [-1, M)");
+      const bool failed = rep.failed && oa.method != NRS_FP64_LU;
+      if (failed && !o.no_fallback && pass == 0) {
+        // a stage solve missed its tolerance: redo this attempt with FP64 LU
+        NRS_HIP(ctx, launch_state_init(rb.report, NRS_FP64_LU, s));
+        oa.method = NRS_FP64_LU;
+        sts.fell_back = 1;
+        continue;
+      }
+      if (failed) return fail(ctx, NRS_E_NOT_CONVERGED, "a stage solve did not converge");
+      if (!std::isfinite(nrm)) return fail(ctx, NRS_E_NONFINITE, "non-finite error estimate");
+      if (nrm <= 1.0) {
+        double fac = nrm == 0.0 ? 10.0 : std::min(10.0, 0.9 * std::pow(nrm, -0.2));
+        if (rejected) fac = std::min(1.0, fac);
+        NRS_HIP(ctx, hipMemcpyAsync(Y, rb.Ynew, bytes12, hipMemcpyDeviceToDevice, s));
+        std::swap(K[0], K[6]);   // first stage of the next step = last stage of this one
+        t += h;
+        h *= fac;
+        rejected = false;
+        sts.accepted += 1;
+      } else {
+        h *= std::max(0.2, 0.9 * std::pow(nrm, -0.2));
+        rejected = true;
+        sts.rejected += 1;
+      }
+      break;
+    }
+  }
+  NRS_HIP(ctx, hipStreamSynchronize(s));
+  sts.t = t;
+  sts.h = h;
+  *h_io = h;
+  if (stats) *stats = sts;
+  return NRS_OK;
 }
 
 // ---- flow at field points and tracers through precomputed flows ----

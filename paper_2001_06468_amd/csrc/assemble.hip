@@ -206,72 +206,7 @@ __global__ void k_rhs(int64_t N, int32_t M, const double* __restrict__ u,
     b[i] = ft ? ft[i - 3 * N] : 0.0;
 }
 
-// Matrix-free FP64 NEAREST product, stage 1.  Workgroup (row block, chunk)
-// stages its chunk of the nu-sorted points in LDS (position and the gathered
-// w_p f[nu_p], loaded in parallel), then lane m of wave w sums
-// S^eps(x_m - X_p) w_p f[nu_p] over every fourth staged point; the four wave
-// sums are added in a fixed order.
-constexpr int kApplyRows = 64;
 constexpr int kApplyThreads = 256;
-constexpr int kApplyPts = 256;  // staged points per round
-__global__ __launch_bounds__(kApplyThreads) void k_apply_part(
-    int64_t N, int64_t chunk, const int32_t* __restrict__ seg, const double* __restrict__ x,
-    const double4* __restrict__ X64, const int32_t* __restrict__ nus,
-    const double* __restrict__ v, double eps2, double* __restrict__ part,
-    const int32_t* __restrict__ stop) {
-  if (stop && *stop) return;
-  __shared__ double sp[6][kApplyPts];  // X, Y, Z, w f_x, w f_y, w f_z
-  __shared__ double red[3][kApplyThreads / 64][kApplyRows];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t m = blockIdx.x * (int64_t)kApplyRows + lane;
-  const int64_t Qv = seg[N];  // points with a valid nearest index
-  const int64_t p0 = blockIdx.y * chunk;
-  const int64_t p1 = min<int64_t>(Qv, p0 + chunk);
-  double px = 0, py = 0, pz = 0;
-  if (m < N) {
-    px = x[m];
-    py = x[N + m];
-    pz = x[2 * N + m];
-  }
-  double ux = 0, uy = 0, uz = 0;
-  for (int64_t base = p0; base < p1; base += kApplyPts) {
-    const int cnt = (int)min<int64_t>(kApplyPts, p1 - base);
-    __syncthreads();
-    if ((int)threadIdx.x < cnt) {
-      const double4 q = X64[base + threadIdx.x];
-      const int nn = nus[base + threadIdx.x];
-      sp[0][threadIdx.x] = q.x;
-      sp[1][threadIdx.x] = q.y;
-      sp[2][threadIdx.x] = q.z;
-      sp[3][threadIdx.x] = q.w * v[nn];
-      sp[4][threadIdx.x] = q.w * v[N + nn];
-      sp[5][threadIdx.x] = q.w * v[2 * N + nn];
-    }
-    __syncthreads();
-    for (int k = w; k < cnt; k += kApplyThreads / 64) {
-      const double fx = sp[3][k], fy = sp[4][k], fz = sp[5][k];
-      const double rx = px - sp[0][k], ry = py - sp[1][k], rz = pz - sp[2][k];
-      const double d = rx * rx + ry * ry + rz * rz + eps2;
-      const double rho = 1.0 / sqrt(d);
-      const double t = rho * rho * rho;
-      const double rf = rx * fx + ry * fy + rz * fz;
-      const double s = d + eps2;
-      ux += t * (s * fx + rx * rf);
-      uy += t * (s * fy + ry * rf);
-      uz += t * (s * fz + rz * rf);
-    }
-  }
-  red[0][w][lane] = ux;
-  red[1][w][lane] = uy;
-  red[2][w][lane] = uz;
-  __syncthreads();
-  if (w < 3 && m < N) {
-    double acc = 0.0;
-#pragma unroll
-    for (int q = 0; q < kApplyThreads / 64; ++q) acc += red[w][q][lane];
-    part[blockIdx.y * 3 * N + w * N + m] = acc;
-  }
-}
 
 // Stage 2 for the 3N velocity rows: sum the chunks in a fixed order (wave w
 // takes a contiguous quarter of them with four running sums), scale,
@@ -431,16 +366,25 @@ hipError_t launch_rhs(int64_t N, int32_t M, const double* u, const double* ftext
   return hipGetLastError();
 }
 
+// Matrix-free FP64 product: the velocity rows are the flow of the force
+// densities v at the force points (the field pair sum of field.hip with the
+// N force points as field points: sources w_q v[nu(q)] gathered once, chunk
+// partial sums), then the fixed-order chunk sum with the rigid-body motion
+// (k_apply_rows) and the balance rows (k_apply_body).  `chunks` bounds the
+// partial buffer (at least field_plan(N, Q).cap).
 hipError_t launch_apply(const nrs_problem& pb, const Sorted& srt, const double* v, double* y,
                         double* part, int32_t chunks, const int32_t* stop, hipStream_t s) {
   const int64_t N = pb.N, Q = pb.Q;
-  const int64_t chunk = (Q + chunks - 1) / chunks;
   if (N > 0) {
-    dim3 g((unsigned)((N + kApplyRows - 1) / kApplyRows), (unsigned)chunks);
-    hipLaunchKernelGGL(k_apply_part, g, dim3(kApplyThreads), 0, s, N, chunk, srt.seg, pb.x,
-                       srt.X64, srt.nus, v, pb.eps * pb.eps, part, stop);
-    hipLaunchKernelGGL(k_apply_rows, grid1(3 * N, 64), dim3(kApplyThreads), 0, s, N, pb.M, chunks,
-                       part, 1.0 / (8.0 * kPi * pb.mu), pb.x, pb.body, pb.Y, v, y, stop);
+    const FieldPlan fp = field_plan(N, Q);
+    if (fp.chunks > chunks) return hipErrorInvalidValue;
+    hipError_t e = launch_field_sources(N, Q, pb.X, pb.w, pb.nu, v, srt.fsrc, s, stop);
+    if (e != hipSuccess) return e;
+    e = launch_field_part(fp, N, Q, pb.x, nullptr, 0.0, srt.fsrc, pb.eps, part, s, stop);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_apply_rows, grid1(3 * N, 64), dim3(kApplyThreads), 0, s, N, pb.M,
+                       fp.chunks, part, 1.0 / (8.0 * kPi * pb.mu), pb.x, pb.body, pb.Y, v, y,
+                       stop);
   }
   if (pb.M > 0) {
     hipLaunchKernelGGL(k_apply_body, dim3(pb.M), dim3(kBodyBlock), 0, s, N, pb.body, pb.x, pb.Y,

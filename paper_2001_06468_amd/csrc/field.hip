@@ -37,7 +37,9 @@ __device__ inline double rsqrt_refined(double d) {
 // consecutive doubles.
 __global__ void k_field_sources(int64_t N, int64_t Q, const double* __restrict__ X,
                                 const double* __restrict__ w, const int32_t* __restrict__ nu,
-                                const double* __restrict__ f, double* __restrict__ src) {
+                                const double* __restrict__ f, double* __restrict__ src,
+                                const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t q = i >> 3;
   const int k = (int)(i & 7);
@@ -63,7 +65,9 @@ __global__ void k_field_sources(int64_t N, int64_t Q, const double* __restrict__
 __global__ __launch_bounds__(kFieldThreads) void k_field_part(
     int64_t P, int64_t Q, int64_t pblocks, int32_t chunks, int64_t chunk,
     const double* __restrict__ y, const double* __restrict__ K, double c,
-    const FieldSrc* __restrict__ src, double eps2, double* __restrict__ part) {
+    const FieldSrc* __restrict__ src, double eps2, double* __restrict__ part,
+    const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
   __shared__ double red[3][kFieldWaves][64];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -186,9 +190,20 @@ FieldPlan field_plan(int64_t P, int64_t Q) {
 
 hipError_t launch_field_sources(int64_t N, int64_t Q, const double* X, const double* w,
                                 const int32_t* nu, const double* f, FieldSrc* src,
-                                hipStream_t s) {
+                                hipStream_t s, const int32_t* stop) {
   hipLaunchKernelGGL(k_field_sources, dim3((unsigned)((8 * Q + 255) / 256)), dim3(256), 0, s, N, Q,
-                     X, w, nu, f, reinterpret_cast<double*>(src));
+                     X, w, nu, f, reinterpret_cast<double*>(src), stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_field_part(const FieldPlan& fp, int64_t P, int64_t Q, const double* y,
+                             const double* K, double c, const FieldSrc* src, double eps,
+                             double* part, hipStream_t s, const int32_t* stop) {
+  if (P <= 0) return hipSuccess;
+  const int64_t slots = fp.chunks >= 8 ? 8 * ((fp.chunks + 7) / 8) : fp.chunks;
+  const unsigned grid = (unsigned)(fp.pblocks * slots);
+  hipLaunchKernelGGL(k_field_part, dim3(grid), dim3(kFieldThreads), 0, s, P, Q, fp.pblocks,
+                     fp.chunks, fp.chunk, y, K, c, src, eps * eps, part, stop);
   return hipGetLastError();
 }
 
@@ -196,10 +211,8 @@ hipError_t launch_field(const FieldPlan& fp, int64_t P, int64_t Q, const double*
                         const double* K, double c, const FieldSrc* src, double eps, double mu,
                         double* part, double* u, hipStream_t s) {
   if (P <= 0) return hipSuccess;
-  const int64_t slots = fp.chunks >= 8 ? 8 * ((fp.chunks + 7) / 8) : fp.chunks;
-  const unsigned grid = (unsigned)(fp.pblocks * slots);
-  hipLaunchKernelGGL(k_field_part, dim3(grid), dim3(kFieldThreads), 0, s, P, Q, fp.pblocks,
-                     fp.chunks, fp.chunk, y, K, c, src, eps * eps, part);
+  hipError_t e = launch_field_part(fp, P, Q, y, K, c, src, eps, part, s, nullptr);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_field_sum, dim3((unsigned)((3 * P + 63) / 64)), dim3(kSumWaves * 64), 0, s,
                      3 * P, fp.chunks, part, 1.0 / (8.0 * kPi * mu), u);
   return hipGetLastError();

@@ -126,6 +126,13 @@ inline int64_t lda_for(int64_t n) { return round_up(n < 1 ? 1 : n, 64); }
 inline int64_t rowsum_chunks(int64_t n) { return n <= 4096 ? (n + 255) / 256 : 16; }
 inline int64_t rowsum_scratch(int64_t n) { return rowsum_chunks(n) * n + 1024; }
 
+// One quadrature point as a source of the field sum: position and
+// g = w_q f[nu(q)] (zero when nu(q) is outside [0, N)); 64 bytes so that a
+// wave reads a record with one scalar load.
+struct alignas(64) FieldSrc {
+  double X, Y, Z, gx, gy, gz, pad0, pad1;
+};
+
 // Sorted quadrature data, produced by build_csr.
 struct Sorted {
   int32_t* seg;      // [N+1] segment offsets into the sorted order
@@ -136,6 +143,7 @@ struct Sorted {
   float4* X32lo;     // [Q] (x_lo, y_lo, z_lo, 0): x = x_hi + x_lo to FP32 x FP32 precision
   double* W;         // [N] patch weights
   int32_t* cnt;      // [N+2] scratch; cnt[N+1] counts quadrature points with nu out of range
+  FieldSrc* fsrc;    // [Q] source records of the matrix-free product (original order)
 };
 
 // All device buffers of one solve, carved from the workspace.
@@ -290,7 +298,7 @@ struct GmresArgs {
   const double* b;
   double* x;
   double* V;          // [n][kGmresLd]
-  double* Z;          // [n][kGmresLd] preconditioned basis (flexible GMRES), else NULL
+  double* Z = nullptr;  // [n][kGmresLd] preconditioned basis (flexible GMRES), else NULL
   double* w0;
   double* w1;
   double* part;       // [gmres_blocks(n)][kGmresLd]
@@ -400,14 +408,20 @@ hipError_t launch_rk_rates(int32_t M, int64_t N, const double* Ys, const double*
                            hipStream_t s);
 hipError_t launch_rk_combine(int32_t M, double* Y, const double* K1, const double* K2,
                              const double* K3, const double* K4, double dt, hipStream_t s);
+// Y + h sum_j c[j] K[j] (j < count <= 7), passed by value to the kernels
+struct RkComb {
+  const double* K[7];
+  double c[7];
+  int32_t count;
+};
+hipError_t launch_rk_lincomb(int64_t n, const double* Y, const RkComb& cb, double h, double* out,
+                             hipStream_t s);
+// out[0] = || h sum_j c[j] K[j] / (atol + rtol max(|Y|, |Yn|)) ||_rms
+hipError_t launch_dp_error(int64_t n, const double* Y, const double* Yn, const RkComb& cb, double h,
+                           double rtol, double atol, double* out, hipStream_t s);
 
 // flow at field points and tracers
-// One quadrature point as a source of the field sum: position and
-// g = w_q f[nu(q)] (zero when nu(q) is outside [0, N)); 64 bytes so that a
-// wave reads a record with one scalar load.
-struct alignas(64) FieldSrc {
-  double X, Y, Z, gx, gy, gz, pad0, pad1;
-};
+
 // Field points in blocks of 64 (one per lane), sources cut into `chunks`
 // ranges of `chunk` records; partial sums need chunks * 3P doubles.
 // cap >= chunks never decreases with Q, so a buffer of cap * 3P doubles
@@ -418,7 +432,12 @@ struct FieldPlan {
 };
 FieldPlan field_plan(int64_t P, int64_t Q);
 hipError_t launch_field_sources(int64_t N, int64_t Q, const double* X, const double* w,
-                                const int32_t* nu, const double* f, FieldSrc* src, hipStream_t s);
+                                const int32_t* nu, const double* f, FieldSrc* src, hipStream_t s,
+                                const int32_t* stop = nullptr);
+// chunk partial sums part[chunk][3][P] of the flow at y + c K (unscaled)
+hipError_t launch_field_part(const FieldPlan& fp, int64_t P, int64_t Q, const double* y,
+                             const double* K, double c, const FieldSrc* src, double eps,
+                             double* part, hipStream_t s, const int32_t* stop);
 // u [3][P] = flow of the sources at y + c K (K may be NULL: at y)
 hipError_t launch_field(const FieldPlan& fp, int64_t P, int64_t Q, const double* y,
                         const double* K, double c, const FieldSrc* src, double eps, double mu,

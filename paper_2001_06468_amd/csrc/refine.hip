@@ -329,6 +329,55 @@ hipError_t launch_rk_rates(int32_t M, int64_t N, const double* Ys, const double*
   return hipGetLastError();
 }
 
+// ---- adaptive Dormand-Prince 5(4) ----
+
+// out = Y + h sum_j c_j K_j over the 12M state entries (up to 7 stage rates).
+__global__ void k_rk_lincomb(int64_t n, const double* __restrict__ Y, RkComb cb, double h,
+                             double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int j = 0; j < cb.count; ++j) acc += cb.c[j] * cb.K[j][i];
+  out[i] = Y[i] + h * acc;
+}
+
+// RMS norm of the error estimate e = h sum_j e_j K_j scaled by
+// atol + rtol max(|y|, |y_new|); one workgroup, fixed-order reduction.
+__global__ __launch_bounds__(kRedThreads) void k_dp_error(int64_t n, const double* __restrict__ Y,
+                                                         const double* __restrict__ Yn, RkComb cb,
+                                                         double h, double rtol, double atol,
+                                                         double* __restrict__ out) {
+  __shared__ double sh[kRedThreads];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += kRedThreads) {
+    double e = 0.0;
+    for (int j = 0; j < cb.count; ++j) e += cb.c[j] * cb.K[j][i];
+    const double sc = atol + rtol * fmax(fabs(Y[i]), fabs(Yn[i]));
+    const double q = h * e / sc;
+    acc = fma(q, q, acc);
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kRedThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) sh[threadIdx.x] += sh[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = n > 0 ? sqrt(sh[0] / (double)n) : 0.0;
+}
+
+hipError_t launch_rk_lincomb(int64_t n, const double* Y, const RkComb& cb, double h, double* out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_rk_lincomb, grid1(n, 256), dim3(256), 0, s, n, Y, cb, h, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dp_error(int64_t n, const double* Y, const double* Yn, const RkComb& cb, double h,
+                           double rtol, double atol, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_dp_error, dim3(1), dim3(kRedThreads), 0, s, n, Y, Yn, cb, h, rtol, atol,
+                     out);
+  return hipGetLastError();
+}
+
 hipError_t launch_rk_combine(int32_t M, double* Y, const double* K1, const double* K2,
                              const double* K3, const double* K4, double dt, hipStream_t s) {
   hipLaunchKernelGGL(k_rk_combine, grid1(M, 64), dim3(64), 0, s, M, Y, K1, K2, K3, K4, dt);
