@@ -36,10 +36,10 @@ PEAK_FP64_TFLOPS = 78.6
 # HBM bytes per launch of the tile LU at n = 3150 from the FETCH_SIZE and
 # WRITE_SIZE counter runs (calibrated against a 256 MiB copy), valid only for
 # the kernel source they were taken on (first 16 hex digits of its SHA-256).
-LU_TRAFFIC = {"source_sha256_16": "5898a348aa994156", "bytes_per_launch": 779262102, "n": 3150}
+LU_TRAFFIC = {"source_sha256_16": "67b4e8d372e0549a", "bytes_per_launch": 783474778, "n": 3150}
 # HBM bytes per nrs_field_velocity call (sources + pair sum + chunk sum) on the
 # tracer workload, from the same two counter runs, valid for that field.hip.
-FIELD_TRAFFIC = {"source_sha256_16": "0e07e3708f3a6a69", "bytes_per_call": 24466341, "Q": 73248,
+FIELD_TRAFFIC = {"source_sha256_16": "7f18d8d2f998ad7c", "bytes_per_call": 24459390, "Q": 73248,
                  "tracers": 806}
 
 
@@ -222,6 +222,27 @@ def run_channel(ctx, nrs, synth, dev):
     return out
 
 
+def run_dopri(ctx, nrs, ds, scene, dev, method, t1=2 * math.pi / 10, rtol=1e-6, atol=1e-9):
+    """Adaptive Dormand-Prince 5(4) over a tenth of a beat period of the same
+    25-filament workload (first step 2 pi / 100, the RK4 step): attempts,
+    solves and solves per second of the whole integration (HIP events)."""
+    import torch
+    ws = torch.empty(nrs.nrs_dopri5_workspace_size(ctx, ds, method), dtype=torch.uint8,
+                     device=dev)
+    Y = torch.from_numpy(scene["Y0"].copy()).to(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    st = nrs.nrs_dopri5_integrate(ctx, ds, Y, 0.0, t1, 2 * math.pi / 100, rtol, atol, ws,
+                                  method=method)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    return {"t1": t1, "rtol": rtol, "atol": atol, "ms": ms, "solves_per_s": st["solves"] / (ms / 1e3),
+            **st}
+
+
 def cpu_oracle_leg(scene, dt, field_pairs_sample=200):
     """The CPU FP64 oracle on bounded samples of the same workloads (timed),
     and its solve of the seeded initial state (the accuracy reference)."""
@@ -360,6 +381,8 @@ def main():
                     help="skip the flow-at-tracers workload")
     ap.add_argument("--no-channel", action="store_true",
                     help="skip the channel configuration (n = 14,244 and 39,504)")
+    ap.add_argument("--channel-only", action="store_true",
+                    help="time only the channel configuration (profiling)")
     ap.add_argument("--field-only", action="store_true",
                     help="time only the flow-at-tracers workload (profiling)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
@@ -413,6 +436,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.channel_only:
+        print(json.dumps({"channel": run_channel(ctx, nrs, synth, dev)}), flush=True)
+        return
 
     if args.field_only:
         print(json.dumps({"field": run_field(ctx, nrs, synth, dev)}), flush=True)
@@ -492,6 +519,7 @@ def main():
     forms = {}
     learned_info = None
     if not args.no_forms:
+        forms["dopri5_" + args.method] = run_dopri(ctx, nrs, ds, scene, dev, method)
         for name, m in METHODS.items():
             if m == method:
                 continue
