@@ -142,7 +142,7 @@ typedef struct {
 typedef struct {
   int32_t method;        /* NRS_FP64_LU, NRS_FP32_IR, NRS_FP32_GEPP_IR, NRS_GMRES,
                             NRS_FP32_GMRES_IR, NRS_BF16_GMRES_IR                 */
-  int32_t max_refine;    /* refinement sweeps (IR) before falling back; <=0: 6   */
+  int32_t max_refine;    /* refinement sweeps (IR) before falling back; <=0: 4   */
   double  tol;           /* IR: stop when |d|_inf <= tol |x|_inf, <=0: 1e-9.
                             GMRES: relative residual |b - A x|_2 <= tol |b|_2,
                             <=0: 1e-11 (NRS_GMRES), 1e-12 (the GMRES-IR forms) */

@@ -332,7 +332,7 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
   hipStream_t s = ctx->stream;
   const int64_t N = pb.N, Q = pb.Q, n = 3 * N + 6 * (int64_t)pb.M;
   const int32_t method = o.method;
-  const int32_t max_refine = o.max_refine > 0 ? o.max_refine : 6;
+  const int32_t max_refine = o.max_refine > 0 ? o.max_refine : 4;
   const double tol = o.tol > 0 ? o.tol : 1e-9;
   NRS_HIP(ctx, launch_state_init(sb.st, method, s));
   NRS_HIP(ctx, launch_fill_i32(sb.tsync, 0, trsv_sync_ints(n), s));

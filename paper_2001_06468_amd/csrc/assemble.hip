@@ -211,12 +211,12 @@ constexpr int kApplyThreads = 256;
 // Stage 2 for the 3N velocity rows: sum the chunks in a fixed order (wave w
 // takes a contiguous quarter of them with four running sums), scale,
 // subtract the rigid-body motion U + Omega x r_m of free-body points.
-__global__ __launch_bounds__(kApplyThreads) void k_apply_rows(
-    int64_t N, int32_t M, int32_t chunks, const double* __restrict__ part, double scale,
-    const double* __restrict__ x, const int32_t* __restrict__ body,
-    const double* __restrict__ Y, const double* __restrict__ v, double* __restrict__ y,
-    const int32_t* __restrict__ stop) {
-  if (stop && *stop) return;
+__device__ inline void apply_velocity_rows(int64_t N, int32_t M, int32_t chunks,
+                                           const double* __restrict__ part, double scale,
+                                           const double* __restrict__ x,
+                                           const int32_t* __restrict__ body,
+                                           const double* __restrict__ Y,
+                                           const double* __restrict__ v, double* __restrict__ y) {
   __shared__ double red[kApplyThreads / 64][64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t row = blockIdx.x * (int64_t)64 + lane;
@@ -252,15 +252,14 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply_rows(
   y[row] = acc;
 }
 
-// Stage 2 for the 6M rigid rows: one workgroup per body, fixed-order
+// Stage 2 for the 6M rigid rows of body s: one workgroup, fixed-order
 // reduction of W_m f_m and W_m r_m x f_m.
 constexpr int kBodyBlock = 256;
-__global__ __launch_bounds__(kBodyBlock) void k_apply_body(
-    int64_t N, const int32_t* __restrict__ body, const double* __restrict__ x,
-    const double* __restrict__ Y, const double* __restrict__ W, const double* __restrict__ v,
-    double* __restrict__ y, const int32_t* __restrict__ stop) {
-  if (stop && *stop) return;
-  const int s = blockIdx.x;
+__device__ inline void apply_body_rows(int s, int64_t N, const int32_t* __restrict__ body,
+                                       const double* __restrict__ x,
+                                       const double* __restrict__ Y,
+                                       const double* __restrict__ W,
+                                       const double* __restrict__ v, double* __restrict__ y) {
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (int64_t m = threadIdx.x; m < N; m += kBodyBlock) {
     if (body[m] != s) continue;
@@ -282,6 +281,22 @@ __global__ __launch_bounds__(kBodyBlock) void k_apply_body(
     __syncthreads();
   }
   if (threadIdx.x < 6) y[3 * N + 6 * s + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Stage 2 of the product in one launch: workgroups [0, rowblocks) take the
+// velocity rows, workgroup rowblocks + s the rigid rows of body s.
+__global__ __launch_bounds__(kApplyThreads) void k_apply_stage2(
+    int64_t N, int32_t M, int32_t chunks, const double* __restrict__ part, double scale,
+    const double* __restrict__ x, const int32_t* __restrict__ body,
+    const double* __restrict__ Y, const double* __restrict__ W, const double* __restrict__ v,
+    double* __restrict__ y, const int32_t* __restrict__ stop) {
+  if (stop && *stop) return;
+  const int64_t rowblocks = (3 * N + 63) / 64;
+  if ((int64_t)blockIdx.x >= rowblocks) {
+    apply_body_rows((int)(blockIdx.x - rowblocks), N, body, x, Y, W, v, y);
+    return;
+  }
+  apply_velocity_rows(N, M, chunks, part, scale, x, body, Y, v, y);
 }
 
 inline dim3 grid1(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)); }
@@ -370,7 +385,7 @@ hipError_t launch_rhs(int64_t N, int32_t M, const double* u, const double* ftext
 // densities v at the force points (the field pair sum of field.hip with the
 // N force points as field points: sources w_q v[nu(q)] gathered once, chunk
 // partial sums), then the fixed-order chunk sum with the rigid-body motion
-// (k_apply_rows) and the balance rows (k_apply_body).  `chunks` bounds the
+// and the balance rows in one launch (k_apply_stage2).  `chunks` bounds the
 // partial buffer (at least field_plan(N, Q).cap).
 hipError_t launch_apply(const nrs_problem& pb, const Sorted& srt, const double* v, double* y,
                         double* part, int32_t chunks, const int32_t* stop, hipStream_t s) {
@@ -382,13 +397,10 @@ hipError_t launch_apply(const nrs_problem& pb, const Sorted& srt, const double* 
     if (e != hipSuccess) return e;
     e = launch_field_part(fp, N, Q, pb.x, nullptr, 0.0, srt.fsrc, pb.eps, part, s, stop);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_apply_rows, grid1(3 * N, 64), dim3(kApplyThreads), 0, s, N, pb.M,
-                       fp.chunks, part, 1.0 / (8.0 * kPi * pb.mu), pb.x, pb.body, pb.Y, v, y,
-                       stop);
-  }
-  if (pb.M > 0) {
-    hipLaunchKernelGGL(k_apply_body, dim3(pb.M), dim3(kBodyBlock), 0, s, N, pb.body, pb.x, pb.Y,
-                       srt.W, v, y, stop);
+    const unsigned blocks = (unsigned)((3 * N + 63) / 64 + pb.M);
+    hipLaunchKernelGGL(k_apply_stage2, dim3(blocks), dim3(kApplyThreads), 0, s, N, pb.M,
+                       fp.chunks, part, 1.0 / (8.0 * kPi * pb.mu), pb.x, pb.body, pb.Y, srt.W, v,
+                       y, stop);
   }
   return hipGetLastError();
 }
