@@ -36,6 +36,10 @@ constexpr int kLuThreads = 256;
 constexpr int kLS = 80;  // LDS row stride of the MFMA staging tiles
 constexpr int kCS = 65;  // LDS column stride of the working tile
 constexpr int64_t kLuSpin = 1 << 22;
+// s_waitcnt operand that waits for vmcnt = 0 and leaves expcnt and lgkmcnt at
+// their maxima (gfx9 layout: vmcnt in bits 3:0 and 15:14, expcnt 6:4,
+// lgkmcnt 11:8).
+constexpr int kWaitVmem = 0x0F70;
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
@@ -626,6 +630,12 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
         }
       }
     }
+    // Every wave waits until its own stores (tile, BF16 copy, pivot order)
+    // are acknowledged before the barrier.  The barrier does not wait for
+    // other waves' global stores, and thread 0's release writes back only
+    // what has already reached its XCD's L2, so without this wait a consumer
+    // on another XCD can, rarely, read part of the tile before it lands.
+    __builtin_amdgcn_s_waitcnt(kWaitVmem);
     __syncthreads();
     if (tid == 0) {
       __hip_atomic_store(&sy.done[i * nt + j], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
