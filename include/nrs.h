@@ -243,7 +243,10 @@ nrs_status nrs_query_info(nrs_ctx* ctx, void* ws, nrs_info* info);
  * in nrs_solve (ftext may be NULL, or hold NULL entries).  The FP32
  * factorisations of all B systems run in one launch of the tile LU, and each
  * triangular sweep of the refinement in one launch over the batch; the
- * remaining per-system steps are queued on the context's stream.
+ * remaining per-system steps are spread over the context's stream and three
+ * side streams the context owns (default priority), forked from and joined
+ * back into the context's stream with events, so the call as a whole is
+ * ordered on the context's stream like every other call.
  * Workspace: nrs_solve_batched_workspace_size() bytes for the same problem
  * list (holds every system's FP32 matrix side by side).  The descriptors are
  * staged through a pinned host buffer owned by the context.

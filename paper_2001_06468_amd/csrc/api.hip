@@ -438,6 +438,14 @@ nrs_status nrs_destroy(nrs_ctx* ctx) {
     }
     if (ctx->staging) hipHostFree(ctx->staging);
     if (ctx->dflags) hipFree(ctx->dflags);
+    for (int j = 0; j < nrs_ctx::kAux; ++j) {
+      if (ctx->aux[j]) {
+        hipStreamSynchronize(ctx->aux[j]);
+        hipStreamDestroy(ctx->aux[j]);
+      }
+      if (ctx->join_ev[j]) hipEventDestroy(ctx->join_ev[j]);
+    }
+    if (ctx->fork_ev) hipEventDestroy(ctx->fork_ev);
     if (!ctx->graphs.empty()) {
       if (ctx->stream) hipStreamSynchronize(ctx->stream);
       for (auto& g : ctx->graphs) {

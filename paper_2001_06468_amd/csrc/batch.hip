@@ -2,7 +2,8 @@
 // together: every factorisation of the batch runs in ONE launch of the tile
 // LU (tasks of all systems interleaved band by band), and every triangular
 // sweep of the batch in one launch per pass.  Assembly and the FP64 residual
-// stay per system (they are short and have no cross-system sharing).
+// stay per system (they are short and have no cross-system sharing); those
+// launches are spread over four streams so that small systems overlap.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -96,6 +97,40 @@ nrs_status stage(nrs_ctx* ctx, size_t bytes, char** host) {
   return NRS_OK;
 }
 
+// Side streams and events of the context (created once, before any capture).
+nrs_status aux_ready(nrs_ctx* ctx) {
+  if (ctx->fork_ev) return NRS_OK;
+  for (int j = 0; j < nrs_ctx::kAux; ++j) {
+    NRS_BHIP(ctx, hipStreamCreateWithFlags(&ctx->aux[j], hipStreamNonBlocking));
+    NRS_BHIP(ctx, hipEventCreateWithFlags(&ctx->join_ev[j], hipEventDisableTiming));
+  }
+  NRS_BHIP(ctx, hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+  return NRS_OK;
+}
+
+// The side streams wait for everything queued so far on the context's stream.
+nrs_status fork_aux(nrs_ctx* ctx) {
+  NRS_BHIP(ctx, hipEventRecord(ctx->fork_ev, ctx->stream));
+  for (int j = 0; j < nrs_ctx::kAux; ++j)
+    NRS_BHIP(ctx, hipStreamWaitEvent(ctx->aux[j], ctx->fork_ev, 0));
+  return NRS_OK;
+}
+
+// The context's stream waits for everything queued on the side streams.
+nrs_status join_aux(nrs_ctx* ctx) {
+  for (int j = 0; j < nrs_ctx::kAux; ++j) {
+    NRS_BHIP(ctx, hipEventRecord(ctx->join_ev[j], ctx->aux[j]));
+    NRS_BHIP(ctx, hipStreamWaitEvent(ctx->stream, ctx->join_ev[j], 0));
+  }
+  return NRS_OK;
+}
+
+// Stream of system k's per-system kernels between a fork and a join.
+hipStream_t lane_stream(const nrs_ctx* ctx, int k) {
+  const int j = k % (nrs_ctx::kAux + 1);
+  return j == 0 ? ctx->stream : ctx->aux[j - 1];
+}
+
 // Host descriptors (systems, ticket prefixes) of a batch layout, in bytes.
 size_t desc_bytes(const BatchLayout& L, int32_t B) {
   return sizeof(LuSys<float>) * B + sizeof(TrsvSys<float>) * B +
@@ -153,11 +188,14 @@ nrs_status enqueue_batch(nrs_ctx* ctx, int32_t B, const nrs_problem* problems,
   if (record_event) NRS_BHIP(ctx, hipEventRecord(ctx->staging_event, s));
   NRS_BHIP(ctx, launch_fill_i32(L.ctl, 0, 8, s));
 
-  // ---- per system: layout, right-hand side, FP32 assembly ----
+  // ---- per system: layout, right-hand side, FP32 assembly (systems spread
+  // over the side streams) ----
+  if ((st = fork_aux(ctx))) return st;
   for (int k = 0; k < B; ++k) {
     const nrs_problem& p = problems[k];
     SolveBuffers& sb = L.sb[k];
     const int64_t n = 3 * p.N + 6 * (int64_t)p.M;
+    hipStream_t s = lane_stream(ctx, k);
     NRS_BHIP(ctx, launch_state_init(sb.st, NRS_FP32_IR, s));
     NRS_BHIP(ctx, launch_fill_i32(sb.tsync, 0, trsv_sync_ints(n), s));
     NRS_BHIP(ctx, launch_fill_i32(sb.lu_done, 0, lu_tiles_nt(n) * lu_tiles_nt(n), s));
@@ -170,6 +208,7 @@ nrs_status enqueue_batch(nrs_ctx* ctx, int32_t B, const nrs_problem* problems,
     if (norm) NRS_BHIP(ctx, launch_anorm32(n, sb.A32, sb.lda, sb.st, sb.red, s));
     NRS_BHIP(ctx, launch_convert_f32(n, sb.b, reinterpret_cast<float*>(sb.r), s));
   }
+  if ((st = join_aux(ctx))) return st;
 
   // ---- every factorisation in one launch ----
   LuBatch<float> lb;
@@ -191,23 +230,29 @@ nrs_status enqueue_batch(nrs_ctx* ctx, int32_t B, const nrs_problem* problems,
 
   // ---- x0 = (LU)^-1 b, then refinement sweeps ----
   NRS_BHIP(ctx, launch_trsv_batch<float>(tb, 1, L.ctl + 4, L.ctl + 6, s));
+  if ((st = fork_aux(ctx))) return st;
   for (int k = 0; k < B; ++k)
     NRS_BHIP(ctx, launch_ir_update32(3 * problems[k].N + 6 * (int64_t)problems[k].M, sol[k],
-                                     L.sb[k].d32, tol, 1, L.sb[k].st, s));
+                                     L.sb[k].d32, tol, 1, L.sb[k].st, lane_stream(ctx, k)));
   for (int it = 0; it < max_refine; ++it) {
+    // the FP64 residual of system k follows its update on the same stream
     for (int k = 0; k < B; ++k) {
       const nrs_problem& p = problems[k];
       SolveBuffers& sb = L.sb[k];
       const int64_t n = 3 * p.N + 6 * (int64_t)p.M;
-      NRS_BHIP(ctx, launch_apply(p, sb.srt, sol[k], sb.d64, sb.part, sb.chunks, &sb.st->stop, s));
+      hipStream_t sk = lane_stream(ctx, k);
+      NRS_BHIP(ctx, launch_apply(p, sb.srt, sol[k], sb.d64, sb.part, sb.chunks, &sb.st->stop, sk));
       NRS_BHIP(ctx, launch_ir_residual2(n, sb.b, sb.d64, sol[k], nullptr,
-                                        reinterpret_cast<float*>(sb.r), nullptr, sb.st, 0, s));
+                                        reinterpret_cast<float*>(sb.r), nullptr, sb.st, 0, sk));
     }
+    if ((st = join_aux(ctx))) return st;
     NRS_BHIP(ctx, launch_trsv_batch<float>(tb, 1, L.ctl + 4, L.ctl + 6, s));
+    if ((st = fork_aux(ctx))) return st;
     for (int k = 0; k < B; ++k)
       NRS_BHIP(ctx, launch_ir_update32(3 * problems[k].N + 6 * (int64_t)problems[k].M, sol[k],
-                                       L.sb[k].d32, tol, 0, L.sb[k].st, s));
+                                       L.sb[k].d32, tol, 0, L.sb[k].st, lane_stream(ctx, k)));
   }
+  if ((st = join_aux(ctx))) return st;
   return NRS_OK;
 }
 
@@ -333,6 +378,7 @@ nrs_status nrs_solve_batched(nrs_ctx* ctx, int32_t B, const nrs_problem* problem
   BatchLayout L;
   if (!carve_batch(ar, B, problems, L)) return bfail(ctx, NRS_E_WORKSPACE, "workspace too small");
   hipStream_t s = ctx->stream;
+  if ((st = aux_ready(ctx))) return st;
 
   if (o.graph) {
     if (infos) return bfail(ctx, NRS_E_ARG, "graph replay is asynchronous: pass infos = NULL");
@@ -345,13 +391,16 @@ nrs_status nrs_solve_batched(nrs_ctx* ctx, int32_t B, const nrs_problem* problem
   if (!infos) return NRS_OK;
 
   // ---- synchronous report: final FP64 backward error of every system ----
+  if ((st = fork_aux(ctx))) return st;
   for (int k = 0; k < B; ++k) {
     const nrs_problem& p = problems[k];
     SolveBuffers& sb = L.sb[k];
     const int64_t n = 3 * p.N + 6 * (int64_t)p.M;
-    NRS_BHIP(ctx, launch_apply(p, sb.srt, sol[k], sb.d64, sb.part, sb.chunks, nullptr, s));
-    NRS_BHIP(ctx, launch_ir_residual2(n, sb.b, sb.d64, sol[k], sb.r, nullptr, nullptr, sb.st, 1, s));
+    hipStream_t sk = lane_stream(ctx, k);
+    NRS_BHIP(ctx, launch_apply(p, sb.srt, sol[k], sb.d64, sb.part, sb.chunks, nullptr, sk));
+    NRS_BHIP(ctx, launch_ir_residual2(n, sb.b, sb.d64, sol[k], sb.r, nullptr, nullptr, sb.st, 1, sk));
   }
+  if ((st = join_aux(ctx))) return st;
   NRS_BHIP(ctx, hipStreamSynchronize(s));
   int32_t ctl_h[8];
   NRS_BHIP(ctx, hipMemcpy(ctl_h, L.ctl, sizeof(ctl_h), hipMemcpyDeviceToHost));

@@ -54,6 +54,14 @@ struct nrs_ctx {
   std::vector<nrs_graph_entry> graphs;
   // autotuned assembly shapes by size class
   std::vector<nrs_tune_entry> tune;
+  // side streams of the batched solve (default priority): the per-system
+  // kernels of a batch are spread over the context's stream and these, forked
+  // from and joined back into the context's stream with events, so that the
+  // short kernels of different systems overlap
+  static constexpr int kAux = 3;
+  hipStream_t aux[kAux] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kAux] = {};
 };
 
 namespace nrs {
