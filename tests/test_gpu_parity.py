@@ -240,6 +240,28 @@ def test_lu_tiles_bf16_updates(ctx):
         assert errs[2] < errs[0], (n, errs)
 
 
+def test_lu_tiles_repeatable(ctx):
+    """Repeated single-system tile-LU factorisations of the same matrix are
+    bit-identical (every tile's stores land before its completion flag), in
+    FP32 and with BF16 update inputs, for a ragged and a tile-aligned order."""
+    rng = np.random.default_rng(21)
+    for n in (3150, 1024):
+        A0 = torch.from_numpy((rng.normal(size=(n, n)) + 3 * np.sqrt(n) * np.eye(n)).T.copy())
+        A0 = A0.to(torch.float32).to(DEV)
+        for bf in (False, True):
+            first = None
+            for rep in range(10):
+                A = A0.clone()
+                ipiv = torch.empty(n, dtype=torch.int32, device=DEV)
+                perm = torch.empty(n, dtype=torch.int32, device=DEV)
+                sing = torch.zeros(1, dtype=torch.int32, device=DEV)
+                nrs.nrs_lu_factor(ctx, A, n, ipiv, perm, sing, pivot_scope=1, bf16_updates=bf)
+                if first is None:
+                    first = (A, perm)
+                    continue
+                assert torch.equal(A, first[0]) and torch.equal(perm, first[1]), (n, bf, rep)
+
+
 SOLVE_CASES = [
     ("sphere_c1", lambda: synth.sphere_scene(4, 16)),
     ("filaments_M1", lambda: synth.filament_scene(1, seed=0)),
