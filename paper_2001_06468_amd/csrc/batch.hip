@@ -31,7 +31,7 @@ struct BatchLayout {
   int32_t* ctl;            // [0..3] LU ticket/exit/timeout, [4..5] trsv ticket/done, [6] trsv err
   LuSys<float>* lusys;     // [B]
   TrsvSys<float>* trsys;   // [B]
-  int32_t* lu_pref;        // [nbands*B + 1]
+  int32_t* lu_pref;        // [2*nbands*B + 1]
   int32_t* tr_pref;        // [nsteps*B + 1]
   std::vector<SolveBuffers> sb;
   std::vector<int32_t> lu_pref_h, tr_pref_h;

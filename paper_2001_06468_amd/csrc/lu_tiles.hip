@@ -10,10 +10,12 @@
 //                    registers, pivot rows relabelled instead of moved);
 //           i <  j : U_mj = L_mm^-1 P_m C   (one lane per column);
 //           i >  j : L_im = C U_mm^-1       (one lane per row).
-// Tasks are numbered band by band (system by system inside a band), which is
-// a topological order; each workgroup of the single launch takes its task
-// number from an atomic ticket, so a task only waits for tasks whose owners
-// already run.  Every wait is bounded (a timeout raises ctl[2] and the kernel
+// Tasks are numbered band by band; inside a band of a batch, first the
+// diagonal tasks of all systems, then the off-diagonal tasks system by
+// system, so that a system's row and column tasks are taken after its
+// diagonal task has had the others' time to finish.  That is a topological
+// order; each workgroup of the single launch takes its task number from an
+// atomic ticket, so a task only waits for tasks whose owners already run.  Every wait is bounded (a timeout raises ctl[2] and the kernel
 // still completes), and the last workgroup to finish clears the ticket and
 // all completion flags.
 //
@@ -442,7 +444,10 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
                    __hip_atomic_load(&sy.done[i * nt + e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &&
                    __hip_atomic_load(&sy.done[e * nt + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
               ++e;
+            // the invalidation must be complete before the barrier lets the
+            // other waves load the tiles
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __builtin_amdgcn_s_waitcnt(kWaitVmem);
             S.task[2] = (int32_t)e;
           }
           __syncthreads();
@@ -499,7 +504,10 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
                  __hip_atomic_load(&sy.done[i * nt + e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &&
                  __hip_atomic_load(&sy.done[e * nt + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             ++e;
+          // the invalidation must be complete before the barrier lets the
+          // other waves load the tiles
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          __builtin_amdgcn_s_waitcnt(kWaitVmem);
           S.task[2] = (int32_t)e;
         }
         __syncthreads();
@@ -554,6 +562,7 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
       if (tid == 0) {
         wait_flag(&sy.done[m * nt + m], err);
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_s_waitcnt(kWaitVmem);
       }
     }
     __syncthreads();
@@ -658,8 +667,9 @@ __global__ __launch_bounds__(kLuThreads, MINB) void k_lu_tiles(LuBatch<T> bt, in
   __syncthreads();
   const int32_t t = S.task[0];
   if (t < bt.total) {
-    // (band, system) of the ticket: last prefix entry <= t.  One system:
-    // band m starts at m (2 nt - m).
+    // (band, part, system) of the ticket: last prefix entry <= t; the
+    // off-diagonal part starts at p = 1.  One system: band m starts at
+    // m (2 nt - m).
     int m, s, p;
     if (bt.sys == nullptr) {
       const int64_t ntt = bt.one.nt;
@@ -672,14 +682,15 @@ __global__ __launch_bounds__(kLuThreads, MINB) void k_lu_tiles(LuBatch<T> bt, in
       s = 0;
       p = (int)(t - (int64_t)lo * (2 * ntt - lo));
     } else {
-      int lo = 0, hi = bt.nbands * B;  // pref[lo] <= t < pref[hi]
+      int lo = 0, hi = 2 * bt.nbands * B;  // pref[lo] <= t < pref[hi]
       while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
         if (bt.pref[mid] <= t) lo = mid; else hi = mid;
       }
-      m = lo / B;
+      const int half = lo / B;
+      m = half >> 1;
       s = lo % B;
-      p = t - bt.pref[lo];
+      p = t - bt.pref[lo] + (half & 1);
     }
     int64_t i, j;
     if (p == 0) {
@@ -716,19 +727,25 @@ __global__ __launch_bounds__(kLuThreads, MINB) void k_lu_tiles(LuBatch<T> bt, in
 
 }  // namespace
 
-// Ticket prefix over (band, system): pref[b*B + s] = first ticket of band b
-// of system s; band b of a system with nt tiles has 2(nt-b)-1 tasks.
+// Ticket prefix over (band, part, system): pref[(2b)*B + s] = ticket of the
+// diagonal task of band b of system s, pref[(2b+1)*B + s] = first ticket of
+// its 2(nt-b)-2 off-diagonal tasks (empty entries once b >= nt).
 void lu_task_prefix(const int32_t* nts, int32_t B, std::vector<int32_t>& pref, int32_t& nbands) {
   nbands = 0;
   for (int s = 0; s < B; ++s) nbands = std::max(nbands, nts[s]);
-  pref.assign((size_t)nbands * B + 1, 0);
+  pref.assign((size_t)2 * nbands * B + 1, 0);
   int32_t acc = 0;
-  for (int b = 0; b < nbands; ++b)
+  for (int b = 0; b < nbands; ++b) {
     for (int s = 0; s < B; ++s) {
-      pref[(size_t)b * B + s] = acc;
-      if (b < nts[s]) acc += 2 * (nts[s] - b) - 1;
+      pref[(size_t)(2 * b) * B + s] = acc;
+      if (b < nts[s]) acc += 1;
     }
-  pref[(size_t)nbands * B] = acc;
+    for (int s = 0; s < B; ++s) {
+      pref[(size_t)(2 * b + 1) * B + s] = acc;
+      if (b < nts[s]) acc += 2 * (nts[s] - b) - 2;
+    }
+  }
+  pref[(size_t)2 * nbands * B] = acc;
 }
 
 template <class T>
