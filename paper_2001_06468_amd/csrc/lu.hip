@@ -312,6 +312,10 @@ __global__ void k_ipiv_to_perm(int64_t n, const int32_t* __restrict__ ipiv, int3
 constexpr int kTb = 64;
 constexpr int kTrsvThreads = 256;
 constexpr int64_t kSpinLimit = 1 << 22;
+// s_waitcnt operand that waits for vmcnt = 0 and leaves expcnt and lgkmcnt at
+// their maxima (gfx9 layout: vmcnt in bits 3:0 and 15:14, expcnt 6:4,
+// lgkmcnt 11:8).
+constexpr int kWaitVmem = 0x0F70;
 
 // Orders a wavefront's LDS accesses around a hand-over between its lanes.
 __device__ inline void wave_sync_lds() {
@@ -422,7 +426,10 @@ __global__ __launch_bounds__(kTrsvThreads) void k_trsv(TrsvBatch<T> bt, int32_t*
       }
       int64_t je = j + jstep;
       while (je != b && ld_relaxed(&flags[je]) != 0) je += jstep;
+      // the L1 invalidation must be complete before the barrier lets the
+      // other waves read the published blocks
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __builtin_amdgcn_s_waitcnt(kWaitVmem);
       s_jend = (int)je;
     }
     __syncthreads();
