@@ -520,6 +520,17 @@ def main():
     learned_info = None
     if not args.no_forms:
         forms["dopri5_" + args.method] = run_dopri(ctx, nrs, ds, scene, dev, method)
+        if method == nrs.NRS_FP32_IR:
+            # the same steps with stages 2-4 refined against the first stage's
+            # FP32 factors (no assembly or factorisation there); final state
+            # compared with the headline run's
+            fm, _, Yr, _, finfo = run_steps(method, args.warmup, args.steps,
+                                            reuse_stage_factors=1)
+            forms["fp32_ir_stage_factor_reuse"] = {
+                "solves_per_s": 4 * args.steps / (fm / 1e3), "ms_per_step": fm / args.steps,
+                "steps": args.steps, "fell_back": finfo["fell_back"],
+                "max_stage_iterations_last_step": finfo["iterations"],
+                "max_abs_state_diff_vs_headline": float((Yr - Y).abs().max())}
         for name, m in METHODS.items():
             if m == method:
                 continue

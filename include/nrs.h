@@ -172,6 +172,15 @@ typedef struct {
      (same sizes, pointers, eps, mu, workspace and refinement settings; the
      array contents may change).  Up to 8 graphs are kept per context. */
   int32_t graph;
+  /* nrs_rk4_step / nrs_rk4_step_tracers with NRS_FP32_IR, non-zero: only the
+     first stage of a step assembles and factors; stages 2-4 refine against
+     those FP32 factors (x0 from them, then FP64 matrix-free residuals and
+     correction sweeps, at most max_refine sweeps, <= 0: 12), since the
+     stage matrices differ from the first one by the motion over dt/2 or dt.
+     The stopping rule and the accuracy are those of NRS_FP32_IR; a stage
+     that does not converge sends the step to the FP64 fallback like any
+     failed stage.  Ignored by every other call. */
+  int32_t reuse_stage_factors;
 } nrs_options;
 
 typedef struct {

@@ -200,6 +200,27 @@ nrs_status run_fp32_ir(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, do
   return NRS_OK;
 }
 
+// Refinement against factors already in sb.A32 / sb.perm (the tile LU of an
+// earlier, nearby system): x0 from them, then FP64 matrix-free residuals of
+// this system and correction sweeps; queued sweeps after convergence skip.
+nrs_status run_fp32_reuse(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, double* x,
+                          int32_t max_refine, double tol, hipStream_t s) {
+  const int64_t n = 3 * pb.N + 6 * (int64_t)pb.M;
+  float* b32 = reinterpret_cast<float*>(sb.r);
+  NRS_HIP(ctx, launch_convert_f32(n, sb.b, b32, s));
+  NRS_HIP(ctx, launch_lu_solve<float>(n, 1, sb.A32, sb.lda, sb.perm, b32, sb.d32, sb.tsync,
+                                      &sb.st->sync_err, &sb.st->stop, s));
+  NRS_HIP(ctx, launch_ir_update32(n, x, sb.d32, tol, 1, sb.st, s));
+  for (int it = 0; it < max_refine; ++it) {
+    NRS_HIP(ctx, launch_apply(pb, sb.srt, x, sb.d64, sb.part, sb.chunks, &sb.st->stop, s));
+    NRS_HIP(ctx, launch_ir_residual2(n, sb.b, sb.d64, x, nullptr, b32, nullptr, sb.st, 0, s));
+    NRS_HIP(ctx, launch_lu_solve<float>(n, 1, sb.A32, sb.lda, sb.perm, b32, sb.d32, sb.tsync,
+                                        &sb.st->sync_err, &sb.st->stop, s));
+    NRS_HIP(ctx, launch_ir_update32(n, x, sb.d32, tol, 0, sb.st, s));
+  }
+  return NRS_OK;
+}
+
 // FP64 GMRES on the stored FP64 matrix from x's initial content (x_init
 // copied in by the caller, else zero).  Synchronises once per chunk of
 // Arnoldi steps to decide whether to queue more.
@@ -328,7 +349,7 @@ void fill_info(const SolveState& h, nrs_info* info) {
 // state is read back and the FP64 fallback may run.
 nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, const double* ftext,
                       const nrs_options& o, SolveBuffers& sb, double* sol, bool sync,
-                      SolveState* hst_out) {
+                      SolveState* hst_out, bool reuse = false) {
   hipStream_t s = ctx->stream;
   const int64_t N = pb.N, Q = pb.Q, n = 3 * N + 6 * (int64_t)pb.M;
   const int32_t method = o.method;
@@ -342,7 +363,9 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
   NRS_HIP(ctx, launch_check_body(N, pb.M, pb.body, sb.st, s));
   NRS_HIP(ctx, launch_rhs(N, pb.M, u, ftext, sb.b, s));
   nrs_status st = NRS_OK;
-  if (method == NRS_FP64_LU) {
+  if (reuse) {
+    st = run_fp32_reuse(ctx, pb, sb, sol, o.max_refine > 0 ? o.max_refine : 12, tol, s);
+  } else if (method == NRS_FP64_LU) {
     st = run_fp64_lu(ctx, pb, sb, sol, sync, s);
   } else if (uses_fp32(method)) {
     const bool fgm = gmres_ir(method);
@@ -803,7 +826,8 @@ bool carve_rk(Arena& ar, const nrs_scene& sc, int32_t method, int64_t P, RkBuffe
 // workspace may seed a GMRES warm start.
 nrs_status stage_solve(nrs_ctx* ctx, const nrs_scene& sc, const GroupTable& gt,
                        const int32_t* groupX, double eps, double mu, const double* ftext,
-                       double tt, const nrs_options& o, RkBuffers& rb, bool warm, double* Kout) {
+                       double tt, const nrs_options& o, RkBuffers& rb, bool warm, double* Kout,
+                       bool reuse = false) {
   hipStream_t s = ctx->stream;
   NRS_HIP(ctx, launch_geometry(sc, tt, rb.Ys, rb.x, rb.X, rb.w, rb.u, s));
   NRS_HIP(ctx, launch_nearest(sc.N, rb.x, gt, sc.Q, rb.X, groupX, rb.nu, s));
@@ -835,7 +859,7 @@ nrs_status stage_solve(nrs_ctx* ctx, const nrs_scene& sc, const GroupTable& gt,
       os.x_init_complete = 1;
     }
   }
-  nrs_status st = solve_core(ctx, pb, rb.u, ftext, os, rb.sb, rb.sol, false, nullptr);
+  nrs_status st = solve_core(ctx, pb, rb.u, ftext, os, rb.sb, rb.sol, false, nullptr, reuse);
   if (st != NRS_OK) return st;
   NRS_HIP(ctx, launch_state_accumulate(rb.report, rb.sb.st, s));
   NRS_HIP(ctx, launch_rk_rates(sc.M, sc.N, rb.Ys, rb.sol, Kout, s));
@@ -851,8 +875,10 @@ nrs_status rk4_pass(nrs_ctx* ctx, const nrs_scene& sc, const GroupTable& gt,
   NRS_HIP(ctx, launch_state_init(rb.report, o.method, s));
   for (int stg = 0; stg < 4; ++stg) {
     NRS_HIP(ctx, launch_rk_stage_state(sc.M, Y, stg ? rb.K[stg - 1] : nullptr, c[stg], rb.Ys, s));
+    // stages 2-4 may refine against the first stage's FP32 factors
+    const bool reuse = stg > 0 && o.reuse_stage_factors && o.method == NRS_FP32_IR;
     nrs_status st = stage_solve(ctx, sc, gt, groupX, eps, mu, ftext, t + c[stg], o, rb,
-                                stg > 0 || prev_valid, rb.K[stg]);
+                                stg > 0 || prev_valid, rb.K[stg], reuse);
     if (st != NRS_OK) return st;
     if (rb.P > 0) {
       // this stage's flow (its geometry and forces) at the tracers' stage positions

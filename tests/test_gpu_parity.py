@@ -320,22 +320,52 @@ def test_solve_is_deterministic(ctx):
     np.testing.assert_array_equal(s1, s2)
 
 
-@pytest.mark.parametrize("method", ["FP64_LU", "FP32_IR"])
+@pytest.mark.parametrize("method", ["FP64_LU", "FP32_IR", "FP32_IR_REUSE"])
 def test_rk4_step_matches_oracle(ctx, method):
+    """Two RK4 steps against the oracle; FP32_IR_REUSE: stages 2-4 refine
+    against the first stage's factors (reuse_stage_factors)."""
     scene = synth.filament_scene(5, seed=0)
     ds = nrs.DeviceScene(scene)
-    m = getattr(nrs, "NRS_" + method)
+    reuse = method.endswith("_REUSE")
+    m = getattr(nrs, "NRS_" + method.replace("_REUSE", ""))
     ws = torch.empty(nrs.nrs_rk4_workspace_size(ctx, ds, m), dtype=torch.uint8, device=DEV)
     Y = T(scene["Y0"])
     Yo = scene["Y0"].copy()
     dt = 2 * math.pi / 100
     for step in range(2):
-        nrs.nrs_rk4_step(ctx, ds, Y, step * dt, dt, ws, method=m)
+        nrs.nrs_rk4_step(ctx, ds, Y, step * dt, dt, ws, method=m, reuse_stage_factors=int(reuse))
         Yo = oracle.rk4_step(scene, Yo, step * dt, dt)
     info = nrs.nrs_query_info(ctx, ws)
     assert info["fell_back"] == 0
     err = np.max(np.abs(Y.cpu().numpy().reshape(-1, 12) - Yo))
     assert err <= 1e-10, err
+
+
+def test_rk4_stage_factor_reuse_at_headline_size(ctx):
+    """25 filaments (n = 3150): three RK4 steps with stages 2-4 refined
+    against the first stage's factors agree with refactoring every stage to
+    the refinement tolerance, with no fallback; the option is ignored by the
+    FP64 method."""
+    scene = synth.filament_scene(25, seed=0)
+    ds = nrs.DeviceScene(scene)
+    m = nrs.NRS_FP32_IR
+    ws = torch.empty(nrs.nrs_rk4_workspace_size(ctx, ds, m), dtype=torch.uint8, device=DEV)
+    dt = 2 * math.pi / 100
+    Ys = []
+    for reuse in (0, 1):
+        Y = T(scene["Y0"])
+        for step in range(3):
+            nrs.nrs_rk4_step(ctx, ds, Y, step * dt, dt, ws, method=m, reuse_stage_factors=reuse)
+            info = nrs.nrs_query_info(ctx, ws)
+            assert info["fell_back"] == 0, (reuse, step, info)
+        Ys.append(Y.cpu().numpy())
+    err = np.abs(Ys[0] - Ys[1]).max()
+    assert err <= 1e-10, err
+    Y64 = [T(scene["Y0"]), T(scene["Y0"])]
+    for reuse, Yd in zip((0, 1), Y64):
+        nrs.nrs_rk4_step(ctx, ds, Yd, 0.0, dt, ws, method=nrs.NRS_FP64_LU,
+                         reuse_stage_factors=reuse)
+    np.testing.assert_array_equal(Y64[0].cpu().numpy(), Y64[1].cpu().numpy())
 
 
 def test_errors_are_reported(ctx):
