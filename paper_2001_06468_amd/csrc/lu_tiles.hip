@@ -388,6 +388,38 @@ __device__ void diag_ipiv(Shared<T>& S, const LuSys<T>& sy, int64_t m) {
   }
 }
 
+// Wave 0 of a task: wait until term k of tile (i, j) is published (its L and
+// U tiles), then return the end e of the run [k, e) of terms whose tiles are
+// all published, the 64 lanes testing 64 terms at a time; the acquire (and
+// the completion of its L1 invalidation) orders every later tile load of the
+// workgroup after the flags.
+template <class T>
+__device__ inline int64_t published_run(const LuSys<T>& sy, int64_t i, int64_t j, int64_t k,
+                                        int64_t m, int32_t* err, int lane) {
+  const int64_t nt = sy.nt;
+  if (lane == 0) {
+    wait_flag(&sy.done[i * nt + k], err);
+    wait_flag(&sy.done[k * nt + j], err);
+  }
+  int64_t e = k + 1;
+  for (;;) {
+    const int64_t q = e + lane;
+    bool ok = false;
+    if (q < m) {
+      const int32_t a = __hip_atomic_load(&sy.done[i * nt + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int32_t b = __hip_atomic_load(&sy.done[q * nt + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      ok = a != 0 && b != 0;
+    }
+    const uint64_t bal = __ballot(ok);
+    const int run = bal == ~0ull ? 64 : __builtin_ctzll(~bal);
+    e += run;
+    if (run < 64) break;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __builtin_amdgcn_s_waitcnt(kWaitVmem);
+  return e;
+}
+
 // One tile task: update, then factor / solve, store, publish.
 template <class T, bool B16>
 __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
@@ -436,19 +468,9 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
       int64_t kend = 0;
       for (int64_t k = 0; k < m; ++k) {
         if (k >= kend) {
-          if (tid == 0) {
-            wait_flag(&sy.done[i * nt + k], err);
-            wait_flag(&sy.done[k * nt + j], err);
-            int64_t e = k + 1;
-            while (e < m &&
-                   __hip_atomic_load(&sy.done[i * nt + e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &&
-                   __hip_atomic_load(&sy.done[e * nt + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-              ++e;
-            // the invalidation must be complete before the barrier lets the
-            // other waves load the tiles
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            __builtin_amdgcn_s_waitcnt(kWaitVmem);
-            S.task[2] = (int32_t)e;
+          if (w == 0) {
+            const int64_t e = published_run(sy, i, j, k, m, err, lane);
+            if (lane == 0) S.task[2] = (int32_t)e;
           }
           __syncthreads();
           kend = S.task[2];
@@ -496,19 +518,9 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
     int64_t kend = 0;
     for (int64_t k = 0; k < m; ++k) {
       if (k >= kend) {
-        if (tid == 0) {
-          wait_flag(&sy.done[i * nt + k], err);
-          wait_flag(&sy.done[k * nt + j], err);
-          int64_t e = k + 1;
-          while (e < m &&
-                 __hip_atomic_load(&sy.done[i * nt + e], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) &&
-                 __hip_atomic_load(&sy.done[e * nt + j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-            ++e;
-          // the invalidation must be complete before the barrier lets the
-          // other waves load the tiles
-          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-          __builtin_amdgcn_s_waitcnt(kWaitVmem);
-          S.task[2] = (int32_t)e;
+        if (w == 0) {
+          const int64_t e = published_run(sy, i, j, k, m, err, lane);
+          if (lane == 0) S.task[2] = (int32_t)e;
         }
         __syncthreads();
         kend = S.task[2];
