@@ -36,7 +36,7 @@ PEAK_FP64_TFLOPS = 78.6
 # HBM bytes per launch of the tile LU at n = 3150 from the FETCH_SIZE and
 # WRITE_SIZE counter runs (calibrated against a 256 MiB copy), valid only for
 # the kernel source they were taken on (first 16 hex digits of its SHA-256).
-LU_TRAFFIC = {"source_sha256_16": "d50c803837789177", "bytes_per_launch": 792564835, "n": 3150}
+LU_TRAFFIC = {"source_sha256_16": "27adf9ab58c1e98f", "bytes_per_launch": 790281869, "n": 3150}
 # HBM bytes per nrs_field_velocity call (sources + pair sum + chunk sum) on the
 # tracer workload, from the same two counter runs, valid for that field.hip.
 FIELD_TRAFFIC = {"source_sha256_16": "7f18d8d2f998ad7c", "bytes_per_call": 24459390, "Q": 73248,

@@ -420,6 +420,12 @@ __device__ inline int64_t published_run(const LuSys<T>& sy, int64_t i, int64_t j
   return e;
 }
 
+// Slot of U(k, c) in the update loop's staging tile S.Us: rows of 64, the
+// column XOR-swizzled by a rotation of the row index, so that the
+// transposing stores (one row per lane) and the matrix-core reads (16
+// columns of 4 rows) each touch 64 different banks.
+__device__ inline int us_at(int k, int c) { return k * TB + (c ^ (((k & 3) << 4) | (k >> 2))); }
+
 // One tile task: update, then factor / solve, store, publish.
 template <class T, bool B16>
 __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
@@ -536,7 +542,7 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
       for (int q = 0; q < 16; ++q) {
         const int c = c0 + 4 * q;
         S.Ls[c * kLS + r] = la[q];
-        S.Us[r * kLS + c] = ua[q];
+        S.Us[us_at(r, c)] = ua[q];
       }
       __syncthreads();
       if (k + 1 < kend) {  // next term's tiles, in flight during this one
@@ -551,7 +557,7 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
       for (int kk = 0; kk < TB; kk += 4) {
         const int kr = kk + (lane >> 4), li = lane & 15;
         const T a0 = S.Ls[kr * kLS + qi + li], a1 = S.Ls[kr * kLS + qi + 16 + li];
-        const T b0 = S.Us[kr * kLS + qj + li], b1 = S.Us[kr * kLS + qj + 16 + li];
+        const T b0 = S.Us[us_at(kr, qj + li)], b1 = S.Us[us_at(kr, qj + 16 + li)];
         acc[0][0] = Mf<T>::run(a0, b0, acc[0][0]);
         acc[0][1] = Mf<T>::run(a0, b1, acc[0][1]);
         acc[1][0] = Mf<T>::run(a1, b0, acc[1][0]);
