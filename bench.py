@@ -208,10 +208,12 @@ def run_channel(ctx, nrs, synth, dev):
         sing = torch.zeros(1, dtype=torch.int32, device=dev)
         for name, bf in (("lu_fp32", False), ("lu_bf16_updates", True)):
             A32.copy_(A0)
+            wl = torch.empty(nrs.nrs_lu_factor_workspace_size(ctx, n, 16 if bf else 32),
+                             dtype=torch.uint8, device=dev)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
-            nrs.nrs_lu_factor(ctx, A32, lda, ipiv, perm, sing, pivot_scope=1, bf16_updates=bf)
+            nrs.nrs_lu_factor(ctx, A32, lda, ipiv, perm, sing, wl, pivot_scope=1, bf16_updates=bf)
             e1.record()
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1)
@@ -481,12 +483,13 @@ def main():
     perm = torch.empty(n, dtype=torch.int32, device=dev)
     sing = torch.zeros(1, dtype=torch.int32, device=dev)
     lu_ms = []
+    wl = torch.empty(nrs.nrs_lu_factor_workspace_size(ctx, n, 32), dtype=torch.uint8, device=dev)
     for rep in range(12):
         A32.copy_(A0)
         a0 = torch.cuda.Event(enable_timing=True)
         a1 = torch.cuda.Event(enable_timing=True)
         a0.record()
-        nrs.nrs_lu_factor(ctx, A32, lda, ipiv, perm, sing, pivot_scope=1)
+        nrs.nrs_lu_factor(ctx, A32, lda, ipiv, perm, sing, wl, pivot_scope=1)
         a1.record()
         torch.cuda.synchronize()
         if rep >= 2:

@@ -70,8 +70,9 @@ typedef int32_t nrs_status;
 typedef struct nrs_ctx nrs_ctx;
 
 /* Create a context on HIP device `device` that enqueues on `stream` (a
- * hipStream_t, borrowed; NULL = the null stream).  The context holds only a
- * few small device buffers (status words, pivots bookkeeping).
+ * hipStream_t, borrowed; NULL = the null stream).  The context's own device
+ * memory is 64 bytes of status words (allocated on first use by the network
+ * calls); every larger buffer is a caller workspace.
  * Returns NRS_E_HIP if the device cannot be selected. */
 nrs_status  nrs_create(nrs_ctx** out, int device, void* stream);
 nrs_status  nrs_destroy(nrs_ctx* ctx);
@@ -281,7 +282,7 @@ nrs_status nrs_solve_batched(nrs_ctx* ctx, int32_t B, const nrs_problem* problem
 /* In-place LU factorisation of the n x n column-major matrix A (precision 32
  * or 64; 16 = FP32 matrix and factors whose trailing updates take BF16
  * copies of the finished tiles on the matrix cores with FP32 accumulation,
- * pivot_scope 1 only, the copies held by the context), n <= 262144.
+ * pivot_scope 1 only), n <= 262144.
  * pivot_scope = 0: partial pivoting over the whole column, P A = L U.
  * pivot_scope = 1: static block pivoting for use with iterative refinement:
  *   pivots are searched only inside each 64 x 64 diagonal tile, and those
@@ -295,17 +296,38 @@ nrs_status nrs_solve_batched(nrs_ctx* ctx, int32_t B, const nrs_problem* problem
  *        scope 1: logical row i of its tile came from original row perm[i];
  *   singular_flag [1] int32: set to 1 if an exact zero pivot is met (left
  *        untouched otherwise; the caller clears it).
- * Needs no workspace (the context keeps a few zeroed synchronisation words).
- * Asynchronous. */
+ * ws: device workspace of at least nrs_lu_factor_workspace_size(n, precision)
+ * bytes, owned by the caller (the tile LU's ticket, flag and timeout words,
+ * cleared by the call itself, and for precision 16 the BF16 tile copies,
+ * 2 n^2 bytes rounded up to whole tiles).  The same workspace must not be in
+ * use by another call that has not completed.  nrs_lu_query() reports
+ * whether a bounded wait of the call timed out (the factors are then not
+ * valid).  Asynchronous.
+ * Errors: NRS_E_ARG (sizes, NULL pointers, lda < n, precision, scope),
+ * NRS_E_UNSUPPORTED (n > 262144), NRS_E_WORKSPACE, NRS_E_HIP. */
+nrs_status nrs_lu_factor_workspace_size(nrs_ctx* ctx, int64_t n, int32_t precision,
+                                        size_t* bytes);
 nrs_status nrs_lu_factor(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivot_scope,
                          void* A, int64_t lda, int32_t* ipiv, int32_t* perm,
-                         int32_t* singular_flag);
+                         int32_t* singular_flag, void* ws, size_t ws_bytes);
 
 /* Solve with the factors of nrs_lu_factor (same pivot_scope and perm):
- * x = A^-1 b, b and x [n] device vectors of the same precision (x may not
- * alias b).  Asynchronous. */
+ * x = A^-1 b, b and x [n] device vectors of the same precision (32 or 64;
+ * x may not alias b).  ws: device workspace of at least
+ * nrs_lu_solve_workspace_size(n) bytes, owned by the caller (the
+ * triangular solves' ticket, flag and solution-word buffers, cleared by the
+ * call itself).  Asynchronous; nrs_lu_query() reports a timed-out wait.
+ * Errors as nrs_lu_factor. */
+nrs_status nrs_lu_solve_workspace_size(nrs_ctx* ctx, int64_t n, size_t* bytes);
 nrs_status nrs_lu_solve(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivot_scope,
-                        const void* LU, int64_t lda, const int32_t* perm, const void* b, void* x);
+                        const void* LU, int64_t lda, const int32_t* perm, const void* b, void* x,
+                        void* ws, size_t ws_bytes);
+
+/* Synchronise the context's stream and report the status of the last
+ * nrs_lu_factor or nrs_lu_solve that used workspace ws: *flags = 1 if one of
+ * its bounded waits between workgroups timed out (its output is then not
+ * valid), else 0.  Each such call clears the word when it starts. */
+nrs_status nrs_lu_query(nrs_ctx* ctx, const void* ws, int32_t* flags);
 
 /* Autotuning of launch shapes.  Times every candidate launch shape of the
  * FP32 and FP64 assembly kernels (rows per workgroup 64 / 128 / 256 x force

@@ -22,6 +22,7 @@ from .core import (  # noqa: F401
     geometry, nearest, assemble_As, patch_weights, assemble_system, rhs,
     solve_system, solve_scene, split_solution, doolittle_solve,
     rates, rk4_step, orthonormalise, rk4_generic, gmres, condition_1,
+    solve_with_condition,
 )
 from .field import (  # noqa: F401
     field_velocity, tracer_rk4_step, rk4_step_tracers,

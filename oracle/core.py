@@ -169,7 +169,9 @@ def assemble_As(x, X, w, nu, eps, mu, chunk_pairs=1 << 21):
     """A_s = (8 pi mu)^-1 * S * diag(w (x) 1_3) * nuhat, literally as the
     product of the dense 3N x 3Q stokeslet matrix with the sparse 3Q x 3N
     nearest-neighbour matrix, the Q dimension taken in blocks (Sec. 3,
-    matrix view after eq. 23).  Row/column index j*N + m (component-major)."""
+    matrix view after eq. 23).  Row/column index j*N + m (component-major).
+    Within a block only the columns of nuhat that hold an entry of the block
+    are formed; every other column of that block's product is zero."""
     N = x.shape[1]
     Q = X.shape[1]
     As = np.zeros((3 * N, 3 * N))
@@ -184,8 +186,10 @@ def assemble_As(x, X, w, nu, eps, mu, chunk_pairs=1 << 21):
         rows = np.concatenate([k * Qc + np.arange(Qc) for k in range(3)])
         cols = np.concatenate([k * N + nu[q0:q1] for k in range(3)])
         vals = np.concatenate([w[q0:q1]] * 3)
-        nuhat = sp.csr_matrix((vals, (rows, cols)), shape=(3 * Qc, 3 * N))
-        As += (nuhat.T @ Sd.T).T
+        nuhat = sp.csc_matrix((vals, (rows, cols)), shape=(3 * Qc, 3 * N))
+        used = np.unique(cols)
+        sub = nuhat[:, used]                       # 3Qc x len(used), sparse
+        As[:, used] += (sub.T @ Sd.T).T            # (S diag(w) nuhat)[:, used]
     return As / (8.0 * math.pi * mu)
 
 
@@ -239,8 +243,29 @@ def solve_system(A, b):
 
 
 def condition_1(A):
-    """1-norm condition number (explicit inverse; oracle-sized systems)."""
-    return float(np.linalg.cond(A, 1))
+    """1-norm condition number |A|_1 |A^-1|_1 with the inverse formed
+    explicitly (oracle-sized systems)."""
+    A = np.asarray(A, dtype=np.float64)
+    Ainv = np.linalg.inv(A)
+    return float(np.abs(A).sum(axis=0).max() * np.abs(Ainv).sum(axis=0).max())
+
+
+def solve_with_condition(A, b, overwrite=False):
+    """Dense solve by LU with partial pivoting (LAPACK getrf / getrs) and the
+    LAPACK 1-norm condition estimate (gecon, Hager's method refined by
+    Higham) from the same factors; for systems too large for an explicit
+    inverse.  Returns (x, kappa1_estimate).  The estimate never exceeds the
+    true kappa_1 and is usually within a factor of a few of it."""
+    import scipy.linalg as sla
+    from scipy.linalg import lapack
+    anorm = float(np.abs(A).sum(axis=0).max())
+    lu, piv = sla.lu_factor(A, overwrite_a=overwrite, check_finite=False)
+    x = sla.lu_solve((lu, piv), b, check_finite=False)
+    gecon = lapack.get_lapack_funcs("gecon", (lu,))
+    rcond, info = gecon(lu, anorm, norm="1")
+    if info != 0:
+        raise RuntimeError(f"gecon info {info}")
+    return x, (1.0 / rcond if rcond > 0 else math.inf)
 
 
 def solve_scene(scene, t=0.0, Y=None, nu=None, return_all=False):

@@ -25,7 +25,8 @@ from ._lib import (NRS_BF16_GMRES_IR, NRS_FP32_GEPP_IR, NRS_FP32_GMRES_IR, NRS_F
 __all__ = [
     "NrsError", "Context", "DeviceScene", "Problem", "nrs_create", "nrs_version", "nrs_geometry",
     "nrs_nearest", "nrs_workspace_size", "nrs_assemble", "nrs_apply", "nrs_solve",
-    "nrs_query_info", "nrs_solve_batched_workspace_size", "nrs_solve_batched", "nrs_lu_factor", "nrs_lu_solve", "nrs_rk4_workspace_size", "nrs_rk4_step",
+    "nrs_query_info", "nrs_solve_batched_workspace_size", "nrs_solve_batched", "nrs_lu_factor", "nrs_lu_solve",
+    "nrs_lu_factor_workspace_size", "nrs_lu_solve_workspace_size", "nrs_lu_query", "nrs_rk4_workspace_size", "nrs_rk4_step",
     "NRS_FP64_LU", "NRS_FP32_IR", "NRS_FP32_GEPP_IR", "NRS_GMRES", "NRS_FP32_GMRES_IR", "NRS_BF16_GMRES_IR",
     "lda_for",
     "NRS_WARM_NONE", "NRS_WARM_PREVIOUS", "NRS_WARM_MODEL", "Model", "nrs_mlp_param_count",
@@ -274,25 +275,52 @@ def nrs_query_info(ctx, ws):
     return inf.as_dict()
 
 
-def nrs_lu_factor(ctx, A, lda, ipiv, perm, singular, pivot_scope=0, bf16_updates=False):
-    """bf16_updates (FP32 A, pivot_scope 1): trailing updates on BF16 tile copies."""
+def _lu_prec(A, bf16_updates=False):
     prec = 32 if A.dtype == torch.float32 else 64
     if bf16_updates:
         if prec != 32:
             raise TypeError("BF16 updates need an FP32 matrix")
         prec = 16
+    return prec
+
+
+def nrs_lu_factor_workspace_size(ctx, n, precision):
+    b = C.c_size_t()
+    _check(_lib.load().nrs_lu_factor_workspace_size(ctx.handle, n, precision, C.byref(b)), ctx)
+    return b.value
+
+
+def nrs_lu_solve_workspace_size(ctx, n):
+    b = C.c_size_t()
+    _check(_lib.load().nrs_lu_solve_workspace_size(ctx.handle, n, C.byref(b)), ctx)
+    return b.value
+
+
+def nrs_lu_factor(ctx, A, lda, ipiv, perm, singular, ws, pivot_scope=0, bf16_updates=False):
+    """bf16_updates (FP32 A, pivot_scope 1): trailing updates on BF16 tile copies.
+    ws: uint8 device tensor of nrs_lu_factor_workspace_size bytes."""
+    prec = _lu_prec(A, bf16_updates)
     n = int(ipiv.numel())
     _check(_lib.load().nrs_lu_factor(ctx.handle, n, prec, pivot_scope, _ptr(A, A.dtype, "A"), lda,
                                      _ptr(ipiv, torch.int32, "ipiv"), _ptr(perm, torch.int32, "perm"),
-                                     _ptr(singular, torch.int32, "singular")), ctx)
+                                     _ptr(singular, torch.int32, "singular"),
+                                     _ptr(ws, torch.uint8, "ws"), ws.numel()), ctx)
 
 
-def nrs_lu_solve(ctx, LU, lda, perm, b, x, pivot_scope=0):
+def nrs_lu_solve(ctx, LU, lda, perm, b, x, ws, pivot_scope=0):
+    """ws: uint8 device tensor of nrs_lu_solve_workspace_size bytes."""
     prec = 32 if LU.dtype == torch.float32 else 64
     n = int(perm.numel())
     _check(_lib.load().nrs_lu_solve(ctx.handle, n, prec, pivot_scope, _ptr(LU, LU.dtype, "LU"), lda,
                                     _ptr(perm, torch.int32, "perm"), _ptr(b, LU.dtype, "b"),
-                                    _ptr(x, LU.dtype, "x")), ctx)
+                                    _ptr(x, LU.dtype, "x"), _ptr(ws, torch.uint8, "ws"),
+                                    ws.numel()), ctx)
+
+
+def nrs_lu_query(ctx, ws):
+    f = C.c_int32()
+    _check(_lib.load().nrs_lu_query(ctx.handle, _ptr(ws, torch.uint8, "ws"), C.byref(f)), ctx)
+    return f.value
 
 
 def nrs_rk4_workspace_size(ctx, scene, method):

@@ -101,8 +101,11 @@ PROTOTYPES = {
     "nrs_solve_batched": (_i32, [_p, _i32, C.POINTER(NrsProblem), C.POINTER(_p), C.POINTER(_p),
                                  C.POINTER(NrsOptions), _p, C.c_size_t, C.POINTER(_p),
                                  C.POINTER(NrsInfo)]),
-    "nrs_lu_factor": (_i32, [_p, _i64, _i32, _i32, _p, _i64, _p, _p, _p]),
-    "nrs_lu_solve": (_i32, [_p, _i64, _i32, _i32, _p, _i64, _p, _p, _p]),
+    "nrs_lu_factor_workspace_size": (_i32, [_p, _i64, _i32, C.POINTER(C.c_size_t)]),
+    "nrs_lu_factor": (_i32, [_p, _i64, _i32, _i32, _p, _i64, _p, _p, _p, _p, C.c_size_t]),
+    "nrs_lu_solve_workspace_size": (_i32, [_p, _i64, C.POINTER(C.c_size_t)]),
+    "nrs_lu_solve": (_i32, [_p, _i64, _i32, _i32, _p, _i64, _p, _p, _p, _p, C.c_size_t]),
+    "nrs_lu_query": (_i32, [_p, _p, C.POINTER(_i32)]),
     "nrs_autotune": (_i32, [_p, C.POINTER(NrsProblem), _p, C.c_size_t, C.POINTER(NrsTuneResult)]),
     "nrs_autotune_clear": (_i32, [_p]),
     "nrs_mlp_param_count": (_i64, []),

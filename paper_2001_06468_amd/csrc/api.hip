@@ -43,27 +43,17 @@ bool gmres_ir(int32_t method) { return method == NRS_FP32_GMRES_IR || method == 
 bool uses_fgmres(int32_t method) { return method == NRS_FP32_IR || gmres_ir(method); }
 constexpr double kFgmresTol = 1e-12;
 
-// Grow the context's zero-initialised synchronisation words to fit order n:
-// the triangular-solve words and, separately, the tile-LU words.
-nrs_status grow_words(nrs_ctx* ctx, int32_t*& p, int64_t& cap, int64_t need) {
-  if (cap >= need) return NRS_OK;
-  NRS_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  if (p) NRS_HIP(ctx, hipFree(p));
-  p = nullptr;
-  cap = 0;
-  NRS_HIP(ctx, hipMalloc(&p, need * sizeof(int32_t)));
-  NRS_HIP(ctx, hipMemset(p, 0, need * sizeof(int32_t)));
-  cap = need;
-  return NRS_OK;
+// Bytes of the caller workspace of nrs_lu_factor / nrs_lu_solve.
+size_t lu_factor_ws_bytes(int64_t n, int32_t precision) {
+  size_t b = (size_t)lu_factor_sync_ints(n) * sizeof(int32_t);
+  if (precision == 16) b += (size_t)lu_shadow_elems(n) * sizeof(uint16_t);
+  return b + 256;
 }
-
-nrs_status ctx_sync_words(nrs_ctx* ctx, int64_t n) {
-  return grow_words(ctx, ctx->tsync, ctx->tsync_cap, 1 + trsv_sync_ints(n));
+size_t lu_solve_ws_bytes(int64_t n) {
+  return (size_t)(kLuHeadInts + round_up(trsv_sync_ints(n), 64)) * sizeof(int32_t) + 256;
 }
-
-nrs_status ctx_lu_words(nrs_ctx* ctx, int64_t n) {
-  const int64_t nt = lu_tiles_nt(n);
-  return grow_words(ctx, ctx->lusync, ctx->lusync_cap, 4 + nt * nt);
+int32_t* align256(void* p) {
+  return reinterpret_cast<int32_t*>((reinterpret_cast<uintptr_t>(p) + 255) & ~uintptr_t(255));
 }
 
 }  // namespace
@@ -452,9 +442,6 @@ nrs_status nrs_create(nrs_ctx** out, int device, void* stream) {
 nrs_status nrs_destroy(nrs_ctx* ctx) {
   if (ctx) {
     hipSetDevice(ctx->device);
-    if (ctx->tsync) hipFree(ctx->tsync);
-    if (ctx->lusync) hipFree(ctx->lusync);
-    if (ctx->lush) hipFree(ctx->lush);
     if (ctx->staging_event) {
       hipEventSynchronize(ctx->staging_event);
       hipEventDestroy(ctx->staging_event);
@@ -609,63 +596,118 @@ nrs_status nrs_query_info(nrs_ctx* ctx, void* ws, nrs_info* info) {
   return NRS_OK;
 }
 
+nrs_status nrs_lu_factor_workspace_size(nrs_ctx* ctx, int64_t n, int32_t precision,
+                                        size_t* bytes) {
+  if (!bytes || n <= 0) return fail(ctx, NRS_E_ARG, "bad LU workspace arguments");
+  if (precision != 16 && precision != 32 && precision != 64)
+    return fail(ctx, NRS_E_ARG, "precision must be 16, 32 or 64");
+  if (n > 262144) return fail(ctx, NRS_E_UNSUPPORTED, "n too large");
+  *bytes = lu_factor_ws_bytes(n, precision);
+  return NRS_OK;
+}
+
+nrs_status nrs_lu_solve_workspace_size(nrs_ctx* ctx, int64_t n, size_t* bytes) {
+  if (!bytes || n <= 0) return fail(ctx, NRS_E_ARG, "bad LU workspace arguments");
+  if (n > 262144) return fail(ctx, NRS_E_UNSUPPORTED, "n too large");
+  *bytes = lu_solve_ws_bytes(n);
+  return NRS_OK;
+}
+
 nrs_status nrs_lu_factor(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivot_scope, void* A,
-                         int64_t lda, int32_t* ipiv, int32_t* perm, int32_t* singular_flag) {
+                         int64_t lda, int32_t* ipiv, int32_t* perm, int32_t* singular_flag,
+                         void* ws, size_t ws_bytes) {
   nrs_status st = use_device(ctx);
   if (st) return st;
   if (n <= 0 || !A || lda < n || !ipiv || !perm || !singular_flag)
     return fail(ctx, NRS_E_ARG, "bad LU arguments");
   if (pivot_scope != 0 && pivot_scope != 1) return fail(ctx, NRS_E_ARG, "pivot_scope is 0 or 1");
+  if (precision != 16 && precision != 32 && precision != 64)
+    return fail(ctx, NRS_E_ARG, "precision must be 16, 32 or 64");
+  if (precision == 16 && pivot_scope != 1)
+    return fail(ctx, NRS_E_ARG, "precision 16 needs pivot_scope 1");
   if (n > 262144) return fail(ctx, NRS_E_UNSUPPORTED, "n too large");
-  if ((st = ctx_lu_words(ctx, n))) return st;
-  int32_t* ctl = ctx->lusync;
-  int32_t* done = ctl + 4;
+  if (!ws || ws_bytes < lu_factor_ws_bytes(n, precision))
+    return fail(ctx, NRS_E_WORKSPACE, "LU workspace missing or too small");
+  // head and tile flags start at zero on every call (this also clears the
+  // previous call's timeout flag)
+  int32_t* ctl = align256(ws);
+  int32_t* done = ctl + kLuHeadInts;
+  const int64_t words = lu_factor_sync_ints(n);
+  NRS_HIP(ctx, launch_fill_i32(ctl, 0, words, ctx->stream));
   if (precision == 16) {
-    if (pivot_scope != 1) return fail(ctx, NRS_E_ARG, "precision 16 needs pivot_scope 1");
-    const int64_t need = lu_shadow_elems(n);
-    if (ctx->lush_cap < need) {
-      NRS_HIP(ctx, hipStreamSynchronize(ctx->stream));
-      if (ctx->lush) NRS_HIP(ctx, hipFree(ctx->lush));
-      ctx->lush = nullptr;
-      ctx->lush_cap = 0;
-      NRS_HIP(ctx, hipMalloc(&ctx->lush, need * sizeof(uint16_t)));
-      ctx->lush_cap = need;
-    }
+    uint16_t* sh = reinterpret_cast<uint16_t*>(ctl + words);
     NRS_HIP(ctx, lu_factor_any<float>(n, 1, static_cast<float*>(A), lda, ipiv, perm, singular_flag,
-                                      done, ctl, ctx->stream, ctx->lush));
-  } else if (precision == 32)
+                                      done, ctl, ctx->stream, sh));
+  } else if (precision == 32) {
     NRS_HIP(ctx, lu_factor_any<float>(n, pivot_scope, static_cast<float*>(A), lda, ipiv, perm,
                                       singular_flag, done, ctl, ctx->stream));
-  else if (precision == 64)
+  } else {
     NRS_HIP(ctx, lu_factor_any<double>(n, pivot_scope, static_cast<double*>(A), lda, ipiv, perm,
                                        singular_flag, done, ctl, ctx->stream));
-  else
-    return fail(ctx, NRS_E_ARG, "precision must be 16, 32 or 64");
+  }
   return NRS_OK;
 }
 
-nrs_status nrs_lu_solve(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivot_scope,
-                        const void* LU, int64_t lda, const int32_t* perm, const void* b, void* x) {
-  nrs_status st = use_device(ctx);
-  if (st) return st;
-  if (n <= 0 || !LU || lda < n || !perm || !b || !x || b == x)
-    return fail(ctx, NRS_E_ARG, "bad LU solve arguments");
-  if (pivot_scope != 0 && pivot_scope != 1) return fail(ctx, NRS_E_ARG, "pivot_scope is 0 or 1");
-  if (n > 262144) return fail(ctx, NRS_E_UNSUPPORTED, "n too large");
-  if ((st = ctx_sync_words(ctx, n))) return st;
-  // the sweep words depend on n: start every call from a clean slate
-  NRS_HIP(ctx, launch_fill_i32(ctx->tsync + 1, 0, trsv_sync_ints(n), ctx->stream));
+}  // extern "C"
+
+namespace {
+
+// Triangular solves of nrs_lu_solve on the synchronisation words at sync
+// (kLuHeadInts head words, then trsv_sync_ints(n) words), all cleared first.
+nrs_status lu_solve_on(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivot_scope,
+                       const void* LU, int64_t lda, const int32_t* perm, const void* b, void* x,
+                       int32_t* sync) {
+  NRS_HIP(ctx, launch_fill_i32(sync, 0, kLuHeadInts + trsv_sync_ints(n), ctx->stream));
+  int32_t* err = sync + kLuTimeoutWord;
+  int32_t* words = sync + kLuHeadInts;
   if (precision == 32)
     NRS_HIP(ctx, launch_lu_solve<float>(n, pivot_scope, static_cast<const float*>(LU), lda, perm,
                                         static_cast<const float*>(b), static_cast<float*>(x),
-                                        ctx->tsync + 1, ctx->tsync, nullptr, ctx->stream));
-  else if (precision == 64)
+                                        words, err, nullptr, ctx->stream));
+  else
     NRS_HIP(ctx, launch_lu_solve<double>(n, pivot_scope, static_cast<const double*>(LU), lda,
                                          perm, static_cast<const double*>(b),
-                                         static_cast<double*>(x), ctx->tsync + 1, ctx->tsync,
-                                         nullptr, ctx->stream));
-  else
-    return fail(ctx, NRS_E_ARG, "precision must be 32 or 64");
+                                         static_cast<double*>(x), words, err, nullptr,
+                                         ctx->stream));
+  return NRS_OK;
+}
+
+nrs_status check_lu_solve(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivot_scope,
+                          const void* LU, int64_t lda, const int32_t* perm, const void* b,
+                          const void* x) {
+  if (n <= 0 || !LU || lda < n || !perm || !b || !x || b == x)
+    return fail(ctx, NRS_E_ARG, "bad LU solve arguments");
+  if (pivot_scope != 0 && pivot_scope != 1) return fail(ctx, NRS_E_ARG, "pivot_scope is 0 or 1");
+  if (precision != 32 && precision != 64) return fail(ctx, NRS_E_ARG, "precision must be 32 or 64");
+  if (n > 262144) return fail(ctx, NRS_E_UNSUPPORTED, "n too large");
+  return NRS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+nrs_status nrs_lu_solve(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivot_scope,
+                        const void* LU, int64_t lda, const int32_t* perm, const void* b, void* x,
+                        void* ws, size_t ws_bytes) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if ((st = check_lu_solve(ctx, n, precision, pivot_scope, LU, lda, perm, b, x))) return st;
+  if (!ws || ws_bytes < lu_solve_ws_bytes(n))
+    return fail(ctx, NRS_E_WORKSPACE, "LU solve workspace missing or too small");
+  return lu_solve_on(ctx, n, precision, pivot_scope, LU, lda, perm, b, x, align256(ws));
+}
+
+nrs_status nrs_lu_query(nrs_ctx* ctx, const void* ws, int32_t* flags) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if (!ws || !flags) return fail(ctx, NRS_E_ARG, "ws and flags required");
+  const int32_t* head = align256(const_cast<void*>(ws));
+  int32_t h = 0;
+  NRS_HIP(ctx, hipMemcpyAsync(&h, head + kLuTimeoutWord, sizeof(h), hipMemcpyDeviceToHost,
+                              ctx->stream));
+  NRS_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  *flags = h ? 1 : 0;
   return NRS_OK;
 }
 

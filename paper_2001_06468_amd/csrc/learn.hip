@@ -330,26 +330,44 @@ __global__ void k_adam(int64_t count, float* __restrict__ th, const float* __res
 
 // start[b] / end[b] of body b's points; bad[0] set when a body's points are not
 // contiguous (counted against the number of points labelled b).
-__global__ void k_body_range(int64_t N, int32_t M, const int32_t* __restrict__ body,
-                             int32_t* __restrict__ off, int32_t* __restrict__ cnt) {
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= N) return;
+// Body offsets from the point-to-body map.  The points of bodies 0..M-1
+// must form one block in which the body index starts at 0, steps up by one
+// at each change and ends at M-1 (every other point has body < 0 or >= M).
+// Each point checks the changes on its two sides; starts[0] counts the
+// block's beginnings (exactly one is allowed), and each run's first point
+// writes its offset.
+__device__ inline int32_t body_or_none(const int32_t* body, int64_t m, int64_t N, int32_t M) {
+  if (m < 0 || m >= N) return -1;
   const int32_t b = body[m];
-  if (b < 0 || b >= M) return;
-  if (m == 0 || body[m - 1] != b) off[b] = (int32_t)m;
-  if (m == N - 1 || body[m + 1] != b) cnt[b] = (int32_t)(m + 1);   // end
-  atomicAdd(&cnt[M + b], 1);
+  return (b >= 0 && b < M) ? b : -1;
 }
 
-__global__ void k_body_check(int32_t M, int32_t* __restrict__ off,
-                             const int32_t* __restrict__ cnt, int32_t* __restrict__ err) {
+__global__ void k_body_runs(int64_t N, int32_t M, const int32_t* __restrict__ body,
+                            int32_t* __restrict__ off, int32_t* __restrict__ starts,
+                            int32_t* __restrict__ err) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= N) return;
+  const int32_t b = body_or_none(body, m, N, M);
+  if (b < 0) return;
+  const int32_t prev = body_or_none(body, m - 1, N, M);
+  const int32_t next = body_or_none(body, m + 1, N, M);
+  if (prev != b) {
+    if (!(prev == b - 1 || (b == 0 && prev < 0))) atomicOr(err, 2);
+    if (b == 0 && prev < 0) atomicAdd(starts, 1);
+    off[b] = (int32_t)m;
+  }
+  if (next != b) {
+    if (!(next == b + 1 || (b == M - 1 && next < 0))) atomicOr(err, 2);
+    if (b == M - 1) off[M] = (int32_t)(m + 1);
+  }
+}
+
+__global__ void k_body_sizes(int32_t M, const int32_t* __restrict__ off,
+                             const int32_t* __restrict__ starts, int32_t* __restrict__ err) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= M) return;
-  const int32_t n = cnt[M + b];
-  if (n <= 0 || cnt[b] - off[b] != n || n > kMlpMaxPts) atomicOr(err, 2);
-  // off holds starts; the end of the last body gives off[M]
-  if (b == M - 1) off[M] = cnt[b];
-  if (b < M - 1 && cnt[b] != off[b + 1] && n > 0) atomicOr(err, 2);
+  const int32_t n = off[b + 1] - off[b];
+  if (n <= 0 || n > kMlpMaxPts || (b == 0 && starts[0] != 1)) atomicOr(err, 2);
 }
 
 // phi[m] = (B^T (x_m - x0), B^T u_m, s_m) for points of bodies 0..M-1
@@ -472,13 +490,14 @@ hipError_t launch_adam(int64_t count, float* th, const float* g, float* m, float
 }
 
 hipError_t launch_body_off(int64_t N, int32_t M, const int32_t* body, int32_t* off,
-                           int32_t* cnt, int32_t* err, hipStream_t s) {
+                           int32_t* starts, int32_t* err, hipStream_t s) {
   if (M <= 0) return hipSuccess;
-  hipError_t e = launch_fill_i32(cnt, 0, 2 * (int64_t)M, s);
+  hipError_t e = launch_fill_i32(starts, 0, 1, s);
   if (e != hipSuccess) return e;
   if ((e = launch_fill_i32(off, 0, (int64_t)M + 1, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_body_range, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, M, body, off, cnt);
-  hipLaunchKernelGGL(k_body_check, dim3(blocks_for(M, 256)), dim3(256), 0, s, M, off, cnt, err);
+  hipLaunchKernelGGL(k_body_runs, dim3(blocks_for(N, 256)), dim3(256), 0, s, N, M, body, off,
+                     starts, err);
+  hipLaunchKernelGGL(k_body_sizes, dim3(blocks_for(M, 256)), dim3(256), 0, s, M, off, starts, err);
   return hipGetLastError();
 }
 

@@ -40,16 +40,13 @@ nrs_status nrs_mlp_body_offsets(nrs_ctx* ctx, int64_t N, const int32_t* body, in
   nrs_status st = begin(ctx);
   if (st) return st;
   if (N <= 0 || M <= 0 || !body || !body_off) return set_error(ctx, NRS_E_ARG, "bad body map");
-  int32_t* cnt = nullptr;
-  NRS_LHIP(ctx, hipMalloc((void**)&cnt, sizeof(int32_t) * 2 * (size_t)M));
   int32_t* err = ctx->dflags + 1;
+  int32_t* starts = ctx->dflags + 2;
   hipError_t e = launch_fill_i32(err, 0, 1, ctx->stream);
-  if (e == hipSuccess) e = launch_body_off(N, M, body, body_off, cnt, err, ctx->stream);
+  if (e == hipSuccess) e = launch_body_off(N, M, body, body_off, starts, err, ctx->stream);
   int32_t h = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&h, err, sizeof(h), hipMemcpyDeviceToHost, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  hipError_t e2 = hipFree(cnt);
-  if (e == hipSuccess) e = e2;
   if (e != hipSuccess)
     return set_error(ctx, NRS_E_HIP, std::string("body offsets: ") + hipGetErrorString(e));
   if (h)

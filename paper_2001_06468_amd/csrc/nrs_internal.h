@@ -30,17 +30,9 @@ struct nrs_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string last_error;
-  // synchronisation words of nrs_lu_solve: [0] timeout flag, [1..] the
-  // triangular-solve words (cleared before every call)
-  int32_t* tsync = nullptr;
-  int64_t tsync_cap = 0;
-  // zero-initialised tile-LU words of nrs_lu_factor: control [4], tile flags
-  // [nt*nt]; kept zero by the kernel
-  int32_t* lusync = nullptr;
-  int64_t lusync_cap = 0;
-  // BF16 tile copies of nrs_lu_factor with precision 16 (grown on demand)
-  uint16_t* lush = nullptr;
-  int64_t lush_cap = 0;
+  // device address of the library's static scratch array on this device
+  // (the no-allocation triangular solve), from hipGetSymbolAddress
+  int32_t* scratch = nullptr;
   // pinned host staging of batch descriptors; the event marks the last copy
   void* staging = nullptr;
   size_t staging_cap = 0;
@@ -270,10 +262,10 @@ hipError_t launch_mlp_grad(const float* th, int32_t nbodies, int64_t npts,
                            float* grad, int32_t* err, hipStream_t s);
 hipError_t launch_adam(int64_t count, float* th, const float* g, float* m, float* v, int32_t t,
                        float lr, float beta1, float beta2, float eps, hipStream_t s);
-// off: [M+1] body point offsets; cnt: [2M] scratch; err |= 2 if a body's points
-// are not one contiguous run in body order or exceed kMlpMaxPts
+// off: [M+1] body point offsets; starts: one counter word; err |= 2 if a
+// body's points are not one contiguous run in body order or exceed kMlpMaxPts
 hipError_t launch_body_off(int64_t N, int32_t M, const int32_t* body, int32_t* off,
-                           int32_t* cnt, int32_t* err, hipStream_t s);
+                           int32_t* starts, int32_t* err, hipStream_t s);
 hipError_t launch_features(int64_t N, const double* x, const double* u, const double* sarc,
                            const int32_t* body, int32_t M, const double* Y, float* phi,
                            hipStream_t s);
@@ -375,6 +367,16 @@ inline int64_t lu_shadow_elems(int64_t n) {
   return nt * nt * 4096;
 }
 inline int64_t lu_tiles_nt(int64_t n) { return (n + 63) / 64; }
+// Caller workspace of nrs_lu_factor / nrs_lu_solve: a head of kLuHeadInts
+// words (factor: [0] ticket, [1] exit count, [2] wait-timeout flag; solve:
+// [2] wait-timeout flag), then the call's synchronisation words, then (factor
+// with BF16 update inputs) the BF16 tile copies, 256-byte aligned.
+constexpr int64_t kLuHeadInts = 64;
+constexpr int64_t kLuTimeoutWord = 2;
+inline int64_t lu_factor_sync_ints(int64_t n) {
+  const int64_t nt = lu_tiles_nt(n);
+  return kLuHeadInts + (nt * nt + 63) / 64 * 64;
+}
 template <class T>
 hipError_t launch_lu_solve(int64_t n, int32_t scope, const T* LU, int64_t lda,
                            const int32_t* perm, const T* b, T* x, int32_t* sync, int32_t* err,

@@ -57,3 +57,15 @@ def rel_force_errors(sol, ref, N):
     else:
         eg = 0.0
     return ef, eg
+
+
+def lu_ws(ctx, n, A, bf16=False):
+    """Workspace of nrs_lu_factor for an order-n matrix like A."""
+    prec = 16 if bf16 else (32 if A.dtype == torch.float32 else 64)
+    return torch.empty(nrs.nrs_lu_factor_workspace_size(ctx, n, prec), dtype=torch.uint8,
+                       device=DEV)
+
+
+def lus_ws(ctx, n):
+    """Workspace of nrs_lu_solve for order n."""
+    return torch.empty(nrs.nrs_lu_solve_workspace_size(ctx, n), dtype=torch.uint8, device=DEV)

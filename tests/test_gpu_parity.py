@@ -9,6 +9,7 @@ seeded inputs (MI355X).  Tolerances:
     target stated for the refined forms.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -21,7 +22,8 @@ pytestmark = pytest.mark.gpu
 
 if torch.cuda.is_available():
     import paper_2001_06468_amd as nrs
-    from gpu_util import T, prepare, oracle_system, workspace, gpu_solve, rel_force_errors, DEV
+    from gpu_util import (T, prepare, oracle_system, workspace, gpu_solve, rel_force_errors, DEV,
+                          lu_ws, lus_ws)
 
 
 @pytest.fixture(scope="module")
@@ -159,7 +161,7 @@ def test_lu_factor_and_solve(ctx, n, precision, scope):
     ipiv = torch.empty(n, dtype=torch.int32, device=DEV)
     perm = torch.empty(n, dtype=torch.int32, device=DEV)
     sing = torch.zeros(1, dtype=torch.int32, device=DEV)
-    nrs.nrs_lu_factor(ctx, A, lda, ipiv, perm, sing, pivot_scope=scope)
+    nrs.nrs_lu_factor(ctx, A, lda, ipiv, perm, sing, lu_ws(ctx, n, A), pivot_scope=scope)
     LU = A.cpu().numpy().astype(np.float64)[:, :n].T
     p = perm.cpu().numpy()
     piv = ipiv.cpu().numpy()
@@ -173,7 +175,7 @@ def test_lu_factor_and_solve(ctx, n, precision, scope):
     _lu_check(A0c, LU, p, scope, tol=1e-13 if precision == 64 else 3e-6)
     b = rng.normal(size=n)
     xs = torch.empty(n, dtype=dt, device=DEV)
-    nrs.nrs_lu_solve(ctx, A, lda, perm, T(b, dt), xs, pivot_scope=scope)
+    nrs.nrs_lu_solve(ctx, A, lda, perm, T(b, dt), xs, lus_ws(ctx, n), pivot_scope=scope)
     ref = np.linalg.solve(A0c, b)
     err = np.linalg.norm(xs.cpu().numpy() - ref) / np.linalg.norm(ref)
     unit = 2.0 ** -53 if precision == 64 else 2.0 ** -24
@@ -189,8 +191,39 @@ def test_lu_singular_flag(ctx, scope):
     ipiv = torch.empty(n, dtype=torch.int32, device=DEV)
     perm = torch.empty(n, dtype=torch.int32, device=DEV)
     sing = torch.zeros(1, dtype=torch.int32, device=DEV)
-    nrs.nrs_lu_factor(ctx, A, n, ipiv, perm, sing, pivot_scope=scope)
+    nrs.nrs_lu_factor(ctx, A, n, ipiv, perm, sing, lu_ws(ctx, n, A), pivot_scope=scope)
     assert sing.item() == 1
+
+
+def test_lu_timeout_word_cleared_each_call(ctx):
+    """The factor and solve workspaces carry the wait-timeout word of their
+    last call: a word left set (here planted from the host) is cleared by the
+    next call, which then runs to the correct result, and nrs_lu_query
+    reports 0."""
+    n = 300
+    rng = np.random.default_rng(3)
+    A0 = rng.normal(size=(n, n)) + 3 * np.sqrt(n) * np.eye(n)
+    b = rng.normal(size=n)
+    A = torch.from_numpy(A0.T.copy()).to(torch.float32).to(DEV)
+    ipiv = torch.empty(n, dtype=torch.int32, device=DEV)
+    perm = torch.empty(n, dtype=torch.int32, device=DEV)
+    sing = torch.zeros(1, dtype=torch.int32, device=DEV)
+    wf, wsv = lu_ws(ctx, n, A), lus_ws(ctx, n)
+    for ws in (wf, wsv):
+        head = (-ws.data_ptr()) % 256          # the head starts at the first 256-byte boundary
+        ws[head + 8:head + 12].view(torch.int32).fill_(1)
+        assert nrs.nrs_lu_query(ctx, ws) == 1
+    nrs.nrs_lu_factor(ctx, A, n, ipiv, perm, sing, wf, pivot_scope=1)
+    assert nrs.nrs_lu_query(ctx, wf) == 0
+    xs = torch.empty(n, dtype=torch.float32, device=DEV)
+    nrs.nrs_lu_solve(ctx, A, n, perm, T(b, torch.float32), xs, wsv, pivot_scope=1)
+    assert nrs.nrs_lu_query(ctx, wsv) == 0
+    ref = np.linalg.solve(A0, b)
+    assert np.linalg.norm(xs.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-4
+    with pytest.raises(nrs.NrsError, match="workspace"):
+        nrs.nrs_lu_factor(ctx, A, n, ipiv, perm, sing, wf[:64], pivot_scope=1)
+    with pytest.raises(nrs.NrsError, match="workspace"):
+        nrs.nrs_lu_solve(ctx, A, n, perm, T(b, torch.float32), xs, wsv[:64], pivot_scope=1)
 
 
 def test_lu_tiles_repeatable_and_large(ctx):
@@ -204,10 +237,10 @@ def test_lu_tiles_repeatable_and_large(ctx):
         ipiv = torch.empty(n, dtype=torch.int32, device=DEV)
         perm = torch.empty(n, dtype=torch.int32, device=DEV)
         sing = torch.zeros(1, dtype=torch.int32, device=DEV)
-        nrs.nrs_lu_factor(ctx, A, n, ipiv, perm, sing, pivot_scope=1)
+        nrs.nrs_lu_factor(ctx, A, n, ipiv, perm, sing, lu_ws(ctx, n, A), pivot_scope=1)
         b = rng.normal(size=n)
         xs = torch.empty(n, dtype=torch.float32, device=DEV)
-        nrs.nrs_lu_solve(ctx, A, n, perm, T(b, torch.float32), xs, pivot_scope=1)
+        nrs.nrs_lu_solve(ctx, A, n, perm, T(b, torch.float32), xs, lus_ws(ctx, n), pivot_scope=1)
         ref = np.linalg.solve(A0, b)
         err = np.linalg.norm(xs.cpu().numpy() - ref) / np.linalg.norm(ref)
         assert err < 1e-4, (n, err)
@@ -229,9 +262,10 @@ def test_lu_tiles_bf16_updates(ctx):
             ipiv = torch.empty(n, dtype=torch.int32, device=DEV)
             perm = torch.empty(n, dtype=torch.int32, device=DEV)
             sing = torch.zeros(1, dtype=torch.int32, device=DEV)
-            nrs.nrs_lu_factor(ctx, A, n, ipiv, perm, sing, pivot_scope=1, bf16_updates=bf)
+            nrs.nrs_lu_factor(ctx, A, n, ipiv, perm, sing, lu_ws(ctx, n, A, bf), pivot_scope=1,
+                              bf16_updates=bf)
             xs = torch.empty(n, dtype=torch.float32, device=DEV)
-            nrs.nrs_lu_solve(ctx, A, n, perm, T(b, torch.float32), xs, pivot_scope=1)
+            nrs.nrs_lu_solve(ctx, A, n, perm, T(b, torch.float32), xs, lus_ws(ctx, n), pivot_scope=1)
             x = xs.cpu().numpy()
             outs.append(A.cpu().numpy())
             errs.append(np.linalg.norm(x - ref) / np.linalg.norm(ref))
@@ -255,7 +289,8 @@ def test_lu_tiles_repeatable(ctx):
                 ipiv = torch.empty(n, dtype=torch.int32, device=DEV)
                 perm = torch.empty(n, dtype=torch.int32, device=DEV)
                 sing = torch.zeros(1, dtype=torch.int32, device=DEV)
-                nrs.nrs_lu_factor(ctx, A, n, ipiv, perm, sing, pivot_scope=1, bf16_updates=bf)
+                nrs.nrs_lu_factor(ctx, A, n, ipiv, perm, sing, lu_ws(ctx, n, A, bf), pivot_scope=1,
+                              bf16_updates=bf)
                 if first is None:
                     first = (A, perm)
                     continue
@@ -339,6 +374,31 @@ def test_rk4_step_matches_oracle(ctx, method):
     assert info["fell_back"] == 0
     err = np.max(np.abs(Y.cpu().numpy().reshape(-1, 12) - Yo))
     assert err <= 1e-10, err
+
+
+@pytest.mark.parametrize("method", ["FP32_IR", "FP64_LU", "FP32_IR_REUSE"])
+def test_rk4_headline_trajectory_matches_oracle(ctx, method):
+    """The benchmark workload (25 filaments, n = 3150): two RK4 steps at
+    dt = 2 pi / 100 against the oracle's states after each step, stored by
+    tests/golden/make_golden.py (every oracle stage a full FP64 solve)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "rk4_filaments_M25_2steps.npz")
+    with np.load(path, allow_pickle=False) as z:
+        gold = [z["Y1"], z["Y2"]]
+        dt = float(z["dt"])
+    scene = synth.filament_scene(25, seed=0)
+    ds = nrs.DeviceScene(scene)
+    reuse = method.endswith("_REUSE")
+    m = getattr(nrs, "NRS_" + method.replace("_REUSE", ""))
+    ws = torch.empty(nrs.nrs_rk4_workspace_size(ctx, ds, m), dtype=torch.uint8, device=DEV)
+    Y = T(scene["Y0"])
+    for step in range(2):
+        nrs.nrs_rk4_step(ctx, ds, Y, step * dt, dt, ws, method=m, reuse_stage_factors=int(reuse))
+        info = nrs.nrs_query_info(ctx, ws)
+        assert info["fell_back"] == 0, (step, info)
+        err = np.max(np.abs(Y.cpu().numpy().reshape(-1, 12) - gold[step]))
+        print(f"rk4 M=25 {method} step {step + 1}: max state error {err:.2e}", flush=True)
+        assert err <= 1e-10, (step, err)
 
 
 def test_rk4_stage_factor_reuse_at_headline_size(ctx):

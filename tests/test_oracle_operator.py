@@ -176,3 +176,50 @@ def test_lapack_solve_matches_textbook_elimination():
     n = len(d["b"])
     bw = np.abs(r).max() / (np.abs(d["A"]).sum(1).max() * np.abs(d["sol"]).max() + np.abs(d["b"]).max())
     assert bw <= 10 * n * 2.0 ** -53
+
+
+def _kappa1_by_columns(A):
+    """kappa_1 = |A|_1 |A^-1|_1 with the columns of A^-1 found one by one by
+    the textbook elimination (pure Python)."""
+    n = A.shape[0]
+    cols = [oracle.doolittle_solve(A, np.eye(n)[:, j]) for j in range(n)]
+    norm_inv = max(sum(abs(v) for v in c) for c in cols)
+    norm_a = max(sum(abs(A[i, j]) for i in range(n)) for j in range(n))
+    return norm_a * norm_inv
+
+
+def test_condition_1_closed_forms():
+    """Diagonal matrix: max |d| / min |d|.  Hilbert matrix of order 4: the
+    textbook value 28375 (|H|_1 = 25/12, |H^-1|_1 = 13620)."""
+    d = np.array([3.0, -0.5, 8.0, 0.25])
+    assert oracle.condition_1(np.diag(d)) == pytest.approx(32.0, rel=1e-14)
+    H = np.array([[1.0 / (i + j + 1) for j in range(4)] for i in range(4)])
+    assert oracle.condition_1(H) == pytest.approx(28375.0, rel=1e-9)
+    rng = np.random.default_rng(4)
+    A = rng.normal(size=(7, 7))
+    assert oracle.condition_1(A) == pytest.approx(_kappa1_by_columns(A), rel=1e-10)
+
+
+def test_solve_with_condition_against_textbook_elimination():
+    """The getrf/getrs solve equals the textbook elimination, and the gecon
+    estimate is a lower bound of the exact kappa_1 within a factor 3 (on the
+    sphere system, a random matrix and the Hilbert matrix of order 6)."""
+    sc = synth.sphere_scene(3, 9)
+    _, _, d = oracle.solve_scene(sc, return_all=True)
+    x, kap = oracle.solve_with_condition(d["A"], d["b"])
+    np.testing.assert_allclose(x, oracle.doolittle_solve(d["A"], d["b"]), rtol=1e-11, atol=1e-13)
+    rng = np.random.default_rng(5)
+    H6 = np.array([[1.0 / (i + j + 1) for j in range(6)] for i in range(6)])
+    for A in (d["A"], rng.normal(size=(40, 40)), H6):
+        b = np.ones(A.shape[0])
+        x, kap = oracle.solve_with_condition(A, b)
+        exact = oracle.condition_1(A)
+        assert exact / 3.0 <= kap <= exact * (1 + 1e-8), (kap, exact)
+        np.testing.assert_allclose(A @ x, b, atol=1e-9 * exact * np.abs(b).max())
+    # overwrite=True leaves the result unchanged
+    A = rng.normal(size=(30, 30))
+    b = rng.normal(size=30)
+    x1, k1 = oracle.solve_with_condition(A, b)
+    x2, k2 = oracle.solve_with_condition(A.copy(order="F"), b, overwrite=True)
+    np.testing.assert_array_equal(x1, x2)
+    assert k1 == k2
