@@ -323,9 +323,27 @@ nrs_status nrs_lu_solve(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivo
                         const void* LU, int64_t lda, const int32_t* perm, const void* b, void* x,
                         void* ws, size_t ws_bytes);
 
+/* For callers that cannot allocate device memory (work recorded under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * nrs_lu_solve without a workspace, same arguments, kernels and results.
+ * Its synchronisation words live in a static device array of the library,
+ * sized for n <= NRS_NOALLOC_MAX_N (about 517 KiB), one copy per GPU, held
+ * until the process ends.  Every call on a GPU uses that GPU's copy: calls
+ * that overlap in time on one GPU race (issue them on one stream or
+ * otherwise serialise them).  The call clears the words it uses before the
+ * solve (with a fill kernel, no memset).  Never calls hipMalloc, hipFree or
+ * an allocating routine.  Asynchronous; nrs_lu_query(ctx, NULL, flags)
+ * reports its wait-timeout word.  Errors as nrs_lu_solve, and
+ * NRS_E_UNSUPPORTED for n > NRS_NOALLOC_MAX_N. */
+#define NRS_NOALLOC_MAX_N 65536
+nrs_status nrs_lu_solve_noalloc(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivot_scope,
+                                const void* LU, int64_t lda, const int32_t* perm, const void* b,
+                                void* x);
+
 /* Synchronise the context's stream and report the status of the last
- * nrs_lu_factor or nrs_lu_solve that used workspace ws: *flags = 1 if one of
- * its bounded waits between workgroups timed out (its output is then not
+ * nrs_lu_factor or nrs_lu_solve that used workspace ws (ws = NULL: the last
+ * nrs_lu_solve_noalloc on the context's device): *flags = 1 if one of its
+ * bounded waits between workgroups timed out (its output is then not
  * valid), else 0.  Each such call clears the word when it starts. */
 nrs_status nrs_lu_query(nrs_ctx* ctx, const void* ws, int32_t* flags);
 

@@ -19,14 +19,14 @@ from . import _lib
 from ._lib import (NRS_BF16_GMRES_IR, NRS_FP32_GEPP_IR, NRS_FP32_GMRES_IR, NRS_FP32_IR,  # noqa: F401
                    NRS_FP64_LU,
                    NRS_GMRES,
-                   NRS_MLP_HIDDEN, NRS_MLP_MAX_POINTS, NRS_WARM_MODEL, NRS_WARM_NONE,
+                   NRS_MLP_HIDDEN, NRS_MLP_MAX_POINTS, NRS_NOALLOC_MAX_N, NRS_WARM_MODEL, NRS_WARM_NONE,
                    NRS_WARM_PREVIOUS, NrsInfo, NrsOptions, NrsProblem, NrsScene)
 
 __all__ = [
     "NrsError", "Context", "DeviceScene", "Problem", "nrs_create", "nrs_version", "nrs_geometry",
     "nrs_nearest", "nrs_workspace_size", "nrs_assemble", "nrs_apply", "nrs_solve",
     "nrs_query_info", "nrs_solve_batched_workspace_size", "nrs_solve_batched", "nrs_lu_factor", "nrs_lu_solve",
-    "nrs_lu_factor_workspace_size", "nrs_lu_solve_workspace_size", "nrs_lu_query", "nrs_rk4_workspace_size", "nrs_rk4_step",
+    "nrs_lu_factor_workspace_size", "nrs_lu_solve_workspace_size", "nrs_lu_query", "nrs_lu_solve_noalloc", "nrs_rk4_workspace_size", "nrs_rk4_step",
     "NRS_FP64_LU", "NRS_FP32_IR", "NRS_FP32_GEPP_IR", "NRS_GMRES", "NRS_FP32_GMRES_IR", "NRS_BF16_GMRES_IR",
     "lda_for",
     "NRS_WARM_NONE", "NRS_WARM_PREVIOUS", "NRS_WARM_MODEL", "Model", "nrs_mlp_param_count",
@@ -317,7 +317,18 @@ def nrs_lu_solve(ctx, LU, lda, perm, b, x, ws, pivot_scope=0):
                                     ws.numel()), ctx)
 
 
-def nrs_lu_query(ctx, ws):
+def nrs_lu_solve_noalloc(ctx, LU, lda, perm, b, x, pivot_scope=0):
+    """nrs_lu_solve on the library's static scratch (no workspace, no allocation)."""
+    prec = 32 if LU.dtype == torch.float32 else 64
+    n = int(perm.numel())
+    _check(_lib.load().nrs_lu_solve_noalloc(ctx.handle, n, prec, pivot_scope,
+                                            _ptr(LU, LU.dtype, "LU"), lda,
+                                            _ptr(perm, torch.int32, "perm"), _ptr(b, LU.dtype, "b"),
+                                            _ptr(x, LU.dtype, "x")), ctx)
+
+
+def nrs_lu_query(ctx, ws=None):
+    """ws = None: the last nrs_lu_solve_noalloc on the context's device."""
     f = C.c_int32()
     _check(_lib.load().nrs_lu_query(ctx.handle, _ptr(ws, torch.uint8, "ws"), C.byref(f)), ctx)
     return f.value

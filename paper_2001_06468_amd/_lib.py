@@ -28,6 +28,7 @@ NRS_WARM_PREVIOUS = 1
 NRS_WARM_MODEL = 2
 NRS_MLP_HIDDEN = 64
 NRS_MLP_MAX_POINTS = 256
+NRS_NOALLOC_MAX_N = 65536
 
 _p = C.c_void_p
 _i64 = C.c_int64
@@ -106,6 +107,7 @@ PROTOTYPES = {
     "nrs_lu_solve_workspace_size": (_i32, [_p, _i64, C.POINTER(C.c_size_t)]),
     "nrs_lu_solve": (_i32, [_p, _i64, _i32, _i32, _p, _i64, _p, _p, _p, _p, C.c_size_t]),
     "nrs_lu_query": (_i32, [_p, _p, C.POINTER(_i32)]),
+    "nrs_lu_solve_noalloc": (_i32, [_p, _i64, _i32, _i32, _p, _i64, _p, _p, _p]),
     "nrs_autotune": (_i32, [_p, C.POINTER(NrsProblem), _p, C.c_size_t, C.POINTER(NrsTuneResult)]),
     "nrs_autotune_clear": (_i32, [_p]),
     "nrs_mlp_param_count": (_i64, []),

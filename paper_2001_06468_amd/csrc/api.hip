@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "nrs_internal.h"
@@ -54,6 +55,41 @@ size_t lu_solve_ws_bytes(int64_t n) {
 }
 int32_t* align256(void* p) {
   return reinterpret_cast<int32_t*>((reinterpret_cast<uintptr_t>(p) + 255) & ~uintptr_t(255));
+}
+
+}  // namespace
+
+// Scratch of nrs_lu_solve_noalloc: the head words and the triangular-solve
+// words of one solve of order up to NRS_NOALLOC_MAX_N (the layout of
+// kLuHeadInts + trsv_sync_ints(n)).  Each GPU holds one copy for the life of
+// the process.  Host code never uses this name as an address: it uses the
+// per-device address from hipGetSymbolAddress (nrs_ctx::scratch).
+constexpr int64_t kNoAllocInts =
+    kLuHeadInts +
+    (2 + (NRS_NOALLOC_MAX_N + 63) / 64 + 2 + 2 * (int64_t)NRS_NOALLOC_MAX_N + 63) / 64 * 64;
+static __device__ __align__(256) int32_t scratch[kNoAllocInts];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+int32_t* g_scratch_at[kMaxScratchDevices] = {};
+
+// Device address of the scratch array on ctx's device (current), looked up
+// once per device.
+nrs_status setup_scratch(nrs_ctx* ctx) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (ctx->device < 0 || ctx->device >= kMaxScratchDevices)
+    return fail(ctx, NRS_E_UNSUPPORTED, "device index too large");
+  if (!g_scratch_at[ctx->device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(ctx, NRS_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_at[ctx->device] = static_cast<int32_t*>(p);
+  }
+  ctx->scratch = g_scratch_at[ctx->device];
+  return NRS_OK;
 }
 
 }  // namespace
@@ -431,7 +467,7 @@ nrs_status nrs_create(nrs_ctx** out, int device, void* stream) {
   if (!c) return NRS_E_HIP;
   c->device = device;
   c->stream = static_cast<hipStream_t>(stream);
-  if (hipSetDevice(device) != hipSuccess) {
+  if (hipSetDevice(device) != hipSuccess || setup_scratch(c) != NRS_OK) {
     delete c;
     return NRS_E_HIP;
   }
@@ -698,11 +734,25 @@ nrs_status nrs_lu_solve(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivo
   return lu_solve_on(ctx, n, precision, pivot_scope, LU, lda, perm, b, x, align256(ws));
 }
 
+nrs_status nrs_lu_solve_noalloc(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivot_scope,
+                                const void* LU, int64_t lda, const int32_t* perm, const void* b,
+                                void* x) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if ((st = check_lu_solve(ctx, n, precision, pivot_scope, LU, lda, perm, b, x))) return st;
+  if (n > NRS_NOALLOC_MAX_N)
+    return fail(ctx, NRS_E_UNSUPPORTED,
+                "nrs_lu_solve_noalloc: n above NRS_NOALLOC_MAX_N (use nrs_lu_solve)");
+  if (!ctx->scratch) return fail(ctx, NRS_E_HIP, "scratch address not set up");
+  return lu_solve_on(ctx, n, precision, pivot_scope, LU, lda, perm, b, x, ctx->scratch);
+}
+
 nrs_status nrs_lu_query(nrs_ctx* ctx, const void* ws, int32_t* flags) {
   nrs_status st = use_device(ctx);
   if (st) return st;
-  if (!ws || !flags) return fail(ctx, NRS_E_ARG, "ws and flags required");
-  const int32_t* head = align256(const_cast<void*>(ws));
+  if (!flags) return fail(ctx, NRS_E_ARG, "flags required");
+  if (!ws && !ctx->scratch) return fail(ctx, NRS_E_HIP, "scratch address not set up");
+  const int32_t* head = ws ? align256(const_cast<void*>(ws)) : ctx->scratch;
   int32_t h = 0;
   NRS_HIP(ctx, hipMemcpyAsync(&h, head + kLuTimeoutWord, sizeof(h), hipMemcpyDeviceToHost,
                               ctx->stream));
