@@ -182,6 +182,15 @@ typedef struct {
      that does not converge sends the step to the FP64 fallback like any
      failed stage.  Ignored by every other call. */
   int32_t reuse_stage_factors;
+  /* The FP32 tile-LU forms (NRS_FP32_IR, NRS_FP32_GMRES_IR,
+     NRS_BF16_GMRES_IR) of nrs_solve, nrs_rk4_step and nrs_dopri5_integrate
+     factor the equilibrated matrix D_r A D_c: D_r, D_c powers of two, row
+     scaling r_i = max_j |a_ij|, dr_i = 2^-floor(log2 r_i), then column
+     scaling of the row-scaled matrix likewise, so every row's and column's
+     largest entry has magnitude in [1, 2) and the scaling adds no rounding.
+     Refinement keeps the unscaled FP64 residual: correction = D_c (LU)^-1
+     D_r r.  Non-zero: factor A itself.  (nrs_solve_batched does not scale.) */
+  int32_t no_equilibration;
 } nrs_options;
 
 typedef struct {
@@ -339,6 +348,15 @@ nrs_status nrs_lu_solve(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivo
 nrs_status nrs_lu_solve_noalloc(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t pivot_scope,
                                 const void* LU, int64_t lda, const int32_t* perm, const void* b,
                                 void* x);
+
+/* Equilibration of an FP32 matrix in place, as nrs_solve applies it before
+ * the FP32 factorisation: A <- D_r A D_c with dr_i = 2^-floor(log2 max_j
+ * |a_ij|) and dc_j = 2^-floor(log2 max_i dr_i |a_ij|) (1 for an all-zero row
+ * or column).  A: n x n column-major, leading dimension lda >= n; dr, dc:
+ * [n] FP32 device outputs.  ws: device workspace of at least 4 n bytes
+ * (row maxima).  Asynchronous.  Errors: NRS_E_ARG, NRS_E_WORKSPACE. */
+nrs_status nrs_equilibrate(nrs_ctx* ctx, int64_t n, float* A, int64_t lda, float* dr, float* dc,
+                           void* ws, size_t ws_bytes);
 
 /* Synchronise the context's stream and report the status of the last
  * nrs_lu_factor or nrs_lu_solve that used workspace ws (ws = NULL: the last

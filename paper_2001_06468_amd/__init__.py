@@ -26,7 +26,7 @@ __all__ = [
     "NrsError", "Context", "DeviceScene", "Problem", "nrs_create", "nrs_version", "nrs_geometry",
     "nrs_nearest", "nrs_workspace_size", "nrs_assemble", "nrs_apply", "nrs_solve",
     "nrs_query_info", "nrs_solve_batched_workspace_size", "nrs_solve_batched", "nrs_lu_factor", "nrs_lu_solve",
-    "nrs_lu_factor_workspace_size", "nrs_lu_solve_workspace_size", "nrs_lu_query", "nrs_lu_solve_noalloc", "nrs_rk4_workspace_size", "nrs_rk4_step",
+    "nrs_lu_factor_workspace_size", "nrs_lu_solve_workspace_size", "nrs_lu_query", "nrs_lu_solve_noalloc", "nrs_equilibrate", "nrs_rk4_workspace_size", "nrs_rk4_step",
     "NRS_FP64_LU", "NRS_FP32_IR", "NRS_FP32_GEPP_IR", "NRS_GMRES", "NRS_FP32_GMRES_IR", "NRS_BF16_GMRES_IR",
     "lda_for",
     "NRS_WARM_NONE", "NRS_WARM_PREVIOUS", "NRS_WARM_MODEL", "Model", "nrs_mlp_param_count",
@@ -174,13 +174,13 @@ class Model:
 
 def _options(method=NRS_FP64_LU, max_refine=0, tol=0.0, gmres_restart=0, gmres_max_iter=0,
              no_fallback=0, x_init=None, warm_start=NRS_WARM_NONE, model=None, body_off=None,
-             x_init_complete=0, graph=0, reuse_stage_factors=0):
+             x_init_complete=0, graph=0, reuse_stage_factors=0, no_equilibration=0):
     sc = (C.c_double * 3)(*(model.scales if model is not None else (0.0, 0.0, 0.0)))
     return NrsOptions(method, max_refine, tol, gmres_restart, gmres_max_iter, no_fallback,
                       _ptr(x_init, torch.float64, "x_init"), warm_start,
                       _ptr(model.theta, torch.float32, "theta") if model is not None else None,
                       sc, _ptr(body_off, torch.int32, "body_off"), int(x_init_complete),
-                      int(graph), int(reuse_stage_factors))
+                      int(graph), int(reuse_stage_factors), int(no_equilibration))
 
 
 def nrs_geometry(ctx, scene, t, Y, x=None, X=None, w=None, u=None):
@@ -325,6 +325,15 @@ def nrs_lu_solve_noalloc(ctx, LU, lda, perm, b, x, pivot_scope=0):
                                             _ptr(LU, LU.dtype, "LU"), lda,
                                             _ptr(perm, torch.int32, "perm"), _ptr(b, LU.dtype, "b"),
                                             _ptr(x, LU.dtype, "x")), ctx)
+
+
+def nrs_equilibrate(ctx, A, lda, dr, dc, ws):
+    """A (FP32, column-major as [n][lda]) <- D_r A D_c in place; dr, dc: [n] FP32."""
+    n = int(dr.numel())
+    f32 = torch.float32
+    _check(_lib.load().nrs_equilibrate(ctx.handle, n, _ptr(A, f32, "A"), lda, _ptr(dr, f32, "dr"),
+                                       _ptr(dc, f32, "dc"), _ptr(ws, torch.uint8, "ws"),
+                                       ws.numel()), ctx)
 
 
 def nrs_lu_query(ctx, ws=None):

@@ -53,7 +53,7 @@ class NrsOptions(C.Structure):
                 ("gmres_restart", _i32), ("gmres_max_iter", _i32), ("no_fallback", _i32),
                 ("x_init", _p), ("warm_start", _i32), ("model_theta", _p),
                 ("model_scales", C.c_double * 3), ("body_off", _p), ("x_init_complete", _i32),
-                ("graph", _i32), ("reuse_stage_factors", _i32)]
+                ("graph", _i32), ("reuse_stage_factors", _i32), ("no_equilibration", _i32)]
 
 
 class NrsInfo(C.Structure):
@@ -108,6 +108,7 @@ PROTOTYPES = {
     "nrs_lu_solve": (_i32, [_p, _i64, _i32, _i32, _p, _i64, _p, _p, _p, _p, C.c_size_t]),
     "nrs_lu_query": (_i32, [_p, _p, C.POINTER(_i32)]),
     "nrs_lu_solve_noalloc": (_i32, [_p, _i64, _i32, _i32, _p, _i64, _p, _p, _p]),
+    "nrs_equilibrate": (_i32, [_p, _i64, _p, _i64, _p, _p, _p, C.c_size_t]),
     "nrs_autotune": (_i32, [_p, C.POINTER(NrsProblem), _p, C.c_size_t, C.POINTER(NrsTuneResult)]),
     "nrs_autotune_clear": (_i32, [_p]),
     "nrs_mlp_param_count": (_i64, []),

@@ -152,6 +152,11 @@ bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, Sol
   sb.part = ar.take<double>((size_t)sb.chunks * 3 * N);
   sb.red = ar.take<double>(rowsum_scratch(n));
   sb.tsync = ar.take<int32_t>(trsv_sync_ints(n));
+  const bool f32 = uses_fp32(method);
+  sb.eqr = f32 ? ar.take<float>(n) : nullptr;
+  sb.eqc = f32 ? ar.take<float>(n) : nullptr;
+  sb.eqmax = f32 ? ar.take<uint32_t>(n) : nullptr;
+  sb.equil = false;
   sb.lu_done = ar.take<int32_t>(lu_tiles_nt(n) * lu_tiles_nt(n));
   sb.AT = sb.V = sb.gw0 = sb.gw1 = sb.gpart = nullptr;
   sb.gst = nullptr;
@@ -202,26 +207,31 @@ nrs_status run_fp64_lu(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, do
 // FP32 factors + FP64 refinement.  Correction solves use the FP32 factors;
 // residuals use the matrix-free FP64 operator.
 nrs_status run_fp32_ir(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, double* x,
-                       int32_t scope, int32_t max_refine, double tol, bool norm, hipStream_t s) {
+                       int32_t scope, int32_t max_refine, double tol, bool norm, bool equil,
+                       hipStream_t s) {
   const int64_t n = 3 * pb.N + 6 * (int64_t)pb.M;
   NRS_HIP(ctx, launch_assemble<float>(pb, sb.srt, sb.A32, sb.lda, s,
                                       asm_shape_for(ctx, pb.N, pb.Q, 32)));
   if (norm) NRS_HIP(ctx, launch_anorm32(n, sb.A32, sb.lda, sb.st, sb.red, s));
+  sb.equil = equil;
+  if (equil) NRS_HIP(ctx, launch_equilibrate(n, sb.A32, sb.lda, sb.eqr, sb.eqc, sb.eqmax, s));
+  const float* er = equil ? sb.eqr : nullptr;
+  const float* ec = equil ? sb.eqc : nullptr;
   NRS_HIP(ctx, lu_factor_any<float>(n, scope, sb.A32, sb.lda, sb.ipiv, sb.perm,
                                      &sb.st->singular, sb.lu_done, sb.st->lu_ctl, s,
                                      scope == 1 ? sb.sh : nullptr));
-  // x0 = (LU)^-1 b
+  // x0 = D_c (LU)^-1 D_r b
   float* b32 = reinterpret_cast<float*>(sb.r);  // r is free until the first residual
-  NRS_HIP(ctx, launch_convert_f32(n, sb.b, b32, s));
+  NRS_HIP(ctx, launch_convert_f32(n, sb.b, b32, s, er));
   NRS_HIP(ctx, launch_lu_solve<float>(n, scope, sb.A32, sb.lda, sb.perm, b32, sb.d32, sb.tsync,
                                       &sb.st->sync_err, &sb.st->stop, s));
-  NRS_HIP(ctx, launch_ir_update32(n, x, sb.d32, tol, 1, sb.st, s));
+  NRS_HIP(ctx, launch_ir_update32(n, x, sb.d32, tol, 1, sb.st, s, ec));
   for (int it = 0; it < max_refine; ++it) {
     NRS_HIP(ctx, launch_apply(pb, sb.srt, x, sb.d64, sb.part, sb.chunks, &sb.st->stop, s));
-    NRS_HIP(ctx, launch_ir_residual2(n, sb.b, sb.d64, x, nullptr, b32, nullptr, sb.st, 0, s));
+    NRS_HIP(ctx, launch_ir_residual2(n, sb.b, sb.d64, x, nullptr, b32, nullptr, sb.st, 0, s, er));
     NRS_HIP(ctx, launch_lu_solve<float>(n, scope, sb.A32, sb.lda, sb.perm, b32, sb.d32,
                                         sb.tsync, &sb.st->sync_err, &sb.st->stop, s));
-    NRS_HIP(ctx, launch_ir_update32(n, x, sb.d32, tol, 0, sb.st, s));
+    NRS_HIP(ctx, launch_ir_update32(n, x, sb.d32, tol, 0, sb.st, s, ec));
   }
   return NRS_OK;
 }
@@ -232,17 +242,20 @@ nrs_status run_fp32_ir(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, do
 nrs_status run_fp32_reuse(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, double* x,
                           int32_t max_refine, double tol, hipStream_t s) {
   const int64_t n = 3 * pb.N + 6 * (int64_t)pb.M;
+  // the factors (and their scale factors, if equilibrated) of the earlier system
+  const float* er = sb.equil ? sb.eqr : nullptr;
+  const float* ec = sb.equil ? sb.eqc : nullptr;
   float* b32 = reinterpret_cast<float*>(sb.r);
-  NRS_HIP(ctx, launch_convert_f32(n, sb.b, b32, s));
+  NRS_HIP(ctx, launch_convert_f32(n, sb.b, b32, s, er));
   NRS_HIP(ctx, launch_lu_solve<float>(n, 1, sb.A32, sb.lda, sb.perm, b32, sb.d32, sb.tsync,
                                       &sb.st->sync_err, &sb.st->stop, s));
-  NRS_HIP(ctx, launch_ir_update32(n, x, sb.d32, tol, 1, sb.st, s));
+  NRS_HIP(ctx, launch_ir_update32(n, x, sb.d32, tol, 1, sb.st, s, ec));
   for (int it = 0; it < max_refine; ++it) {
     NRS_HIP(ctx, launch_apply(pb, sb.srt, x, sb.d64, sb.part, sb.chunks, &sb.st->stop, s));
-    NRS_HIP(ctx, launch_ir_residual2(n, sb.b, sb.d64, x, nullptr, b32, nullptr, sb.st, 0, s));
+    NRS_HIP(ctx, launch_ir_residual2(n, sb.b, sb.d64, x, nullptr, b32, nullptr, sb.st, 0, s, er));
     NRS_HIP(ctx, launch_lu_solve<float>(n, 1, sb.A32, sb.lda, sb.perm, b32, sb.d32, sb.tsync,
                                         &sb.st->sync_err, &sb.st->stop, s));
-    NRS_HIP(ctx, launch_ir_update32(n, x, sb.d32, tol, 0, sb.st, s));
+    NRS_HIP(ctx, launch_ir_update32(n, x, sb.d32, tol, 0, sb.st, s, ec));
   }
   return NRS_OK;
 }
@@ -324,6 +337,10 @@ nrs_status run_fgmres(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, dou
   a.w1 = sb.gw1;
   a.part = sb.gpart;
   a.st = sb.gst;
+  if (sb.equil) {
+    a.eqr = sb.eqr;
+    a.eqc = sb.eqc;
+  }
   const int32_t* halt = &sb.gst->halt;
   NRS_HIP(ctx, launch_gmres_init(sb.gst, tol, m, max_iter, s));
   NRS_HIP(ctx, launch_apply(pb, sb.srt, x, sb.fax, sb.part, sb.chunks, nullptr, s));
@@ -395,8 +412,11 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
     st = run_fp64_lu(ctx, pb, sb, sol, sync, s);
   } else if (uses_fp32(method)) {
     const bool fgm = gmres_ir(method);
-    st = run_fp32_ir(ctx, pb, sb, sol, method == NRS_FP32_GEPP_IR ? 0 : 1, fgm ? 0 : max_refine,
-                     tol, sync, s);
+    // equilibration serves the static block pivots of the tile LU; the fully
+    // pivoted form factors A itself
+    const bool gepp = method == NRS_FP32_GEPP_IR;
+    st = run_fp32_ir(ctx, pb, sb, sol, gepp ? 0 : 1, fgm ? 0 : max_refine, tol, sync,
+                     !gepp && !o.no_equilibration, s);
     if (st == NRS_OK && fgm) st = run_fgmres(ctx, pb, sb, sol, o, s);
   } else if (method == NRS_GMRES) {
     st = run_gmres(ctx, pb, sb, sol, o, sync, s);
@@ -745,6 +765,17 @@ nrs_status nrs_lu_solve_noalloc(nrs_ctx* ctx, int64_t n, int32_t precision, int3
                 "nrs_lu_solve_noalloc: n above NRS_NOALLOC_MAX_N (use nrs_lu_solve)");
   if (!ctx->scratch) return fail(ctx, NRS_E_HIP, "scratch address not set up");
   return lu_solve_on(ctx, n, precision, pivot_scope, LU, lda, perm, b, x, ctx->scratch);
+}
+
+nrs_status nrs_equilibrate(nrs_ctx* ctx, int64_t n, float* A, int64_t lda, float* dr, float* dc,
+                           void* ws, size_t ws_bytes) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if (n <= 0 || !A || lda < n || !dr || !dc) return fail(ctx, NRS_E_ARG, "bad equilibration arguments");
+  if (!ws || ws_bytes < (size_t)n * sizeof(uint32_t))
+    return fail(ctx, NRS_E_WORKSPACE, "equilibration workspace missing or too small");
+  NRS_HIP(ctx, launch_equilibrate(n, A, lda, dr, dc, static_cast<uint32_t*>(ws), ctx->stream));
+  return NRS_OK;
 }
 
 nrs_status nrs_lu_query(nrs_ctx* ctx, const void* ws, int32_t* flags) {

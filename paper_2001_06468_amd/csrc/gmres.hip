@@ -369,7 +369,7 @@ __global__ void k_fg_begin(GmresArgs a, float* __restrict__ v32) {
   if (r < a.n) {
     const double v = vin[r] * s;
     a.V[r * kGmresLd + k] = v;
-    v32[r] = (float)v;
+    v32[r] = (float)(a.eqr ? v * (double)a.eqr[r] : v);
   }
 }
 
@@ -380,7 +380,7 @@ __global__ void k_fg_zstore(GmresArgs a, const float* __restrict__ d32, double* 
   const int k = st->k;
   const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (r < a.n) {
-    const double z = (double)d32[r];
+    const double z = a.eqc ? (double)d32[r] * (double)a.eqc[r] : (double)d32[r];
     a.Z[r * kGmresLd + k] = z;
     zv[r] = z;
   }

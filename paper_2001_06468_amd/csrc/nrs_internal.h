@@ -178,6 +178,10 @@ struct SolveBuffers {
   double* fzv;       // [n] z_k, the operator's input
   double* fax;       // [n] A x for the true residual
   uint16_t* sh;      // BF16 tile copies of the tile LU (NRS_BF16_GMRES_IR)
+  float* eqr;        // [n] row scale factors of the equilibrated FP32 matrix
+  float* eqc;        // [n] column scale factors
+  uint32_t* eqmax;   // [n] row maxima (scratch of the equilibration)
+  bool equil;        // the FP32 factors are of D_r A D_c (eqr, eqc valid)
 };
 
 size_t solve_workspace_bytes(int64_t N, int64_t Q, int32_t M, int32_t method);
@@ -303,6 +307,8 @@ struct GmresArgs {
   double* w1;
   double* part;       // [gmres_blocks(n)][kGmresLd]
   GmresState* st;
+  const float* eqr = nullptr;  // flexible GMRES on equilibrated factors: the
+  const float* eqc = nullptr;  // preconditioner is D_c (LU)^-1 D_r
 };
 int64_t gmres_blocks(int64_t n);
 hipError_t launch_transpose64(int64_t n, const double* A, int64_t lda, double* AT, int64_t ld,
@@ -400,12 +406,20 @@ hipError_t launch_anorm32(int64_t n, const float* A, int64_t lda, SolveState* st
                           hipStream_t s);
 hipError_t launch_anorm64(int64_t n, const double* A, int64_t lda, SolveState* st, double* red,
                           hipStream_t s);
+// eqr / eqc (may be NULL): the row / column scale factors of an equilibrated
+// FP32 factorisation (residual rows scaled by eqr before the correction
+// solve, the correction's entries by eqc after it)
 hipError_t launch_ir_residual2(int64_t n, const double* b, const double* Ax, const double* x,
                                double* r, float* r32, double* r64, SolveState* st, int force,
-                               hipStream_t s);
+                               hipStream_t s, const float* eqr = nullptr);
 hipError_t launch_ir_update32(int64_t n, double* x, const float* d, double tol, int32_t first,
-                              SolveState* st, hipStream_t s);
-hipError_t launch_convert_f32(int64_t n, const double* a, float* b, hipStream_t s);
+                              SolveState* st, hipStream_t s, const float* eqc = nullptr);
+hipError_t launch_convert_f32(int64_t n, const double* a, float* b, hipStream_t s,
+                              const float* scale = nullptr);
+// A <- D_r A D_c in place (FP32, powers of two, the largest entry of every row
+// and column then in [1, 2)); dr [n], dc [n] out; rmax [n] scratch.
+hipError_t launch_equilibrate(int64_t n, float* A, int64_t lda, float* dr, float* dc,
+                              uint32_t* rmax, hipStream_t s);
 hipError_t launch_check_nu(int64_t N, const int32_t* cnt, SolveState* st, hipStream_t s);
 hipError_t launch_check_body(int64_t N, int32_t M, const int32_t* body, SolveState* st,
                              hipStream_t s);

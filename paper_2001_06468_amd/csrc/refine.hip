@@ -68,6 +68,63 @@ __global__ void k_rowsum_final(int nblk, const double* red, SolveState* st) {
   if (threadIdx.x == 0) st->anorm = v;
 }
 
+// Equilibration of the FP32 matrix (row, then column scaling by powers of
+// two, so that the scaled matrix D_r A D_c is exact and the largest entry of
+// every row and column has magnitude in [1, 2)):
+//   r_i = max_j |a_ij|,  dr_i = 2^-floor(log2 r_i);
+//   c_j = max_i dr_i |a_ij|,  dc_j = 2^-floor(log2 c_j);   (1 for zero rows / columns)
+// Row maxima: thread = row over a chunk of 64 columns, combined with an
+// integer atomic maximum on the FP32 bit patterns (non-negative values order
+// as their bits).
+__device__ inline float pow2_scale(float v) {
+  return v > 0.f ? ldexpf(1.f, -ilogbf(v)) : 1.f;
+}
+
+__global__ void k_eq_rowmax(int64_t n, const float* __restrict__ A, int64_t lda,
+                            uint32_t* __restrict__ rmax) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j0 = (int64_t)blockIdx.y * 64, j1 = min<int64_t>(n, j0 + 64);
+  float m = 0.f;
+  for (int64_t j = j0; j < j1; ++j) m = fmaxf(m, fabsf(A[i + j * lda]));
+  atomicMax(&rmax[i], __float_as_uint(m));
+}
+
+// One workgroup per column: c_j over the row-scaled column, then dc_j; the
+// first n threads of the grid also turn the row maxima into dr.
+__global__ void k_eq_colscale(int64_t n, const float* __restrict__ A, int64_t lda,
+                              const uint32_t* __restrict__ rmax, float* __restrict__ dr,
+                              float* __restrict__ dc) {
+  __shared__ float sh[4];
+  const int64_t j = blockIdx.x;
+  const float* col = A + j * lda;
+  float m = 0.f;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+    m = fmaxf(m, fabsf(col[i]) * pow2_scale(__uint_as_float(rmax[i])));
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) dc[j] = pow2_scale(fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3])));
+  const int64_t g = j * blockDim.x + threadIdx.x;
+  if (g < n) dr[g] = pow2_scale(__uint_as_float(rmax[g]));
+}
+
+__global__ void k_eq_apply(int64_t n, float* __restrict__ A, int64_t lda,
+                           const float* __restrict__ dr, const float* __restrict__ dc) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j0 = (int64_t)blockIdx.y * 64, j1 = min<int64_t>(n, j0 + 64);
+  const float r = dr[i];
+  for (int64_t j = j0; j < j1; ++j) A[i + j * lda] *= r * dc[j];
+}
+
+// b32 = FP32(scale * a) (scale may be NULL)
+__global__ void k_convert_scaled(int64_t n, const double* __restrict__ a,
+                                 const float* __restrict__ scale, float* __restrict__ b) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)(scale ? a[i] * (double)scale[i] : a[i]);
+}
+
 // r = b - A x (FP64), r in the correction precision; backward error from
 // |r|, |x| (x is the solution the residual was taken at) and |b|.
 __global__ __launch_bounds__(kRedThreads) void k_ir_residual(int64_t n,
@@ -77,7 +134,8 @@ __global__ __launch_bounds__(kRedThreads) void k_ir_residual(int64_t n,
                                                              double* __restrict__ r,
                                                              float* __restrict__ r32,
                                                              double* __restrict__ r64,
-                                                             SolveState* st, int force) {
+                                                             SolveState* st, int force,
+                                                             const float* __restrict__ eqr) {
   __shared__ double sh[64];
   if (!force && (st->converged || st->failed)) return;
   double rmax = 0.0, bmax = 0.0, xmax = 0.0;
@@ -86,7 +144,7 @@ __global__ __launch_bounds__(kRedThreads) void k_ir_residual(int64_t n,
     const double v = b[i] - Ax[i];
     ok = ok && finite(v);
     if (r) r[i] = v;
-    if (r32) r32[i] = (float)v;
+    if (r32) r32[i] = (float)(eqr ? v * (double)eqr[i] : v);
     if (r64) r64[i] = v;
     rmax = fmax(rmax, fabs(v));
     bmax = fmax(bmax, fabs(b[i]));
@@ -113,13 +171,14 @@ __global__ __launch_bounds__(kRedThreads) void k_ir_residual(int64_t n,
 template <class T>
 __global__ __launch_bounds__(kRedThreads) void k_ir_update(int64_t n, double* __restrict__ x,
                                                            const T* __restrict__ d, double tol,
-                                                           int32_t first, SolveState* st) {
+                                                           int32_t first, SolveState* st,
+                                                           const float* __restrict__ eqc) {
   __shared__ double sh[64];
   if (st->converged || st->failed) return;
   double dmax = 0.0, xmax = 0.0;
   bool ok = true;
   for (int64_t i = threadIdx.x; i < n; i += kRedThreads) {
-    const double dv = (double)d[i];
+    const double dv = eqc ? (double)d[i] * (double)eqc[i] : (double)d[i];
     const double xv = first ? dv : x[i] + dv;
     ok = ok && finite(xv);
     x[i] = xv;
@@ -287,21 +346,37 @@ hipError_t launch_anorm64(int64_t n, const double* A, int64_t lda, SolveState* s
 
 hipError_t launch_ir_residual2(int64_t n, const double* b, const double* Ax, const double* x,
                                double* r, float* r32, double* r64, SolveState* st, int force,
-                               hipStream_t s) {
+                               hipStream_t s, const float* eqr) {
   hipLaunchKernelGGL(k_ir_residual, dim3(1), dim3(kRedThreads), 0, s, n, b, Ax, x, r, r32, r64,
-                     st, force);
+                     st, force, eqr);
   return hipGetLastError();
 }
 
 hipError_t launch_ir_update32(int64_t n, double* x, const float* d, double tol, int32_t first,
-                              SolveState* st, hipStream_t s) {
+                              SolveState* st, hipStream_t s, const float* eqc) {
   hipLaunchKernelGGL(k_ir_update<float>, dim3(1), dim3(kRedThreads), 0, s, n, x, d, tol, first,
-                     st);
+                     st, eqc);
   return hipGetLastError();
 }
 
-hipError_t launch_convert_f32(int64_t n, const double* a, float* b, hipStream_t s) {
-  hipLaunchKernelGGL(k_convert<float>, grid1(n, 256), dim3(256), 0, s, n, a, b);
+hipError_t launch_convert_f32(int64_t n, const double* a, float* b, hipStream_t s,
+                              const float* scale) {
+  if (scale)
+    hipLaunchKernelGGL(k_convert_scaled, grid1(n, 256), dim3(256), 0, s, n, a, scale, b);
+  else
+    hipLaunchKernelGGL(k_convert<float>, grid1(n, 256), dim3(256), 0, s, n, a, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_equilibrate(int64_t n, float* A, int64_t lda, float* dr, float* dc,
+                              uint32_t* rmax, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipError_t e = launch_fill_i32(reinterpret_cast<int32_t*>(rmax), 0, n, s);
+  if (e != hipSuccess) return e;
+  const dim3 g2((unsigned)((n + 255) / 256), (unsigned)((n + 63) / 64));
+  hipLaunchKernelGGL(k_eq_rowmax, g2, dim3(256), 0, s, n, A, lda, rmax);
+  hipLaunchKernelGGL(k_eq_colscale, dim3((unsigned)n), dim3(256), 0, s, n, A, lda, rmax, dr, dc);
+  hipLaunchKernelGGL(k_eq_apply, g2, dim3(256), 0, s, n, A, lda, dr, dc);
   return hipGetLastError();
 }
 

@@ -195,6 +195,48 @@ def test_lu_singular_flag(ctx, scope):
     assert sing.item() == 1
 
 
+def _pow2_scale(v):
+    """2^-floor(log2 v) for v > 0, else 1 (FP32 values)."""
+    out = np.ones_like(v)
+    pos = v > 0
+    out[pos] = np.ldexp(np.float32(1.0), -np.floor(np.log2(v[pos].astype(np.float64))).astype(int))
+    return out.astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [1, 65, 300])
+def test_equilibrate_matches_definition(ctx, n):
+    """nrs_equilibrate against its definition computed here in NumPy: the
+    power-of-two row factors from the row maxima, the column factors from the
+    maxima of the row-scaled columns, and the scaled matrix, all bit for bit
+    (powers of two scale exactly); an all-zero row and column keep factor 1;
+    every row and column maximum of the result is in [1, 2)."""
+    rng = np.random.default_rng(n)
+    A0 = (rng.normal(size=(n, n)) * np.exp(rng.uniform(-20, 20, size=(n, 1)))
+          * np.exp(rng.uniform(-20, 20, size=(1, n)))).astype(np.float32)
+    if n > 2:
+        A0[1, :] = 0.0
+        A0[:, 2] = 0.0
+    lda = nrs.lda_for(n) + 3
+    A = torch.zeros((n, lda), dtype=torch.float32, device=DEV)
+    A[:, :n] = torch.from_numpy(A0.T.copy()).to(DEV)
+    dr = torch.empty(n, dtype=torch.float32, device=DEV)
+    dc = torch.empty(n, dtype=torch.float32, device=DEV)
+    ws = torch.empty(4 * n, dtype=torch.uint8, device=DEV)
+    nrs.nrs_equilibrate(ctx, A, lda, dr, dc, ws)
+    r_ref = _pow2_scale(np.abs(A0).max(axis=1))
+    c_ref = _pow2_scale((np.abs(A0) * r_ref[:, None]).max(axis=0))
+    np.testing.assert_array_equal(dr.cpu().numpy(), r_ref)
+    np.testing.assert_array_equal(dc.cpu().numpy(), c_ref)
+    S = A.cpu().numpy()[:, :n].T
+    np.testing.assert_array_equal(S, A0 * r_ref[:, None] * c_ref[None, :])
+    rows, cols = np.abs(S).max(axis=1), np.abs(S).max(axis=0)
+    nz_r, nz_c = rows > 0, cols > 0
+    assert np.all(cols[nz_c] >= 1) and np.all(cols[nz_c] < 2)
+    assert np.all(rows[nz_r] < 2)
+    if n > 2:
+        assert dr[1].item() == 1.0 and dc[2].item() == 1.0
+
+
 def test_lu_timeout_word_cleared_each_call(ctx):
     """The factor and solve workspaces carry the wait-timeout word of their
     last call: a word left set (here planted from the host) is cleared by the
@@ -308,14 +350,18 @@ SOLVE_CASES = [
 
 @pytest.mark.parametrize("name,mk", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
 @pytest.mark.parametrize("method", ["FP64_LU", "FP32_IR", "FP32_GEPP_IR", "FP32_GMRES_IR",
-                                    "BF16_GMRES_IR"])
+                                    "BF16_GMRES_IR", "FP32_IR_UNSCALED"])
 def test_solve_matches_oracle(ctx, name, mk, method):
+    """Every method against the oracle; the FP32 forms factor the equilibrated
+    matrix D_r A D_c, FP32_IR_UNSCALED factors A itself."""
     scene = mk()
     pb, host = prepare(scene, 0.3)
     A_ref, b_ref = oracle_system(scene, host)
     ref = np.linalg.solve(A_ref, b_ref)
+    unscaled = method.endswith("_UNSCALED")
+    method = method.replace("_UNSCALED", "")
     m = getattr(nrs, "NRS_" + method)
-    sol, info = gpu_solve(ctx, scene, pb, host, m)
+    sol, info = gpu_solve(ctx, scene, pb, host, m, no_equilibration=int(unscaled))
     ef, eg = rel_force_errors(sol, ref, scene["N"])
     assert ef <= 1e-8 and eg <= 1e-8, (ef, eg, info)
     assert info["fell_back"] == 0
