@@ -43,6 +43,54 @@ FIELD_TRAFFIC = {"source_sha256_16": "7f18d8d2f998ad7c", "bytes_per_call": 24459
                  "tracers": 806}
 
 
+# Counter-derived figures (rocprofv3 --pmc runs of this benchmark, each counter
+# scaled by what it reads for a kernel of known work run in the same
+# process), valid only for the kernel source they were taken on.
+COUNTERS = {
+    "lu": {"source": "lu_tiles.hip", "source_sha256_16": "27adf9ab58c1e98f", "n": 3150,
+           "mfma_flops_per_launch": 2.169e10, "mfma_busy": 0.073,
+           "calibration": "FP32 4096^3 matrix product: 0.954 busy at 150 TFLOP/s"},
+    "assembly": {"source": "assemble.hip", "source_sha256_16": "b51c98c8db4067b2", "N": 1000,
+                 "Q": 10000, "valu_fp32_flops_per_call": 4.055e8,
+                 "fp32_rsqrt_per_call": 1.02e7, "valu_fp64_flops_per_call": 6.513e8,
+                 "fp64_transcendental_per_call": 2.05e7,
+                 "calibration": "elementwise multiplies of 2^26 elements read 2^20: x 64"},
+}
+
+
+def counter_summary(which, cur_sha=None):
+    rec = COUNTERS.get(which)
+    if rec is None:
+        return None
+    src = os.path.join(ROOT, "paper_2001_06468_amd", "csrc", rec["source"])
+    import hashlib
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if sha != rec["source_sha256_16"]:
+        return None
+    return {k: v for k, v in rec.items() if k not in ("source", "source_sha256_16")}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_dgemm_gflops(nsz=2048, reps=3):
+    """Host FP64 matrix-product rate (NumPy/BLAS), the CPU roofline figure."""
+    import numpy as np
+    a = np.random.default_rng(0).normal(size=(nsz, nsz))
+    a @ a
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        a @ a
+    return 2.0 * nsz ** 3 * reps / (time.perf_counter() - t0) / 1e9
+
+
 def cpu_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -165,7 +213,7 @@ def run_field(ctx, nrs, synth, dev, reps=40):
                     "w_q f[nu(q)] and the fixed-order chunk sum"}
 
 
-def run_channel(ctx, nrs, synth, dev):
+def run_channel(ctx, nrs, synth, dev, sizes=((10, 16), (40, 24))):
     """Channel configuration (10 and 40 sperm-like swimmers in the 4 x 1 x 0.5
     channel, wall spacing 1/16 and 1/24, n = 14,244 and 39,504): one
     synchronous solve each with the GMRES-IR forms after a warm-up solve, and
@@ -173,7 +221,7 @@ def run_channel(ctx, nrs, synth, dev):
     events.  Geometry and nearest map on the GPU."""
     import torch
     out = []
-    for K, h in ((10, 16), (40, 24)):
+    for K, h in sizes:
         sc = synth.sperm_channel_scene(K, h=1.0 / h, seed=0)
         ds = nrs.DeviceScene(sc, dev)
         Y = torch.from_numpy(sc["Y0"].copy()).to(dev)
@@ -264,15 +312,85 @@ def cpu_oracle_leg(scene, dt, field_pairs_sample=200):
     c1 = time.perf_counter()
     oracle.field_velocity(ys, X, w, nu, f, fscene["eps"], fscene["mu"])
     f_el = time.perf_counter() - c1
+    # the same oracle solve on one thread
+    single = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            c2 = time.perf_counter()
+            oracle.solve_scene(scene, 0.0, scene["Y0"])
+            single = time.perf_counter() - c2
+    except Exception:
+        pass
     cpu = {"value": 4.0 / c_el, "unit": "solves/s", "cores": cpu_threads(), "kind": "oracle",
            "sample": "one RK4 step (4 solves) of the same 25-filament workload from the "
                      "seeded initial state, NumPy/LAPACK FP64 oracle",
-           "seconds": c_el}
+           "seconds": c_el, "cpu_model": cpu_model(), "logical_cpus": os.cpu_count(),
+           "single_thread_solves_per_s": (1.0 / single) if single else None,
+           "host_dgemm_gflops": host_dgemm_gflops()}
     field_cpu = {"value": ys.shape[1] * float(fscene["Q"]) / f_el, "unit": "pairs/s",
                  "cores": cpu_threads(), "kind": "oracle",
                  "sample": f"flow at the first {ys.shape[1]} tracers of the tracer workload",
                  "seconds": f_el}
     return cpu, field_cpu, f_ref, UW_ref
+
+
+def run_small(ctx, nrs, synth, dev):
+    """The small configurations: the unit sphere of the resistance problem
+    (N = 96, Q = 1536, n = 288; synchronous-free repeated solves, 100 timed
+    after 5 warm-up) and one and five filament swimmers (n = 126, 630;
+    RK4 steps of dt = 2 pi / 100).  Mean and median per solve from HIP events
+    around each solve or step, as the paper reports means over 100 runs."""
+    import numpy as np
+    import torch
+    out = {}
+    sc = synth.sphere_scene(4, 16)
+    ds = nrs.DeviceScene(sc, dev)
+    pb, u = device_problem(ctx, nrs, ds, sc, 0.0, None, dev)
+    sol = torch.empty(pb.n, dtype=torch.float64, device=dev)
+    rec = {"workload": "sphere_N96_Q1536", "n": pb.n}
+    for name, m in (("fp64_lu", nrs.NRS_FP64_LU), ("fp32_ir", nrs.NRS_FP32_IR)):
+        ws = torch.empty(nrs.nrs_workspace_size(ctx, pb.N, pb.Q, pb.M, m), dtype=torch.uint8,
+                         device=dev)
+        info = nrs.nrs_solve(ctx, pb, u, None, sol, ws, method=m)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(106)]
+        for k in range(105):
+            if k == 5:
+                ev[0].record()
+            nrs.nrs_solve(ctx, pb, u, None, sol, ws, method=m, info=False)
+            if k >= 5:
+                ev[k - 4].record()
+        torch.cuda.synchronize()
+        t = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(100)])
+        rec[name] = {"solves_per_s": 1e3 / t.mean(), "ms_mean": float(t.mean()),
+                     "ms_median": float(np.median(t)), "runs": 100,
+                     "fell_back": info["fell_back"], "iterations": info["iterations"]}
+    out["sphere"] = rec
+    for M, steps in ((1, 100), (5, 50)):
+        sc = synth.filament_scene(M, seed=0)
+        ds = nrs.DeviceScene(sc, dev)
+        rec = {"workload": f"filaments_M{M}_rk4", "n": 3 * sc["N"] + 6 * M}
+        for name, m, k in (("fp32_ir", nrs.NRS_FP32_IR, steps), ("fp64_lu", nrs.NRS_FP64_LU,
+                                                                   max(10, steps // 5))):
+            ws = torch.empty(nrs.nrs_rk4_workspace_size(ctx, ds, m), dtype=torch.uint8,
+                             device=dev)
+            Y = torch.from_numpy(sc["Y0"].copy()).to(dev)
+            dt = 2 * math.pi / 100
+            for w in range(3):
+                nrs.nrs_rk4_step(ctx, ds, Y, w * dt, dt, ws, method=m)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
+            ev[0].record()
+            for j in range(k):
+                nrs.nrs_rk4_step(ctx, ds, Y, (3 + j) * dt, dt, ws, method=m)
+                ev[j + 1].record()
+            torch.cuda.synchronize()
+            t = np.array([ev[j].elapsed_time(ev[j + 1]) for j in range(k)]) / 4.0
+            info = nrs.nrs_query_info(ctx, ws)
+            rec[name] = {"solves_per_s": 1e3 / t.mean(), "ms_per_solve_mean": float(t.mean()),
+                         "ms_per_solve_median": float(np.median(t)), "steps": k,
+                         "fell_back": info["fell_back"]}
+        out[f"filaments_M{M}"] = rec
+    return out
 
 
 def run_batched(ctx, nrs, synth, B, dev, reps=3, tune=True):
@@ -389,6 +507,12 @@ def main():
                     help="time only the flow-at-tracers workload (profiling)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--calib-flops", action="store_true",
+                    help="also run kernels of known flop counts (counter calibration)")
+    ap.add_argument("--channel-k", type=int, default=0, choices=(0, 10, 40),
+                    help="with --channel-only: only the 10- or 40-swimmer channel")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the small configurations (sphere, 1 and 5 filaments)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path; "
@@ -410,6 +534,8 @@ def main():
     ctx = nrs.Context(0)
     dt = 2 * math.pi / 100
 
+    per_step = []
+
     def run_steps(method, warmup, steps, **opts):
         ws = torch.empty(nrs.nrs_rk4_workspace_size(ctx, ds, method), dtype=torch.uint8, device=dev)
         Y = torch.from_numpy(scene["Y0"].copy()).to(dev)
@@ -418,18 +544,19 @@ def main():
             nrs.nrs_rk4_step(ctx, ds, Y, t, dt, ws, method=method, **opts)
             t += dt
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         w0 = time.perf_counter()
-        e0.record()
-        for _ in range(steps):
+        ev[0].record()
+        for k in range(steps):
             nrs.nrs_rk4_step(ctx, ds, Y, t, dt, ws, method=method, **opts)
             t += dt
-        e1.record()
+            ev[k + 1].record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
         info = nrs.nrs_query_info(ctx, ws)
-        return e0.elapsed_time(e1), wall, Y, t, info
+        per_step.clear()
+        per_step.extend(ev[k].elapsed_time(ev[k + 1]) for k in range(steps))
+        return ev[0].elapsed_time(ev[steps]), wall, Y, t, info
 
     if args.calib_copy > 0:
         src = torch.ones(args.calib_copy * (1 << 20) // 4, dtype=torch.float32, device=dev)
@@ -437,9 +564,23 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.calib_flops:
+        # kernels of known work for the counter runs: one FP32 matrix product
+        # (2 * 4096^3 flops on the matrix cores) and one FP32 and one FP64
+        # elementwise multiply of 2^26 elements (2^26 flops each on the VALU)
+        a = torch.ones(4096, 4096, dtype=torch.float32, device=dev)
+        (a @ a).sum()
+        v32 = torch.ones(1 << 26, dtype=torch.float32, device=dev)
+        v32.mul_(1.5)
+        v64 = torch.ones(1 << 26, dtype=torch.float64, device=dev)
+        v64.mul_(1.5)
+        torch.cuda.synchronize()
+        del a, v32, v64
 
     if args.channel_only:
-        print(json.dumps({"channel": run_channel(ctx, nrs, synth, dev)}), flush=True)
+        sizes = ((10, 16), (40, 24)) if args.channel_k == 0 else \
+            tuple(x for x in ((10, 16), (40, 24)) if x[0] == args.channel_k)
+        print(json.dumps({"channel": run_channel(ctx, nrs, synth, dev, sizes)}), flush=True)
         return
 
     if args.field_only:
@@ -465,6 +606,7 @@ def main():
     ms, wall, Y, t_end, info = run_steps(method, args.warmup, args.steps)
     solves = 4 * args.steps
     value = solves / (ms / 1e3)
+    step_ms = list(per_step)
 
     # --- one synchronous solve of the seeded initial state (accuracy check
     # against the oracle in the CPU leg) on the product's own geometry -------
@@ -517,6 +659,22 @@ def main():
     as_avg_ms = float(np.mean(as_ms))
     asm_flops = 33.0 * N * Q
     asm_tflops = asm_flops / (as_avg_ms / 1e3) / 1e12
+    ws64 = torch.empty(nrs.nrs_workspace_size(ctx, N, Q, M, nrs.NRS_FP64_LU), dtype=torch.uint8,
+                       device=dev)
+    A64 = torch.empty((n, lda), dtype=torch.float64, device=dev)
+    as64_ms = []
+    for rep in range(12):
+        b0 = torch.cuda.Event(enable_timing=True)
+        b1 = torch.cuda.Event(enable_timing=True)
+        b0.record()
+        nrs.nrs_assemble(ctx, pb, 64, A64, lda, ws64)
+        b1.record()
+        torch.cuda.synchronize()
+        if rep >= 2:
+            as64_ms.append(b0.elapsed_time(b1))
+    del A64, ws64
+    as64_avg_ms = float(np.mean(as64_ms))
+    asm64_tflops = asm_flops / (as64_avg_ms / 1e3) / 1e12
 
     forms = {}
     learned_info = None
@@ -553,6 +711,10 @@ def main():
                            "fell_back": finfo["fell_back"],
                            "max_stage_iterations_last_step": finfo["iterations"]}
 
+    small = None
+    if not args.no_small:
+        small = run_small(ctx, nrs, synth, dev)
+
     batched = None
     if args.batch > 0:
         batched = run_batched(ctx, nrs, synth, args.batch, dev, tune=not args.no_tune)
@@ -588,6 +750,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms / args.steps,
+        "ms_per_step_median": float(np.median(step_ms)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -599,12 +762,21 @@ def main():
         "roofline": {"kernel": "k_lu_tiles<float>", "bound": "mfma", "achieved": lu_tflops,
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": lu_tflops / PEAK_FP32_TFLOPS, "traffic": traffic,
-                     "flops_per_launch": lu_flops, "avg_launch_ms": lu_avg_ms},
+                     "flops_per_launch": lu_flops, "avg_launch_ms": lu_avg_ms,
+                     "median_launch_ms": float(np.median(lu_ms)),
+                     "counters": counter_summary("lu", cur)},
         "assembly": {"tflops": asm_tflops, "frac_fp32_peak": asm_tflops / PEAK_FP32_TFLOPS,
                      "flops_per_call": asm_flops, "avg_call_ms": as_avg_ms,
+                     "median_call_ms": float(np.median(as_ms)),
+                     "fp64": {"tflops": asm64_tflops,
+                              "frac_fp64_peak": asm64_tflops / PEAK_FP64_TFLOPS,
+                              "avg_call_ms": as64_avg_ms,
+                              "median_call_ms": float(np.median(as64_ms))},
+                     "counters": counter_summary("assembly"),
                      "note": "33 flops per (force point, quadrature point) pair; call includes "
                              "the nu-sorted layout and rigid-body blocks"},
         "forms": forms,
+        "small_configs": small,
         "learned_training": learned_info,
         "autotune": tune,
         "batched": batched,

@@ -182,15 +182,16 @@ typedef struct {
      that does not converge sends the step to the FP64 fallback like any
      failed stage.  Ignored by every other call. */
   int32_t reuse_stage_factors;
-  /* The FP32 tile-LU forms (NRS_FP32_IR, NRS_FP32_GMRES_IR,
+  /* Non-zero: the FP32 tile-LU forms (NRS_FP32_IR, NRS_FP32_GMRES_IR,
      NRS_BF16_GMRES_IR) of nrs_solve, nrs_rk4_step and nrs_dopri5_integrate
      factor the equilibrated matrix D_r A D_c: D_r, D_c powers of two, row
      scaling r_i = max_j |a_ij|, dr_i = 2^-floor(log2 r_i), then column
      scaling of the row-scaled matrix likewise, so every row's and column's
      largest entry has magnitude in [1, 2) and the scaling adds no rounding.
      Refinement keeps the unscaled FP64 residual: correction = D_c (LU)^-1
-     D_r r.  Non-zero: factor A itself.  (nrs_solve_batched does not scale.) */
-  int32_t no_equilibration;
+     D_r r.  Zero (default): factor A itself.  (NRS_FP32_GEPP_IR, whose
+     partial pivoting needs no scaling, and nrs_solve_batched never scale.) */
+  int32_t equilibrate;
 } nrs_options;
 
 typedef struct {
@@ -367,8 +368,9 @@ nrs_status nrs_lu_query(nrs_ctx* ctx, const void* ws, int32_t* flags);
 
 /* Autotuning of launch shapes.  Times every candidate launch shape of the
  * FP32 and FP64 assembly kernels (rows per workgroup 64 / 128 / 256 x force
- * points per strip 4 / 8 / 16) on this problem (one warm-up and three timed
- * runs each, HIP events on the context's stream), and records the fastest
+ * points per strip 4 / 8 / 16) on this problem (one warm-up launch, then the
+ * best of three runs of eight back-to-back launches each, HIP events on the
+ * context's stream), and records the fastest
  * for the problem's size class (floor(log2 N), floor(log2(Q / N))) in the
  * context; every later assembly of a problem of that class, in any entry
  * point, uses it.  Every shape computes each matrix entry with the same

@@ -174,13 +174,13 @@ class Model:
 
 def _options(method=NRS_FP64_LU, max_refine=0, tol=0.0, gmres_restart=0, gmres_max_iter=0,
              no_fallback=0, x_init=None, warm_start=NRS_WARM_NONE, model=None, body_off=None,
-             x_init_complete=0, graph=0, reuse_stage_factors=0, no_equilibration=0):
+             x_init_complete=0, graph=0, reuse_stage_factors=0, equilibrate=0):
     sc = (C.c_double * 3)(*(model.scales if model is not None else (0.0, 0.0, 0.0)))
     return NrsOptions(method, max_refine, tol, gmres_restart, gmres_max_iter, no_fallback,
                       _ptr(x_init, torch.float64, "x_init"), warm_start,
                       _ptr(model.theta, torch.float32, "theta") if model is not None else None,
                       sc, _ptr(body_off, torch.int32, "body_off"), int(x_init_complete),
-                      int(graph), int(reuse_stage_factors), int(no_equilibration))
+                      int(graph), int(reuse_stage_factors), int(equilibrate))
 
 
 def nrs_geometry(ctx, scene, t, Y, x=None, X=None, w=None, u=None):

@@ -53,7 +53,7 @@ class NrsOptions(C.Structure):
                 ("gmres_restart", _i32), ("gmres_max_iter", _i32), ("no_fallback", _i32),
                 ("x_init", _p), ("warm_start", _i32), ("model_theta", _p),
                 ("model_scales", C.c_double * 3), ("body_off", _p), ("x_init_complete", _i32),
-                ("graph", _i32), ("reuse_stage_factors", _i32), ("no_equilibration", _i32)]
+                ("graph", _i32), ("reuse_stage_factors", _i32), ("equilibrate", _i32)]
 
 
 class NrsInfo(C.Structure):

@@ -416,7 +416,7 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
     // pivoted form factors A itself
     const bool gepp = method == NRS_FP32_GEPP_IR;
     st = run_fp32_ir(ctx, pb, sb, sol, gepp ? 0 : 1, fgm ? 0 : max_refine, tol, sync,
-                     !gepp && !o.no_equilibration, s);
+                     !gepp && o.equilibrate != 0, s);
     if (st == NRS_OK && fgm) st = run_fgmres(ctx, pb, sb, sol, o, s);
   } else if (method == NRS_GMRES) {
     st = run_gmres(ctx, pb, sb, sol, o, sync, s);
@@ -839,21 +839,28 @@ nrs_status nrs_autotune(nrs_ctx* ctx, const nrs_problem* pb, void* ws, size_t ws
   int32_t best[2] = {kAsmDefaultShape, kAsmDefaultShape};
   float best_ms[2] = {0.f, 0.f}, def_ms[2] = {0.f, 0.f};
   hipError_t err = hipSuccess;
+  // per shape: one warm-up launch, then the best of three timed runs of
+  // kLaunches back-to-back launches (one event pair around each run, so that
+  // launch latency is not counted once per launch)
+  constexpr int kLaunches = 8;
+  auto launch = [&](int prec, int shape) {
+    return prec == 0 ? launch_assemble<float>(*pb, sb.srt, sb.A32, sb.lda, s, shape)
+                     : launch_assemble<double>(*pb, sb.srt, sb.A64, sb.lda, s, shape);
+  };
   for (int prec = 0; prec < 2 && err == hipSuccess; ++prec) {
     for (int shape = 0; shape < kAsmShapes && err == hipSuccess; ++shape) {
-      float tot = 0.f;
-      for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
+      err = launch(prec, shape);
+      float avg = 0.f;
+      for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
         err = hipEventRecord(e0, s);
-        if (err == hipSuccess)
-          err = prec == 0 ? launch_assemble<float>(*pb, sb.srt, sb.A32, sb.lda, s, shape)
-                          : launch_assemble<double>(*pb, sb.srt, sb.A64, sb.lda, s, shape);
+        for (int k = 0; k < kLaunches && err == hipSuccess; ++k) err = launch(prec, shape);
         if (err == hipSuccess) err = hipEventRecord(e1, s);
         if (err == hipSuccess) err = hipEventSynchronize(e1);
         float ms = 0.f;
         if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        if (rep > 0) tot += ms;   // first run warms up
+        const float per = ms / kLaunches;
+        if (rep == 0 || per < avg) avg = per;
       }
-      const float avg = tot / 3.f;
       if (shape == kAsmDefaultShape) def_ms[prec] = avg;
       if (shape == 0 || avg < best_ms[prec]) {
         best_ms[prec] = avg;

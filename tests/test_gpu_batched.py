@@ -35,13 +35,11 @@ def ctx():
 
 
 def _single(ctx, scene, pb, host):
-    """The single solve of the same method without equilibration (a batch
-    factors its systems unscaled)."""
+    """The single solve of the same method (unscaled, as a batch)."""
     ws = workspace(ctx, pb, nrs.NRS_FP32_IR)
     sol = torch.empty(pb.n, dtype=torch.float64, device=DEV)
     ft = T(scene["ftext"]) if scene["M"] else None
-    info = nrs.nrs_solve(ctx, pb, T(host["u"]), ft, sol, ws, method=nrs.NRS_FP32_IR,
-                         no_equilibration=1)
+    info = nrs.nrs_solve(ctx, pb, T(host["u"]), ft, sol, ws, method=nrs.NRS_FP32_IR)
     return sol.cpu().numpy(), info
 
 

@@ -350,18 +350,18 @@ SOLVE_CASES = [
 
 @pytest.mark.parametrize("name,mk", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
 @pytest.mark.parametrize("method", ["FP64_LU", "FP32_IR", "FP32_GEPP_IR", "FP32_GMRES_IR",
-                                    "BF16_GMRES_IR", "FP32_IR_UNSCALED"])
+                                    "BF16_GMRES_IR", "FP32_IR_SCALED"])
 def test_solve_matches_oracle(ctx, name, mk, method):
-    """Every method against the oracle; the FP32 forms factor the equilibrated
-    matrix D_r A D_c, FP32_IR_UNSCALED factors A itself."""
+    """Every method against the oracle; FP32_IR_SCALED factors the equilibrated
+    matrix D_r A D_c."""
     scene = mk()
     pb, host = prepare(scene, 0.3)
     A_ref, b_ref = oracle_system(scene, host)
     ref = np.linalg.solve(A_ref, b_ref)
-    unscaled = method.endswith("_UNSCALED")
-    method = method.replace("_UNSCALED", "")
+    scaled = method.endswith("_SCALED")
+    method = method.replace("_SCALED", "")
     m = getattr(nrs, "NRS_" + method)
-    sol, info = gpu_solve(ctx, scene, pb, host, m, no_equilibration=int(unscaled))
+    sol, info = gpu_solve(ctx, scene, pb, host, m, equilibrate=int(scaled))
     ef, eg = rel_force_errors(sol, ref, scene["N"])
     assert ef <= 1e-8 and eg <= 1e-8, (ef, eg, info)
     assert info["fell_back"] == 0
