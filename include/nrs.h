@@ -304,8 +304,9 @@ nrs_status nrs_solve_batched(nrs_ctx* ctx, int32_t B, const nrs_problem* problem
  *        LAPACK order; for scope 1 the interchanges stay inside a tile);
  *   perm [n] int32: scope 0: the composite permutation, (P b)[i] = b[perm[i]];
  *        scope 1: logical row i of its tile came from original row perm[i];
- *   singular_flag [1] int32: set to 1 if an exact zero pivot is met (left
- *        untouched otherwise; the caller clears it).
+ *   singular_flag [1] int32: bit 0 set if an exact zero pivot is met, bit 1
+ *        if a bounded wait between the workgroups of a partial-pivoting
+ *        panel timed out (left untouched otherwise; the caller clears it).
  * ws: device workspace of at least nrs_lu_factor_workspace_size(n, precision)
  * bytes, owned by the caller (the tile LU's ticket, flag and timeout words,
  * cleared by the call itself, and for precision 16 the BF16 tile copies,

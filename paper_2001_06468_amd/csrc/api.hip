@@ -48,6 +48,7 @@ constexpr double kFgmresTol = 1e-12;
 size_t lu_factor_ws_bytes(int64_t n, int32_t precision) {
   size_t b = (size_t)lu_factor_sync_ints(n) * sizeof(int32_t);
   if (precision == 16) b += (size_t)lu_shadow_elems(n) * sizeof(uint16_t);
+  else b += gepp_scratch_bytes(n);
   return b + 256;
 }
 size_t lu_solve_ws_bytes(int64_t n) {
@@ -152,6 +153,7 @@ bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, Sol
   sb.part = ar.take<double>((size_t)sb.chunks * 3 * N);
   sb.red = ar.take<double>(rowsum_scratch(n));
   sb.tsync = ar.take<int32_t>(trsv_sync_ints(n));
+  sb.gepp = ar.take<char>(gepp_scratch_bytes(n));
   const bool f32 = uses_fp32(method);
   sb.eqr = f32 ? ar.take<float>(n) : nullptr;
   sb.eqc = f32 ? ar.take<float>(n) : nullptr;
@@ -198,7 +200,8 @@ nrs_status run_fp64_lu(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, do
                                        asm_shape_for(ctx, pb.N, pb.Q, 64)));
   if (norm) NRS_HIP(ctx, launch_anorm64(n, sb.A64, sb.lda, sb.st, sb.red, s));
   NRS_HIP(ctx, lu_factor_any<double>(n, 0, sb.A64, sb.lda, sb.ipiv64, sb.perm64,
-                                      &sb.st->singular, sb.lu_done, sb.st->lu_ctl, s));
+                                      &sb.st->singular, sb.lu_done, sb.st->lu_ctl, s, nullptr,
+                                      sb.gepp));
   NRS_HIP(ctx, launch_lu_solve<double>(n, 0, sb.A64, sb.lda, sb.perm64, sb.b, x, sb.tsync,
                                        &sb.st->sync_err, nullptr, s));
   return NRS_OK;
@@ -219,7 +222,7 @@ nrs_status run_fp32_ir(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, do
   const float* ec = equil ? sb.eqc : nullptr;
   NRS_HIP(ctx, lu_factor_any<float>(n, scope, sb.A32, sb.lda, sb.ipiv, sb.perm,
                                      &sb.st->singular, sb.lu_done, sb.st->lu_ctl, s,
-                                     scope == 1 ? sb.sh : nullptr));
+                                     scope == 1 ? sb.sh : nullptr, sb.gepp));
   // x0 = D_c (LU)^-1 D_r b
   float* b32 = reinterpret_cast<float*>(sb.r);  // r is free until the first residual
   NRS_HIP(ctx, launch_convert_f32(n, sb.b, b32, s, er));
@@ -696,10 +699,12 @@ nrs_status nrs_lu_factor(nrs_ctx* ctx, int64_t n, int32_t precision, int32_t piv
                                       done, ctl, ctx->stream, sh));
   } else if (precision == 32) {
     NRS_HIP(ctx, lu_factor_any<float>(n, pivot_scope, static_cast<float*>(A), lda, ipiv, perm,
-                                      singular_flag, done, ctl, ctx->stream));
+                                      singular_flag, done, ctl, ctx->stream, nullptr,
+                                      ctl + words));
   } else {
     NRS_HIP(ctx, lu_factor_any<double>(n, pivot_scope, static_cast<double*>(A), lda, ipiv, perm,
-                                       singular_flag, done, ctl, ctx->stream));
+                                       singular_flag, done, ctl, ctx->stream, nullptr,
+                                       ctl + words));
   }
   return NRS_OK;
 }

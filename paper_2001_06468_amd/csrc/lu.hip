@@ -103,6 +103,201 @@ __global__ __launch_bounds__(kPanelThreads) void k_getf2(int64_t n, int64_t k, i
   }
 }
 
+// Panel factorisation with partial pivoting spread over G workgroups (a
+// cooperative launch, so all of them are resident): workgroup g holds rows
+// k + g R .. k + (g+1) R - 1 of the jb-column panel in LDS.  Per column one
+// grid-wide barrier: before it, every workgroup publishes its largest
+// remaining entry (value, row, and that row's jb entries) and the owner of
+// the column's diagonal row publishes that row; after it, every workgroup
+// reduces the G candidates to the same pivot (largest magnitude, lowest row
+// on ties, as LAPACK), swaps in LDS where it owns one of the two rows, and
+// applies the rank-1 update to its rows.  Candidates are double-buffered by
+// column parity, so one barrier per column suffices.
+constexpr int kCoopThreads = 256;
+constexpr int kSlot = 72;          // doubles per candidate: value, row, 64 entries, pad
+constexpr int kCoopMaxG = 256;
+constexpr int64_t kCoopSpin = 1 << 24;
+
+template <class T>
+inline int64_t coop_rows(int64_t m) {
+  // all rows in one workgroup when they fit in 120 KiB of LDS (no grid-wide
+  // barrier at all), else at least 64 rows and at most kCoopMaxG workgroups
+  if (m * kNb * (int64_t)sizeof(T) <= 120 * 1024) return m;
+  return std::max<int64_t>(64, (m + kCoopMaxG - 1) / kCoopMaxG);
+}
+
+template <class T>
+__global__ __launch_bounds__(kCoopThreads) void k_getf2_coop(int64_t n, int64_t k, int jb,
+                                                             int64_t R, T* __restrict__ A,
+                                                             int64_t lda,
+                                                             int32_t* __restrict__ ipiv,
+                                                             int32_t* __restrict__ sing,
+                                                             double* __restrict__ slots,
+                                                             int32_t* __restrict__ bar) {
+  extern __shared__ __align__(16) unsigned char coop_lds[];
+  T* P = reinterpret_cast<T*>(coop_lds);            // [jb][R] column-major panel rows
+  __shared__ T s_prow[kNb];                         // pivot row
+  __shared__ T s_top[kNb];                          // the diagonal row before the swap
+  __shared__ double s_v[kCoopThreads / 64];
+  __shared__ int64_t s_i[kCoopThreads / 64];
+  __shared__ int64_t s_p;
+  __shared__ int s_w;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int G = gridDim.x, g = blockIdx.x;
+  const int64_t r0 = k + (int64_t)g * R;
+  const int nr = (int)std::max<int64_t>(0, std::min<int64_t>(n, r0 + R) - r0);
+  for (int c = wid; c < jb; c += kCoopThreads / 64)
+    for (int r = lane; r < nr; r += 64) P[c * R + r] = A[(r0 + r) + (k + c) * lda];
+  __syncthreads();
+  for (int j = 0; j < jb; ++j) {
+    const int64_t gj = k + j;                       // diagonal row of this column
+    double* slot = slots + (size_t)((j & 1) * kCoopMaxG + g) * kSlot;
+    double* top = slots + (size_t)(2 * kCoopMaxG + (j & 1)) * kSlot;
+    // local candidate: largest |a| over this workgroup's rows >= gj
+    double best = -1.0;
+    int64_t bi = n;
+    for (int r = tid; r < nr; r += kCoopThreads) {
+      if (r0 + r < gj) continue;
+      const double v = fabs((double)P[j * R + r]);
+      if (v > best || (v == best && r0 + r < bi)) {
+        best = v;
+        bi = r0 + r;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(best, off);
+      const int64_t oi = __shfl_xor(bi, off);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      s_v[wid] = best;
+      s_i[wid] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int w = 1; w < kCoopThreads / 64; ++w)
+        if (s_v[w] > best || (s_v[w] == best && s_i[w] < bi)) {
+          best = s_v[w];
+          bi = s_i[w];
+        }
+      slot[0] = best;
+      slot[1] = (double)bi;
+      s_p = bi;
+    }
+    __syncthreads();
+    if (G == 1) {
+      // one workgroup holds every row: the pivot is the local one
+      const int64_t p = s_p;
+      if (tid < jb) {
+        s_prow[tid] = P[tid * R + (p - r0)];
+        s_top[tid] = P[tid * R + (gj - r0)];
+      }
+      if (tid == 0) ipiv[gj] = (int32_t)p;
+      __syncthreads();
+      if (p != gj && tid < jb) {
+        P[tid * R + (p - r0)] = s_top[tid];
+        P[tid * R + (gj - r0)] = s_prow[tid];
+      }
+    } else {
+      const int64_t mine = s_p;
+      if (tid < jb) {
+        slot[2 + tid] = (mine >= r0 && mine < r0 + nr) ? (double)P[tid * R + (mine - r0)] : 0.0;
+        if (gj >= r0 && gj < r0 + nr) top[2 + tid] = (double)P[tid * R + (gj - r0)];
+      }
+      // grid-wide barrier (bounded wait; a timeout raises bit 1 of the
+      // singular flag and the launch still completes)
+      __builtin_amdgcn_s_waitcnt(0);
+      __syncthreads();
+      if (tid == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const int32_t target = (j + 1) * G;
+        atomicAdd(bar, 1);
+        int64_t spins = 0;
+        while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+          __builtin_amdgcn_s_sleep(1);
+          if (++spins > kCoopSpin) {
+            atomicOr(sing, 2);
+            break;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __builtin_amdgcn_s_waitcnt(0);
+      }
+      __syncthreads();
+      // the pivot: the candidates reduced in the same order by every
+      // workgroup; the diagonal row is fetched in the same round
+      const double* cand = slots + (size_t)((j & 1) * kCoopMaxG) * kSlot;
+      if (tid >= kCoopThreads - 64 && tid - (kCoopThreads - 64) < jb)
+        s_top[tid - (kCoopThreads - 64)] = (T)__hip_atomic_load(
+            &top[2 + tid - (kCoopThreads - 64)], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      best = -1.0;
+      bi = n;
+      for (int q = tid; q < G; q += kCoopThreads) {
+        const double v = __hip_atomic_load(&cand[(size_t)q * kSlot], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+        const int64_t i = (int64_t)__hip_atomic_load(&cand[(size_t)q * kSlot + 1],
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v > best || (v == best && i < bi)) {
+          best = v;
+          bi = i;
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(best, off);
+        const int64_t oi = __shfl_xor(bi, off);
+        if (ov > best || (ov == best && oi < bi)) {
+          best = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        s_v[wid] = best;
+        s_i[wid] = bi;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int wbest = 0;
+        for (int w = 1; w < kCoopThreads / 64; ++w)
+          if (s_v[w] > s_v[wbest] || (s_v[w] == s_v[wbest] && s_i[w] < s_i[wbest])) wbest = w;
+        s_p = s_i[wbest];
+      }
+      __syncthreads();
+      const int64_t p = s_p;
+      const int pw = (int)((p - k) / R);   // the workgroup whose rows hold row p
+      if (tid < jb)
+        s_prow[tid] = (T)__hip_atomic_load(&cand[(size_t)pw * kSlot + 2 + tid], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+      if (g == 0 && tid == 0) ipiv[gj] = (int32_t)p;
+      __syncthreads();
+      if (p != gj && tid < jb) {
+        if (p >= r0 && p < r0 + nr) P[tid * R + (p - r0)] = s_top[tid];
+        if (gj >= r0 && gj < r0 + nr) P[tid * R + (gj - r0)] = s_prow[tid];
+      }
+    }
+    __syncthreads();
+    const T piv = s_prow[j];
+    if (piv == T(0)) {
+      if (g == 0 && tid == 0) atomicOr(sing, 1);
+      continue;
+    }
+    // rank-1 update of this workgroup's rows below the diagonal row: the
+    // multipliers first, then (row, column) pairs over all threads
+    const int rlo = (int)std::max<int64_t>(0, gj + 1 - r0);
+    for (int r = rlo + tid; r < nr; r += kCoopThreads) P[j * R + r] /= piv;
+    __syncthreads();
+    for (int c = j + 1 + wid; c < jb; c += kCoopThreads / 64) {
+      const T u = s_prow[c];
+      for (int r = (int)rlo + lane; r < nr; r += 64) P[c * R + r] -= P[j * R + r] * u;
+    }
+    __syncthreads();
+  }
+  for (int c = wid; c < jb; c += kCoopThreads / 64)
+    for (int r = lane; r < nr; r += 64) A[(r0 + r) + (k + c) * lda] = P[c * R + r];
+}
+
 // Columns handled: [0, k) (interchanges only), [k+jb, n) (interchanges and
 // the unit-lower solve for U12), and the permutation column (interchanges
 // only): one wavefront per column.
@@ -794,16 +989,59 @@ inline dim3 grid1(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)); 
 
 }  // namespace
 
-// Blocked LU with partial pivoting over whole columns (GEPP).
+size_t gepp_scratch_bytes(int64_t n) {
+  return (size_t)(2 * kCoopMaxG + 2) * kSlot * sizeof(double) +
+         (size_t)((n + kNb - 1) / kNb + 64) * sizeof(int32_t) + 256;
+}
+
+namespace {
+
+// Panel of columns k .. k+jb-1 over rows k .. n-1: spread over workgroups
+// (cooperative launch) when its rows fit their LDS, else one workgroup.
+template <class T>
+hipError_t launch_panel(int64_t n, int64_t k, int jb, T* A, int64_t lda, int32_t* ipiv,
+                        int32_t* sing, void* scratch, hipStream_t s) {
+  int64_t m = n - k;
+  int64_t R = coop_rows<T>(m);
+  const size_t lds = (size_t)R * kNb * sizeof(T);
+  if (scratch && lds <= 128 * 1024) {
+    double* slots = static_cast<double*>(scratch);
+    int32_t* bar =
+        reinterpret_cast<int32_t*>(slots + (size_t)(2 * kCoopMaxG + 2) * kSlot) + k / kNb;
+    const unsigned G = (unsigned)((m + R - 1) / R);
+    if (G == 1) {  // one workgroup: no co-residency to guarantee
+      hipLaunchKernelGGL(k_getf2_coop<T>, dim3(1), dim3(kCoopThreads), (unsigned)lds, s, n, k, jb,
+                         R, A, lda, ipiv, sing, slots, bar);
+      return hipGetLastError();
+    }
+    void* args[] = {&n, &k, &jb, &R, &A, &lda, &ipiv, &sing, &slots, &bar};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_getf2_coop<T>), dim3(G),
+                                      dim3(kCoopThreads), args, (unsigned)lds, s);
+  }
+  hipLaunchKernelGGL(k_getf2<T>, dim3(1), dim3(kPanelThreads), 0, s, n, k, jb, 0, A, lda, ipiv,
+                     sing);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Blocked LU with partial pivoting over whole columns (GEPP).  scratch: NULL
+// or gepp_scratch_bytes(n) bytes (candidate rows and barrier counters of the
+// multi-workgroup panel; cleared here).
 template <class T>
 hipError_t launch_lu_factor(int64_t n, T* A, int64_t lda, int32_t* ipiv, int32_t* perm,
-                            int32_t* sing, hipStream_t s) {
+                            int32_t* sing, hipStream_t s, void* scratch) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_iota, grid1(n, 256), dim3(256), 0, s, perm, n);
+  if (scratch) {
+    const int64_t words = (int64_t)(gepp_scratch_bytes(n) / sizeof(int32_t));
+    hipError_t e = launch_fill_i32(static_cast<int32_t*>(scratch), 0, words - 64, s);
+    if (e != hipSuccess) return e;
+  }
   for (int64_t k = 0; k < n; k += kNb) {
     const int jb = (int)std::min<int64_t>(kNb, n - k);
-    hipLaunchKernelGGL(k_getf2<T>, dim3(1), dim3(kPanelThreads), 0, s, n, k, jb, 0, A, lda, ipiv,
-                       sing);
+    hipError_t e = launch_panel<T>(n, k, jb, A, lda, ipiv, sing, scratch, s);
+    if (e != hipSuccess) return e;
     const int64_t ncols = (n - jb) + 1;
     hipLaunchKernelGGL(k_laswp_trsm<T>, dim3((unsigned)((ncols + 3) / 4)), dim3(256), 0, s, n, k,
                        jb, A, lda, ipiv, perm);
@@ -872,9 +1110,9 @@ hipError_t launch_ipiv_to_perm(int64_t n, const int32_t* ipiv, int32_t* perm, hi
 }
 
 template hipError_t launch_lu_factor<float>(int64_t, float*, int64_t, int32_t*, int32_t*,
-                                            int32_t*, hipStream_t);
+                                            int32_t*, hipStream_t, void*);
 template hipError_t launch_lu_factor<double>(int64_t, double*, int64_t, int32_t*, int32_t*,
-                                             int32_t*, hipStream_t);
+                                             int32_t*, hipStream_t, void*);
 template hipError_t launch_trsv_batch<float>(const TrsvBatch<float>&, int32_t, int32_t*,
                                              int32_t*, hipStream_t);
 template hipError_t launch_trsv_batch<double>(const TrsvBatch<double>&, int32_t, int32_t*,

@@ -789,8 +789,8 @@ hipError_t launch_lu_tiles(const LuBatch<T>& bt, int32_t* ctl, hipStream_t s) {
 template <class T>
 hipError_t lu_factor_any(int64_t n, int32_t scope, T* A, int64_t lda, int32_t* ipiv,
                          int32_t* perm, int32_t* sing, int32_t* done, int32_t* ctl,
-                         hipStream_t s, uint16_t* sh) {
-  if (scope == 0) return launch_lu_factor<T>(n, A, lda, ipiv, perm, sing, s);
+                         hipStream_t s, uint16_t* sh, void* gepp) {
+  if (scope == 0) return launch_lu_factor<T>(n, A, lda, ipiv, perm, sing, s, gepp);
   LuBatch<T> bt;
   const int64_t nt = lu_tiles_nt(n);
   bt.one.A = A;
@@ -811,9 +811,11 @@ hipError_t lu_factor_any(int64_t n, int32_t scope, T* A, int64_t lda, int32_t* i
 }
 
 template hipError_t lu_factor_any<float>(int64_t, int32_t, float*, int64_t, int32_t*, int32_t*,
-                                         int32_t*, int32_t*, int32_t*, hipStream_t, uint16_t*);
+                                         int32_t*, int32_t*, int32_t*, hipStream_t, uint16_t*,
+                                         void*);
 template hipError_t lu_factor_any<double>(int64_t, int32_t, double*, int64_t, int32_t*, int32_t*,
-                                          int32_t*, int32_t*, int32_t*, hipStream_t, uint16_t*);
+                                          int32_t*, int32_t*, int32_t*, hipStream_t, uint16_t*,
+                                          void*);
 template hipError_t launch_lu_tiles<float>(const LuBatch<float>&, int32_t*, hipStream_t);
 template hipError_t launch_lu_tiles<double>(const LuBatch<double>&, int32_t*, hipStream_t);
 

@@ -178,6 +178,7 @@ struct SolveBuffers {
   double* fzv;       // [n] z_k, the operator's input
   double* fax;       // [n] A x for the true residual
   uint16_t* sh;      // BF16 tile copies of the tile LU (NRS_BF16_GMRES_IR)
+  void* gepp;        // scratch of the partial-pivoting panel (gepp_scratch_bytes)
   float* eqr;        // [n] row scale factors of the equilibrated FP32 matrix
   float* eqc;        // [n] column scale factors
   uint32_t* eqmax;   // [n] row maxima (scratch of the equilibration)
@@ -360,13 +361,16 @@ hipError_t launch_apply(const nrs_problem& pb, const Sorted& srt, const double* 
                         double* part, int32_t chunks, const int32_t* stop, hipStream_t s);
 template <class T>
 hipError_t launch_lu_factor(int64_t n, T* A, int64_t lda, int32_t* ipiv, int32_t* perm,
-                            int32_t* sing, hipStream_t s);
+                            int32_t* sing, hipStream_t s, void* scratch = nullptr);
+// bytes of the GEPP panel scratch (candidate rows, barrier counters) for order n
+size_t gepp_scratch_bytes(int64_t n);
 // Factor with scope 0 (GEPP, lu.hip) or 1 (tile LU with static block
 // pivoting, lu_tiles.hip; done [nt*nt] and ctl [4] zero before the call).
+// gepp: NULL or gepp_scratch_bytes(n) bytes for scope 0 (multi-workgroup panel).
 template <class T>
 hipError_t lu_factor_any(int64_t n, int32_t scope, T* A, int64_t lda, int32_t* ipiv,
                          int32_t* perm, int32_t* sing, int32_t* done, int32_t* ctl,
-                         hipStream_t s, uint16_t* sh = nullptr);
+                         hipStream_t s, uint16_t* sh = nullptr, void* gepp = nullptr);
 // elements of the BF16 tile copies of an order-n tile LU
 inline int64_t lu_shadow_elems(int64_t n) {
   const int64_t nt = (n + 63) / 64;
