@@ -66,6 +66,22 @@ typedef int32_t nrs_status;
                                  updates take BF16 copies of the finished tiles on
                                  the matrix cores (FP32 accumulation, FP32 pivots and
                                  tile solves); the workspace also holds those copies */
+#define NRS_GMRES_BLOCK    6  /* flexible GMRES(m) in FP64 on the matrix-free operator,
+                                 from x_init, with a block-diagonal right
+                                 preconditioner: one dense block per free body
+                                 (its force and (U, Omega) unknowns; rows of
+                                 fixed points unpreconditioned), the exact
+                                 inverse of the body's diagonal block
+                                 (NRS_PRECOND_EXACT) or a learned prediction of
+                                 it (NRS_PRECOND_MODEL, nrs_block_model_fit)    */
+
+/* Body blocks of NRS_GMRES_BLOCK (nrs_options.precond). */
+#define NRS_PRECOND_EXACT  0  /* FP64 assembly, then the inverse of every body's
+                                 diagonal block (Gauss-Jordan in LDS)          */
+#define NRS_PRECOND_MODEL  1  /* no assembly: each body's block inverse is
+                                 R_b K(psi_b) R_b^T from the Fourier model K of
+                                 nrs_block_model_fit at the body's beat phase  */
+#define NRS_BLOCK_MAX_HARMONICS 16
 
 typedef struct nrs_ctx nrs_ctx;
 
@@ -192,6 +208,25 @@ typedef struct {
      D_r r.  Zero (default): factor A itself.  (NRS_FP32_GEPP_IR, whose
      partial pivoting needs no scaling, and nrs_solve_batched never scale.) */
   int32_t equilibrate;
+  /* NRS_GMRES_BLOCK: which body blocks precondition the GMRES (NRS_PRECOND_
+     EXACT or NRS_PRECOND_MODEL).  With NRS_PRECOND_MODEL: precond_model is
+     the device model [2H+1][nb][nb] of nrs_block_model_fit (H =
+     precond_harmonics, nb = precond_nb = 3 N_b + 6 for bodies of N_b force
+     points), precond_phase the device beat phases psi_b = omega t - phi [M]
+     of the bodies (nrs_solve only; the time stepping entry points take each
+     body's phase from its first wave point of the scene at the stage time).
+     Every free body's points must form one contiguous run, bodies in order;
+     a body whose block order exceeds nrs_block_limit() or differs from
+     precond_nb is left unpreconditioned (nrs_solve with info then returns
+     NRS_E_UNSUPPORTED after writing the solution).  x_init and tol,
+     gmres_restart, gmres_max_iter as for the GMRES-IR forms (defaults
+     1e-12, 60, 300); warm_start (NRS_WARM_PREVIOUS, NRS_WARM_MODEL) applies
+     inside the time stepping entry points as for NRS_GMRES. */
+  int32_t precond;
+  int32_t precond_harmonics;
+  int32_t precond_nb;
+  const double* precond_model;
+  const double* precond_phase;
 } nrs_options;
 
 typedef struct {
@@ -388,6 +423,53 @@ nrs_status nrs_autotune(nrs_ctx* ctx, const nrs_problem* pb, void* ws, size_t ws
                         nrs_tune_result* out);
 /* Forget every tuned shape of the context (defaults again). */
 nrs_status nrs_autotune_clear(nrs_ctx* ctx);
+
+/* ------------------------------------------------------------------------ */
+/* Learned block preconditioner for GMRES (not part of the paper's method:  */
+/* a preconditioner for the same linear system; the GMRES residual decides).*/
+/* ------------------------------------------------------------------------ */
+/* A free body's diagonal block of the swimming problem (Sec. 2 and Sec. 4:
+ * its rows of the NEAREST operator, Sec. 3 eq. 23, restricted to its own
+ * force points, with its rigid-body columns and force and moment rows) is,
+ * in the body's own frame, the same for every identical swimmer at the same
+ * beat phase psi = omega t - phi: the regularized stokeslet, the nearest map
+ * within the body's group and the patch weights do not change when the body
+ * is rotated and translated.  The model stores the inverse of that block as
+ * a Fourier series in psi, K(psi) = C_0 + sum_{h<=H} (C_ch cos h psi +
+ * C_sh sin h psi); NRS_GMRES_BLOCK with NRS_PRECOND_MODEL applies R_b
+ * K(psi_b) R_b^T to body b's unknowns (R_b = its frame B on every 3-vector).
+ * Blocks here are column-major nb x nb, unknowns ordered as in the system
+ * of a single body at the origin with B = I: (f_x of its points, f_y, f_z,
+ * U, Omega), nb = 3 N_b + 6. */
+
+/* *nb_max = largest block order this device can invert (the LDS of one
+ * workgroup holds the block in FP64); larger bodies are not preconditioned. */
+nrs_status nrs_block_limit(nrs_ctx* ctx, int32_t* nb_max);
+
+/* In-place inverses of `count` blocks of order nb (1 <= nb <= nb_max):
+ * blocks [count][nb][nb] column-major, each replaced by its inverse (Gauss-
+ * Jordan elimination with partial pivoting, FP64).  singular: device int32,
+ * |= 1 if a block had a zero or non-finite pivot (that block's output is
+ * then not an inverse).  Asynchronous.  Errors: NRS_E_ARG, NRS_E_UNSUPPORTED
+ * (nb > nb_max). */
+nrs_status nrs_block_invert(nrs_ctx* ctx, int32_t count, int32_t nb, double* blocks,
+                            int32_t* singular);
+
+/* Fit of the model to the inverses K_s at the S phases psi_s = 2 pi s / S
+ * (s = 0..S-1; inverses [S][nb][nb], e.g. nrs_assemble of a one-body problem
+ * in its own frame at each phase followed by nrs_block_invert):
+ *   C_0 = (1/S) sum_s K_s,  C_ch = (2/S) sum_s cos(h psi_s) K_s,
+ *   C_sh = (2/S) sum_s sin(h psi_s) K_s,   h = 1..H,
+ * the least-squares trigonometric fit of degree H since S >= 2H + 1.
+ * model: device [2H+1][nb][nb] (C_0, C_c1, C_s1, C_c2, ...).  Asynchronous.
+ * Errors: NRS_E_ARG (S < 2H + 1, H outside 0..NRS_BLOCK_MAX_HARMONICS, NULL). */
+nrs_status nrs_block_model_fit(nrs_ctx* ctx, int32_t S, int32_t nb, int32_t H,
+                               const double* inverses, double* model);
+
+/* The model's K(psi_i) for `count` phases psi [count] (device): blocks
+ * [count][nb][nb] column-major.  Asynchronous.  Errors: NRS_E_ARG. */
+nrs_status nrs_block_model_eval(nrs_ctx* ctx, int32_t nb, int32_t H, const double* model,
+                                int32_t count, const double* psi, double* blocks);
 
 /* ------------------------------------------------------------------------ */
 /* Learned warm start for GMRES (not part of the paper's method: an initial */

@@ -31,3 +31,4 @@ from .dopri import (  # noqa: F401
     dopri_attempt, dopri_integrate, dopri_swimmers, error_norm,
 )
 
+from . import precond  # noqa: F401

@@ -18,7 +18,8 @@ import torch
 from . import _lib
 from ._lib import (NRS_BF16_GMRES_IR, NRS_FP32_GEPP_IR, NRS_FP32_GMRES_IR, NRS_FP32_IR,  # noqa: F401
                    NRS_FP64_LU,
-                   NRS_GMRES,
+                   NRS_GMRES, NRS_GMRES_BLOCK, NRS_PRECOND_EXACT, NRS_PRECOND_MODEL,
+                   NRS_BLOCK_MAX_HARMONICS,
                    NRS_MLP_HIDDEN, NRS_MLP_MAX_POINTS, NRS_NOALLOC_MAX_N, NRS_WARM_MODEL, NRS_WARM_NONE,
                    NRS_WARM_PREVIOUS, NrsInfo, NrsOptions, NrsProblem, NrsScene)
 
@@ -37,6 +38,9 @@ __all__ = [
     "nrs_field_workspace_size", "nrs_field_velocity", "nrs_tracer_rk4_step",
     "nrs_rk4_tracers_workspace_size", "nrs_rk4_step_tracers",
     "nrs_dopri5_workspace_size", "nrs_dopri5_integrate",
+    "NRS_GMRES_BLOCK", "NRS_PRECOND_EXACT", "NRS_PRECOND_MODEL", "NRS_BLOCK_MAX_HARMONICS",
+    "BlockModel", "nrs_block_limit", "nrs_block_invert", "nrs_block_model_fit",
+    "nrs_block_model_eval",
 ]
 
 
@@ -172,15 +176,31 @@ class Model:
         self.scales = tuple(float(v) for v in scales)
 
 
+class BlockModel:
+    """Learned body-block inverse of NRS_GMRES_BLOCK: device FP64 model
+    [2H+1][nb][nb] (each block column-major, i.e. the torch view of a block
+    is its transpose) from nrs_block_model_fit, harmonics H, order nb."""
+
+    def __init__(self, coef, nb, H):
+        if coef.dtype != torch.float64 or tuple(coef.shape) != (2 * H + 1, nb, nb):
+            raise ValueError("coef must be float64 of shape (2H+1, nb, nb)")
+        self.coef, self.nb, self.H = coef, int(nb), int(H)
+
+
 def _options(method=NRS_FP64_LU, max_refine=0, tol=0.0, gmres_restart=0, gmres_max_iter=0,
              no_fallback=0, x_init=None, warm_start=NRS_WARM_NONE, model=None, body_off=None,
-             x_init_complete=0, graph=0, reuse_stage_factors=0, equilibrate=0):
+             x_init_complete=0, graph=0, reuse_stage_factors=0, equilibrate=0,
+             precond=NRS_PRECOND_EXACT, block_model=None, precond_phase=None):
     sc = (C.c_double * 3)(*(model.scales if model is not None else (0.0, 0.0, 0.0)))
+    bm = block_model
     return NrsOptions(method, max_refine, tol, gmres_restart, gmres_max_iter, no_fallback,
                       _ptr(x_init, torch.float64, "x_init"), warm_start,
                       _ptr(model.theta, torch.float32, "theta") if model is not None else None,
                       sc, _ptr(body_off, torch.int32, "body_off"), int(x_init_complete),
-                      int(graph), int(reuse_stage_factors), int(equilibrate))
+                      int(graph), int(reuse_stage_factors), int(equilibrate), int(precond),
+                      bm.H if bm is not None else 0, bm.nb if bm is not None else 0,
+                      _ptr(bm.coef, torch.float64, "block model") if bm is not None else None,
+                      _ptr(precond_phase, torch.float64, "precond_phase"))
 
 
 def nrs_geometry(ctx, scene, t, Y, x=None, X=None, w=None, u=None):
@@ -539,6 +559,35 @@ def nrs_autotune(ctx, problem, ws):
     _check(_lib.load().nrs_autotune(ctx.handle, C.byref(pb), _ptr(ws, torch.uint8, "ws"),
                                     ws.numel(), C.byref(out)), ctx)
     return out.as_dict()
+
+
+def nrs_block_limit(ctx):
+    v = C.c_int32()
+    _check(_lib.load().nrs_block_limit(ctx.handle, C.byref(v)), ctx)
+    return v.value
+
+
+def nrs_block_invert(ctx, blocks, singular):
+    """blocks: float64 [count, nb, nb] (column-major blocks: blocks[i] is the
+    transpose of block i), inverted in place; singular: int32 [1]."""
+    count, nb = int(blocks.shape[0]), int(blocks.shape[-1])
+    _check(_lib.load().nrs_block_invert(ctx.handle, count, nb, _ptr(blocks, torch.float64, "blocks"),
+                                        _ptr(singular, torch.int32, "singular")), ctx)
+
+
+def nrs_block_model_fit(ctx, inverses, H, model):
+    """inverses: float64 [S, nb, nb]; model: float64 [2H+1, nb, nb] output."""
+    S, nb = int(inverses.shape[0]), int(inverses.shape[-1])
+    _check(_lib.load().nrs_block_model_fit(ctx.handle, S, nb, int(H),
+                                           _ptr(inverses, torch.float64, "inverses"),
+                                           _ptr(model, torch.float64, "model")), ctx)
+
+
+def nrs_block_model_eval(ctx, model, H, psi, blocks):
+    nb = int(model.shape[-1])
+    _check(_lib.load().nrs_block_model_eval(ctx.handle, nb, int(H), _ptr(model, torch.float64, "model"),
+                                            int(psi.numel()), _ptr(psi, torch.float64, "psi"),
+                                            _ptr(blocks, torch.float64, "blocks")), ctx)
 
 
 def nrs_autotune_clear(ctx):

@@ -22,6 +22,11 @@ NRS_FP32_GEPP_IR = 2
 NRS_GMRES = 3
 NRS_FP32_GMRES_IR = 4
 NRS_BF16_GMRES_IR = 5
+NRS_GMRES_BLOCK = 6
+
+NRS_PRECOND_EXACT = 0
+NRS_PRECOND_MODEL = 1
+NRS_BLOCK_MAX_HARMONICS = 16
 
 NRS_WARM_NONE = 0
 NRS_WARM_PREVIOUS = 1
@@ -53,7 +58,9 @@ class NrsOptions(C.Structure):
                 ("gmres_restart", _i32), ("gmres_max_iter", _i32), ("no_fallback", _i32),
                 ("x_init", _p), ("warm_start", _i32), ("model_theta", _p),
                 ("model_scales", C.c_double * 3), ("body_off", _p), ("x_init_complete", _i32),
-                ("graph", _i32), ("reuse_stage_factors", _i32), ("equilibrate", _i32)]
+                ("graph", _i32), ("reuse_stage_factors", _i32), ("equilibrate", _i32),
+                ("precond", _i32), ("precond_harmonics", _i32), ("precond_nb", _i32),
+                ("precond_model", _p), ("precond_phase", _p)]
 
 
 class NrsInfo(C.Structure):
@@ -111,6 +118,10 @@ PROTOTYPES = {
     "nrs_equilibrate": (_i32, [_p, _i64, _p, _i64, _p, _p, _p, C.c_size_t]),
     "nrs_autotune": (_i32, [_p, C.POINTER(NrsProblem), _p, C.c_size_t, C.POINTER(NrsTuneResult)]),
     "nrs_autotune_clear": (_i32, [_p]),
+    "nrs_block_limit": (_i32, [_p, C.POINTER(_i32)]),
+    "nrs_block_invert": (_i32, [_p, _i32, _i32, _p, _p]),
+    "nrs_block_model_fit": (_i32, [_p, _i32, _i32, _i32, _p, _p]),
+    "nrs_block_model_eval": (_i32, [_p, _i32, _i32, _p, _i32, _p, _p]),
     "nrs_mlp_param_count": (_i64, []),
     "nrs_mlp_body_offsets": (_i32, [_p, _i64, _p, _i32, _p]),
     "nrs_mlp_features": (_i32, [_p, _i64, _p, _p, _p, _p, _i32, _p, _p]),

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnrs.so")
-SOURCES = ["api.hip", "points.hip", "assemble.hip", "lu.hip", "lu_tiles.hip", "refine.hip", "batch.hip", "learn.hip", "learn_api.hip", "gmres.hip", "field.hip"]
+SOURCES = ["api.hip", "points.hip", "assemble.hip", "lu.hip", "lu_tiles.hip", "refine.hip", "batch.hip", "learn.hip", "learn_api.hip", "gmres.hip", "field.hip", "precond.hip"]
 
 # Packed-FP32 instructions are disabled for all device code: hipcc -O3 would
 # otherwise form v_pk_* FP32 operations from scalar float code.

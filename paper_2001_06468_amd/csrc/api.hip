@@ -42,6 +42,8 @@ bool uses_fp32(int32_t method) {
 bool gmres_ir(int32_t method) { return method == NRS_FP32_GMRES_IR || method == NRS_BF16_GMRES_IR; }
 // methods whose single-system solves can run the flexible GMRES on the FP32 factors
 bool uses_fgmres(int32_t method) { return method == NRS_FP32_IR || gmres_ir(method); }
+// methods that iterate from an initial guess (x_init, warm starts)
+bool krylov_warm(int32_t method) { return method == NRS_GMRES || method == NRS_GMRES_BLOCK; }
 constexpr double kFgmresTol = 1e-12;
 
 // Bytes of the caller workspace of nrs_lu_factor / nrs_lu_solve.
@@ -164,7 +166,14 @@ bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, Sol
   sb.gst = nullptr;
   sb.Z = sb.fzv = sb.fax = nullptr;
   sb.sh = (with64 && method == NRS_BF16_GMRES_IR) ? ar.take<uint16_t>(lu_shadow_elems(n)) : nullptr;
-  const bool fg = with64 && uses_fgmres(method);
+  const bool blk = method == NRS_GMRES_BLOCK;
+  sb.boff = blk ? ar.take<int32_t>((size_t)M + 1) : nullptr;
+  sb.bstarts = blk ? ar.take<int32_t>(1) : nullptr;
+  sb.bpsi = blk ? ar.take<double>((size_t)M + 1) : nullptr;
+  sb.blocks = blk ? ar.take<double>((size_t)M * kBlockStride) : nullptr;
+  sb.phase_scene = nullptr;
+  sb.phase_t = 0.0;
+  const bool fg = (with64 && uses_fgmres(method)) || blk;
   if (fg) {
     sb.Z = ar.take<double>((size_t)n * kGmresLd);
     sb.fzv = ar.take<double>(n);
@@ -376,6 +385,108 @@ nrs_status run_fgmres(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, dou
   return NRS_OK;
 }
 
+// Flexible GMRES(m) in FP64 on the matrix-free operator from x's initial
+// content (x_init, else zero), right-preconditioned by one dense block per
+// free body: the inverses of the bodies' diagonal blocks of the assembled
+// FP64 matrix (NRS_PRECOND_EXACT) or the learned model's blocks at the
+// bodies' phases (NRS_PRECOND_MODEL, psi: [M] device).  Host checks every
+// kChunk steps as in run_fgmres.
+nrs_status run_gmres_block(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, double* x,
+                           const nrs_options& o, const double* psi, bool norm, hipStream_t s) {
+  const int64_t N = pb.N, n = 3 * N + 6 * (int64_t)pb.M;
+  const int32_t M = pb.M;
+  const int32_t m = (o.gmres_restart > 0 && o.gmres_restart < kGmresLd) ? o.gmres_restart : 60;
+  const int32_t max_iter = o.gmres_max_iter > 0 ? o.gmres_max_iter : 300;
+  const double tol = o.tol > 0 ? o.tol : kFgmresTol;
+  const bool model = o.precond == NRS_PRECOND_MODEL;
+  const int32_t lim = ctx->block_lim;
+  if (o.x_init && o.x_init != x)
+    NRS_HIP(ctx, hipMemcpyAsync(x, o.x_init, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  else if (!o.x_init)
+    NRS_HIP(ctx, launch_fill_f64(x, 0.0, n, s));
+  if (M > 0) {
+    NRS_HIP(ctx, launch_body_off(N, M, pb.body, sb.boff, sb.bstarts, &sb.st->prec_err, s));
+    NRS_HIP(ctx, launch_block_check(M, N, sb.boff, lim, model ? o.precond_nb : 0,
+                                    &sb.st->prec_err, s));
+  }
+  if (model && sb.phase_scene && M > 0) {
+    NRS_HIP(ctx, launch_body_phase(M, N, sb.boff, sb.phase_scene->part, sb.phase_scene->wave,
+                                   sb.phase_scene->P, sb.phase_t, sb.bpsi, s));
+    psi = sb.bpsi;
+  }
+  if (model) {
+    NRS_HIP(ctx, launch_block_model(M, N, sb.boff, lim, o.precond_nb, o.precond_harmonics,
+                                    o.precond_model, psi, kBlockStride, sb.blocks, s));
+  } else {
+    NRS_HIP(ctx, launch_assemble<double>(pb, sb.srt, sb.A64, sb.lda, s,
+                                         asm_shape_for(ctx, pb.N, pb.Q, 64)));
+    if (norm) NRS_HIP(ctx, launch_anorm64(n, sb.A64, sb.lda, sb.st, sb.red, s));
+    NRS_HIP(ctx, launch_block_extract(M, N, sb.boff, lim, sb.A64, sb.lda, sb.blocks, s));
+    NRS_HIP(ctx, launch_block_inverse(M, 0, kBlockStride, N, sb.boff, lim, sb.blocks,
+                                      &sb.st->singular, s));
+  }
+  GmresArgs a;
+  a.n = n;
+  a.ld = kGmresLd;
+  a.AT = nullptr;
+  a.b = sb.b;
+  a.x = x;
+  a.V = sb.V;
+  a.Z = sb.Z;
+  a.w0 = sb.gw0;
+  a.w1 = sb.gw1;
+  a.part = sb.gpart;
+  a.st = sb.gst;
+  const int32_t* halt = &sb.gst->halt;
+  const double* Yrot = model ? pb.Y : nullptr;
+  NRS_HIP(ctx, launch_gmres_init(sb.gst, tol, m, max_iter, s));
+  NRS_HIP(ctx, launch_apply(pb, sb.srt, x, sb.fax, sb.part, sb.chunks, nullptr, s));
+  NRS_HIP(ctx, launch_fgmres_residual(a, sb.fax, s));
+  struct Hdr {
+    int32_t done, stop, fail, k, iters;
+  } h;
+  constexpr int kChunk = 4;
+  for (;;) {
+    for (int i = 0; i < kChunk; ++i) {
+      NRS_HIP(ctx, launch_prec_block(a, M, N, sb.boff, lim, model ? o.precond_nb : 0, Yrot,
+                                     sb.blocks, sb.fzv, s));
+      NRS_HIP(ctx, launch_apply(pb, sb.srt, sb.fzv, sb.d64, sb.part, sb.chunks, halt, s));
+      NRS_HIP(ctx, launch_fgmres_orth(a, sb.d64, s));
+    }
+    NRS_HIP(ctx, hipMemcpyAsync(&h, sb.gst, sizeof(h), hipMemcpyDeviceToHost, s));
+    NRS_HIP(ctx, hipStreamSynchronize(s));
+    if (h.fail || h.done) break;
+    if (!h.stop) continue;
+    NRS_HIP(ctx, launch_gmres_update(a, s));
+    NRS_HIP(ctx, launch_apply(pb, sb.srt, x, sb.fax, sb.part, sb.chunks, nullptr, s));
+    NRS_HIP(ctx, launch_fgmres_residual(a, sb.fax, s));
+    NRS_HIP(ctx, hipMemcpyAsync(&h, sb.gst, sizeof(h), hipMemcpyDeviceToHost, s));
+    NRS_HIP(ctx, hipStreamSynchronize(s));
+    if (h.fail || h.done || h.iters >= max_iter) break;
+  }
+  NRS_HIP(ctx, launch_fgmres_report(sb.st, sb.gst, s));
+  return NRS_OK;
+}
+
+// Options of NRS_GMRES_BLOCK; need_phase: the caller supplies precond_phase.
+nrs_status check_block_options(nrs_ctx* ctx, const nrs_options& o, int32_t M, bool need_phase) {
+  if (o.method != NRS_GMRES_BLOCK) return NRS_OK;
+  if (o.precond != NRS_PRECOND_EXACT && o.precond != NRS_PRECOND_MODEL)
+    return fail(ctx, NRS_E_ARG, "precond must be NRS_PRECOND_EXACT or NRS_PRECOND_MODEL");
+  if (o.precond == NRS_PRECOND_MODEL) {
+    if (!o.precond_model) return fail(ctx, NRS_E_ARG, "precond_model required");
+    if (o.precond_harmonics < 0 || o.precond_harmonics > kBlockHarmonicsMax)
+      return fail(ctx, NRS_E_ARG, "precond_harmonics outside 0..NRS_BLOCK_MAX_HARMONICS");
+    if (o.precond_nb < 9 || (o.precond_nb - 6) % 3 != 0)
+      return fail(ctx, NRS_E_ARG, "precond_nb must be 3 N_b + 6 with N_b >= 1");
+    if (o.precond_nb > ctx->block_lim)
+      return fail(ctx, NRS_E_UNSUPPORTED, "precond_nb exceeds nrs_block_limit()");
+    if (need_phase && M > 0 && !o.precond_phase)
+      return fail(ctx, NRS_E_ARG, "precond_phase required");
+  }
+  return NRS_OK;
+}
+
 nrs_status read_state(nrs_ctx* ctx, const SolveState* dst, SolveState& hst) {
   NRS_HIP(ctx, hipMemcpyAsync(&hst, dst, sizeof(SolveState), hipMemcpyDeviceToHost, ctx->stream));
   NRS_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -423,6 +534,8 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
     if (st == NRS_OK && fgm) st = run_fgmres(ctx, pb, sb, sol, o, s);
   } else if (method == NRS_GMRES) {
     st = run_gmres(ctx, pb, sb, sol, o, sync, s);
+  } else if (method == NRS_GMRES_BLOCK) {
+    st = run_gmres_block(ctx, pb, sb, sol, o, o.precond_phase, sync, s);
   } else {
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
   }
@@ -432,6 +545,7 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
   if ((st = read_state(ctx, sb.st, h)) != NRS_OK) return st;
   if (h.nonfinite == 2)
     return fail(ctx, NRS_E_ARG, "nu outside [0, N) or body outside [-1, M)");
+  const int32_t prec_err = method == NRS_GMRES_BLOCK ? h.prec_err : 0;
   bool ok = method == NRS_FP64_LU ? true : (h.converged && !h.failed);
   if (!ok && method == NRS_FP32_IR && sb.Z && !h.nonfinite && !h.sync_err && !h.lu_ctl[2]) {
     // the refinement stalled: GMRES-IR from its iterate on the same factors
@@ -460,6 +574,13 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
   if (h.singular && h.method_used == NRS_FP64_LU)
     return fail(ctx, NRS_E_SINGULAR, "zero pivot in the FP64 factorisation");
   if (!ok) return fail(ctx, NRS_E_NOT_CONVERGED, "refinement did not converge");
+  if (prec_err)
+    return fail(ctx, NRS_E_UNSUPPORTED,
+                std::string("block preconditioner: ") +
+                    ((prec_err & 2) ? "body points are not one contiguous run per body; " : "") +
+                    ((prec_err & 4) ? "a body block exceeds nrs_block_limit(); " : "") +
+                    ((prec_err & 8) ? "a body block differs from precond_nb; " : "") +
+                    "those bodies were left unpreconditioned");
   return NRS_OK;
 }
 
@@ -494,6 +615,17 @@ nrs_status nrs_create(nrs_ctx** out, int device, void* stream) {
     delete c;
     return NRS_E_HIP;
   }
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) {
+    delete c;
+    return NRS_E_HIP;
+  }
+  int optin = 0;   // the larger opt-in figure where the runtime reports one
+  if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, device) == hipSuccess &&
+      optin > lds)
+    lds = optin;
+  (void)hipGetLastError();
+  c->block_lim = block_order_limit((size_t)lds);
   *out = c;
   return NRS_OK;
 }
@@ -572,7 +704,7 @@ nrs_status nrs_nearest(nrs_ctx* ctx, int64_t N, const double* x, int32_t G,
 nrs_status nrs_workspace_size(nrs_ctx* ctx, int64_t N, int64_t Q, int32_t M, int32_t method,
                               size_t* bytes) {
   if (!bytes || N <= 0 || Q <= 0 || M < 0) return fail(ctx, NRS_E_ARG, "bad sizes");
-  if (method < NRS_FP64_LU || method > NRS_BF16_GMRES_IR)
+  if (method < NRS_FP64_LU || method > NRS_GMRES_BLOCK)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
   *bytes = solve_workspace_bytes(N, Q, M, method);
   return NRS_OK;
@@ -631,10 +763,12 @@ nrs_status nrs_solve(nrs_ctx* ctx, const nrs_problem* pb, const double* u, const
   nrs_options o = {};
   o.method = NRS_FP64_LU;
   if (opt) o = *opt;
-  if (o.method < NRS_FP64_LU || o.method > NRS_BF16_GMRES_IR)
+  if (o.method < NRS_FP64_LU || o.method > NRS_GMRES_BLOCK)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
-  if ((o.method == NRS_GMRES || gmres_ir(o.method)) && o.gmres_restart >= kGmresLd)
+  if ((o.method == NRS_GMRES || gmres_ir(o.method) || o.method == NRS_GMRES_BLOCK) &&
+      o.gmres_restart >= kGmresLd)
     return fail(ctx, NRS_E_UNSUPPORTED, "GMRES restart length must be below 64");
+  if ((st = check_block_options(ctx, o, pb->M, true)) != NRS_OK) return st;
   Arena ar(ws, ws_bytes);
   SolveBuffers sb;
   if (!carve_solve(ar, pb->N, pb->Q, pb->M, o.method, sb))
@@ -903,6 +1037,46 @@ nrs_status nrs_autotune_clear(nrs_ctx* ctx) {
   return NRS_OK;
 }
 
+nrs_status nrs_block_limit(nrs_ctx* ctx, int32_t* nb_max) {
+  if (!ctx || !nb_max) return fail(ctx, NRS_E_ARG, "ctx and nb_max required");
+  *nb_max = ctx->block_lim;
+  return NRS_OK;
+}
+
+nrs_status nrs_block_invert(nrs_ctx* ctx, int32_t count, int32_t nb, double* blocks,
+                            int32_t* singular) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if (count < 0 || nb < 1 || !blocks || !singular)
+    return fail(ctx, NRS_E_ARG, "bad block inversion arguments");
+  if (nb > ctx->block_lim) return fail(ctx, NRS_E_UNSUPPORTED, "nb exceeds nrs_block_limit()");
+  NRS_HIP(ctx, launch_block_inverse(count, nb, (int64_t)nb * nb, 0, nullptr, nb, blocks, singular,
+                                    ctx->stream));
+  return NRS_OK;
+}
+
+nrs_status nrs_block_model_fit(nrs_ctx* ctx, int32_t S, int32_t nb, int32_t H,
+                               const double* inverses, double* model) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if (nb < 1 || H < 0 || H > kBlockHarmonicsMax || S < 2 * H + 1 || !inverses || !model)
+    return fail(ctx, NRS_E_ARG, "bad block model fit arguments");
+  NRS_HIP(ctx, launch_block_fit(S, nb, H, inverses, model, ctx->stream));
+  return NRS_OK;
+}
+
+nrs_status nrs_block_model_eval(nrs_ctx* ctx, int32_t nb, int32_t H, const double* model,
+                                int32_t count, const double* psi, double* blocks) {
+  nrs_status st = use_device(ctx);
+  if (st) return st;
+  if (nb < 1 || H < 0 || H > kBlockHarmonicsMax || count < 0 || !model ||
+      (count > 0 && (!psi || !blocks)))
+    return fail(ctx, NRS_E_ARG, "bad block model arguments");
+  NRS_HIP(ctx, launch_block_model(count, 0, nullptr, 0, nb, H, model, psi, (int64_t)nb * nb,
+                                  blocks, ctx->stream));
+  return NRS_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -937,7 +1111,7 @@ bool carve_rk(Arena& ar, const nrs_scene& sc, int32_t method, int64_t P, RkBuffe
   rb.Ysave = ar.take<double>(12 * M);
   rb.sol = ar.take<double>(n);
   rb.phi = rb.my = rb.mz = nullptr;
-  if (method == NRS_GMRES) {
+  if (krylov_warm(method)) {
     rb.phi = ar.take<float>(7 * N);
     rb.my = ar.take<float>(3 * N);
     rb.mz = ar.take<float>(6 * M);
@@ -979,7 +1153,10 @@ nrs_status stage_solve(nrs_ctx* ctx, const nrs_scene& sc, const GroupTable& gt,
   pb.eps = eps;
   pb.mu = mu;
   nrs_options os = o;
-  if (o.method == NRS_GMRES) {
+  // the learned block model takes each body's phase from the scene at tt
+  rb.sb.phase_scene = &sc;
+  rb.sb.phase_t = tt;
+  if (krylov_warm(o.method)) {
     // warm start of this stage's GMRES solve
     os.x_init = nullptr;
     if (o.warm_start == NRS_WARM_PREVIOUS && warm) {
@@ -991,7 +1168,7 @@ nrs_status stage_solve(nrs_ctx* ctx, const nrs_scene& sc, const GroupTable& gt,
       NRS_HIP(ctx, launch_to_lab(sc.N, sc.M, sc.body, rb.Ys, rb.my, rb.mz, o.model_scales,
                                  rb.sol, s));
       os.x_init = rb.sol;
-      os.x_init_complete = 1;
+      os.x_init_complete = o.method == NRS_GMRES;
     }
   }
   nrs_status st = solve_core(ctx, pb, rb.u, ftext, os, rb.sb, rb.sol, false, nullptr, reuse);
@@ -1075,7 +1252,7 @@ nrs_status nrs_rk4_tracers_workspace_size(nrs_ctx* ctx, const nrs_scene* sc, int
   if (st) return st;
   if (!bytes) return fail(ctx, NRS_E_ARG, "bytes is NULL");
   if (P < 0 || P > kMaxFieldPoints) return fail(ctx, NRS_E_ARG, "tracer count out of range");
-  if (method < NRS_FP64_LU || method > NRS_BF16_GMRES_IR)
+  if (method < NRS_FP64_LU || method > NRS_GMRES_BLOCK)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
   Arena ar(nullptr, 0);
   RkBuffers rb;
@@ -1113,10 +1290,12 @@ nrs_status nrs_rk4_step_tracers(nrs_ctx* ctx, const nrs_scene* sc, int32_t G,
   nrs_options o = {};
   o.method = NRS_FP64_LU;
   if (opt) o = *opt;
-  if (o.method < NRS_FP64_LU || o.method > NRS_BF16_GMRES_IR)
+  if (o.method < NRS_FP64_LU || o.method > NRS_GMRES_BLOCK)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
-  if ((o.method == NRS_GMRES || gmres_ir(o.method)) && o.gmres_restart >= kGmresLd)
+  if ((o.method == NRS_GMRES || gmres_ir(o.method) || o.method == NRS_GMRES_BLOCK) &&
+      o.gmres_restart >= kGmresLd)
     return fail(ctx, NRS_E_UNSUPPORTED, "GMRES restart length must be below 64");
+  if ((st = check_block_options(ctx, o, sc->M, false)) != NRS_OK) return st;
   Arena ar(ws, ws_bytes);
   RkBuffers rb;
   if (!carve_rk(ar, *sc, o.method, P, rb)) return fail(ctx, NRS_E_WORKSPACE, "workspace too small");
@@ -1124,7 +1303,7 @@ nrs_status nrs_rk4_step_tracers(nrs_ctx* ctx, const nrs_scene* sc, int32_t G,
   NRS_HIP(ctx, hipMemcpyAsync(rb.Ysave, Y, 12 * sizeof(double) * sc->M, hipMemcpyDeviceToDevice, s));
   if (P > 0)
     NRS_HIP(ctx, hipMemcpyAsync(rb.ysave, ytr, 3 * sizeof(double) * P, hipMemcpyDeviceToDevice, s));
-  if (o.method == NRS_GMRES && o.warm_start == NRS_WARM_MODEL) {
+  if (krylov_warm(o.method) && o.warm_start == NRS_WARM_MODEL) {
     if (!o.model_theta || !o.body_off || !sc->s)
       return fail(ctx, NRS_E_ARG, "model warm start needs model_theta, body_off and scene s");
     if (!(o.model_scales[0] > 0) || !(o.model_scales[1] > 0) || !(o.model_scales[2] > 0))
@@ -1172,7 +1351,7 @@ nrs_status nrs_dopri5_workspace_size(nrs_ctx* ctx, const nrs_scene* sc, int32_t 
   nrs_status st = check_scene(ctx, sc);
   if (st) return st;
   if (!bytes) return fail(ctx, NRS_E_ARG, "bytes is NULL");
-  if (method < NRS_FP64_LU || method > NRS_BF16_GMRES_IR)
+  if (method < NRS_FP64_LU || method > NRS_GMRES_BLOCK)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
   Arena ar(nullptr, 0);
   RkBuffers rb;
@@ -1206,11 +1385,13 @@ nrs_status nrs_dopri5_integrate(nrs_ctx* ctx, const nrs_scene* sc, int32_t G,
   nrs_options o = {};
   o.method = NRS_FP64_LU;
   if (opt) o = *opt;
-  if (o.method < NRS_FP64_LU || o.method > NRS_BF16_GMRES_IR)
+  if (o.method < NRS_FP64_LU || o.method > NRS_GMRES_BLOCK)
     return fail(ctx, NRS_E_UNSUPPORTED, "method not implemented");
-  if ((o.method == NRS_GMRES || gmres_ir(o.method)) && o.gmres_restart >= kGmresLd)
+  if ((o.method == NRS_GMRES || gmres_ir(o.method) || o.method == NRS_GMRES_BLOCK) &&
+      o.gmres_restart >= kGmresLd)
     return fail(ctx, NRS_E_UNSUPPORTED, "GMRES restart length must be below 64");
-  if (o.method == NRS_GMRES && o.warm_start == NRS_WARM_MODEL) {
+  if ((st = check_block_options(ctx, o, sc->M, false)) != NRS_OK) return st;
+  if (krylov_warm(o.method) && o.warm_start == NRS_WARM_MODEL) {
     if (!o.model_theta || !o.body_off || !sc->s)
       return fail(ctx, NRS_E_ARG, "model warm start needs model_theta, body_off and scene s");
     if ((st = ctx_dev_flags(ctx)) != NRS_OK) return st;

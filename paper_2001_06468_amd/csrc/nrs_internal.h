@@ -33,6 +33,8 @@ struct nrs_ctx {
   // device address of the library's static scratch array on this device
   // (the no-allocation triangular solve), from hipGetSymbolAddress
   int32_t* scratch = nullptr;
+  // largest body block order of the block preconditioner on this device
+  int32_t block_lim = 0;
   // pinned host staging of batch descriptors; the event marks the last copy
   void* staging = nullptr;
   size_t staging_cap = 0;
@@ -92,7 +94,8 @@ struct SolveState {
   int32_t nonfinite;
   int32_t stop;
   int32_t sync_err;     // a bounded wait in the triangular solves timed out
-  int32_t pad2;
+  int32_t prec_err;     // block preconditioner set-up: 2 bodies not runs, 4 block too large,
+                        // 8 block order differs from the model's
   int32_t lu_ctl[4];    // tile LU: ticket, exit count, wait-timeout flag         // converged || failed: refinement kernels become no-ops
   double bwd;           // normwise backward error of the last residual
   double corr;          // last |d|/|x|
@@ -183,6 +186,13 @@ struct SolveBuffers {
   float* eqc;        // [n] column scale factors
   uint32_t* eqmax;   // [n] row maxima (scratch of the equilibration)
   bool equil;        // the FP32 factors are of D_r A D_c (eqr, eqc valid)
+  // block preconditioner (NRS_GMRES_BLOCK)
+  int32_t* boff;     // [M+1] body point offsets
+  int32_t* bstarts;  // [1] counter of the body-run check
+  double* bpsi;      // [M] beat phase of every body
+  double* blocks;    // [M][kBlockStride] body blocks / their inverses
+  const nrs_scene* phase_scene;   // time stepping: the scene whose wave parts give
+  double phase_t;                 // every body's phase at time phase_t (else NULL)
 };
 
 size_t solve_workspace_bytes(int64_t N, int64_t Q, int32_t M, int32_t method);
@@ -280,6 +290,40 @@ hipError_t launch_targets(int64_t N, int32_t M, const int32_t* body, const doubl
 hipError_t launch_to_lab(int64_t N, int32_t M, const int32_t* body, const double* Y,
                          const float* y, const float* z, const double* sc, double* x0,
                          hipStream_t s);
+
+// ---- block preconditioner (precond.hip) ----
+constexpr int32_t kBlockMax = 144;            // largest body block order (LDS arrays)
+constexpr int64_t kBlockStride = (int64_t)kBlockMax * kBlockMax;
+constexpr int32_t kBlockHarmonicsMax = 16;    // harmonics of the learned block model
+// largest block order whose inversion fits lds_per_block bytes of LDS
+int32_t block_order_limit(size_t lds_per_block);
+size_t block_inverse_lds(int32_t nb);
+// err |= 4 for a body block above nb_lim, 8 for one whose order is not nb_model (> 0)
+hipError_t launch_block_check(int32_t M, int64_t N, const int32_t* off, int32_t nb_lim,
+                              int32_t nb_model, int32_t* err, hipStream_t s);
+// psi[b] = omega t - phi of body b's first wave point (scene arrays part, wave)
+hipError_t launch_body_phase(int32_t M, int64_t N, const int32_t* off, const int32_t* part,
+                             const double* wave, int32_t P, double t, double* psi, hipStream_t s);
+// the diagonal body blocks of the stored FP64 matrix, column-major, stride kBlockStride
+hipError_t launch_block_extract(int32_t M, int64_t N, const int32_t* off, int32_t nb_lim,
+                                const double* A, int64_t lda, double* blocks, hipStream_t s);
+// in-place inverses of `count` blocks: off == NULL -> all of order nb_uniform
+// at the given stride; else the bodies' blocks (orders from off, <= nb_lim)
+hipError_t launch_block_inverse(int32_t count, int32_t nb_uniform, int64_t stride, int64_t N,
+                                const int32_t* off, int32_t nb_lim, double* blocks, int32_t* sing,
+                                hipStream_t s);
+// Fourier coefficients [2H+1][nb*nb] of S inverses at phases 2 pi s / S
+hipError_t launch_block_fit(int32_t S, int32_t nb, int32_t H, const double* inv, double* model,
+                            hipStream_t s);
+// blocks[b] = K(psi[b]) of the model; off != NULL: only bodies of order nb
+hipError_t launch_block_model(int32_t count, int64_t N, const int32_t* off, int32_t nb_lim,
+                              int32_t nb, int32_t H, const double* model, const double* psi,
+                              int64_t stride, double* blocks, hipStream_t s);
+struct GmresArgs;
+// z_k = M^-1 v_k of the flexible GMRES in a (Y != NULL: body-frame blocks)
+hipError_t launch_prec_block(const GmresArgs& a, int32_t M, int64_t N, const int32_t* off,
+                             int32_t nb_lim, int32_t nb_model, const double* Y,
+                             const double* blocks, double* zv, hipStream_t s);
 
 // ---- GMRES (gmres.hip) ----
 constexpr int kGmresLd = 64;       // basis row length; restart m <= kGmresLd - 1

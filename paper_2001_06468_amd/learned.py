@@ -1,4 +1,5 @@
-"""Training data and training loop of the learned GMRES warm start.
+"""Training data and training loops of the learned parts of the GMRES forms:
+the warm-start network and the block preconditioner model.
 
 The network (include/nrs.h, "Learned warm start") maps body-frame features of
 each free body's force points to the body-frame force density and the body's
@@ -19,7 +20,9 @@ import torch
 
 import synth
 
-from . import (Context, DeviceScene, Model, Problem, nrs_adam_step, nrs_geometry,  # noqa: F401
+from . import (BlockModel, Context, DeviceScene, Model, Problem, nrs_adam_step,  # noqa: F401
+               nrs_assemble, nrs_block_invert, nrs_block_model_fit, nrs_geometry,
+               nrs_workspace_size, NRS_FP64_LU,
                nrs_mlp_body_offsets, nrs_mlp_features, nrs_mlp_grad, nrs_mlp_grad_workspace_size,
                nrs_mlp_param_count, nrs_mlp_status, nrs_mlp_targets, nrs_nearest,
                nrs_solve_batched, nrs_solve_batched_workspace_size, NRS_FP32_IR)
@@ -209,3 +212,59 @@ def evaluate_loss(ctx, theta, data):
         total += float(grad[P]) * sel.numel()
         count += sel.numel()
     return total / count
+
+
+def fit_block_model(ctx, scene, S=48, H=6, dev="cuda"):
+    """Learned body-block inverse of NRS_GMRES_BLOCK from the method's own
+    blocks.  scene: host scene dict (``synth`` layout) of ONE free body whose
+    points are all the body's (no fixed points), its frame at the origin with
+    B = I.  At the S beat phases psi_s = 2 pi s / S (time t_s = (psi_s + phi)
+    / omega of the body's wave part) the library assembles the one-body
+    system in FP64 (geometry, nearest map, assembly: the body's diagonal
+    block in its own frame), inverts the S blocks and fits the Fourier model
+    of degree H.  Returns a BlockModel (with .fit_seconds)."""
+    if int(scene["M"]) != 1 or np.any(np.asarray(scene["body"]) != 0):
+        raise ValueError("the block model is fitted on a scene of one free body and nothing else")
+    wave = np.asarray(scene["wave"], dtype=np.float64).reshape(-1, 6)
+    part = np.asarray(scene["part"])
+    parts = part[part >= 0]
+    if parts.size == 0:
+        if H != 0:
+            raise ValueError("a body without a wave part has one block: use H = 0")
+        omega, phi = 1.0, 0.0
+    else:
+        omega, phi = float(wave[parts[0], 4]), float(wave[parts[0], 5])
+        if omega == 0.0 and H != 0:
+            raise ValueError("a body whose wave does not move has one block: use H = 0")
+        omega = omega or 1.0
+    sc = dict(scene)
+    Y = np.zeros((1, 12))
+    Y[0, 3:] = np.eye(3).ravel()
+    sc["Y0"] = Y
+    t0 = time.perf_counter()
+    ds = DeviceScene(sc, dev)
+    N, Q = ds.N, ds.Q
+    nb = 3 * N + 6
+    x = torch.empty((3, N), dtype=torch.float64, device=dev)
+    X = torch.empty((3, Q), dtype=torch.float64, device=dev)
+    w = torch.empty(Q, dtype=torch.float64, device=dev)
+    nu = torch.empty(Q, dtype=torch.int32, device=dev)
+    blocks = torch.empty((S, nb, nb), dtype=torch.float64, device=dev)
+    ws = torch.empty(nrs_workspace_size(ctx, N, Q, 1, NRS_FP64_LU), dtype=torch.uint8, device=dev)
+    Yd = ds.t["Y0"]
+    for s in range(S):
+        t = (2.0 * math.pi * s / S + phi) / omega
+        nrs_geometry(ctx, ds, t, Yd, x, X, w, None)
+        nrs_nearest(ctx, x, ds.group_off, X, ds.t["groupX"], nu)
+        pb = Problem(x, X, w, nu, ds.t["body"], Yd, ds.eps, ds.mu)
+        nrs_assemble(ctx, pb, 64, blocks[s], nb, ws)
+    singular = torch.zeros(1, dtype=torch.int32, device=dev)
+    nrs_block_invert(ctx, blocks, singular)
+    coef = torch.empty((2 * H + 1, nb, nb), dtype=torch.float64, device=dev)
+    nrs_block_model_fit(ctx, blocks, H, coef)
+    torch.cuda.synchronize()
+    if int(singular.item()):
+        raise RuntimeError("a sampled body block is singular")
+    model = BlockModel(coef, nb, H)
+    model.fit_seconds = time.perf_counter() - t0
+    return model
