@@ -102,7 +102,7 @@ def cpu_threads():
     return os.cpu_count() or 1
 
 
-def train_model(ctx, nrs, solves=2000, steps=8000):
+def train_model(ctx, nrs, solves=20000, steps=8000):
     """Warm-start network for the GMRES form: training data are solves of the
     method on seeded filament swimmers (random phases, times, M in {1,5,25}),
     fitted with the library's own forward/backward/Adam kernels."""
@@ -710,6 +710,25 @@ def main():
             forms[name] = {"solves_per_s": 4 * k / (fm / 1e3), "steps": k,
                            "fell_back": finfo["fell_back"],
                            "max_stage_iterations_last_step": finfo["iterations"]}
+        # block-diagonal preconditioned GMRES from the previous stage's
+        # solution: exact body-block inverses, and the learned block model
+        # (Fourier fit in the beat phase of one filament's blocks)
+        from paper_2001_06468_amd import learned as learned_mod
+        bm = learned_mod.fit_block_model(ctx, synth.filament_scene(1, seed=0), S=48, H=6)
+        block_info = {"fit_s": bm.fit_seconds, "phases": 48, "harmonics": bm.H, "order": bm.nb,
+                      "source": "one filament in its own frame (the method's FP64 blocks)"}
+        for name, opts in (("gmres_block_exact", {"precond": nrs.NRS_PRECOND_EXACT}),
+                           ("gmres_block_learned", {"precond": nrs.NRS_PRECOND_MODEL,
+                                                    "block_model": bm})):
+            fm, _, Yb, _, finfo = run_steps(nrs.NRS_GMRES_BLOCK, args.warmup, args.steps,
+                                            warm_start=nrs.NRS_WARM_PREVIOUS, **opts)
+            forms[name] = {"solves_per_s": 4 * args.steps / (fm / 1e3),
+                           "ms_per_step": fm / args.steps,
+                           "ms_per_step_median": float(np.median(per_step)),
+                           "steps": args.steps, "fell_back": finfo["fell_back"],
+                           "max_stage_iterations_last_step": finfo["iterations"],
+                           "max_abs_state_diff_vs_headline": float((Yb - Y).abs().max())}
+        forms["gmres_block_learned"]["model"] = block_info
 
     small = None
     if not args.no_small:

@@ -77,7 +77,8 @@ typedef int32_t nrs_status;
 
 /* Body blocks of NRS_GMRES_BLOCK (nrs_options.precond). */
 #define NRS_PRECOND_EXACT  0  /* FP64 assembly, then the inverse of every body's
-                                 diagonal block (Gauss-Jordan in LDS)          */
+                                 diagonal block (Gauss-Jordan, one workgroup
+                                 per body)                                     */
 #define NRS_PRECOND_MODEL  1  /* no assembly: each body's block inverse is
                                  R_b K(psi_b) R_b^T from the Fourier model K of
                                  nrs_block_model_fit at the body's beat phase  */
@@ -442,8 +443,9 @@ nrs_status nrs_autotune_clear(nrs_ctx* ctx);
  * of a single body at the origin with B = I: (f_x of its points, f_y, f_z,
  * U, Omega), nb = 3 N_b + 6. */
 
-/* *nb_max = largest block order this device can invert (the LDS of one
- * workgroup holds the block in FP64); larger bodies are not preconditioned. */
+/* *nb_max = largest block order the library inverts and applies (192: one
+ * workgroup holds the block in registers, FP64); larger bodies are not
+ * preconditioned. */
 nrs_status nrs_block_limit(nrs_ctx* ctx, int32_t* nb_max);
 
 /* In-place inverses of `count` blocks of order nb (1 <= nb <= nb_max):

@@ -439,17 +439,44 @@ nrs_status run_gmres_block(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb
   a.st = sb.gst;
   const int32_t* halt = &sb.gst->halt;
   const double* Yrot = model ? pb.Y : nullptr;
+  const int32_t nbm = model ? o.precond_nb : 0;
   NRS_HIP(ctx, launch_gmres_init(sb.gst, tol, m, max_iter, s));
   NRS_HIP(ctx, launch_apply(pb, sb.srt, x, sb.fax, sb.part, sb.chunks, nullptr, s));
-  NRS_HIP(ctx, launch_fgmres_residual(a, sb.fax, s));
   struct Hdr {
     int32_t done, stop, fail, k, iters;
   } h;
+  if (n <= kGmresSmallN) {
+    // one workgroup per Arnoldi step; the end of a cycle (update, true
+    // residual, restart) is queued behind every batch of steps and skips
+    // unless the cycle stopped, so a solve that converges within its first
+    // batch synchronises with the host once.  The batch length follows the
+    // previous solve's iteration count.
+    NRS_HIP(ctx, launch_bg_residual(a, sb.fax, false, sb.fzv, s));
+    int32_t chunk = std::min(16, std::max(2, ctx->bg_chunk));
+    for (;;) {
+      for (int i = 0; i < chunk; ++i) {
+        NRS_HIP(ctx, launch_prec_block(a, M, N, sb.boff, lim, nbm, Yrot, sb.blocks, sb.fzv, false,
+                                       s));
+        NRS_HIP(ctx, launch_apply(pb, sb.srt, sb.fzv, sb.d64, sb.part, sb.chunks, halt, s));
+        NRS_HIP(ctx, launch_bg_orth(a, sb.d64, sb.fzv, s));
+      }
+      NRS_HIP(ctx, launch_bg_update(a, s));
+      NRS_HIP(ctx, launch_apply(pb, sb.srt, x, sb.fax, sb.part, sb.chunks, &sb.gst->skip_true, s));
+      NRS_HIP(ctx, launch_bg_residual(a, sb.fax, true, sb.fzv, s));
+      NRS_HIP(ctx, hipMemcpyAsync(&h, sb.gst, sizeof(h), hipMemcpyDeviceToHost, s));
+      NRS_HIP(ctx, hipStreamSynchronize(s));
+      if (h.fail || h.done || h.iters >= max_iter) break;
+      chunk = 4;
+    }
+    ctx->bg_chunk = h.iters + 1;
+    NRS_HIP(ctx, launch_fgmres_report(sb.st, sb.gst, s));
+    return NRS_OK;
+  }
+  NRS_HIP(ctx, launch_fgmres_residual(a, sb.fax, s));
   constexpr int kChunk = 4;
   for (;;) {
     for (int i = 0; i < kChunk; ++i) {
-      NRS_HIP(ctx, launch_prec_block(a, M, N, sb.boff, lim, model ? o.precond_nb : 0, Yrot,
-                                     sb.blocks, sb.fzv, s));
+      NRS_HIP(ctx, launch_prec_block(a, M, N, sb.boff, lim, nbm, Yrot, sb.blocks, sb.fzv, true, s));
       NRS_HIP(ctx, launch_apply(pb, sb.srt, sb.fzv, sb.d64, sb.part, sb.chunks, halt, s));
       NRS_HIP(ctx, launch_fgmres_orth(a, sb.d64, s));
     }
@@ -513,8 +540,10 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
   const int32_t max_refine = o.max_refine > 0 ? o.max_refine : 4;
   const double tol = o.tol > 0 ? o.tol : 1e-9;
   NRS_HIP(ctx, launch_state_init(sb.st, method, s));
-  NRS_HIP(ctx, launch_fill_i32(sb.tsync, 0, trsv_sync_ints(n), s));
-  NRS_HIP(ctx, launch_fill_i32(sb.lu_done, 0, lu_tiles_nt(n) * lu_tiles_nt(n), s));
+  if (method != NRS_GMRES_BLOCK) {   // synchronisation words of the factorisation paths
+    NRS_HIP(ctx, launch_fill_i32(sb.tsync, 0, trsv_sync_ints(n), s));
+    NRS_HIP(ctx, launch_fill_i32(sb.lu_done, 0, lu_tiles_nt(n) * lu_tiles_nt(n), s));
+  }
   NRS_HIP(ctx, launch_build_csr(N, Q, pb.X, pb.w, pb.nu, sb.srt, s));
   NRS_HIP(ctx, launch_check_nu(N, sb.srt.cnt, sb.st, s));
   NRS_HIP(ctx, launch_check_body(N, pb.M, pb.body, sb.st, s));
@@ -555,6 +584,10 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
   }
   if (!ok && !o.no_fallback) {
     NRS_HIP(ctx, launch_state_init(sb.st, NRS_FP64_LU, s));
+    if (method == NRS_GMRES_BLOCK) {
+      NRS_HIP(ctx, launch_fill_i32(sb.tsync, 0, trsv_sync_ints(n), s));
+      NRS_HIP(ctx, launch_fill_i32(sb.lu_done, 0, lu_tiles_nt(n) * lu_tiles_nt(n), s));
+    }
     if ((st = run_fp64_lu(ctx, pb, sb, sol, true, s)) != NRS_OK) return st;
     if ((st = read_state(ctx, sb.st, h)) != NRS_OK) return st;
     h.fell_back = 1;
@@ -615,17 +648,6 @@ nrs_status nrs_create(nrs_ctx** out, int device, void* stream) {
     delete c;
     return NRS_E_HIP;
   }
-  int lds = 0;
-  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) {
-    delete c;
-    return NRS_E_HIP;
-  }
-  int optin = 0;   // the larger opt-in figure where the runtime reports one
-  if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, device) == hipSuccess &&
-      optin > lds)
-    lds = optin;
-  (void)hipGetLastError();
-  c->block_lim = block_order_limit((size_t)lds);
   *out = c;
   return NRS_OK;
 }

@@ -595,6 +595,7 @@ __global__ void k_gm_init(GmresState* st, double tol, int32_t m, int32_t max_ite
     st->beta = 0.0;
     st->nrm = 1.0;
     st->halt = 0;
+    st->skip_true = 1;
   }
 }
 

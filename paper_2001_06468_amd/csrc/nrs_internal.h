@@ -10,6 +10,10 @@
 
 #include "../../include/nrs.h"
 
+namespace nrs {
+constexpr int32_t kBlockMax = 192;   // largest body block order of the block preconditioner (62 points)
+}
+
 // A captured batched solve (nrs_solve_batched with options.graph): the
 // executable graph, the argument hash it was captured for, and the pinned
 // host copy of the batch descriptors its copy nodes read.
@@ -33,8 +37,11 @@ struct nrs_ctx {
   // device address of the library's static scratch array on this device
   // (the no-allocation triangular solve), from hipGetSymbolAddress
   int32_t* scratch = nullptr;
-  // largest body block order of the block preconditioner on this device
-  int32_t block_lim = 0;
+  // largest body block order of the block preconditioner
+  int32_t block_lim = nrs::kBlockMax;
+  // Arnoldi steps queued ahead of the first host check of a block-preconditioned
+  // GMRES solve (the previous solve's iteration count plus one)
+  int32_t bg_chunk = 6;
   // pinned host staging of batch descriptors; the event marks the last copy
   void* staging = nullptr;
   size_t staging_cap = 0;
@@ -292,12 +299,8 @@ hipError_t launch_to_lab(int64_t N, int32_t M, const int32_t* body, const double
                          hipStream_t s);
 
 // ---- block preconditioner (precond.hip) ----
-constexpr int32_t kBlockMax = 144;            // largest body block order (LDS arrays)
 constexpr int64_t kBlockStride = (int64_t)kBlockMax * kBlockMax;
 constexpr int32_t kBlockHarmonicsMax = 16;    // harmonics of the learned block model
-// largest block order whose inversion fits lds_per_block bytes of LDS
-int32_t block_order_limit(size_t lds_per_block);
-size_t block_inverse_lds(int32_t nb);
 // err |= 4 for a body block above nb_lim, 8 for one whose order is not nb_model (> 0)
 hipError_t launch_block_check(int32_t M, int64_t N, const int32_t* off, int32_t nb_lim,
                               int32_t nb_model, int32_t* err, hipStream_t s);
@@ -320,10 +323,26 @@ hipError_t launch_block_model(int32_t count, int64_t N, const int32_t* off, int3
                               int32_t nb, int32_t H, const double* model, const double* psi,
                               int64_t stride, double* blocks, hipStream_t s);
 struct GmresArgs;
-// z_k = M^-1 v_k of the flexible GMRES in a (Y != NULL: body-frame blocks)
+// z_k = M^-1 v_k of the flexible GMRES in a (Y != NULL: body-frame blocks).
+// begin = true: first normalise the new basis vector into V[:, k] and copy
+// it to Z[:, k] and zv (the multi-workgroup Arnoldi kernels leave it
+// unnormalised); false: V[:, k], Z[:, k] and zv already hold it (the
+// one-workgroup kernels below write it).
 hipError_t launch_prec_block(const GmresArgs& a, int32_t M, int64_t N, const int32_t* off,
                              int32_t nb_lim, int32_t nb_model, const double* Y,
-                             const double* blocks, double* zv, hipStream_t s);
+                             const double* blocks, double* zv, bool begin, hipStream_t s);
+// One-workgroup flexible GMRES kernels for n <= kGmresSmallN (rows held in
+// registers, no inter-workgroup reductions): the residual (only_if_stopped:
+// skips unless the current cycle has stopped), the Arnoldi orthogonalisation
+// of A z_k (CGS2, Givens rotations, stop rules as the multi-workgroup
+// kernels) and the end-of-cycle update x += Z y (skips unless stopped).  The
+// residual and the orthogonalisation also write the next basis vector into
+// V, Z (identity outside the bodies) and zv.
+constexpr int64_t kGmresSmallN = 8192;
+hipError_t launch_bg_residual(const GmresArgs& a, const double* Ax, bool only_if_stopped,
+                              double* zv, hipStream_t s);
+hipError_t launch_bg_orth(const GmresArgs& a, const double* Aw, double* zv, hipStream_t s);
+hipError_t launch_bg_update(const GmresArgs& a, hipStream_t s);
 
 // ---- GMRES (gmres.hip) ----
 constexpr int kGmresLd = 64;       // basis row length; restart m <= kGmresLd - 1
@@ -337,6 +356,7 @@ struct GmresState {
   int32_t counter;    // last-workgroup ticket (zero between launches)
   int32_t m, max_iter;
   int32_t halt;       // done | stop | fail: launches queued behind a finished cycle skip
+  int32_t skip_true;  // !stop | done | fail: the end-of-cycle launches queued ahead skip
   double tol, bnorm, beta, nrm;
   double g[kGmresLd + 1], cs[kGmresLd], sn[kGmresLd], h1[kGmresLd], h2[kGmresLd];
   double H[(kGmresLd + 1) * kGmresLd];   // column-major, leading dimension kGmresLd + 1

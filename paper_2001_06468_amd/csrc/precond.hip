@@ -28,7 +28,7 @@
 namespace nrs {
 namespace {
 
-constexpr int kInvThreads = 1024;   // 16 waves: 128 columns x 8 row groups
+constexpr int kInvThreads = 1024;   // 16 waves
 constexpr int kPrecThreads = 1024;
 
 // Order of body b's block, or 0 when the body cannot be preconditioned: its
@@ -96,105 +96,154 @@ __global__ void k_block_extract(int64_t N, const int32_t* __restrict__ off, int3
 }
 
 // In-place Gauss-Jordan inversion with partial pivoting of one block per
-// workgroup, the block held in LDS: row interchanges during the elimination,
-// the matching column interchanges of the inverse afterwards in reverse
-// order.  The elimination treats the block as row-major; on a column-major
-// block it therefore inverts the transpose, whose row-major inverse is the
-// column-major inverse of the block.  Orders: off == NULL -> every block
-// nb_uniform; else body b's order (skipped if 0).  sing |= 1 on a zero or
-// non-finite pivot (the block is then left partly eliminated).
+// workgroup, the block held in registers: lane l owns rows l, l + 64,
+// l + 128 and wave w columns w, w + 16, ...  Rows are not interchanged: step
+// k takes as pivot the unused row p_k with the largest |a_pk| (lowest index
+// on ties), scales it by 1 / a_pk (its column-k entry becoming 1 / a_pk) and
+// eliminates column k from every other row (their column-k entries becoming
+// -a_ik / a_pk).  The stored array is then the inverse of the row-permuted
+// block with its rows in pivot-row order, so entry (i, c) is written to
+// (step at which row i was the pivot, pivot row of step c).  The elimination
+// treats the block as row-major; on a column-major block it therefore
+// inverts the transpose, whose row-major inverse is the column-major inverse
+// of the block.  Orders: off == NULL -> every block nb_uniform; else body
+// b's order (skipped if 0).  sing |= 1 on a zero or non-finite pivot (the
+// output is then not an inverse).
+//
+// One barrier per step: the wave that owns column k finds the pivot with a
+// wave reduction and publishes the column, the pivot row index and value
+// (LDS slots double-buffered by step parity); after the barrier every wave
+// takes the pivot row's entries of its own columns from the owning lane by
+// shuffles and updates its entries.
+constexpr int kInvWaves = kInvThreads / 64;                    // 16
+constexpr int kInvRowsL = (kBlockMax + 63) / 64;               // rows per lane
+constexpr int kInvColsW = (kBlockMax + kInvWaves - 1) / kInvWaves;   // columns per wave
+
 __global__ __launch_bounds__(kInvThreads) void k_block_inverse(int32_t nb_uniform, int64_t stride,
                                                                int64_t N,
                                                                const int32_t* __restrict__ off,
                                                                int32_t nb_lim,
                                                                double* __restrict__ blocks,
                                                                int32_t* __restrict__ sing) {
-  extern __shared__ double Ab[];
-  __shared__ double colk[kBlockMax];
-  __shared__ int32_t piv[kBlockMax];
-  __shared__ double s_v[kInvThreads / 64];
-  __shared__ int s_i[kInvThreads / 64];
-  __shared__ int s_p;
+  __shared__ double colk[2][kBlockMax];
+  __shared__ double s_d[2];
+  __shared__ int s_p[2];
+  __shared__ int32_t step_of[kBlockMax];   // step at which the row was the pivot
+  __shared__ int32_t pivot_of[kBlockMax];  // pivot row of each step
   const int32_t b = blockIdx.x;
   const int nb = off ? body_order(off, b, N, nb_lim, 0) : nb_uniform;
   if (nb <= 0 || nb > kBlockMax) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int tx = tid & 127, ty = tid >> 7;
   double* g = blocks + (size_t)b * stride;
-  for (int e = tid; e < nb * nb; e += kInvThreads) Ab[e] = g[e];
-  __syncthreads();
+  double reg[kInvRowsL][kInvColsW];
+#pragma unroll
+  for (int q = 0; q < kInvRowsL; ++q)
+#pragma unroll
+    for (int j = 0; j < kInvColsW; ++j) {
+      const int i = lane + 64 * q, c = w + kInvWaves * j;
+      reg[q][j] = (c < nb && i < nb) ? g[(size_t)i * nb + c] : 0.0;
+    }
+  // columns of this wave below nb (wave-uniform): j < jn
+  const int jn = nb > w ? (nb - w + kInvWaves - 1) / kInvWaves : 0;
+  uint32_t used = 0;   // bit q: row lane + 64 q was a pivot
   bool zero = false;
+  // column slots of rows past nb stay zero (no wave writes them; the first
+  // barrier below orders these stores before any read)
+  for (int i = nb + tid; i < kBlockMax; i += kInvThreads) colk[0][i] = colk[1][i] = 0.0;
   for (int k = 0; k < nb; ++k) {
-    double best = -1.0;
-    int bi = nb;
-    if (k + tid < nb) {
-      const double v = fabs(Ab[(k + tid) * nb + k]);
-      if (v > best) {   // false for NaN: such a row is never chosen
-        best = v;
-        bi = k + tid;
+    const int buf = k & 1;
+    if (w == (k & (kInvWaves - 1))) {
+      const int jk = k / kInvWaves;
+      double best = -1.0, bd = 0.0;
+      int bi = nb;
+#pragma unroll
+      for (int q = 0; q < kInvRowsL; ++q) {
+        double a = 0.0;
+#pragma unroll
+        for (int j = 0; j < kInvColsW; ++j)
+          if (j == jk) a = reg[q][j];
+        const int i = lane + 64 * q;
+        if (i < nb) {
+          colk[buf][i] = a;
+          double v = fabs(a);
+          if (!(v >= 0.0)) v = -0.5;   // a NaN ranks below every number
+          if (!((used >> q) & 1u) && v > best) {
+            best = v;
+            bd = a;
+            bi = i;
+          }
+        }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(best, o);
+        const double od = __shfl_xor(bd, o);
+        const int oi = __shfl_xor(bi, o);
+        if (ov > best || (ov == best && oi < bi)) {
+          best = ov;
+          bd = od;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        s_p[buf] = bi;
+        s_d[buf] = bd;
+        step_of[bi] = k;
+        pivot_of[k] = bi;
       }
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(best, o);
-      const int oi = __shfl_xor(bi, o);
-      if (ov > best || (ov == best && oi < bi)) {
-        best = ov;
-        bi = oi;
-      }
-    }
-    if (lane == 0) {
-      s_v[w] = best;
-      s_i[w] = bi;
-    }
     __syncthreads();
-    if (tid == 0) {
-      int q = 0;
-      for (int u = 1; u < kInvThreads / 64; ++u)
-        if (s_v[u] > s_v[q] || (s_v[u] == s_v[q] && s_i[u] < s_i[q])) q = u;
-      const int p = s_i[q] < nb ? s_i[q] : k;
-      s_p = p;
-      piv[k] = p;
-    }
-    __syncthreads();
-    const int p = s_p;
-    if (p != k)
-      for (int c = tid; c < nb; c += kInvThreads) {
-        const double t = Ab[k * nb + c];
-        Ab[k * nb + c] = Ab[p * nb + c];
-        Ab[p * nb + c] = t;
-      }
-    __syncthreads();
-    const double d = Ab[k * nb + k];
-    if (d == 0.0 || !isfinite(d)) {
-      zero = true;
-      continue;
-    }
+    const int p = s_p[buf];
+    const double d = s_d[buf];
+    double f[kInvRowsL];
+#pragma unroll
+    for (int q = 0; q < kInvRowsL; ++q) f[q] = colk[buf][lane + 64 * q];
+    if (d == 0.0 || !isfinite(d)) zero = true;
     const double dinv = 1.0 / d;
-    for (int i = tid; i < nb; i += kInvThreads) colk[i] = Ab[i * nb + k];
-    __syncthreads();
-    for (int c = tid; c < nb; c += kInvThreads) Ab[k * nb + c] = c == k ? dinv : Ab[k * nb + c] * dinv;
-    __syncthreads();
-    // every other row: row_i -= colk[i] * row_k; column k of the inverse
-    // takes -colk[i] / d in place
-    for (int i = ty; i < nb; i += kInvThreads / 128) {
-      if (i == k) continue;
-      const double f = colk[i];
-      for (int c = tx; c < nb; c += 128)
-        Ab[i * nb + c] = c == k ? -f * dinv : fma(-f, Ab[k * nb + c], Ab[i * nb + c]);
+    // the pivot row's entries of this wave's columns, from the lane owning it
+    const int lp = p & 63, qp = p >> 6;
+    if (lane == lp) used |= 1u << qp;
+    double pr[kInvColsW];
+#pragma unroll
+    for (int j = 0; j < kInvColsW; ++j) {
+      double v = reg[0][j];
+#pragma unroll
+      for (int q = 1; q < kInvRowsL; ++q)
+        if (q == qp) v = reg[q][j];
+      pr[j] = __shfl(v, lp);
     }
-    __syncthreads();
-  }
-  for (int k = nb - 1; k >= 0; --k) {
-    const int p = piv[k];
-    if (p != k)
-      for (int r = tid; r < nb; r += kInvThreads) {
-        const double t = Ab[r * nb + k];
-        Ab[r * nb + k] = Ab[r * nb + p];
-        Ab[r * nb + p] = t;
+    // one multiply and one FMA per entry: a_ic <- keep_i keep_c a_ic - f_i r_c
+    // with r the scaled pivot row (1 / a_pk in column k), f_i = a_ik and
+    // keep = 1, except the pivot row (f = -1, keep = 0: it becomes r) and
+    // column k (keep = 0: it becomes -a_ik / a_pk).  Rows past nb hold
+    // zeros throughout (their column entries are zero); columns past nb are
+    // skipped.
+    double fe[kInvRowsL], kr[kInvRowsL];
+#pragma unroll
+    for (int q = 0; q < kInvRowsL; ++q) {
+      const bool piv_row = lane + 64 * q == p;
+      fe[q] = piv_row ? -1.0 : f[q];
+      kr[q] = piv_row ? 0.0 : 1.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kInvColsW; ++j) {
+      if (j < jn) {   // wave-uniform
+        const int c = w + kInvWaves * j;
+        const double kc = c == k ? 0.0 : 1.0;
+        const double prj = c == k ? dinv : pr[j] * dinv;
+#pragma unroll
+        for (int q = 0; q < kInvRowsL; ++q) reg[q][j] = fma(-fe[q], prj, (kr[q] * kc) * reg[q][j]);
       }
-    __syncthreads();
+    }
   }
-  for (int e = tid; e < nb * nb; e += kInvThreads) g[e] = Ab[e];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kInvRowsL; ++q)
+#pragma unroll
+    for (int j = 0; j < kInvColsW; ++j) {
+      const int i = lane + 64 * q, c = w + kInvWaves * j;
+      if (c < nb && i < nb) g[(size_t)step_of[i] * nb + pivot_of[c]] = reg[q][j];
+    }
   if (zero && tid == 0) atomicOr(sing, 1);
 }
 
@@ -328,19 +377,294 @@ __global__ __launch_bounds__(kPrecThreads) void k_prec_block(GmresArgs a, int64_
   }
 }
 
-}  // namespace
+// ---- one-workgroup flexible GMRES for n <= kGmresSmallN: thread t owns rows
+// t, t + 1024, ... (at most kRows) in registers; sums over rows are reduced
+// within the workgroup in a fixed order (deterministic). ----
+constexpr int kOne = 1024;
+// rows per thread: 4 or 8 (n <= 4096, kGmresSmallN), so that small systems
+// hold only the registers they use
+inline int rows_for(int64_t n) { return n <= 4 * kOne ? 4 : 8; }
 
-size_t block_inverse_lds(int32_t nb) { return (size_t)nb * nb * sizeof(double); }
-
-int32_t block_order_limit(size_t lds_per_block) {
-  // static LDS of the inversion kernel: colk, piv and the reduction slots
-  const size_t fixed = kBlockMax * (sizeof(double) + sizeof(int32_t)) +
-                       (kInvThreads / 64) * (sizeof(double) + sizeof(int)) + 64;
-  if (lds_per_block <= fixed) return 0;
-  int32_t nb = (int32_t)std::sqrt((double)(lds_per_block - fixed) / sizeof(double));
-  while (nb > 0 && block_inverse_lds(nb) + fixed > lds_per_block) --nb;
-  return nb < kBlockMax ? nb : kBlockMax;
+__device__ inline double wsum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
+
+// out[c] = sum over the workgroup of v[c] (c < CNT); every thread calls it.
+template <int CNT>
+__device__ inline void group_sum(double (&v)[CNT], double* __restrict__ s_part,
+                                 double* __restrict__ out) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < CNT; ++c) {
+    const double t = wsum(v[c]);
+    if (lane == 0) s_part[w * CNT + c] = t;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < CNT) {
+    double t = 0.0;
+    for (int q = 0; q < kOne / 64; ++q) t += s_part[q * CNT + threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+  __syncthreads();
+}
+
+// Next basis vector v = w / nrm into V[:, col], Z[:, col] and zv.
+template <int kRows>
+__device__ inline void store_basis(const GmresArgs& a, int col, const double (&wr)[kRows],
+                                   double scale, double* __restrict__ zv) {
+#pragma unroll
+  for (int j = 0; j < kRows; ++j) {
+    const int64_t r = threadIdx.x + (int64_t)j * kOne;
+    if (r < a.n) {
+      const double v = wr[j] * scale;
+      a.V[r * kGmresLd + col] = v;
+      a.Z[r * kGmresLd + col] = v;
+      zv[r] = v;
+    }
+  }
+}
+
+// r = b - Ax; |r|, |b| (first call); converged, failed, or a new cycle with
+// v_0 = r / |r| stored.
+template <int kRows>
+__global__ __launch_bounds__(kOne) void k_bg_residual(GmresArgs a, const double* __restrict__ Ax,
+                                                      int32_t only_if_stopped,
+                                                      double* __restrict__ zv) {
+  GmresState* st = a.st;
+  if (st->done | st->fail) return;
+  if (only_if_stopped && !st->stop) return;
+  __shared__ double s_part[(kOne / 64) * 2];
+  __shared__ double s_r[2];
+  __shared__ double s_scale;
+  __shared__ int s_new;
+  __shared__ double s_bt[2];   // |b| (negative before the first residual), tol
+  if (threadIdx.x == 0) {
+    s_bt[0] = st->bnorm;
+    s_bt[1] = st->tol;
+  }
+  double rr[kRows];
+  double acc[2] = {0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < kRows; ++j) {
+    const int64_t r = threadIdx.x + (int64_t)j * kOne;
+    rr[j] = 0.0;
+    if (r < a.n) {
+      const double br = a.b[r];
+      rr[j] = br - Ax[r];
+      acc[0] = fma(rr[j], rr[j], acc[0]);
+      acc[1] = fma(br, br, acc[1]);
+    }
+  }
+  group_sum<2>(acc, s_part, s_r);
+  if (threadIdx.x == 0) {
+    const double beta = sqrt(s_r[0]);
+    double bnorm = s_bt[0];
+    if (bnorm < 0.0) {
+      bnorm = sqrt(s_r[1]);
+      st->bnorm = bnorm;
+    }
+    st->beta = beta;
+    int fresh = 0;
+    if (!isfinite(beta)) {
+      st->fail = 1;
+    } else if (beta <= s_bt[1] * bnorm) {
+      st->done = 1;
+    } else {
+      st->nrm = beta;
+      st->g[0] = beta;
+      st->k = 0;
+      st->stop = 0;
+      st->cur = 0;
+      fresh = 1;
+    }
+    st->halt = !fresh;   // done or failed, else a new cycle (this kernel runs only when
+                         // neither was set before)
+    st->skip_true = 1;
+    s_new = fresh;
+    s_scale = fresh ? 1.0 / beta : 0.0;
+  }
+  __syncthreads();
+  if (s_new) store_basis<kRows>(a, 0, rr, s_scale, zv);
+}
+
+// Arnoldi step k on w = A z_k (CGS2): h1 = V^T w, w -= V h1, h2 = V^T w,
+// w -= V h2, then the Givens rotations and stop rules; v_{k+1} = w / |w|.
+template <int kRows>
+__global__ __launch_bounds__(kOne) void k_bg_orth(GmresArgs a, const double* __restrict__ Aw,
+                                                  double* __restrict__ zv) {
+  GmresState* st = a.st;
+  if (st->halt) return;
+  const int k = st->k;
+  constexpr int kDotW = 4;   // basis columns per pass over the rows (past the cached ones)
+  __shared__ double s_part[(kOne / 64) * 8];
+  __shared__ double s_h[2][kGmresLd];
+  __shared__ double s_n[1];
+  __shared__ double s_scale;
+  __shared__ int s_next;
+  // the Givens state, staged in LDS by one round of parallel loads issued
+  // before the passes over the rows (thread 0's rotations then read no
+  // global memory)
+  __shared__ double s_cs[kGmresLd], s_sn[kGmresLd], s_hk[kGmresLd + 1];
+  __shared__ double s_sc[3];   // g[k], tol, |b|
+  __shared__ int s_si[3];      // m, iterations, max_iter
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x;
+    if (l < k) {
+      s_cs[l] = st->cs[l];
+      s_sn[l] = st->sn[l];
+    }
+    if (l == 0) {
+      s_sc[0] = st->g[k];
+      s_sc[1] = st->tol;
+      s_sc[2] = st->bnorm;
+      s_si[0] = st->m;
+      s_si[1] = st->iters;
+      s_si[2] = st->max_iter;
+    }
+  }
+  // w and the first kVC basis columns of every row in one burst of loads,
+  // kept in registers for both Gram-Schmidt passes
+  constexpr int kVC = kRows == 4 ? 6 : 3;
+  double wr[kRows];
+  double vc[kRows][kVC];
+#pragma unroll
+  for (int j = 0; j < kRows; ++j) {
+    const int64_t r = threadIdx.x + (int64_t)j * kOne;
+    wr[j] = r < a.n ? Aw[r] : 0.0;
+#pragma unroll
+    for (int c = 0; c < kVC; ++c) vc[j][c] = (r < a.n && c <= k) ? a.V[r * kGmresLd + c] : 0.0;
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    double* h = s_h[pass];
+    {
+      double acc[kVC];
+#pragma unroll
+      for (int c = 0; c < kVC; ++c) {
+        acc[c] = 0.0;
+#pragma unroll
+        for (int j = 0; j < kRows; ++j) acc[c] = fma(vc[j][c], wr[j], acc[c]);
+      }
+      group_sum<kVC>(acc, s_part, h);   // zero for columns past k
+    }
+    for (int i0 = kVC; i0 <= k; i0 += kDotW) {
+      double acc[kDotW];
+#pragma unroll
+      for (int c = 0; c < kDotW; ++c) acc[c] = 0.0;
+#pragma unroll
+      for (int j = 0; j < kRows; ++j) {
+        const int64_t r = threadIdx.x + (int64_t)j * kOne;
+        if (r < a.n) {
+          const double* Vr = a.V + r * kGmresLd + i0;
+#pragma unroll
+          for (int c = 0; c < kDotW; ++c)
+            if (i0 + c <= k) acc[c] = fma(Vr[c], wr[j], acc[c]);
+        }
+      }
+      group_sum<kDotW>(acc, s_part, h + i0);
+    }
+    double hc[kVC];
+#pragma unroll
+    for (int c = 0; c < kVC; ++c) hc[c] = h[c];
+#pragma unroll
+    for (int j = 0; j < kRows; ++j) {
+      const int64_t r = threadIdx.x + (int64_t)j * kOne;
+      double t = 0.0;
+#pragma unroll
+      for (int c = 0; c < kVC; ++c) t = fma(vc[j][c], hc[c], t);
+      if (r < a.n) {
+        const double* Vr = a.V + r * kGmresLd;
+        for (int i = kVC; i <= k; ++i) t = fma(Vr[i], h[i], t);
+      }
+      wr[j] -= t;
+    }
+  }
+  double nn[1] = {0.0};
+#pragma unroll
+  for (int j = 0; j < kRows; ++j) nn[0] = fma(wr[j], wr[j], nn[0]);
+  group_sum<1>(nn, s_part, s_n);
+  if (threadIdx.x == 0) {
+    const double nrm = sqrt(s_n[0]);
+    double* hk = s_hk;
+    for (int i = 0; i <= k; ++i) hk[i] = s_h[0][i] + s_h[1][i];
+    hk[k + 1] = nrm;
+    for (int i = 0; i < k; ++i) {
+      const double t0 = s_cs[i] * hk[i] + s_sn[i] * hk[i + 1];
+      hk[i + 1] = -s_sn[i] * hk[i] + s_cs[i] * hk[i + 1];
+      hk[i] = t0;
+    }
+    const double den = hypot(hk[k], hk[k + 1]);
+    double c = 1.0, sn = 0.0;
+    if (den > 0.0) {
+      c = hk[k] / den;
+      sn = hk[k + 1] / den;
+    }
+    hk[k] = den;
+    hk[k + 1] = 0.0;
+    double* Hk = st->H + (int64_t)k * (kGmresLd + 1);
+    for (int i = 0; i <= k + 1; ++i) Hk[i] = hk[i];
+    st->cs[k] = c;
+    st->sn[k] = sn;
+    const double gk1 = -sn * s_sc[0];
+    st->g[k + 1] = gk1;
+    st->g[k] = c * s_sc[0];
+    st->k = k + 1;
+    const int iters = s_si[1] + 1;
+    st->iters = iters;
+    st->nrm = nrm;
+    int fail = 0, stop = 0;
+    if (!isfinite(nrm) || !isfinite(gk1)) {
+      fail = 1;
+    } else if (fabs(gk1) <= s_sc[1] * s_sc[2] || nrm == 0.0 || k + 1 >= s_si[0] ||
+               iters >= s_si[2]) {
+      stop = 1;
+    }
+    // done is 0 here (the kernel returns at once on a halted state)
+    st->fail = fail;
+    st->stop = stop;
+    st->halt = stop | fail;
+    st->skip_true = !stop | fail;
+    s_next = !(stop | fail) && nrm > 0.0 && k + 1 < kGmresLd;
+    s_scale = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  }
+  __syncthreads();
+  if (s_next) store_basis<kRows>(a, k + 1, wr, s_scale, zv);
+}
+
+// End of a stopped cycle: y = R^-1 g (wave 0, back substitution), x += Z y.
+__global__ __launch_bounds__(kOne) void k_bg_update(GmresArgs a) {
+  GmresState* st = a.st;
+  if (!st->stop || st->done || st->fail) return;
+  const int k = st->k;
+  if (k <= 0) return;
+  __shared__ double s_y[kGmresLd];
+  __shared__ double s_H[kGmresLd * (kGmresLd + 1)];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  constexpr int ldh = kGmresLd + 1;
+  // the leading k columns of the triangular factor, in LDS (parallel loads)
+  for (int e = threadIdx.x; e < k * ldh; e += kOne) s_H[e] = st->H[e];
+  if (w == 0) s_y[lane] = lane < k ? st->g[lane] : 0.0;
+  __syncthreads();
+  if (w == 0) {
+    double yi = s_y[lane];
+    for (int j = k - 1; j >= 0; --j) {
+      const double yj = __shfl(yi, j, 64) / s_H[j * ldh + j];
+      if (lane == j) yi = yj;
+      if (lane < j) yi -= s_H[j * ldh + lane] * yj;
+    }
+    s_y[lane] = lane < k ? yi : 0.0;
+  }
+  __syncthreads();
+  for (int64_t r = threadIdx.x; r < a.n; r += kOne) {
+    const double* Zr = a.Z + r * kGmresLd;
+    double d = 0.0;
+    for (int i = 0; i < k; ++i) d = fma(Zr[i], s_y[i], d);
+    a.x[r] += d;
+  }
+}
+
+}  // namespace
 
 hipError_t launch_block_check(int32_t M, int64_t N, const int32_t* off, int32_t nb_lim,
                               int32_t nb_model, int32_t* err, hipStream_t s) {
@@ -371,10 +695,8 @@ hipError_t launch_block_inverse(int32_t count, int32_t nb_uniform, int64_t strid
                                 const int32_t* off, int32_t nb_lim, double* blocks, int32_t* sing,
                                 hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  const int32_t nb_max = off ? nb_lim : nb_uniform;
-  hipLaunchKernelGGL(k_block_inverse, dim3((unsigned)count), dim3(kInvThreads),
-                     (unsigned)block_inverse_lds(nb_max), s, nb_uniform, stride, N, off, nb_lim,
-                     blocks, sing);
+  hipLaunchKernelGGL(k_block_inverse, dim3((unsigned)count), dim3(kInvThreads), 0, s, nb_uniform,
+                     stride, N, off, nb_lim, blocks, sing);
   return hipGetLastError();
 }
 
@@ -398,8 +720,9 @@ hipError_t launch_block_model(int32_t count, int64_t N, const int32_t* off, int3
 
 hipError_t launch_prec_block(const GmresArgs& a, int32_t M, int64_t N, const int32_t* off,
                              int32_t nb_lim, int32_t nb_model, const double* Y,
-                             const double* blocks, double* zv, hipStream_t s) {
-  hipLaunchKernelGGL(k_prec_begin, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, zv);
+                             const double* blocks, double* zv, bool begin, hipStream_t s) {
+  if (begin)
+    hipLaunchKernelGGL(k_prec_begin, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a, zv);
   if (M > 0) {
     if (Y)
       hipLaunchKernelGGL(k_prec_block<true>, dim3((unsigned)M), dim3(kPrecThreads), 0, s, a, N, off,
@@ -408,6 +731,32 @@ hipError_t launch_prec_block(const GmresArgs& a, int32_t M, int64_t N, const int
       hipLaunchKernelGGL(k_prec_block<false>, dim3((unsigned)M), dim3(kPrecThreads), 0, s, a, N,
                          off, nb_lim, nb_model, Y, blocks, kBlockStride, zv);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_bg_residual(const GmresArgs& a, const double* Ax, bool only_if_stopped,
+                              double* zv, hipStream_t s) {
+  if (a.n > kGmresSmallN) return hipErrorInvalidValue;
+  const int32_t f = only_if_stopped;
+  switch (rows_for(a.n)) {
+    case 4: hipLaunchKernelGGL(k_bg_residual<4>, dim3(1), dim3(kOne), 0, s, a, Ax, f, zv); break;
+    default: hipLaunchKernelGGL(k_bg_residual<8>, dim3(1), dim3(kOne), 0, s, a, Ax, f, zv); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bg_orth(const GmresArgs& a, const double* Aw, double* zv, hipStream_t s) {
+  if (a.n > kGmresSmallN) return hipErrorInvalidValue;
+  switch (rows_for(a.n)) {
+    case 4: hipLaunchKernelGGL(k_bg_orth<4>, dim3(1), dim3(kOne), 0, s, a, Aw, zv); break;
+    default: hipLaunchKernelGGL(k_bg_orth<8>, dim3(1), dim3(kOne), 0, s, a, Aw, zv); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bg_update(const GmresArgs& a, hipStream_t s) {
+  if (a.n > kGmresSmallN) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_bg_update, dim3(1), dim3(kOne), 0, s, a);
   return hipGetLastError();
 }
 

@@ -76,7 +76,7 @@ def test_block_limit_covers_the_filament_block(ctx):
     assert lim >= 126
 
 
-@pytest.mark.parametrize("nb", [1, 9, 126, "limit"])
+@pytest.mark.parametrize("nb", [1, 9, 17, 113, 126, 129, 177, "limit"])
 def test_block_invert_matches_lapack(ctx, nb):
     if nb == "limit":
         nb = nrs.nrs_block_limit(ctx)
@@ -253,3 +253,31 @@ def test_block_option_errors(ctx, model):
     assert ef <= 1e-8 and eg <= 1e-8
     with pytest.raises(nrs.NrsError):
         nrs.nrs_solve(ctx, pb, u, ft, sol, ws, method=nrs.NRS_GMRES_BLOCK, precond=7)
+
+
+@pytest.mark.parametrize("M", [50, 140])
+@pytest.mark.parametrize("variant", ["exact", "model"])
+def test_gmres_block_larger_systems(ctx, model, variant, M):
+    """50 filaments (n = 6,300: the one-workgroup Arnoldi kernels with eight
+    rows per thread) and 140 filaments (n = 17,640: above their limit, the
+    multi-workgroup kernels) reach the FP64 LU solution (itself checked
+    against the oracle elsewhere) within the same few iterations."""
+    sc = synth.filament_scene(M, seed=5, phase_random=True)
+    t = 0.4
+    pb, host = prepare(sc, t)
+    assert (4096 < pb.n <= 8192) if M == 50 else pb.n > 8192
+    if variant == "exact":
+        kw = dict(precond=nrs.NRS_PRECOND_EXACT)
+    else:
+        kw = dict(precond=nrs.NRS_PRECOND_MODEL, block_model=model,
+                  precond_phase=T(_phases(sc, t)))
+    sol, info = _gmres_counts(ctx, sc, t, pb, host, **kw)
+    ws = workspace(ctx, pb, nrs.NRS_FP64_LU)
+    ref = torch.empty(pb.n, dtype=torch.float64, device=DEV)
+    nrs.nrs_solve(ctx, pb, T(host["u"]), T(sc["ftext"]), ref, ws, method=nrs.NRS_FP64_LU)
+    ef, eg = rel_force_errors(sol, ref.cpu().numpy(), sc["N"])
+    print(f"n = {pb.n}, block {variant}: {info['iterations']} iterations, errors f {ef:.2e} "
+          f"(U, Omega) {eg:.2e}", flush=True)
+    assert info["fell_back"] == 0 and info["method_used"] == nrs.NRS_GMRES_BLOCK, info
+    assert ef <= 1e-8 and eg <= 1e-8
+    assert info["iterations"] <= 12, info
