@@ -544,8 +544,7 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
     NRS_HIP(ctx, launch_fill_i32(sb.tsync, 0, trsv_sync_ints(n), s));
     NRS_HIP(ctx, launch_fill_i32(sb.lu_done, 0, lu_tiles_nt(n) * lu_tiles_nt(n), s));
   }
-  NRS_HIP(ctx, launch_build_csr(N, Q, pb.X, pb.w, pb.nu, sb.srt, s));
-  NRS_HIP(ctx, launch_check_nu(N, sb.srt.cnt, sb.st, s));
+  NRS_HIP(ctx, launch_build_csr(N, Q, pb.X, pb.w, pb.nu, sb.srt, sb.st, s));
   NRS_HIP(ctx, launch_check_body(N, pb.M, pb.body, sb.st, s));
   NRS_HIP(ctx, launch_rhs(N, pb.M, u, ftext, sb.b, s));
   nrs_status st = NRS_OK;
@@ -746,8 +745,7 @@ nrs_status nrs_assemble(nrs_ctx* ctx, const nrs_problem* pb, int32_t precision, 
     return fail(ctx, NRS_E_WORKSPACE, "workspace too small");
   hipStream_t s = ctx->stream;
   NRS_HIP(ctx, launch_state_init(sb.st, NRS_FP64_LU, s));
-  NRS_HIP(ctx, launch_build_csr(pb->N, pb->Q, pb->X, pb->w, pb->nu, sb.srt, s));
-  NRS_HIP(ctx, launch_check_nu(pb->N, sb.srt.cnt, sb.st, s));
+  NRS_HIP(ctx, launch_build_csr(pb->N, pb->Q, pb->X, pb->w, pb->nu, sb.srt, sb.st, s));
   if (precision == 32)
     NRS_HIP(ctx, launch_assemble<float>(*pb, sb.srt, static_cast<float*>(A), lda, s,
                                         asm_shape_for(ctx, pb->N, pb->Q, 32)));
@@ -769,8 +767,7 @@ nrs_status nrs_apply(nrs_ctx* ctx, const nrs_problem* pb, const double* v, doubl
     return fail(ctx, NRS_E_WORKSPACE, "workspace too small");
   hipStream_t s = ctx->stream;
   NRS_HIP(ctx, launch_state_init(sb.st, NRS_FP64_LU, s));
-  NRS_HIP(ctx, launch_build_csr(pb->N, pb->Q, pb->X, pb->w, pb->nu, sb.srt, s));
-  NRS_HIP(ctx, launch_check_nu(pb->N, sb.srt.cnt, sb.st, s));
+  NRS_HIP(ctx, launch_build_csr(pb->N, pb->Q, pb->X, pb->w, pb->nu, sb.srt, sb.st, s));
   NRS_HIP(ctx, launch_apply(*pb, sb.srt, v, y, sb.part, sb.chunks, nullptr, s));
   return NRS_OK;
 }
@@ -992,8 +989,7 @@ nrs_status nrs_autotune(nrs_ctx* ctx, const nrs_problem* pb, void* ws, size_t ws
     return fail(ctx, NRS_E_WORKSPACE, "workspace too small (size it for NRS_FP32_IR)");
   hipStream_t s = ctx->stream;
   NRS_HIP(ctx, launch_state_init(sb.st, NRS_FP64_LU, s));
-  NRS_HIP(ctx, launch_build_csr(pb->N, pb->Q, pb->X, pb->w, pb->nu, sb.srt, s));
-  NRS_HIP(ctx, launch_check_nu(pb->N, sb.srt.cnt, sb.st, s));
+  NRS_HIP(ctx, launch_build_csr(pb->N, pb->Q, pb->X, pb->w, pb->nu, sb.srt, sb.st, s));
   hipEvent_t e0, e1;
   NRS_HIP(ctx, hipEventCreate(&e0));
   NRS_HIP(ctx, hipEventCreate(&e1));

@@ -21,13 +21,98 @@ namespace {
 constexpr int kShapeBlk[kAsmShapes] = {64, 64, 64, 128, 128, 128, 256, 256, 256};
 constexpr int kShapeTN[kAsmShapes] = {4, 8, 16, 4, 8, 16, 4, 8, 16};
 
+// Component j of e_i x r.
+__device__ inline double cross_unit(int i, int j, const double r[3]) {
+  // (e_i x r)_j = eps_{j i k} r_k
+  if (i == j) return 0.0;
+  const int k = 3 - i - j;
+  // eps_{j i k} = +1 for cyclic (j,i,k)
+  const bool cyc = (j == 0 && i == 1) || (j == 1 && i == 2) || (j == 2 && i == 0);
+  return cyc ? r[k] : -r[k];
+}
+
+// The rigid-body rows and columns of the swimming problem, written by extra
+// workgroups of the assembly launch.  Task t < 3N M: row `row` of the
+// velocity equations and body s = t / 3N, its six entries in columns
+// 3N + 6s .. 3N + 6s + 5 (-1 for U_j on its own component, -(e_i x r_m)_j
+// for Omega_i, zero for other bodies).  Task 3N M + t', t' < n M: column
+// col = t' / M and body s = t' % M, the six entries of rows 3N + 6s ..
+// (force rows W_m delta_jk, moment rows W_m (r_m x e_k)_i for the body's
+// points, zero elsewhere and in the rigid-rigid block).  r_m = x_m - x0.
+struct RigidArgs {
+  int64_t N;
+  int32_t M;
+  const int32_t* body;
+  const double* x;
+  const double* Y;
+  const double* W;
+};
+
+template <class T>
+__device__ inline void rigid_task(int64_t t, const RigidArgs& g, T* __restrict__ A, int64_t lda) {
+  const int64_t N = g.N, M = g.M, n = 3 * N + 6 * M;
+  const int64_t ta = 3 * N * M;
+  if (t < ta) {
+    const int s = (int)(t / (3 * N));
+    const int64_t row = t - (int64_t)s * 3 * N;
+    const int j = (int)(row / N);
+    const int64_t m = row - j * N;
+    const bool own = g.body[m] == s;
+    double r[3] = {0.0, 0.0, 0.0};
+    if (own) {
+      r[0] = g.x[m] - g.Y[12 * s + 0];
+      r[1] = g.x[N + m] - g.Y[12 * s + 1];
+      r[2] = g.x[2 * N + m] - g.Y[12 * s + 2];
+    }
+    T* col = A + (3 * N + 6 * (int64_t)s) * lda + row;
+    for (int c = 0; c < 6; ++c) {
+      double v = 0.0;
+      if (own) v = c < 3 ? (c == j ? -1.0 : 0.0) : -cross_unit(c - 3, j, r);
+      col[c * lda] = (T)v;
+    }
+    return;
+  }
+  t -= ta;
+  if (t >= n * M) return;
+  const int64_t col = t / M;
+  const int s = (int)(t - col * M);
+  T* out = A + col * lda + 3 * N + 6 * (int64_t)s;
+  if (col < 3 * N) {
+    const int k = (int)(col / N);
+    const int64_t m = col - k * N;
+    if (g.body[m] == s) {
+      const double r[3] = {g.x[m] - g.Y[12 * s], g.x[N + m] - g.Y[12 * s + 1],
+                           g.x[2 * N + m] - g.Y[12 * s + 2]};
+      const double wm = g.W[m];
+      for (int c = 0; c < 6; ++c)
+        // (r x e_k)_i = -(e_k x r)_i
+        out[c] = (T)(c < 3 ? (c == k ? wm : 0.0) : -wm * cross_unit(k, c - 3, r));
+      return;
+    }
+  }
+  for (int c = 0; c < 6; ++c) out[c] = (T)0.0;
+}
+
+// Workgroups past the force-point strips (blockIdx.y >= strips) take the
+// rigid-body tasks, kAsmBlock consecutive tasks each.
+template <class T, int kAsmBlock, int kTN>
+__device__ inline bool rigid_part(const RigidArgs& g, T* __restrict__ A, int64_t lda) {
+  const int64_t strips = (g.N + kTN - 1) / kTN;
+  if ((int64_t)blockIdx.y < strips) return false;
+  const int64_t t = (((int64_t)blockIdx.y - strips) * gridDim.x + blockIdx.x) * kAsmBlock +
+                    threadIdx.x;
+  if (g.M > 0) rigid_task<T>(t, g, A, lda);
+  return true;
+}
+
 // FP32 form: coordinates carried as hi + lo floats so that r = x_m - X_q keeps
 // FP32 relative accuracy even when |r| << |x|.
 template <int kAsmBlock, int kTN>
 __global__ __launch_bounds__(kAsmBlock) void k_assemble32(
     int64_t N, const double* __restrict__ x, const int32_t* __restrict__ seg,
     const float4* __restrict__ Xhi, const float4* __restrict__ Xlo, float eps2, float scale,
-    float* __restrict__ A, int64_t lda) {
+    float* __restrict__ A, int64_t lda, RigidArgs rg) {
+  if (rigid_part<float, kAsmBlock, kTN>(rg, A, lda)) return;
   const int64_t m = blockIdx.x * (int64_t)kAsmBlock + threadIdx.x;
   const int64_t n0 = (int64_t)blockIdx.y * kTN;
   const bool live = m < N;
@@ -84,7 +169,8 @@ template <int kAsmBlock, int kTN>
 __global__ __launch_bounds__(kAsmBlock) void k_assemble64(
     int64_t N, const double* __restrict__ x, const int32_t* __restrict__ seg,
     const double4* __restrict__ X64, double eps2, double scale, double* __restrict__ A,
-    int64_t lda) {
+    int64_t lda, RigidArgs rg) {
+  if (rigid_part<double, kAsmBlock, kTN>(rg, A, lda)) return;
   const int64_t m = blockIdx.x * (int64_t)kAsmBlock + threadIdx.x;
   const int64_t n0 = (int64_t)blockIdx.y * kTN;
   const bool live = m < N;
@@ -128,71 +214,6 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble64(
       c2[2 * N + m] = scale * a22;
     }
   }
-}
-
-// Component j of e_i x r.
-__device__ inline double cross_unit(int i, int j, const double r[3]) {
-  // (e_i x r)_j = eps_{j i k} r_k
-  if (i == j) return 0.0;
-  const int k = 3 - i - j;
-  // eps_{j i k} = +1 for cyclic (j,i,k)
-  const bool cyc = (j == 0 && i == 1) || (j == 1 && i == 2) || (j == 2 && i == 0);
-  return cyc ? r[k] : -r[k];
-}
-
-// Columns 3N .. n-1 of rows 0 .. 3N-1: -1 for U, -(e_i x r_m) for Omega_i.
-template <class T>
-__global__ void k_rigid_cols(int64_t N, int32_t M, const int32_t* __restrict__ body,
-                             const double* __restrict__ x, const double* __restrict__ Y,
-                             T* __restrict__ A, int64_t lda) {
-  const int64_t row = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (row >= 3 * N) return;
-  const int j = (int)(row / N);
-  const int64_t m = row - j * N;
-  const int b = (body[m] >= 0 && body[m] < M) ? body[m] : -1;
-  double r[3] = {0, 0, 0};
-  if (b >= 0) {
-    r[0] = x[m] - Y[12 * b + 0];
-    r[1] = x[N + m] - Y[12 * b + 1];
-    r[2] = x[2 * N + m] - Y[12 * b + 2];
-  }
-  for (int s = 0; s < M; ++s) {
-    T* col = A + (3 * N + 6 * (int64_t)s) * lda + row;
-    for (int c = 0; c < 6; ++c) {
-      double v = 0.0;
-      if (s == b) v = c < 3 ? (c == j ? -1.0 : 0.0) : -cross_unit(c - 3, j, r);
-      col[c * lda] = (T)v;
-    }
-  }
-}
-
-// Rows 3N .. n-1 (all columns): force rows W_m delta_jk, moment rows
-// W_m (r_m x e_k)_i, zero in the rigid-rigid block.  One thread per entry,
-// threads of a block run down one column (contiguous stores).
-template <class T>
-__global__ void k_rigid_rows(int64_t N, int32_t M, const int32_t* __restrict__ body,
-                             const double* __restrict__ x, const double* __restrict__ Y,
-                             const double* __restrict__ W, T* __restrict__ A, int64_t lda) {
-  const int64_t rr = blockIdx.y * (int64_t)blockDim.x + threadIdx.x;  // rigid row
-  const int64_t col = blockIdx.x;
-  const int64_t nrows = 6 * (int64_t)M;
-  if (rr >= nrows) return;
-  const int s = (int)(rr / 6), c = (int)(rr % 6);
-  double v = 0.0;
-  if (col < 3 * N) {
-    const int k = (int)(col / N);
-    const int64_t m = col - k * N;
-    if (body[m] == s) {
-      if (c < 3) {
-        v = (c == k) ? W[m] : 0.0;
-      } else {
-        const double r[3] = {x[m] - Y[12 * s], x[N + m] - Y[12 * s + 1], x[2 * N + m] - Y[12 * s + 2]};
-        // (r x e_k)_i = -(e_k x r)_i
-        v = -W[m] * cross_unit(k, c - 3, r);
-      }
-    }
-  }
-  A[3 * N + rr + col * lda] = (T)v;
 }
 
 __global__ void k_rhs(int64_t N, int32_t M, const double* __restrict__ u,
@@ -301,21 +322,33 @@ __global__ __launch_bounds__(kApplyThreads) void k_apply_stage2(
 
 inline dim3 grid1(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)); }
 
+// Grid: x = row blocks of BLK, y = strips of TN force points, then enough
+// extra y rows of workgroups for the rigid-body tasks.
+template <int BLK, int TN>
+dim3 asm_grid(const nrs_problem& pb) {
+  const int64_t N = pb.N, M = pb.M, n = 3 * N + 6 * M;
+  const int64_t gx = (N + BLK - 1) / BLK, strips = (N + TN - 1) / TN;
+  const int64_t tasks = 3 * N * M + n * M;
+  const int64_t extra = (tasks + gx * BLK - 1) / (gx * BLK);
+  return dim3((unsigned)gx, (unsigned)(strips + extra));
+}
+inline RigidArgs rigid_args(const nrs_problem& pb, const Sorted& srt) {
+  return RigidArgs{pb.N, pb.M, pb.body, pb.x, pb.Y, srt.W};
+}
 template <int BLK, int TN>
 void asm32(const nrs_problem& pb, const Sorted& srt, float* A, int64_t lda, float scale,
            hipStream_t s) {
-  const int64_t N = pb.N;
-  dim3 g((unsigned)((N + BLK - 1) / BLK), (unsigned)((N + TN - 1) / TN));
-  hipLaunchKernelGGL((k_assemble32<BLK, TN>), g, dim3(BLK), 0, s, N, pb.x, srt.seg, srt.X32hi,
-                     srt.X32lo, (float)(pb.eps * pb.eps), scale, A, lda);
+  const dim3 g = asm_grid<BLK, TN>(pb);
+  hipLaunchKernelGGL((k_assemble32<BLK, TN>), g, dim3(BLK), 0, s, pb.N, pb.x,
+                     srt.seg, srt.X32hi, srt.X32lo, (float)(pb.eps * pb.eps), scale, A, lda,
+                     rigid_args(pb, srt));
 }
 template <int BLK, int TN>
 void asm64(const nrs_problem& pb, const Sorted& srt, double* A, int64_t lda, double scale,
            hipStream_t s) {
-  const int64_t N = pb.N;
-  dim3 g((unsigned)((N + BLK - 1) / BLK), (unsigned)((N + TN - 1) / TN));
-  hipLaunchKernelGGL((k_assemble64<BLK, TN>), g, dim3(BLK), 0, s, N, pb.x, srt.seg, srt.X64,
-                     pb.eps * pb.eps, scale, A, lda);
+  const dim3 g = asm_grid<BLK, TN>(pb);
+  hipLaunchKernelGGL((k_assemble64<BLK, TN>), g, dim3(BLK), 0, s, pb.N, pb.x,
+                     srt.seg, srt.X64, pb.eps * pb.eps, scale, A, lda, rigid_args(pb, srt));
 }
 
 template <class T>
@@ -359,14 +392,10 @@ hipError_t launch_assemble(const nrs_problem& pb, const Sorted& srt, T* A, int64
   const int64_t N = pb.N;
   const int64_t n = 3 * N + 6 * (int64_t)pb.M;
   const T scale = (T)(1.0 / (8.0 * kPi * pb.mu));
+  // one launch: the fused operator and, in extra workgroups, the rigid-body
+  // rows and columns
   if (N > 0) asm_dispatch<T>(shape, pb, srt, A, lda, scale, s);
-  if (pb.M > 0) {
-    hipLaunchKernelGGL(k_rigid_cols<T>, grid1(3 * N, 256), dim3(256), 0, s, N, pb.M, pb.body,
-                       pb.x, pb.Y, A, lda);
-    dim3 g((unsigned)n, grid1(6 * (int64_t)pb.M, 64).x);
-    hipLaunchKernelGGL(k_rigid_rows<T>, g, dim3(64), 0, s, N, pb.M, pb.body, pb.x, pb.Y, srt.W,
-                       A, lda);
-  }
+  (void)n;
   return hipGetLastError();
 }
 template hipError_t launch_assemble<float>(const nrs_problem&, const Sorted&, float*, int64_t,

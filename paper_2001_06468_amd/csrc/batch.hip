@@ -199,8 +199,7 @@ nrs_status enqueue_batch(nrs_ctx* ctx, int32_t B, const nrs_problem* problems,
     NRS_BHIP(ctx, launch_state_init(sb.st, NRS_FP32_IR, s));
     NRS_BHIP(ctx, launch_fill_i32(sb.tsync, 0, trsv_sync_ints(n), s));
     NRS_BHIP(ctx, launch_fill_i32(sb.lu_done, 0, lu_tiles_nt(n) * lu_tiles_nt(n), s));
-    NRS_BHIP(ctx, launch_build_csr(p.N, p.Q, p.X, p.w, p.nu, sb.srt, s));
-    NRS_BHIP(ctx, launch_check_nu(p.N, sb.srt.cnt, sb.st, s));
+    NRS_BHIP(ctx, launch_build_csr(p.N, p.Q, p.X, p.w, p.nu, sb.srt, sb.st, s));
     NRS_BHIP(ctx, launch_check_body(p.N, p.M, p.body, sb.st, s));
     NRS_BHIP(ctx, launch_rhs(p.N, p.M, u[k], ftext ? ftext[k] : nullptr, sb.b, s));
     NRS_BHIP(ctx, launch_assemble<float>(p, sb.srt, sb.A32, sb.lda, s,

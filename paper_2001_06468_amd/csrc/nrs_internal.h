@@ -409,8 +409,11 @@ hipError_t launch_geometry(const nrs_scene& sc, double t, const double* Y, doubl
                            double* w, double* u, hipStream_t s);
 hipError_t launch_nearest(int64_t N, const double* x, const GroupTable& gt, int64_t Q,
                           const double* X, const int32_t* groupX, int32_t* nu, hipStream_t s);
+// nu-sorted layout (counting sort, deterministic order inside segments),
+// packed coordinates and patch weights; st (may be NULL) gets the argument
+// error of a nu outside [0, N)
 hipError_t launch_build_csr(int64_t N, int64_t Q, const double* X, const double* w,
-                            const int32_t* nu, Sorted& srt, hipStream_t s);
+                            const int32_t* nu, Sorted& srt, SolveState* st, hipStream_t s);
 // Assembly launch shapes: shape index -> (rows per workgroup, force points
 // per strip); -1 = default.  Results do not depend on the shape.
 constexpr int kAsmShapes = 9;
@@ -488,7 +491,6 @@ hipError_t launch_convert_f32(int64_t n, const double* a, float* b, hipStream_t 
 // and column then in [1, 2)); dr [n], dc [n] out; rmax [n] scratch.
 hipError_t launch_equilibrate(int64_t n, float* A, int64_t lda, float* dr, float* dc,
                               uint32_t* rmax, hipStream_t s);
-hipError_t launch_check_nu(int64_t N, const int32_t* cnt, SolveState* st, hipStream_t s);
 hipError_t launch_check_body(int64_t N, int32_t M, const int32_t* body, SolveState* st,
                              hipStream_t s);
 hipError_t launch_state_accumulate(SolveState* total, const SolveState* stage, hipStream_t s);

@@ -173,8 +173,16 @@ __global__ void k_csr_count(int64_t N, int64_t Q, const int32_t* __restrict__ nu
 }
 
 // Exclusive scan of cnt[0..N) into seg[0..N]; cnt becomes the scatter cursor.
+// st (may be NULL): argument error when some nu was outside [0, N) (counted
+// in cnt[N + 1]).
 constexpr int kScanBlock = 1024;
-__global__ __launch_bounds__(kScanBlock) void k_csr_scan(int64_t N, int32_t* cnt, int32_t* seg) {
+__global__ __launch_bounds__(kScanBlock) void k_csr_scan(int64_t N, int32_t* cnt, int32_t* seg,
+                                                         SolveState* st) {
+  if (threadIdx.x == 0 && st && cnt[N + 1] > 0) {
+    st->nonfinite = 2;
+    st->failed = 1;
+    st->stop = 1;
+  }
   __shared__ int32_t part[kScanBlock];
   const int tid = threadIdx.x;
   const int64_t per = (N + kScanBlock - 1) / kScanBlock;
@@ -211,39 +219,83 @@ __global__ void k_csr_scatter(int64_t N, int64_t Q, const int32_t* __restrict__ 
   }
 }
 
-// Per segment: order the members by original index (deterministic layout),
-// pack the sorted coordinates and sum the patch weight in that order.
-__global__ void k_csr_finish(int64_t N, int64_t Q, const int32_t* __restrict__ seg,
-                             int32_t* __restrict__ perm, const double* __restrict__ X,
-                             const double* __restrict__ w, int32_t* __restrict__ nus,
-                             double4* __restrict__ X64, float4* __restrict__ X32hi,
-                             float4* __restrict__ X32lo, double* __restrict__ W) {
-  const int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  const int a = seg[n], b = seg[n + 1];
-  for (int i = a + 1; i < b; ++i) {
-    const int32_t key = perm[i];
-    int j = i - 1;
-    while (j >= a && perm[j] > key) {
-      perm[j + 1] = perm[j];
-      --j;
-    }
-    perm[j + 1] = key;
-  }
-  double acc = 0.0;
-  for (int i = a; i < b; ++i) {
-    const int q = perm[i];
-    const double px = X[q], py = X[Q + q], pz = X[2 * Q + q];
-    const double wq = w ? w[q] : 1.0;
-    acc += wq;
-    nus[i] = (int32_t)n;
-    X64[i] = make_double4(px, py, pz, wq);
-    const float hx = (float)px, hy = (float)py, hz = (float)pz;
-    X32hi[i] = make_float4(hx, hy, hz, (float)wq);
-    X32lo[i] = make_float4((float)(px - (double)hx), (float)(py - (double)hy),
+// Per segment (one wavefront each): order the members by original index
+// (deterministic layout), pack the sorted coordinates and sum the patch
+// weight.  A member's place is the number of members with a smaller index
+// (the indices are distinct), found by comparing against every member
+// broadcast from its lane; segments longer than 256 members (not met by
+// the workloads) are sorted by insertion in lane 0.
+constexpr int kFinishWaves = 4;
+__device__ inline double csr_store(int64_t Q, int64_t n, int pos, int q, const double* __restrict__ X,
+                                   const double* __restrict__ w, int32_t* __restrict__ perm,
+                                   int32_t* __restrict__ nus, double4* __restrict__ X64,
+                                   float4* __restrict__ X32hi, float4* __restrict__ X32lo) {
+  const double px = X[q], py = X[Q + q], pz = X[2 * Q + q];
+  const double wq = w ? w[q] : 1.0;
+  perm[pos] = q;
+  nus[pos] = (int32_t)n;
+  X64[pos] = make_double4(px, py, pz, wq);
+  const float hx = (float)px, hy = (float)py, hz = (float)pz;
+  X32hi[pos] = make_float4(hx, hy, hz, (float)wq);
+  X32lo[pos] = make_float4((float)(px - (double)hx), (float)(py - (double)hy),
                            (float)(pz - (double)hz), 0.0f);
+  return wq;
+}
+
+__global__ __launch_bounds__(kFinishWaves * 64) void k_csr_finish(
+    int64_t N, int64_t Q, const int32_t* __restrict__ seg, int32_t* __restrict__ perm,
+    const double* __restrict__ X, const double* __restrict__ w, int32_t* __restrict__ nus,
+    double4* __restrict__ X64, float4* __restrict__ X32hi, float4* __restrict__ X32lo,
+    double* __restrict__ W) {
+  // weights by sorted position, so that the patch weight is summed in an
+  // order that does not depend on the (atomic, unordered) scatter
+  __shared__ double s_w[kFinishWaves][256];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t n = (int64_t)blockIdx.x * kFinishWaves + wv;
+  if (n >= N) return;
+  const int a = seg[n], len = seg[n + 1] - a;
+  double wsum = 0.0;
+  if (len <= 256) {
+    int key[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) key[c] = c * 64 + lane < len ? perm[a + c * 64 + lane] : 0x7fffffff;
+    int rank[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int cj = 0; cj < 4; ++cj) {
+      if (cj * 64 < len) {   // wave-uniform
+        const int top = min(64, len - cj * 64);
+        for (int jj = 0; jj < top; ++jj) {
+          const int kj = __shfl(key[cj], jj, 64);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) rank[c] += kj < key[c] ? 1 : 0;
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c * 64 + lane < len)
+        s_w[wv][rank[c]] = csr_store(Q, n, a + rank[c], key[c], X, w, perm, nus, X64, X32hi, X32lo);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // lane l adds sorted places l, l + 64, ...; then a fixed tree over lanes
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (c * 64 + lane < len) wsum += s_w[wv][c * 64 + lane];
+  } else if (lane == 0) {
+    for (int i = a + 1; i < a + len; ++i) {
+      const int32_t k = perm[i];
+      int j = i - 1;
+      while (j >= a && perm[j] > k) {
+        perm[j + 1] = perm[j];
+        --j;
+      }
+      perm[j + 1] = k;
+    }
+    for (int i = a; i < a + len; ++i) wsum += csr_store(Q, n, i, perm[i], X, w, perm, nus, X64, X32hi, X32lo);
   }
-  W[n] = acc;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) wsum += __shfl_xor(wsum, o, 64);
+  if (lane == 0) W[n] = wsum;
 }
 
 inline dim3 grid1(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)); }
@@ -288,19 +340,20 @@ hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s) {
 }
 
 hipError_t launch_build_csr(int64_t N, int64_t Q, const double* X, const double* w,
-                            const int32_t* nu, Sorted& srt, hipStream_t s) {
+                            const int32_t* nu, Sorted& srt, SolveState* st, hipStream_t s) {
   hipError_t e = launch_fill_i32(srt.cnt, 0, N + 2, s);
   if (e != hipSuccess) return e;
   if (Q > 0) {
     hipLaunchKernelGGL(k_csr_count, grid1(Q, 256), dim3(256), 0, s, N, Q, nu, srt.cnt);
   }
-  hipLaunchKernelGGL(k_csr_scan, dim3(1), dim3(kScanBlock), 0, s, N, srt.cnt, srt.seg);
+  hipLaunchKernelGGL(k_csr_scan, dim3(1), dim3(kScanBlock), 0, s, N, srt.cnt, srt.seg, st);
   if (Q > 0) {
     hipLaunchKernelGGL(k_csr_scatter, grid1(Q, 256), dim3(256), 0, s, N, Q, nu, srt.cnt,
                        srt.perm);
   }
-  hipLaunchKernelGGL(k_csr_finish, grid1(N, 64), dim3(64), 0, s, N, Q, srt.seg, srt.perm, X, w,
-                     srt.nus, srt.X64, srt.X32hi, srt.X32lo, srt.W);
+  hipLaunchKernelGGL(k_csr_finish, dim3((unsigned)((N + kFinishWaves - 1) / kFinishWaves)),
+                     dim3(kFinishWaves * 64), 0, s, N, Q, srt.seg, srt.perm, X, w, srt.nus, srt.X64,
+                     srt.X32hi, srt.X32lo, srt.W);
   return hipGetLastError();
 }
 

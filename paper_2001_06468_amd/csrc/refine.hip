@@ -218,13 +218,6 @@ __global__ void k_convert(int64_t n, const double* __restrict__ a, T* __restrict
   if (i < n) b[i] = (T)a[i];
 }
 
-__global__ void k_check_nu(int64_t N, const int32_t* cnt, SolveState* st) {
-  if (threadIdx.x == 0 && cnt[N + 1] > 0) {
-    st->nonfinite = 2;
-    st->failed = 1;
-    st->stop = 1;
-  }
-}
 
 // body[m] must lie in [-1, M): anything else is an argument error.
 __global__ void k_check_body(int64_t N, int32_t M, const int32_t* __restrict__ body,
@@ -380,10 +373,6 @@ hipError_t launch_equilibrate(int64_t n, float* A, int64_t lda, float* dr, float
   return hipGetLastError();
 }
 
-hipError_t launch_check_nu(int64_t N, const int32_t* cnt, SolveState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_check_nu, dim3(1), dim3(64), 0, s, N, cnt, st);
-  return hipGetLastError();
-}
 
 hipError_t launch_check_body(int64_t N, int32_t M, const int32_t* body, SolveState* st,
                              hipStream_t s) {
