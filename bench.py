@@ -505,6 +505,8 @@ def main():
                     help="time only the channel configuration (profiling)")
     ap.add_argument("--field-only", action="store_true",
                     help="time only the flow-at-tracers workload (profiling)")
+    ap.add_argument("--block-only", action="store_true",
+                    help="time only the learned block-preconditioned GMRES form (profiling)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--calib-flops", action="store_true",
@@ -585,6 +587,37 @@ def main():
 
     if args.field_only:
         print(json.dumps({"field": run_field(ctx, nrs, synth, dev)}), flush=True)
+        return
+
+    def block_forms(Yref, names=("gmres_block_exact", "gmres_block_learned")):
+        # block-diagonal preconditioned GMRES from the previous stage's
+        # solution: exact body-block inverses, and the learned block model
+        # (Fourier fit in the beat phase of one filament's blocks)
+        from paper_2001_06468_amd import learned as learned_mod
+        bm = learned_mod.fit_block_model(ctx, synth.filament_scene(1, seed=0), S=48, H=6)
+        block_info = {"fit_s": bm.fit_seconds, "phases": 48, "harmonics": bm.H, "order": bm.nb,
+                      "source": "one filament in its own frame (the method's FP64 blocks)"}
+        out = {}
+        for name, opts in (("gmres_block_exact", {"precond": nrs.NRS_PRECOND_EXACT}),
+                           ("gmres_block_learned", {"precond": nrs.NRS_PRECOND_MODEL,
+                                                    "block_model": bm})):
+            if name not in names:
+                continue
+            fm, _, Yb, _, finfo = run_steps(nrs.NRS_GMRES_BLOCK, args.warmup, args.steps,
+                                            warm_start=nrs.NRS_WARM_PREVIOUS, **opts)
+            out[name] = {"solves_per_s": 4 * args.steps / (fm / 1e3),
+                         "ms_per_step": fm / args.steps,
+                         "ms_per_step_median": float(np.median(per_step)),
+                         "steps": args.steps, "fell_back": finfo["fell_back"],
+                         "max_stage_iterations_last_step": finfo["iterations"]}
+            if Yref is not None:
+                out[name]["max_abs_state_diff_vs_headline"] = float((Yb - Yref).abs().max())
+        if "gmres_block_learned" in out:
+            out["gmres_block_learned"]["model"] = block_info
+        return out
+
+    if args.block_only:
+        print(json.dumps({"forms": block_forms(None, ("gmres_block_learned",))}), flush=True)
         return
 
     if args.batch_only:
@@ -676,6 +709,14 @@ def main():
     as64_avg_ms = float(np.mean(as64_ms))
     asm64_tflops = asm_flops / (as64_avg_ms / 1e3) / 1e12
 
+    # the 512-system batch next, before the forms' training data and models
+    # take device memory (its workspace is about 14.5 GB)
+    batched = None
+    if args.batch > 0:
+        torch.cuda.empty_cache()
+        batched = run_batched(ctx, nrs, synth, args.batch, dev, tune=not args.no_tune)
+        torch.cuda.empty_cache()
+
     forms = {}
     learned_info = None
     if not args.no_forms:
@@ -710,33 +751,12 @@ def main():
             forms[name] = {"solves_per_s": 4 * k / (fm / 1e3), "steps": k,
                            "fell_back": finfo["fell_back"],
                            "max_stage_iterations_last_step": finfo["iterations"]}
-        # block-diagonal preconditioned GMRES from the previous stage's
-        # solution: exact body-block inverses, and the learned block model
-        # (Fourier fit in the beat phase of one filament's blocks)
-        from paper_2001_06468_amd import learned as learned_mod
-        bm = learned_mod.fit_block_model(ctx, synth.filament_scene(1, seed=0), S=48, H=6)
-        block_info = {"fit_s": bm.fit_seconds, "phases": 48, "harmonics": bm.H, "order": bm.nb,
-                      "source": "one filament in its own frame (the method's FP64 blocks)"}
-        for name, opts in (("gmres_block_exact", {"precond": nrs.NRS_PRECOND_EXACT}),
-                           ("gmres_block_learned", {"precond": nrs.NRS_PRECOND_MODEL,
-                                                    "block_model": bm})):
-            fm, _, Yb, _, finfo = run_steps(nrs.NRS_GMRES_BLOCK, args.warmup, args.steps,
-                                            warm_start=nrs.NRS_WARM_PREVIOUS, **opts)
-            forms[name] = {"solves_per_s": 4 * args.steps / (fm / 1e3),
-                           "ms_per_step": fm / args.steps,
-                           "ms_per_step_median": float(np.median(per_step)),
-                           "steps": args.steps, "fell_back": finfo["fell_back"],
-                           "max_stage_iterations_last_step": finfo["iterations"],
-                           "max_abs_state_diff_vs_headline": float((Yb - Y).abs().max())}
-        forms["gmres_block_learned"]["model"] = block_info
+        forms.update(block_forms(Y))
 
     small = None
     if not args.no_small:
         small = run_small(ctx, nrs, synth, dev)
 
-    batched = None
-    if args.batch > 0:
-        batched = run_batched(ctx, nrs, synth, args.batch, dev, tune=not args.no_tune)
 
     field = None
     if not args.no_field:
