@@ -709,15 +709,9 @@ def main():
     as64_avg_ms = float(np.mean(as64_ms))
     asm64_tflops = asm_flops / (as64_avg_ms / 1e3) / 1e12
 
-    # the 512-system batch next, before the forms' training data and models
-    # take device memory (its workspace is about 14.5 GB)
-    batched = None
-    if args.batch > 0:
-        torch.cuda.empty_cache()
-        batched = run_batched(ctx, nrs, synth, args.batch, dev, tune=not args.no_tune)
-        torch.cuda.empty_cache()
-
     forms = {}
+    small = None
+    batched = None
     learned_info = None
     if not args.no_forms:
         forms["dopri5_" + args.method] = run_dopri(ctx, nrs, ds, scene, dev, method)
@@ -739,6 +733,18 @@ def main():
             fm, _, _, _, finfo = run_steps(m, 1, k)
             forms[name] = {"solves_per_s": 4 * k / (fm / 1e3), "steps": k,
                            "fell_back": finfo["fell_back"]}
+    # Order: the light, latency-bound measurements first (the small
+    # configurations), then the 512-system batch (its 14.5 GB workspace
+    # before the training data take memory), then the sustained GPU work of
+    # the learned forms (training data of 20,000 solves), so that the short
+    # timings are not taken on a GPU that has been busy for tens of seconds.
+    if not args.no_small:
+        small = run_small(ctx, nrs, synth, dev)
+    if args.batch > 0:
+        torch.cuda.empty_cache()
+        batched = run_batched(ctx, nrs, synth, args.batch, dev, tune=not args.no_tune)
+        torch.cuda.empty_cache()
+    if not args.no_forms:
         # GMRES forms: cold, previous-solve warm start, learned warm start
         model, learned_info = train_model(ctx, nrs)
         body_off = nrs.nrs_mlp_body_offsets(ctx, ds.t["body"], M)
@@ -752,11 +758,6 @@ def main():
                            "fell_back": finfo["fell_back"],
                            "max_stage_iterations_last_step": finfo["iterations"]}
         forms.update(block_forms(Y))
-
-    small = None
-    if not args.no_small:
-        small = run_small(ctx, nrs, synth, dev)
-
 
     field = None
     if not args.no_field:

@@ -207,6 +207,59 @@ __global__ __launch_bounds__(kScanBlock) void k_csr_scan(int64_t N, int32_t* cnt
   if (tid == kScanBlock - 1) seg[N] = part[tid];
 }
 
+// Count, scan and scatter in one workgroup with the counters in LDS, for
+// N <= kCsrSmallN and Q <= kCsrSmallQ (the single-system workloads): the
+// same segments (seg) as the three-kernel path; the order inside a segment
+// is arbitrary until k_csr_finish sorts it.
+constexpr int64_t kCsrSmallN = 8192;
+constexpr int64_t kCsrSmallQ = 1 << 17;
+__global__ __launch_bounds__(kScanBlock) void k_csr_small(int64_t N, int64_t Q,
+                                                          const int32_t* __restrict__ nu,
+                                                          int32_t* __restrict__ seg,
+                                                          int32_t* __restrict__ perm,
+                                                          SolveState* st) {
+  __shared__ int32_t c[kCsrSmallN + 2];
+  __shared__ int32_t part[kScanBlock];
+  const int tid = threadIdx.x;
+  for (int64_t i = tid; i < N + 2; i += kScanBlock) c[i] = 0;
+  __syncthreads();
+  for (int64_t q = tid; q < Q; q += kScanBlock) {
+    const int32_t v = nu[q];
+    atomicAdd(&c[(v >= 0 && v < N) ? v : N + 1], 1);
+  }
+  __syncthreads();
+  if (tid == 0 && st && c[N + 1] > 0) {
+    st->nonfinite = 2;
+    st->failed = 1;
+    st->stop = 1;
+  }
+  const int64_t per = (N + kScanBlock - 1) / kScanBlock;
+  const int64_t a = tid * per, b = min<int64_t>(N, a + per);
+  int32_t sum = 0;
+  for (int64_t i = a; i < b; ++i) sum += c[i];
+  part[tid] = sum;
+  __syncthreads();
+  for (int off = 1; off < kScanBlock; off <<= 1) {
+    const int32_t v = tid >= off ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int32_t run = part[tid] - sum;
+  for (int64_t i = a; i < b; ++i) {
+    const int32_t k = c[i];
+    seg[i] = run;
+    c[i] = run;
+    run += k;
+  }
+  if (tid == kScanBlock - 1) seg[N] = part[tid];
+  __syncthreads();
+  for (int64_t q = tid; q < Q; q += kScanBlock) {
+    const int32_t v = nu[q];
+    if (v >= 0 && v < N) perm[atomicAdd(&c[v], 1)] = (int32_t)q;
+  }
+}
+
 __global__ void k_csr_scatter(int64_t N, int64_t Q, const int32_t* __restrict__ nu,
                               int32_t* cursor, int32_t* perm) {
   const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -341,15 +394,20 @@ hipError_t launch_fill_f64(double* p, double v, int64_t n, hipStream_t s) {
 
 hipError_t launch_build_csr(int64_t N, int64_t Q, const double* X, const double* w,
                             const int32_t* nu, Sorted& srt, SolveState* st, hipStream_t s) {
-  hipError_t e = launch_fill_i32(srt.cnt, 0, N + 2, s);
-  if (e != hipSuccess) return e;
-  if (Q > 0) {
-    hipLaunchKernelGGL(k_csr_count, grid1(Q, 256), dim3(256), 0, s, N, Q, nu, srt.cnt);
-  }
-  hipLaunchKernelGGL(k_csr_scan, dim3(1), dim3(kScanBlock), 0, s, N, srt.cnt, srt.seg, st);
-  if (Q > 0) {
-    hipLaunchKernelGGL(k_csr_scatter, grid1(Q, 256), dim3(256), 0, s, N, Q, nu, srt.cnt,
-                       srt.perm);
+  if (N <= kCsrSmallN && Q <= kCsrSmallQ) {
+    hipLaunchKernelGGL(k_csr_small, dim3(1), dim3(kScanBlock), 0, s, N, Q, nu, srt.seg, srt.perm,
+                       st);
+  } else {
+    hipError_t e = launch_fill_i32(srt.cnt, 0, N + 2, s);
+    if (e != hipSuccess) return e;
+    if (Q > 0) {
+      hipLaunchKernelGGL(k_csr_count, grid1(Q, 256), dim3(256), 0, s, N, Q, nu, srt.cnt);
+    }
+    hipLaunchKernelGGL(k_csr_scan, dim3(1), dim3(kScanBlock), 0, s, N, srt.cnt, srt.seg, st);
+    if (Q > 0) {
+      hipLaunchKernelGGL(k_csr_scatter, grid1(Q, 256), dim3(256), 0, s, N, Q, nu, srt.cnt,
+                         srt.perm);
+    }
   }
   hipLaunchKernelGGL(k_csr_finish, dim3((unsigned)((N + kFinishWaves - 1) / kFinishWaves)),
                      dim3(kFinishWaves * 64), 0, s, N, Q, srt.seg, srt.perm, X, w, srt.nus, srt.X64,
