@@ -644,7 +644,10 @@ def main():
     # --- one synchronous solve of the seeded initial state (accuracy check
     # against the oracle in the CPU leg) on the product's own geometry -------
     pb, u = device_problem(ctx, nrs, ds, scene, 0.0, Y0d, dev)
-    ws1 = torch.empty(nrs.nrs_workspace_size(ctx, N, Q, M, method), dtype=torch.uint8, device=dev)
+    # sized for the solve's method and for the FP32 assembly timed below
+    ws1 = torch.empty(max(nrs.nrs_workspace_size(ctx, N, Q, M, method),
+                          nrs.nrs_workspace_size(ctx, N, Q, M, nrs.NRS_FP32_IR)),
+                      dtype=torch.uint8, device=dev)
     sol = torch.empty(n, dtype=torch.float64, device=dev)
     sinfo = nrs.nrs_solve(ctx, pb, u, None, sol, ws1, method=method)
     s = sol.cpu().numpy()

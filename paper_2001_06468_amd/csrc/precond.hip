@@ -325,15 +325,17 @@ __global__ __launch_bounds__(kPrecThreads) void k_prec_block(GmresArgs a, int64_
   __shared__ double vb[kBlockMax];
   __shared__ double part[kPrecThreads / 128][kBlockMax];
   const GmresState* st = a.st;
-  if (st->halt) return;
-  const int k = st->k;
   const int32_t b = blockIdx.x;
+  // independent loads together: the state words and the body's range
+  const int32_t halt = st->halt;
+  const int k = st->k;
   const int nb = body_order(off, b, N, nb_lim, nb_model);
-  if (nb == 0) return;
+  if (halt || nb == 0) return;
   const int nbp = (nb - 6) / 3;
   const int64_t lo = off[b];
   const int tid = threadIdx.x, tx = tid & 127, ty = tid >> 7;
-  for (int r = tid; r < nb; r += kPrecThreads) vb[r] = a.V[block_row(r, nbp, N, lo, b) * kGmresLd + k];
+  // v_k from zv, which holds it on every row (written with V[:, k])
+  for (int r = tid; r < nb; r += kPrecThreads) vb[r] = zv[block_row(r, nbp, N, lo, b)];
   __syncthreads();
   // B row-major at Y + 12 b + 3: lab = B body, body = B^T lab.  The
   // 3-vectors of the block: point g < nbp at (g, nbp + g, 2 nbp + g), then
