@@ -216,7 +216,8 @@ def run_field(ctx, nrs, synth, dev, reps=40):
 def run_channel(ctx, nrs, synth, dev, sizes=((10, 16), (40, 24))):
     """Channel configuration (10 and 40 sperm-like swimmers in the 4 x 1 x 0.5
     channel, wall spacing 1/16 and 1/24, n = 14,244 and 39,504): one
-    synchronous solve each with the GMRES-IR forms after a warm-up solve, and
+    synchronous solve each with the GMRES-IR forms (and, at K = 10, the FP64
+    partial-pivoting form) after a warm-up solve, and
     the tile LU alone (FP32 updates, and BF16-input updates) timed with HIP
     events.  Geometry and nearest map on the GPU."""
     import torch
@@ -230,7 +231,8 @@ def run_channel(ctx, nrs, synth, dev, sizes=((10, 16), (40, 24))):
         rec = {"workload": f"sperm_K{K}_h{h}", "N": pb.N, "Q": pb.Q, "n": n, "solves": {}}
         methods = [("fp32_gmres_ir", nrs.NRS_FP32_GMRES_IR)]
         if K == 10:
-            methods.append(("bf16_gmres_ir", nrs.NRS_BF16_GMRES_IR))
+            # and the plain FP64 form (partial pivoting) as the reference rate
+            methods += [("bf16_gmres_ir", nrs.NRS_BF16_GMRES_IR), ("fp64_lu", nrs.NRS_FP64_LU)]
         wsz = max(nrs.nrs_workspace_size(ctx, pb.N, pb.Q, pb.M, m) for _, m in methods)
         ws = torch.empty(wsz, dtype=torch.uint8, device=dev)
         sol = torch.empty(n, dtype=torch.float64, device=dev)
