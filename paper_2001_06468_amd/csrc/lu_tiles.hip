@@ -6,6 +6,8 @@
 // one task, in "band" m = min(i, j):
 //   update : C = A_ij - sum_{k<m} L_ik U_kj   (matrix cores, 16x16x4 MFMA),
 //            each rank-64 term folded in as soon as its two tiles are final;
+//            in the FP32 forms the two tiles of a term go from memory
+//            straight into LDS (global-to-LDS loads), one term ahead;
 //   then    i == j : partial pivoting inside the tile (one wavefront, rows in
 //                    registers, pivot rows relabelled instead of moved);
 //           i <  j : U_mj = L_mm^-1 P_m C   (one lane per column);
@@ -46,7 +48,6 @@ constexpr int kWaitVmem = 0x0F70;
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-constexpr int kL16 = 72;  // LDS row stride (bf16) of the BF16 staging tiles
 
 template <class T>
 struct Mf;
@@ -130,17 +131,28 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// LDS of a task.  Cs is the working tile and Ws the staging tile of the
+// diagonal factors (L_mm for the column solves and the diagonal panels, U_mm
+// for the row solves: never both in one task).  During the update loop they
+// are the two stages that hold the operand tiles of consecutive rank-64
+// terms (L part first, then U part).  Two separate fields, so that the
+// compiler can tell their accesses apart.
+// The small fields come first, so that they stay within the 64 KB reach of
+// an LDS instruction's immediate offset.
 template <class T>
 struct Shared {
-  T Cs[TB * kCS];
   T row[TB];
   int32_t perm[TB];
   int32_t pos[TB];
   int32_t task[4];
   uint64_t live[2];  // diagonal tile, per panel parity: bit r set while row r is no pivot
-  T Ls[TB * kLS];
-  T Us[TB * kLS];
+  alignas(16) T Cs[2 * TB * TB];
+  alignas(16) T Ws[2 * TB * TB];
 };
+static_assert(TB * kCS <= 2 * TB * TB && TB * kLS <= 2 * TB * TB, "working tiles fit a stage");
+
+template <class T>
+__device__ inline T* stage_of(Shared<T>& S, int stage) { return stage ? S.Ws : S.Cs; }
 
 template <class T>
 __device__ inline T pivot_inverse(T piv) {
@@ -179,7 +191,7 @@ __device__ __attribute__((noinline)) void diag_factor(Shared<T>& S, const LuSys<
 #pragma unroll
   for (int b = 0; b < TB / kPW; ++b) {
     const int c0 = b * kPW;
-    T* Lp = S.Ls + (b & 1) * kPW * kPW;  // [k][k2]: multiplier of pivot k2 at panel column k
+    T* Lp = S.Ws + (b & 1) * kPW * kPW;  // [k][k2]: multiplier of pivot k2 at panel column k
     if (w == 0) {
       wave_sync();  // this panel's columns were last written in MFMA layout
       T v[kPW];
@@ -269,7 +281,7 @@ __device__ __attribute__((noinline)) void diag_factor(Shared<T>& S, const LuSys<
 }
 
 // U_mj = L_mm^-1 P_m C, in place in the working tile S.Cs; L_mm (unit lower)
-// is staged column-major in S.Ls, the permutation in S.perm.  Called by all
+// is staged column-major in S.Ws, the permutation in S.perm.  Called by all
 // four waves; wave w owns columns 16w..16w+15 and needs no other wave: per
 // block of 16 rows, a substitution with the diagonal block (one lane per
 // column) and then the rows below on the matrix cores.
@@ -297,7 +309,7 @@ __device__ __attribute__((noinline)) void col_solve(Shared<T>& S) {
 #pragma unroll
       for (int k = 0; k < 16; ++k)
 #pragma unroll
-        for (int k2 = k + 1; k2 < 16; ++k2) x[k2] -= S.Ls[(rb + k) * kLS + rb + k2] * x[k];
+        for (int k2 = k + 1; k2 < 16; ++k2) x[k2] -= S.Ws[(rb + k) * kLS + rb + k2] * x[k];
 #pragma unroll
       for (int k = 0; k < 16; ++k) col[rb + k] = x[k];
     }
@@ -310,7 +322,7 @@ __device__ __attribute__((noinline)) void col_solve(Shared<T>& S) {
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
         const int k = rb + ks * 4 + g;
-        acc = Mf<T>::run(-S.Ls[k * kLS + rt * 16 + (lane & 15)], col[k], acc);
+        acc = Mf<T>::run(-S.Ws[k * kLS + rt * 16 + (lane & 15)], col[k], acc);
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) col[rt * 16 + Mf<T>::row(lane, r)] = acc[r];
@@ -319,7 +331,7 @@ __device__ __attribute__((noinline)) void col_solve(Shared<T>& S) {
 }
 
 // L_im = C U_mm^-1, in place in S.Cs.  With U = D Uh (D its diagonal, Uh unit
-// upper), Y = C Uh^-1 and L = Y D^-1.  S.Us holds Uh row-major, S.row the
+// upper), Y = C Uh^-1 and L = Y D^-1.  S.Ws holds Uh row-major, S.row the
 // reciprocals of D.  Called by all four waves; wave w owns rows 16w..16w+15:
 // per block of 16 columns, a substitution with the diagonal block (one lane
 // per row) and then the columns to the right on the matrix cores.
@@ -339,7 +351,7 @@ __device__ __attribute__((noinline)) void row_solve(Shared<T>& S) {
 #pragma unroll
       for (int k = 0; k < 16; ++k)
 #pragma unroll
-        for (int k2 = k + 1; k2 < 16; ++k2) y[k2] -= y[k] * S.Us[(cb + k) * kLS + cb + k2];
+        for (int k2 = k + 1; k2 < 16; ++k2) y[k2] -= y[k] * S.Ws[(cb + k) * kLS + cb + k2];
 #pragma unroll
       for (int k = 0; k < 16; ++k) S.Cs[(cb + k) * kCS + r0 + lane] = y[k];
     }
@@ -353,7 +365,7 @@ __device__ __attribute__((noinline)) void row_solve(Shared<T>& S) {
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
         const int k = cb + ks * 4 + g;
-        acc = Mf<T>::run(-S.Cs[k * kCS + r0 + (lane & 15)], S.Us[k * kLS + ct * 16 + (lane & 15)],
+        acc = Mf<T>::run(-S.Cs[k * kCS + r0 + (lane & 15)], S.Ws[k * kLS + ct * 16 + (lane & 15)],
                          acc);
       }
 #pragma unroll
@@ -420,7 +432,7 @@ __device__ inline int64_t published_run(const LuSys<T>& sy, int64_t i, int64_t j
   return e;
 }
 
-// Slot of U(k, c) in the update loop's staging tile S.Us: rows of 64, the
+// Slot of U(k, c) in the register-staged update loop's U tile (S.Ws): rows of 64, the
 // column XOR-swizzled by a rotation of the row index, so that the
 // transposing stores (one row per lane) and the matrix-core reads (16
 // columns of 4 rows) each touch 64 different banks.
@@ -463,16 +475,71 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
     // every term whose two tiles are already published ([k, kend)), and inside
     // such a run the tiles of term k+1 are loaded while term k runs on the
     // matrix cores.
-    if constexpr (B16) {
-      // BF16 inputs: the tiles' BF16 copies (L_ik as [row][k], U_kj as
-      // [column][k]) staged in LDS with k contiguous, so that each lane reads
-      // its eight k values of a 16x16x32 matrix-core step with one load.
-      __bf16* L16 = reinterpret_cast<__bf16*>(S.Ls);
-      __bf16* U16 = reinterpret_cast<__bf16*>(S.Us);
+    if constexpr (std::is_same<T, float>::value) {
+      // FP32 A: each term's two operand tiles go from memory straight into
+      // LDS (16-byte global-to-LDS loads, no registers), the next term's into
+      // the other stage while the current one runs on the matrix cores; one
+      // barrier per term.  Term k uses stage (k + m) % 2, so the last term
+      // reads stage 1 (Ws) and the working tile (stage 0, Cs) is free once it
+      // ends.
+      // In both layouts the 16-byte chunks are XOR-swizzled so that each
+      // matrix-core operand read touches every LDS bank once.
+      //   FP32 operands (A's columns), 64 floats per k or per column:
+      //     L part: (k, row) at k*64 + 4*((row/4) ^ 4*(k%4)) + row%4
+      //     U part: (k, col) at 4096 + col*64 + 4*((k/4) ^ (col%16)) + k%4
+      //     L rows past the order read the padding rows of A's columns (lda
+      //     is a multiple of 64) and U columns past the order repeat column
+      //     n-1; both only reach entries of the product outside the matrix,
+      //     which C below does not take.  k < m <= nt-1, so the term's L
+      //     columns and U rows lie inside the matrix.
+      //   BF16 operands (the tiles' copies: L_ik as [row][k], U_kj as
+      //     [column][k], 64 values per row, zero past the order):
+      //     row r, chunk c (8 values) at r*64 + 8*(c ^ ((r/2) % 8)),
+      //     U part 4096 values further.
+      const int sub = lane >> 4, li = lane & 15;
       const __bf16* sh = reinterpret_cast<const __bf16*>(sy.sh);
-      uint4 lq[2], uq[2];
+      auto issue = [&](int64_t k, int stage) {
+        if constexpr (B16) {
+          const __bf16* Lt = sh + (i * nt + k) * (TB * TB);
+          const __bf16* Ut = sh + (k * nt + j) * (TB * TB);
+          __bf16* Lb = reinterpret_cast<__bf16*>(stage_of(S, stage));
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int q = w * 2 + h, r = 8 * q + (lane >> 3);
+            const int c = (lane & 7) ^ ((r >> 1) & 7);
+            __builtin_amdgcn_global_load_lds(Lt + r * TB + 8 * c, Lb + q * 512, 16, 0, 0);
+            __builtin_amdgcn_global_load_lds(Ut + r * TB + 8 * c, Lb + TB * TB + q * 512, 16, 0, 0);
+          }
+        } else {
+          float* Lb = stage_of(S, stage);
+          const int p = lane & 15;
+#pragma unroll
+          for (int q4 = 0; q4 < 4; ++q4) {
+            const int q = w * 4 + q4, kc = 4 * q + sub;
+            const float* gl = A + (i * TB + 4 * (p ^ (4 * sub))) + (k * TB + kc) * lda;
+            __builtin_amdgcn_global_load_lds(gl, Lb + q * 256, 16, 0, 0);
+            const int64_t cg = min(j * TB + kc, n - 1);
+            const float* gu = A + (k * TB + 4 * (p ^ (kc & 15))) + cg * lda;
+            __builtin_amdgcn_global_load_lds(gu, Lb + TB * TB + q * 256, 16, 0, 0);
+          }
+        }
+      };
+      // per-lane parts of the operand addresses
+      int la0, la1, lb0, lb1;
+      if constexpr (B16) {  // rows qi + li, qi + 16 + li (L) and qj + li, qj + 16 + li (U)
+        la0 = (qi + li) * TB;
+        la1 = (qi + 16 + li) * TB;
+        lb0 = TB * TB + (qj + li) * TB;
+        lb1 = TB * TB + (qj + 16 + li) * TB;
+      } else {  // L rows qi + li, qi + 16 + li at k = kk + sub; U columns qj + li, qj + 16 + li
+        la0 = sub * TB + 4 * (((qi + li) >> 2) ^ (4 * sub)) + (li & 3);
+        la1 = sub * TB + 4 * (((qi + 16 + li) >> 2) ^ (4 * sub)) + (li & 3);
+        lb0 = TB * TB + (qj + li) * TB + sub;
+        lb1 = TB * TB + (qj + 16 + li) * TB + sub;
+      }
       int64_t kend = 0;
       for (int64_t k = 0; k < m; ++k) {
+        const int stage = (int)((k + m) & 1);
         if (k >= kend) {
           if (w == 0) {
             const int64_t e = published_run(sy, i, j, k, m, err, lane);
@@ -480,45 +547,45 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
           }
           __syncthreads();
           kend = S.task[2];
-          const uint4* Lt = reinterpret_cast<const uint4*>(sh + (i * nt + k) * (TB * TB));
-          const uint4* Ut = reinterpret_cast<const uint4*>(sh + (k * nt + j) * (TB * TB));
+          issue(k, stage);
+        }
+        __builtin_amdgcn_s_waitcnt(kWaitVmem);  // this wave's share of term k has landed
+        __syncthreads();  // all shares landed; term k-1's reads of the other stage are done
+        if (k + 1 < kend) issue(k + 1, stage ^ 1);
+        if constexpr (B16) {
+          const __bf16* Sb = reinterpret_cast<const __bf16*>(stage_of(S, stage));
+          const int key = (li >> 1) & 7;
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            lq[h] = Lt[tid + h * kLuThreads];
-            uq[h] = Ut[tid + h * kLuThreads];
+          for (int kk = 0; kk < TB; kk += 32) {
+            const int c = 8 * ((kk / 8 + sub) ^ key);
+            const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(Sb + la0 + c);
+            const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(Sb + la1 + c);
+            const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(Sb + lb0 + c);
+            const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(Sb + lb1 + c);
+            acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
           }
-        }
-        __syncthreads();  // the previous term's reads of the staging tiles are done
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int q = tid + h * kLuThreads, row = q >> 3, k0 = (q & 7) * 8;
-          *reinterpret_cast<uint4*>(L16 + row * kL16 + k0) = lq[h];
-          *reinterpret_cast<uint4*>(U16 + row * kL16 + k0) = uq[h];
-        }
-        __syncthreads();
-        if (k + 1 < kend) {  // next term's tiles, in flight during this one
-          const uint4* Lt = reinterpret_cast<const uint4*>(sh + (i * nt + k + 1) * (TB * TB));
-          const uint4* Ut = reinterpret_cast<const uint4*>(sh + ((k + 1) * nt + j) * (TB * TB));
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            lq[h] = Lt[tid + h * kLuThreads];
-            uq[h] = Ut[tid + h * kLuThreads];
+        } else {
+          const float* Sb = stage_of(S, stage);
+#pragma unroll 4
+          for (int kk = 0; kk < TB; kk += 4) {
+            const int ub = 4 * ((kk >> 2) ^ li);
+            const float a0 = Sb[la0 + kk * TB], a1 = Sb[la1 + kk * TB];
+            const float b0 = Sb[lb0 + ub], b1 = Sb[lb1 + ub];
+            acc[0][0] = Mf<T>::run(a0, b0, acc[0][0]);
+            acc[0][1] = Mf<T>::run(a0, b1, acc[0][1]);
+            acc[1][0] = Mf<T>::run(a1, b0, acc[1][0]);
+            acc[1][1] = Mf<T>::run(a1, b1, acc[1][1]);
           }
-        }
-#pragma unroll
-        for (int kk = 0; kk < TB; kk += 32) {
-          const int li = lane & 15, kg = kk + 8 * (lane >> 4);
-          const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(L16 + (qi + li) * kL16 + kg);
-          const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(L16 + (qi + 16 + li) * kL16 + kg);
-          const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(U16 + (qj + li) * kL16 + kg);
-          const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(U16 + (qj + 16 + li) * kL16 + kg);
-          acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
-          acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
-          acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
-          acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
         }
       }
     } else {
+    // FP64: the tiles pass through registers (loaded one term ahead) into
+    // the staging tiles, L in Cs (kLS layout) and U in Ws
+    T* Ls = S.Cs;
+    T* Us = S.Ws;
     const int r = tid & 63, c0 = tid >> 6;
     T la[16], ua[16];
     int64_t kend = 0;
@@ -537,12 +604,12 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
           ua[q] = ld_pad(A, lda, n, k * TB + r, j * TB + c);
         }
       }
-      __syncthreads();  // the previous term's reads of S.Ls / S.Us are done
+      __syncthreads();  // the previous term's reads of the staging tiles are done
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int c = c0 + 4 * q;
-        S.Ls[c * kLS + r] = la[q];
-        S.Us[us_at(r, c)] = ua[q];
+        Ls[c * kLS + r] = la[q];
+        Us[us_at(r, c)] = ua[q];
       }
       __syncthreads();
       if (k + 1 < kend) {  // next term's tiles, in flight during this one
@@ -556,16 +623,18 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
 #pragma unroll 4
       for (int kk = 0; kk < TB; kk += 4) {
         const int kr = kk + (lane >> 4), li = lane & 15;
-        const T a0 = S.Ls[kr * kLS + qi + li], a1 = S.Ls[kr * kLS + qi + 16 + li];
-        const T b0 = S.Us[us_at(kr, qj + li)], b1 = S.Us[us_at(kr, qj + 16 + li)];
+        const T a0 = Ls[kr * kLS + qi + li], a1 = Ls[kr * kLS + qi + 16 + li];
+        const T b0 = Us[us_at(kr, qj + li)], b1 = Us[us_at(kr, qj + 16 + li)];
         acc[0][0] = Mf<T>::run(a0, b0, acc[0][0]);
         acc[0][1] = Mf<T>::run(a0, b1, acc[0][1]);
         acc[1][0] = Mf<T>::run(a1, b0, acc[1][0]);
         acc[1][1] = Mf<T>::run(a1, b1, acc[1][1]);
       }
     }
+    __syncthreads();  // the last term's reads of the stages are done: Cs is stage 0
     }
-    // ---- C = A_ij - acc into the working tile ----
+    // ---- C = A_ij - acc into the working tile (entries outside the matrix
+    // keep the padding of A: the products there are not used) ----
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -574,7 +643,9 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
         for (int r = 0; r < 4; ++r) {
           const int rr = qi + a * 16 + Mf<T>::row(lane, r);
           const int cc = qj + b * 16 + (lane & 15);
-          S.Cs[cc * kCS + rr] = a_ij[(a * 2 + b) * 4 + r] - acc[a][b][r];
+          const T v = a_ij[(a * 2 + b) * 4 + r];
+          S.Cs[cc * kCS + rr] =
+              (i * TB + rr < n && j * TB + cc < n) ? v - acc[a][b][r] : v;
         }
     if (i != j) {
       if (tid == 0) {
@@ -598,7 +669,7 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
 #pragma unroll
         for (int q = 0; q < TB * TB / kLuThreads; ++q) {
           const int e = tid + q * kLuThreads, r = e % TB, c = e / TB;
-          S.Ls[c * kLS + r] = la[q];
+          S.Ws[c * kLS + r] = la[q];
         }
       }
       if (tid < TB) {
@@ -621,7 +692,7 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
 #pragma unroll
         for (int q = 0; q < TB * TB / kLuThreads; ++q) {
           const int e = tid + q * kLuThreads, r = e % TB, c = e / TB;
-          S.Us[r * kLS + c] = ua[q] / S.row[r];
+          S.Ws[r * kLS + c] = ua[q] / S.row[r];
         }
         __syncthreads();
         if (tid < TB) S.row[tid] = T(1) / S.row[tid];
@@ -769,20 +840,18 @@ void lu_task_prefix(const int32_t* nts, int32_t B, std::vector<int32_t>& pref, i
 template <class T>
 hipError_t launch_lu_tiles(const LuBatch<T>& bt, int32_t* ctl, hipStream_t s) {
   if (bt.total <= 0) return hipSuccess;
+  const dim3 grid((unsigned)bt.total), block(kLuThreads);
   if (bt.sys) {
-    hipLaunchKernelGGL((k_lu_tiles<T, 2, false>), dim3((unsigned)bt.total), dim3(kLuThreads), 0, s,
-                       bt, ctl);
+    hipLaunchKernelGGL((k_lu_tiles<T, 2, false>), grid, block, 0, s, bt, ctl);
     return hipGetLastError();
   }
   if constexpr (std::is_same<T, float>::value) {
     if (bt.one.sh) {
-      hipLaunchKernelGGL((k_lu_tiles<float, 1, true>), dim3((unsigned)bt.total), dim3(kLuThreads),
-                         0, s, bt, ctl);
+      hipLaunchKernelGGL((k_lu_tiles<float, 1, true>), grid, block, 0, s, bt, ctl);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_lu_tiles<T, 1, false>), dim3((unsigned)bt.total), dim3(kLuThreads), 0, s,
-                     bt, ctl);
+  hipLaunchKernelGGL((k_lu_tiles<T, 1, false>), grid, block, 0, s, bt, ctl);
   return hipGetLastError();
 }
 
