@@ -568,16 +568,32 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
             acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
           }
         } else {
+          // operands read two matrix-core steps ahead (the scheduling groups
+          // keep each step's reads in front of the products two steps back),
+          // so the LDS latency overlaps the matrix-core work
           const float* Sb = stage_of(S, stage);
-#pragma unroll 4
-          for (int kk = 0; kk < TB; kk += 4) {
-            const int ub = 4 * ((kk >> 2) ^ li);
-            const float a0 = Sb[la0 + kk * TB], a1 = Sb[la1 + kk * TB];
-            const float b0 = Sb[lb0 + ub], b1 = Sb[lb1 + ub];
-            acc[0][0] = Mf<T>::run(a0, b0, acc[0][0]);
-            acc[0][1] = Mf<T>::run(a0, b1, acc[0][1]);
-            acc[1][0] = Mf<T>::run(a1, b0, acc[1][0]);
-            acc[1][1] = Mf<T>::run(a1, b1, acc[1][1]);
+          float a0[TB / 4], a1[TB / 4], b0[TB / 4], b1[TB / 4];
+          auto rd = [&](int t) {
+            const int ub = 4 * (t ^ li);
+            a0[t] = Sb[la0 + 4 * t * TB];
+            a1[t] = Sb[la1 + 4 * t * TB];
+            b0[t] = Sb[lb0 + ub];
+            b1[t] = Sb[lb1 + ub];
+          };
+          rd(0);
+          rd(1);
+          __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+#pragma unroll
+          for (int t = 0; t < TB / 4; ++t) {
+            if (t + 2 < TB / 4) {
+              rd(t + 2);
+              __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+            }
+            acc[0][0] = Mf<T>::run(a0[t], b0[t], acc[0][0]);
+            acc[0][1] = Mf<T>::run(a0[t], b1[t], acc[0][1]);
+            acc[1][0] = Mf<T>::run(a1[t], b0[t], acc[1][0]);
+            acc[1][1] = Mf<T>::run(a1[t], b1[t], acc[1][1]);
+            __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
           }
         }
       }
