@@ -36,7 +36,7 @@ PEAK_FP64_TFLOPS = 78.6
 # HBM bytes per launch of the tile LU at n = 3150 from the FETCH_SIZE and
 # WRITE_SIZE counter runs (calibrated against a 256 MiB copy), valid only for
 # the kernel source they were taken on (first 16 hex digits of its SHA-256).
-LU_TRAFFIC = {"source_sha256_16": "27adf9ab58c1e98f", "bytes_per_launch": 790281869, "n": 3150}
+LU_TRAFFIC = {"source_sha256_16": "d576eb3e9389374c", "bytes_per_launch": 798823646, "n": 3150}
 # HBM bytes per nrs_field_velocity call (sources + pair sum + chunk sum) on the
 # tracer workload, from the same two counter runs, valid for that field.hip.
 FIELD_TRAFFIC = {"source_sha256_16": "7f18d8d2f998ad7c", "bytes_per_call": 24459390, "Q": 73248,
@@ -47,12 +47,12 @@ FIELD_TRAFFIC = {"source_sha256_16": "7f18d8d2f998ad7c", "bytes_per_call": 24459
 # scaled by what it reads for a kernel of known work run in the same
 # process), valid only for the kernel source they were taken on.
 COUNTERS = {
-    "lu": {"source": "lu_tiles.hip", "source_sha256_16": "27adf9ab58c1e98f", "n": 3150,
-           "mfma_flops_per_launch": 2.169e10, "mfma_busy": 0.073,
-           "calibration": "FP32 4096^3 matrix product: 0.954 busy at 150 TFLOP/s"},
-    "assembly": {"source": "assemble.hip", "source_sha256_16": "b51c98c8db4067b2", "N": 1000,
-                 "Q": 10000, "valu_fp32_flops_per_call": 4.055e8,
-                 "fp32_rsqrt_per_call": 1.02e7, "valu_fp64_flops_per_call": 6.513e8,
+    "lu": {"source": "lu_tiles.hip", "source_sha256_16": "d576eb3e9389374c", "n": 3150,
+           "mfma_flops_per_launch": 2.169e10, "mfma_busy": 0.075,
+           "calibration": "FP32 4096^3 matrix product: 0.961 busy at 151 TFLOP/s"},
+    "assembly": {"source": "assemble.hip", "source_sha256_16": "e4b7a436078fef13", "N": 1000,
+                 "Q": 10000, "valu_fp32_flops_per_call": 4.061e8,
+                 "fp32_rsqrt_per_call": 1.05e7, "valu_fp64_flops_per_call": 6.517e8,
                  "fp64_transcendental_per_call": 2.05e7,
                  "calibration": "elementwise multiplies of 2^26 elements read 2^20: x 64"},
 }
@@ -485,6 +485,20 @@ def run_batched(ctx, nrs, synth, B, dev, reps=3, tune=True):
                     "instances; lu_equiv_tflops = sum of (2/3) n^3 over the batch time"}
 
 
+def run_batched_child(args):
+    """run_batched in a fresh process (`bench.py --batch-only`); its JSON."""
+    import subprocess
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--batch-only",
+           "--batch", str(args.batch)] + (["--no-tune"] if args.no_tune else [])
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError(f"batched benchmark failed ({r.returncode}):\n{r.stderr[-2000:]}")
+    line = [ln for ln in r.stdout.splitlines() if ln.startswith("{")][-1]
+    out = json.loads(line)["batched"]
+    out["process"] = "child (bench.py --batch-only)"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -718,15 +732,14 @@ def main():
     small = None
     batched = None
     learned_info = None
-    # The 512-system batch first: its per-system kernels run on four streams,
-    # and after the first cooperative launch in a process (the multi-workgroup
-    # partial-pivoting panel of the fp64_lu and fp32_gepp_ir forms, also used
-    # by the small configurations) this runtime overlaps such streams less:
-    # the same batch then takes about 295 instead of 241 ms.
+    # The 512-system batch runs in a child process of its own: its per-system
+    # kernels use four streams, and in one process with the cooperative
+    # launches of the partial-pivoting panel (fp64_lu, fp32_gepp_ir, the
+    # small configurations) this runtime slows both: the batch after a
+    # cooperative launch takes about 295 instead of 241 ms, and the FP64
+    # partial-pivoting forms after the batch lose about a quarter.
     if args.batch > 0:
-        torch.cuda.empty_cache()
-        batched = run_batched(ctx, nrs, synth, args.batch, dev, tune=not args.no_tune)
-        torch.cuda.empty_cache()
+        batched = run_batched_child(args)
     if not args.no_forms:
         forms["dopri5_" + args.method] = run_dopri(ctx, nrs, ds, scene, dev, method)
         if method == nrs.NRS_FP32_IR:
