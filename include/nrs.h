@@ -228,6 +228,17 @@ typedef struct {
   int32_t precond_nb;
   const double* precond_model;
   const double* precond_phase;
+  /* nrs_rk4_step / nrs_rk4_step_tracers with NRS_FP32_IR or NRS_FP32_GEPP_IR
+     (stages that factor): correction sweeps queued per stage before the
+     step's one host check.  0 (default): adaptive, the largest number of
+     sweeps a stage needed in the previous step on the same workspace plus
+     one (max_refine while unknown); k > 0: k.  Never more than max_refine
+     (<= 0: 4).  A step whose stages miss the tolerance with fewer than
+     max_refine sweeps queued is redone with max_refine before the FP64
+     fallback, so the result is that of max_refine queued sweeps; sweeps
+     queued after convergence skip their work but still cost their launches.
+     Ignored by every other call and with reuse_stage_factors. */
+  int32_t ir_queue;
 } nrs_options;
 
 typedef struct {

@@ -190,7 +190,7 @@ class BlockModel:
 def _options(method=NRS_FP64_LU, max_refine=0, tol=0.0, gmres_restart=0, gmres_max_iter=0,
              no_fallback=0, x_init=None, warm_start=NRS_WARM_NONE, model=None, body_off=None,
              x_init_complete=0, graph=0, reuse_stage_factors=0, equilibrate=0,
-             precond=NRS_PRECOND_EXACT, block_model=None, precond_phase=None):
+             precond=NRS_PRECOND_EXACT, block_model=None, precond_phase=None, ir_queue=0):
     sc = (C.c_double * 3)(*(model.scales if model is not None else (0.0, 0.0, 0.0)))
     bm = block_model
     return NrsOptions(method, max_refine, tol, gmres_restart, gmres_max_iter, no_fallback,
@@ -200,7 +200,7 @@ def _options(method=NRS_FP64_LU, max_refine=0, tol=0.0, gmres_restart=0, gmres_m
                       int(graph), int(reuse_stage_factors), int(equilibrate), int(precond),
                       bm.H if bm is not None else 0, bm.nb if bm is not None else 0,
                       _ptr(bm.coef, torch.float64, "block model") if bm is not None else None,
-                      _ptr(precond_phase, torch.float64, "precond_phase"))
+                      _ptr(precond_phase, torch.float64, "precond_phase"), int(ir_queue))
 
 
 def nrs_geometry(ctx, scene, t, Y, x=None, X=None, w=None, u=None):

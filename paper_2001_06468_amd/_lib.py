@@ -60,7 +60,7 @@ class NrsOptions(C.Structure):
                 ("model_scales", C.c_double * 3), ("body_off", _p), ("x_init_complete", _i32),
                 ("graph", _i32), ("reuse_stage_factors", _i32), ("equilibrate", _i32),
                 ("precond", _i32), ("precond_harmonics", _i32), ("precond_nb", _i32),
-                ("precond_model", _p), ("precond_phase", _p)]
+                ("precond_model", _p), ("precond_phase", _p), ("ir_queue", _i32)]
 
 
 class NrsInfo(C.Structure):

@@ -1328,16 +1328,41 @@ nrs_status nrs_rk4_step_tracers(nrs_ctx* ctx, const nrs_scene* sc, int32_t G,
       return fail(ctx, NRS_E_ARG, "model scales must be positive");
     if ((st = ctx_dev_flags(ctx)) != NRS_OK) return st;
   }
+  if (o.ir_queue < 0) return fail(ctx, NRS_E_ARG, "ir_queue must be >= 0");
   const bool prev_valid = ctx->rk_prev_ws == ws;
+  const int32_t hint = prev_valid ? ctx->rk_sweeps : 0;
   ctx->rk_prev_ws = nullptr;
-  if ((st = rk4_pass(ctx, *sc, gt, groupX, eps, mu, ftext, Y, ytr, t, dt, o, rb, prev_valid)) !=
+  ctx->rk_sweeps = 0;
+  // correction sweeps queued per stage of the factoring refinement forms:
+  // ir_queue, else the previous step's largest need plus one (the step's one
+  // host check below learns it), never more than max_refine
+  const int32_t full = o.max_refine > 0 ? o.max_refine : 4;
+  const bool adapt = (o.method == NRS_FP32_IR || o.method == NRS_FP32_GEPP_IR) &&
+                     !o.reuse_stage_factors && !o.no_fallback;
+  nrs_options oq = o;
+  if (adapt) oq.max_refine = std::min(full, o.ir_queue > 0 ? o.ir_queue : (hint > 0 ? hint + 1 : full));
+  if ((st = rk4_pass(ctx, *sc, gt, groupX, eps, mu, ftext, Y, ytr, t, dt, oq, rb, prev_valid)) !=
       NRS_OK)
     return st;
   ctx->rk_prev_ws = ws;
   if (o.no_fallback || o.method == NRS_FP64_LU) return NRS_OK;
   SolveState h;
   if ((st = read_state(ctx, rb.report, h)) != NRS_OK) return st;
-  if (!h.failed) return NRS_OK;
+  if (h.failed && adapt && oq.max_refine < full && !h.nonfinite && !h.sync_err) {
+    // the queue was too short for a stage: the step again with max_refine sweeps
+    NRS_HIP(ctx, hipMemcpyAsync(Y, rb.Ysave, 12 * sizeof(double) * sc->M, hipMemcpyDeviceToDevice, s));
+    if (P > 0)
+      NRS_HIP(ctx, hipMemcpyAsync(ytr, rb.ysave, 3 * sizeof(double) * P, hipMemcpyDeviceToDevice, s));
+    oq.max_refine = full;
+    if ((st = rk4_pass(ctx, *sc, gt, groupX, eps, mu, ftext, Y, ytr, t, dt, oq, rb, prev_valid)) !=
+        NRS_OK)
+      return st;
+    if ((st = read_state(ctx, rb.report, h)) != NRS_OK) return st;
+  }
+  if (!h.failed) {
+    if (adapt) ctx->rk_sweeps = std::max(1, h.iterations - 1);
+    return NRS_OK;
+  }
   // a stage missed its tolerance: redo the whole step with FP64 LU
   NRS_HIP(ctx, hipMemcpyAsync(Y, rb.Ysave, 12 * sizeof(double) * sc->M, hipMemcpyDeviceToDevice, s));
   if (P > 0)

@@ -51,6 +51,9 @@ struct nrs_ctx {
   // workspace of the last completed nrs_rk4_step (its solution seeds the next
   // step's first GMRES solve under NRS_WARM_PREVIOUS)
   const void* rk_prev_ws = nullptr;
+  // correction sweeps the stages of that step needed at most (0: unknown);
+  // sizes the adaptive refinement queue of the next step
+  int32_t rk_sweeps = 0;
   // captured batched solves, oldest first (at most kMaxGraphs)
   std::vector<nrs_graph_entry> graphs;
   // autotuned assembly shapes by size class

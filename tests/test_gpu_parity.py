@@ -447,6 +447,45 @@ def test_rk4_headline_trajectory_matches_oracle(ctx, method):
         assert err <= 1e-10, (step, err)
 
 
+def test_rk4_refinement_queue(ctx):
+    """The refinement sweeps an RK4 step queues per stage (nrs_options.
+    ir_queue): the adaptive default (the previous step's need plus one), a
+    queue of one sweep under a tolerance that needs two (the step is redone
+    with max_refine sweeps, no FP64 fallback) and the full queue of
+    max_refine give bit-identical states (five filaments, n = 630, four
+    steps each)."""
+    scene = synth.filament_scene(5, seed=0)
+    ds = nrs.DeviceScene(scene)
+    m = nrs.NRS_FP32_IR
+    dt = 2 * math.pi / 100
+
+    def run(tol, queue):
+        ws = torch.empty(nrs.nrs_rk4_workspace_size(ctx, ds, m), dtype=torch.uint8, device=DEV)
+        Y = T(scene["Y0"])
+        its = []
+        for step in range(4):
+            nrs.nrs_rk4_step(ctx, ds, Y, step * dt, dt, ws, method=m, tol=tol, max_refine=4,
+                             ir_queue=queue)
+            info = nrs.nrs_query_info(ctx, ws)
+            assert info["fell_back"] == 0, (tol, queue, step, info)
+            its.append(info["iterations"])
+        return Y.cpu().numpy(), its
+
+    for tol in (0.0, 1e-13):
+        full, its_full = run(tol, 4)
+        adaptive, its_adapt = run(tol, 0)
+        one, its_one = run(tol, 1)
+        print(f"tol {tol}: updates per stage {its_full} / {its_adapt} / {its_one}", flush=True)
+        assert its_adapt == its_full and its_one == its_full
+        assert np.array_equal(adaptive, full) and np.array_equal(one, full)
+    # the tight tolerance needs two corrections per stage, so the one-sweep
+    # queue went through the redo
+    assert max(its_full) >= 3, its_full
+    with pytest.raises(nrs.NrsError, match="ir_queue"):
+        ws = torch.empty(nrs.nrs_rk4_workspace_size(ctx, ds, m), dtype=torch.uint8, device=DEV)
+        nrs.nrs_rk4_step(ctx, ds, T(scene["Y0"]), 0.0, dt, ws, method=m, ir_queue=-1)
+
+
 def test_rk4_stage_factor_reuse_at_headline_size(ctx):
     """25 filaments (n = 3150): three RK4 steps with stages 2-4 refined
     against the first stage's factors agree with refactoring every stage to
