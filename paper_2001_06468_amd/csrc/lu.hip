@@ -398,70 +398,143 @@ struct Mfma<double> {
 };
 
 constexpr int kGT = 128;       // output tile edge per workgroup
-constexpr int kGK = 32;        // k-chunk staged in LDS
-constexpr int kGPad = 16;      // LDS row padding (elements)
-constexpr int kGS = kGT + kGPad;
+constexpr int kGK = 64;        // the panel width: every update is rank 64 (K <= kGK)
+constexpr int kGES = kGT + 2;  // column stride of the epilogue tile
 
-// C (m x nc) -= A (m x K) * B (K x nc); all column-major with leading dim lda.
-// 256 threads = 2 x 2 waves, each wave a 64 x 64 sub-tile of 4 x 4 MFMA blocks.
-// MFMA 16x16x4 operand layout: lane l holds A[l%16][l/16] and B[l/16][l%16];
-// the output row of register r is Mfma<T>::row(l, r), the column l%16.
+// LDS of one update tile: the A panel [kGK][kGT] and the B panel [kGT][kGK]
+// (k contiguous per column) in 16-byte chunks of E elements, XOR-swizzled so
+// that each matrix-core operand read touches every bank once:
+//   A: (k, row) at k*kGT + E*((row/E) ^ sa(k)) + row%E,  sa = 8(k%2) (FP64), 4(k%4) (FP32)
+//   B: (k, col) at kGK*kGT + col*kGK + E*((k/E) ^ (col%16)) + k%E
+// then the output tile [col][row] (stride kGES) for the coalesced epilogue.
+template <class T>
+struct GemmLds {
+  static constexpr int E = 16 / (int)sizeof(T);
+  static constexpr int kSize =
+      2 * kGK * kGT > kGT * kGES ? 2 * kGK * kGT : kGT * kGES;
+  static __device__ inline int sa(int k) { return sizeof(T) == 8 ? 8 * (k & 1) : 4 * (k & 3); }
+  static __device__ inline int a_at(int k, int row) {
+    return k * kGT + E * ((row / E) ^ sa(k)) + row % E;
+  }
+  static __device__ inline int b_at(int k, int col) {
+    return kGK * kGT + col * kGK + E * ((k / E) ^ (col & 15)) + k % E;
+  }
+};
+
+// The A and B panels of an interior tile straight into LDS: each wave-wide
+// 16-byte global-to-LDS load fills 1 KB (64 lanes x one chunk) in the layout
+// of GemmLds; returns once this wave's loads have landed.
+template <class T>
+__device__ inline void gemm_panels_lds(T* S, const T* __restrict__ Ap, const T* __restrict__ Bp,
+                                       int64_t lda, int64_t i0, int64_t j0, int wid, int lane) {
+  typedef GemmLds<T> G;
+  constexpr int E = G::E;
+  constexpr int kPer = 1024 / (int)sizeof(T);   // elements per wave-wide load
+  constexpr int kLoads = kGK * kGT / kPer;       // per panel
+  for (int q = wid; q < kLoads; q += 4) {
+    const int e = q * kPer + lane * E;           // A: (k, slot) of this lane
+    const int k = e / kGT, p = (e % kGT) / E;
+    const T* g = Ap + (i0 + E * (p ^ G::sa(k))) + (int64_t)k * lda;
+    __builtin_amdgcn_global_load_lds(g, S + q * kPer, 16, 0, 0);
+  }
+  for (int q = wid; q < kLoads; q += 4) {
+    const int e = q * kPer + lane * E;           // B: (column, slot) of this lane
+    const int col = e / kGK, p = (e % kGK) / E;
+    const T* g = Bp + E * (p ^ (col & 15)) + (j0 + col) * lda;
+    __builtin_amdgcn_global_load_lds(g, S + kGK * kGT + q * kPer, 16, 0, 0);
+  }
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+}
+
+// C (m x nc) -= A (m x K) * B (K x nc); all column-major with leading dim lda,
+// K <= kGK.  256 threads = 2 x 2 waves, each wave a 64 x 64 sub-tile of 4 x 4
+// MFMA blocks.  MFMA 16x16x4 operand layout: lane l holds A[l%16][l/16] and
+// B[l/16][l%16]; the output row of register r is Mfma<T>::row(l, r), the
+// column l%16.  Interior tiles of a full panel (dma != 0: 16-byte aligned
+// panels) load both panels with 16-byte global-to-LDS loads; edge tiles load
+// element by element with zeros outside.  The products run over k up to K
+// rounded up to 32, in increasing k, and C is updated through LDS one column
+// per 64 lanes.
 template <class T>
 __global__ __launch_bounds__(256) void k_gemm_update(int64_t m, int64_t nc, int K,
                                                      const T* __restrict__ Ap,
                                                      const T* __restrict__ Bp,
-                                                     T* __restrict__ C, int64_t lda) {
-  __shared__ T As[kGK * kGS];
-  __shared__ T Bs[kGK * kGS];
+                                                     T* __restrict__ C, int64_t lda, int dma) {
+  typedef GemmLds<T> G;
+  constexpr int E = G::E;
+  __shared__ __align__(16) T S[G::kSize];
   typedef typename Mfma<T>::acc_t acc_t;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int64_t i0 = blockIdx.x * (int64_t)kGT, j0 = blockIdx.y * (int64_t)kGT;
   const int wr = (wid >> 1) * 64, wc = (wid & 1) * 64;
-  acc_t acc[4][4];
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b)
-      for (int r = 0; r < 4; ++r) acc[a][b][r] = T(0);
-  for (int kc = 0; kc < K; kc += kGK) {
-    {  // A tile: 128 rows x kGK columns -> As[kk][row]
-      const int row = tid & 127, cg = tid >> 7;
+  if (dma && K == kGK && i0 + kGT <= m && j0 + kGT <= nc) {
+    gemm_panels_lds<T>(S, Ap, Bp, lda, i0, j0, wid, lane);
+  } else {
+    for (int e = tid; e < kGK * kGT; e += 256) {   // A: rows fastest (coalesced)
+      const int row = e % kGT, k = e / kGT;
       const int64_t gi = i0 + row;
-      for (int c = cg; c < kGK; c += 2) {
-        const int gk = kc + c;
-        T v = T(0);
-        if (gi < m && gk < K) v = Ap[gi + (int64_t)gk * lda];
-        As[c * kGS + row] = v;
-      }
+      S[G::a_at(k, row)] = (gi < m && k < K) ? Ap[gi + (int64_t)k * lda] : T(0);
     }
-    {  // B tile: kGK rows x 128 columns -> Bs[kk][col]
-      const int kk = tid & (kGK - 1), cg = tid / kGK;
-      const int gk = kc + kk;
-      for (int c = cg; c < kGT; c += 256 / kGK) {
-        const int64_t gj = j0 + c;
-        T v = T(0);
-        if (gj < nc && gk < K) v = Bp[gk + gj * lda];
-        Bs[kk * kGS + c] = v;
-      }
+    for (int e = tid; e < kGK * kGT; e += 256) {   // B: k fastest (coalesced)
+      const int k = e % kGK, col = e / kGK;
+      const int64_t gj = j0 + col;
+      S[G::b_at(k, col)] = (gj < nc && k < K) ? Bp[k + gj * lda] : T(0);
     }
-    __syncthreads();
-    for (int kk = 0; kk < kGK; kk += 4) {
-      const int kr = kk + (lane >> 4), li = lane & 15;
-      T av[4], bv[4];
-      for (int a = 0; a < 4; ++a) av[a] = As[kr * kGS + wr + a * 16 + li];
-      for (int b = 0; b < 4; ++b) bv[b] = Bs[kr * kGS + wc + b * 16 + li];
-      for (int a = 0; a < 4; ++a)
-        for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::run(av[a], bv[b], acc[a][b]);
-    }
-    __syncthreads();
   }
-  const int lc = lane & 15;
-  for (int a = 0; a < 4; ++a) {
-    for (int b = 0; b < 4; ++b) {
-      const int64_t gj = j0 + wc + b * 16 + lc;
-      if (gj >= nc) continue;
-      T* cc = C + gj * lda;
-      for (int r = 0; r < 4; ++r) {
-        const int64_t gi = i0 + wr + a * 16 + Mfma<T>::row(lane, r);
-        if (gi < m) cc[gi] -= acc[a][b][r];
+  __syncthreads();
+  acc_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[a][b][r] = T(0);
+  const int kend = ((K + 31) / 32) * 32;
+  const int li = lane & 15;
+  for (int kk = 0; kk < kend; kk += 4) {
+    const int kr = kk + (lane >> 4);
+    T av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) av[a] = S[G::a_at(kr, wr + a * 16 + li)];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bv[b] = S[G::b_at(kr, wc + b * 16 + li)];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = Mfma<T>::run(av[a], bv[b], acc[a][b]);
+  }
+  __syncthreads();  // every operand read is done: the tile becomes the output
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        S[(wc + b * 16 + li) * kGES + wr + a * 16 + Mfma<T>::row(lane, r)] = acc[a][b][r];
+  __syncthreads();
+  // C -= tile, 16 of the wave's columns at a time: every load of a batch is
+  // issued before its stores (C's columns could alias for the compiler, so a
+  // store would otherwise hold back the next column's load)
+  constexpr int kBatch = 16;
+  for (int c0 = 0; c0 < kGT / 4; c0 += kBatch) {
+    T cv[kBatch][kGT / 64];
+#pragma unroll
+    for (int t = 0; t < kBatch; ++t) {
+      const int64_t gj = j0 + wid + 4 * (c0 + t);
+#pragma unroll
+      for (int h = 0; h < kGT / 64; ++h) {
+        const int64_t gi = i0 + 64 * h + lane;
+        cv[t][h] = (gj < nc && gi < m) ? C[gi + gj * lda] : T(0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kBatch; ++t) {
+      const int col = wid + 4 * (c0 + t);
+      const int64_t gj = j0 + col;
+#pragma unroll
+      for (int h = 0; h < kGT / 64; ++h) {
+        const int64_t gi = i0 + 64 * h + lane;
+        if (gj < nc && gi < m) C[gi + gj * lda] = cv[t][h] - S[col * kGES + 64 * h + lane];
       }
     }
   }
@@ -1048,9 +1121,12 @@ hipError_t launch_lu_factor(int64_t n, T* A, int64_t lda, int32_t* ipiv, int32_t
     const int64_t rest = n - k - jb;
     if (rest > 0) {
       dim3 g((unsigned)((rest + kGT - 1) / kGT), (unsigned)((rest + kGT - 1) / kGT));
+      // global-to-LDS panel loads need 16-byte aligned panels
+      const int E = 16 / (int)sizeof(T);
+      const int dma = ((uintptr_t)A % 16 == 0 && lda % E == 0 && (k + jb) % E == 0 && k % E == 0);
       hipLaunchKernelGGL(k_gemm_update<T>, g, dim3(256), 0, s, rest, rest, jb,
                          A + (k + jb) + k * lda, A + k + (k + jb) * lda,
-                         A + (k + jb) + (k + jb) * lda, lda);
+                         A + (k + jb) + (k + jb) * lda, lda, dma);
     }
   }
   return hipGetLastError();
