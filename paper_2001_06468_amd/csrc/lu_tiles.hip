@@ -40,6 +40,16 @@ constexpr int kLuThreads = 256;
 constexpr int kLS = 80;  // LDS row stride of the MFMA staging tiles
 constexpr int kCS = 65;  // LDS column stride of the working tile
 constexpr int64_t kLuSpin = 1 << 22;
+// A single FP32 system of at most this many tile rows runs one workgroup per
+// CU: its launch reserves kLuSoloPad bytes of unused dynamic LDS, so a
+// workgroup needs more than half of the CU's 160 KB.  Its time is the latency
+// of the diagonal chain, and a second workgroup on the chain task's CU slows
+// the pivot steps; at larger orders the update throughput of two workgroups
+// per CU wins (measured, two per CU -> one: n = 3150 1.83 -> 1.73 ms, n = 6300
+// 4.10 -> 3.67 ms, n = 8000 5.69 -> 5.65 ms, n = 10,000 8.78 -> 10.0 ms,
+// n = 14,244 21.6 -> 25.4 ms).
+constexpr int64_t kLuSoloTiles = 112;
+constexpr unsigned kLuSoloPad = 16 * 1024;
 // s_waitcnt operand that waits for vmcnt = 0 and leaves expcnt and lgkmcnt at
 // their maxima (gfx9 layout: vmcnt in bits 3:0 and 15:14, expcnt 6:4,
 // lgkmcnt 11:8).
@@ -861,13 +871,14 @@ hipError_t launch_lu_tiles(const LuBatch<T>& bt, int32_t* ctl, hipStream_t s) {
     hipLaunchKernelGGL((k_lu_tiles<T, 2, false>), grid, block, 0, s, bt, ctl);
     return hipGetLastError();
   }
+  const unsigned pad = (std::is_same<T, float>::value && bt.one.nt <= kLuSoloTiles) ? kLuSoloPad : 0;
   if constexpr (std::is_same<T, float>::value) {
     if (bt.one.sh) {
-      hipLaunchKernelGGL((k_lu_tiles<float, 1, true>), grid, block, 0, s, bt, ctl);
+      hipLaunchKernelGGL((k_lu_tiles<float, 1, true>), grid, block, pad, s, bt, ctl);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_lu_tiles<T, 1, false>), grid, block, 0, s, bt, ctl);
+  hipLaunchKernelGGL((k_lu_tiles<T, 1, false>), grid, block, pad, s, bt, ctl);
   return hipGetLastError();
 }
 
