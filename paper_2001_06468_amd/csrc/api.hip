@@ -220,7 +220,7 @@ nrs_status run_fp64_lu(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, do
 // residuals use the matrix-free FP64 operator.
 nrs_status run_fp32_ir(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, double* x,
                        int32_t scope, int32_t max_refine, double tol, bool norm, bool equil,
-                       hipStream_t s) {
+                       hipStream_t s, bool b32_ready = false) {
   const int64_t n = 3 * pb.N + 6 * (int64_t)pb.M;
   NRS_HIP(ctx, launch_assemble<float>(pb, sb.srt, sb.A32, sb.lda, s,
                                       asm_shape_for(ctx, pb.N, pb.Q, 32)));
@@ -232,9 +232,10 @@ nrs_status run_fp32_ir(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, do
   NRS_HIP(ctx, lu_factor_any<float>(n, scope, sb.A32, sb.lda, sb.ipiv, sb.perm,
                                      &sb.st->singular, sb.lu_done, sb.st->lu_ctl, s,
                                      scope == 1 ? sb.sh : nullptr, sb.gepp));
-  // x0 = D_c (LU)^-1 D_r b
+  // x0 = D_c (LU)^-1 D_r b (b32_ready: the right-hand side kernel wrote the
+  // unscaled FP32 copy already)
   float* b32 = reinterpret_cast<float*>(sb.r);  // r is free until the first residual
-  NRS_HIP(ctx, launch_convert_f32(n, sb.b, b32, s, er));
+  if (!b32_ready || equil) NRS_HIP(ctx, launch_convert_f32(n, sb.b, b32, s, er));
   NRS_HIP(ctx, launch_lu_solve<float>(n, scope, sb.A32, sb.lda, sb.perm, b32, sb.d32, sb.tsync,
                                       &sb.st->sync_err, &sb.st->stop, s));
   NRS_HIP(ctx, launch_ir_update32(n, x, sb.d32, tol, 1, sb.st, s, ec));
@@ -252,13 +253,13 @@ nrs_status run_fp32_ir(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, do
 // earlier, nearby system): x0 from them, then FP64 matrix-free residuals of
 // this system and correction sweeps; queued sweeps after convergence skip.
 nrs_status run_fp32_reuse(nrs_ctx* ctx, const nrs_problem& pb, SolveBuffers& sb, double* x,
-                          int32_t max_refine, double tol, hipStream_t s) {
+                          int32_t max_refine, double tol, hipStream_t s, bool b32_ready = false) {
   const int64_t n = 3 * pb.N + 6 * (int64_t)pb.M;
   // the factors (and their scale factors, if equilibrated) of the earlier system
   const float* er = sb.equil ? sb.eqr : nullptr;
   const float* ec = sb.equil ? sb.eqc : nullptr;
   float* b32 = reinterpret_cast<float*>(sb.r);
-  NRS_HIP(ctx, launch_convert_f32(n, sb.b, b32, s, er));
+  if (!b32_ready || sb.equil) NRS_HIP(ctx, launch_convert_f32(n, sb.b, b32, s, er));
   NRS_HIP(ctx, launch_lu_solve<float>(n, 1, sb.A32, sb.lda, sb.perm, b32, sb.d32, sb.tsync,
                                       &sb.st->sync_err, &sb.st->stop, s));
   NRS_HIP(ctx, launch_ir_update32(n, x, sb.d32, tol, 1, sb.st, s, ec));
@@ -539,17 +540,22 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
   const int32_t method = o.method;
   const int32_t max_refine = o.max_refine > 0 ? o.max_refine : 4;
   const double tol = o.tol > 0 ? o.tol : 1e-9;
-  NRS_HIP(ctx, launch_state_init(sb.st, method, s));
-  if (method != NRS_GMRES_BLOCK) {   // synchronisation words of the factorisation paths
-    NRS_HIP(ctx, launch_fill_i32(sb.tsync, 0, trsv_sync_ints(n), s));
-    NRS_HIP(ctx, launch_fill_i32(sb.lu_done, 0, lu_tiles_nt(n) * lu_tiles_nt(n), s));
-  }
+  // the status record and (factorisation paths) the synchronisation words
+  const bool fact = method != NRS_GMRES_BLOCK;
+  NRS_HIP(ctx, launch_solve_begin(sb.st, method, fact ? sb.tsync : nullptr,
+                                  fact ? trsv_sync_ints(n) : 0, fact ? sb.lu_done : nullptr,
+                                  fact ? lu_tiles_nt(n) * lu_tiles_nt(n) : 0, s));
   NRS_HIP(ctx, launch_build_csr(N, Q, pb.X, pb.w, pb.nu, sb.srt, sb.st, s));
-  NRS_HIP(ctx, launch_check_body(N, pb.M, pb.body, sb.st, s));
-  NRS_HIP(ctx, launch_rhs(N, pb.M, u, ftext, sb.b, s));
+  // the right-hand side with the body check; the FP32 forms that factor the
+  // unscaled matrix also get its FP32 copy here
+  const bool b32_ready =
+      uses_fp32(method) &&
+      !(reuse ? sb.equil : (method != NRS_FP32_GEPP_IR && o.equilibrate != 0));
+  NRS_HIP(ctx, launch_rhs(N, pb.M, u, ftext, sb.b, s,
+                          b32_ready ? reinterpret_cast<float*>(sb.r) : nullptr, pb.body, sb.st));
   nrs_status st = NRS_OK;
   if (reuse) {
-    st = run_fp32_reuse(ctx, pb, sb, sol, o.max_refine > 0 ? o.max_refine : 12, tol, s);
+    st = run_fp32_reuse(ctx, pb, sb, sol, o.max_refine > 0 ? o.max_refine : 12, tol, s, b32_ready);
   } else if (method == NRS_FP64_LU) {
     st = run_fp64_lu(ctx, pb, sb, sol, sync, s);
   } else if (uses_fp32(method)) {
@@ -558,7 +564,7 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
     // pivoted form factors A itself
     const bool gepp = method == NRS_FP32_GEPP_IR;
     st = run_fp32_ir(ctx, pb, sb, sol, gepp ? 0 : 1, fgm ? 0 : max_refine, tol, sync,
-                     !gepp && o.equilibrate != 0, s);
+                     !gepp && o.equilibrate != 0, s, b32_ready);
     if (st == NRS_OK && fgm) st = run_fgmres(ctx, pb, sb, sol, o, s);
   } else if (method == NRS_GMRES) {
     st = run_gmres(ctx, pb, sb, sol, o, sync, s);
@@ -1154,7 +1160,7 @@ bool carve_rk(Arena& ar, const nrs_scene& sc, int32_t method, int64_t P, RkBuffe
 nrs_status stage_solve(nrs_ctx* ctx, const nrs_scene& sc, const GroupTable& gt,
                        const int32_t* groupX, double eps, double mu, const double* ftext,
                        double tt, const nrs_options& o, RkBuffers& rb, bool warm, double* Kout,
-                       bool reuse = false) {
+                       bool reuse = false, const double* Ynext = nullptr, double anext = 0.0) {
   hipStream_t s = ctx->stream;
   NRS_HIP(ctx, launch_geometry(sc, tt, rb.Ys, rb.x, rb.X, rb.w, rb.u, s));
   NRS_HIP(ctx, launch_nearest(sc.N, rb.x, gt, sc.Q, rb.X, groupX, rb.nu, s));
@@ -1191,8 +1197,9 @@ nrs_status stage_solve(nrs_ctx* ctx, const nrs_scene& sc, const GroupTable& gt,
   }
   nrs_status st = solve_core(ctx, pb, rb.u, ftext, os, rb.sb, rb.sol, false, nullptr, reuse);
   if (st != NRS_OK) return st;
-  NRS_HIP(ctx, launch_state_accumulate(rb.report, rb.sb.st, s));
-  NRS_HIP(ctx, launch_rk_rates(sc.M, sc.N, rb.Ys, rb.sol, Kout, s));
+  // the report, the rates and (Ynext) the next RK4 stage's state
+  NRS_HIP(ctx, launch_stage_end(rb.report, rb.sb.st, sc.M, sc.N, rb.Ys, rb.sol, Kout, Ynext, anext,
+                                s));
   return NRS_OK;
 }
 
@@ -1203,12 +1210,14 @@ nrs_status rk4_pass(nrs_ctx* ctx, const nrs_scene& sc, const GroupTable& gt,
   hipStream_t s = ctx->stream;
   const double c[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
   NRS_HIP(ctx, launch_state_init(rb.report, o.method, s));
+  // stage 1 starts from Y; the end of stages 1-3 forms the next stage's state
+  NRS_HIP(ctx, launch_rk_stage_state(sc.M, Y, nullptr, 0.0, rb.Ys, s));
   for (int stg = 0; stg < 4; ++stg) {
-    NRS_HIP(ctx, launch_rk_stage_state(sc.M, Y, stg ? rb.K[stg - 1] : nullptr, c[stg], rb.Ys, s));
     // stages 2-4 may refine against the first stage's FP32 factors
     const bool reuse = stg > 0 && o.reuse_stage_factors && o.method == NRS_FP32_IR;
     nrs_status st = stage_solve(ctx, sc, gt, groupX, eps, mu, ftext, t + c[stg], o, rb,
-                                stg > 0 || prev_valid, rb.K[stg], reuse);
+                                stg > 0 || prev_valid, rb.K[stg], reuse, stg < 3 ? Y : nullptr,
+                                stg < 3 ? c[stg + 1] : 0.0);
     if (st != NRS_OK) return st;
     if (rb.P > 0) {
       // this stage's flow (its geometry and forces) at the tracers' stage positions

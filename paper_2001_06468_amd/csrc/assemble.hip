@@ -216,15 +216,22 @@ __global__ __launch_bounds__(kAsmBlock) void k_assemble64(
   }
 }
 
+// b = [u; f_ext or 0]; with b32 != NULL also its FP32 copy; with st != NULL
+// also the body-index check (body[m] in [-1, M), else an argument error).
 __global__ void k_rhs(int64_t N, int32_t M, const double* __restrict__ u,
-                      const double* __restrict__ ft, double* __restrict__ b) {
+                      const double* __restrict__ ft, double* __restrict__ b,
+                      float* __restrict__ b32, const int32_t* __restrict__ body, SolveState* st) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t n = 3 * N + 6 * (int64_t)M;
+  if (st && i < N && (body[i] < -1 || body[i] >= M)) {
+    st->nonfinite = 2;
+    st->failed = 1;
+    st->stop = 1;
+  }
   if (i >= n) return;
-  if (i < 3 * N)
-    b[i] = u[i];
-  else
-    b[i] = ft ? ft[i - 3 * N] : 0.0;
+  const double v = i < 3 * N ? u[i] : (ft ? ft[i - 3 * N] : 0.0);
+  b[i] = v;
+  if (b32) b32[i] = (float)v;
 }
 
 constexpr int kApplyThreads = 256;
@@ -404,9 +411,10 @@ template hipError_t launch_assemble<double>(const nrs_problem&, const Sorted&, d
                                             hipStream_t, int32_t);
 
 hipError_t launch_rhs(int64_t N, int32_t M, const double* u, const double* ftext, double* b,
-                      hipStream_t s) {
+                      hipStream_t s, float* b32, const int32_t* body, SolveState* st) {
   const int64_t n = 3 * N + 6 * (int64_t)M;
-  hipLaunchKernelGGL(k_rhs, grid1(n, 256), dim3(256), 0, s, N, M, u, ftext, b);
+  hipLaunchKernelGGL(k_rhs, grid1(std::max(n, st ? N : 0), 256), dim3(256), 0, s, N, M, u, ftext,
+                     b, b32, body, st);
   return hipGetLastError();
 }
 

@@ -196,16 +196,15 @@ nrs_status enqueue_batch(nrs_ctx* ctx, int32_t B, const nrs_problem* problems,
     SolveBuffers& sb = L.sb[k];
     const int64_t n = 3 * p.N + 6 * (int64_t)p.M;
     hipStream_t s = lane_stream(ctx, k);
-    NRS_BHIP(ctx, launch_state_init(sb.st, NRS_FP32_IR, s));
-    NRS_BHIP(ctx, launch_fill_i32(sb.tsync, 0, trsv_sync_ints(n), s));
-    NRS_BHIP(ctx, launch_fill_i32(sb.lu_done, 0, lu_tiles_nt(n) * lu_tiles_nt(n), s));
+    NRS_BHIP(ctx, launch_solve_begin(sb.st, NRS_FP32_IR, sb.tsync, trsv_sync_ints(n), sb.lu_done,
+                                     lu_tiles_nt(n) * lu_tiles_nt(n), s));
     NRS_BHIP(ctx, launch_build_csr(p.N, p.Q, p.X, p.w, p.nu, sb.srt, sb.st, s));
-    NRS_BHIP(ctx, launch_check_body(p.N, p.M, p.body, sb.st, s));
-    NRS_BHIP(ctx, launch_rhs(p.N, p.M, u[k], ftext ? ftext[k] : nullptr, sb.b, s));
+    // the right-hand side, its FP32 copy and the body check in one launch
+    NRS_BHIP(ctx, launch_rhs(p.N, p.M, u[k], ftext ? ftext[k] : nullptr, sb.b, s,
+                             reinterpret_cast<float*>(sb.r), p.body, sb.st));
     NRS_BHIP(ctx, launch_assemble<float>(p, sb.srt, sb.A32, sb.lda, s,
                                          asm_shape_for(ctx, p.N, p.Q, 32)));
     if (norm) NRS_BHIP(ctx, launch_anorm32(n, sb.A32, sb.lda, sb.st, sb.red, s));
-    NRS_BHIP(ctx, launch_convert_f32(n, sb.b, reinterpret_cast<float*>(sb.r), s));
   }
   if ((st = join_aux(ctx))) return st;
 

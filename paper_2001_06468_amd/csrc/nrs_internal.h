@@ -426,7 +426,8 @@ template <class T>
 hipError_t launch_assemble(const nrs_problem& pb, const Sorted& srt, T* A, int64_t lda,
                            hipStream_t s, int32_t shape = -1);
 hipError_t launch_rhs(int64_t N, int32_t M, const double* u, const double* ftext, double* b,
-                      hipStream_t s);
+                      hipStream_t s, float* b32 = nullptr, const int32_t* body = nullptr,
+                      SolveState* st = nullptr);
 hipError_t launch_apply(const nrs_problem& pb, const Sorted& srt, const double* v, double* y,
                         double* part, int32_t chunks, const int32_t* stop, hipStream_t s);
 template <class T>
@@ -497,6 +498,13 @@ hipError_t launch_equilibrate(int64_t n, float* A, int64_t lda, float* dr, float
 hipError_t launch_check_body(int64_t N, int32_t M, const int32_t* body, SolveState* st,
                              hipStream_t s);
 hipError_t launch_state_accumulate(SolveState* total, const SolveState* stage, hipStream_t s);
+// a solve's status record and its two synchronisation-word arrays in one launch
+hipError_t launch_solve_begin(SolveState* st, int32_t method, int32_t* a, int64_t na, int32_t* b,
+                              int64_t nb, hipStream_t s);
+// the end of an RK stage: report, body rates, and (Y != NULL) Ys = Y + a K
+hipError_t launch_stage_end(SolveState* total, const SolveState* stage, int32_t M, int64_t N,
+                            double* Ys, const double* sol, double* K, const double* Y, double a,
+                            hipStream_t s);
 
 // time stepping
 hipError_t launch_rk_stage_state(int32_t M, const double* Y, const double* K, double a,

@@ -26,16 +26,33 @@ __device__ inline void wave_terms(const double* __restrict__ wave, int p, double
   ddt[2] = 0.0;
 }
 
-// mode 0: force points -> positions and prescribed velocities
-// mode 1: quadrature points -> positions and weights
-__global__ void k_geometry(int64_t n, int mode, int32_t M, int32_t P,
-                           const double* __restrict__ xi,
-                           const int32_t* __restrict__ body, const int32_t* __restrict__ part,
-                           const double* __restrict__ s, const double* __restrict__ aux,
-                           const double* __restrict__ wave, const double* __restrict__ Y,
-                           double t, double* __restrict__ pos, double* __restrict__ out2) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
+// One point set of a scene for k_geometry.  mode 0: force points ->
+// positions and prescribed velocities; mode 1: quadrature points ->
+// positions and weights.
+struct GeomSet {
+  int64_t n;
+  int32_t mode;
+  const double* xi;
+  const int32_t* body;
+  const int32_t* part;
+  const double* s;
+  const double* aux;
+  double* pos;
+  double* out2;
+};
+
+__device__ inline void geometry_point(const GeomSet& g, int64_t i, int32_t M, int32_t P,
+                                      const double* __restrict__ wave,
+                                      const double* __restrict__ Y, double t) {
+  const int64_t n = g.n;
+  const int mode = g.mode;
+  const double* __restrict__ xi = g.xi;
+  const int32_t* __restrict__ body = g.body;
+  const int32_t* __restrict__ part = g.part;
+  const double* __restrict__ s = g.s;
+  const double* __restrict__ aux = g.aux;
+  double* __restrict__ pos = g.pos;
+  double* __restrict__ out2 = g.out2;
   double p[3] = {xi[i], xi[n + i], xi[2 * n + i]};
   double d[3] = {0, 0, 0}, dds[3] = {0, 0, 0}, ddt[3] = {0, 0, 0};
   // out-of-range indices are treated as "none" (no wave / fixed point)
@@ -81,6 +98,18 @@ __global__ void k_geometry(int64_t n, int mode, int32_t M, int32_t P,
       out2[i] = w;
     }
   }
+}
+
+// Both point sets of a scene in one launch: the first nb0 workgroups take
+// set 0 (force points), the rest set 1 (quadrature points).
+__global__ void k_geometry(GeomSet g0, GeomSet g1, int64_t nb0, int32_t M, int32_t P,
+                           const double* __restrict__ wave, const double* __restrict__ Y,
+                           double t) {
+  const bool first = blockIdx.x < nb0;
+  const GeomSet& g = first ? g0 : g1;
+  const int64_t i = (blockIdx.x - (first ? 0 : nb0)) * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  geometry_point(g, i, M, P, wave, Y, t);
 }
 
 // One thread per quadrature point; force points of the block's groups are
@@ -357,18 +386,12 @@ inline dim3 grid1(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)); 
 
 hipError_t launch_geometry(const nrs_scene& sc, double t, const double* Y, double* x, double* X,
                            double* w, double* u, hipStream_t s) {
-  if (sc.N > 0 && (x || u)) {
-    hipLaunchKernelGGL(k_geometry, grid1(sc.N, 256), dim3(256), 0, s, sc.N, 0, sc.M, sc.P, sc.xi,
-                       sc.body,
-                       sc.part, sc.s, sc.ufix, sc.wave, Y, t, x, u);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  if (sc.Q > 0 && (X || w)) {
-    hipLaunchKernelGGL(k_geometry, grid1(sc.Q, 256), dim3(256), 0, s, sc.Q, 1, sc.M, sc.P, sc.Xi,
-                       sc.bodyX,
-                       sc.partX, sc.sX, sc.w0, sc.wave, Y, t, X, w);
-  }
+  GeomSet g0 = {(sc.N > 0 && (x || u)) ? sc.N : 0, 0, sc.xi, sc.body, sc.part, sc.s, sc.ufix, x, u};
+  GeomSet g1 = {(sc.Q > 0 && (X || w)) ? sc.Q : 0, 1, sc.Xi, sc.bodyX, sc.partX, sc.sX, sc.w0, X, w};
+  const int64_t nb0 = (g0.n + 255) / 256, nb1 = (g1.n + 255) / 256;
+  if (nb0 + nb1 == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_geometry, dim3((unsigned)(nb0 + nb1)), dim3(256), 0, s, g0, g1, nb0, sc.M,
+                     sc.P, sc.wave, Y, t);
   return hipGetLastError();
 }
 

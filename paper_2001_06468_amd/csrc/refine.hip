@@ -35,6 +35,20 @@ __global__ void k_state_init(SolveState* st, int32_t method) {
   }
 }
 
+// The start of a solve in one launch: the status record, and the
+// triangular-solve and tile-LU synchronisation words zeroed.
+__global__ void k_solve_begin(SolveState* st, int32_t method, int32_t* __restrict__ a, int64_t na,
+                              int32_t* __restrict__ b, int64_t nb) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i == 0) {
+    SolveState z = {};
+    z.method_used = method;
+    *st = z;
+  }
+  if (i < na) a[i] = 0;
+  if (i < nb) b[i] = 0;
+}
+
 // |A|_inf = max_i sum_j |a_ij| (column-major).  Stage 1: thread = row,
 // grid.y = column chunk, partial sums part[chunk][row]; stage 2: per-row sum
 // of the chunks in order and block maxima; stage 3: maximum of the maxima.
@@ -239,10 +253,8 @@ __global__ void k_rk_stage_state(int32_t M, const double* __restrict__ Y,
 }
 
 // dx0/dt = U; dB/dt = [Omega]x B (column i of B is body axis i).
-__global__ void k_rk_rates(int32_t M, int64_t N, const double* __restrict__ Ys,
-                           const double* __restrict__ sol, double* __restrict__ K) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= M) return;
+__device__ inline void body_rates(int b, int64_t N, const double* __restrict__ Ys,
+                                  const double* __restrict__ sol, double* __restrict__ K) {
   const double* uw = sol + 3 * N + 6 * (int64_t)b;
   const double* B = Ys + 12 * b + 3;
   double* k = K + 12 * b;
@@ -256,6 +268,12 @@ __global__ void k_rk_rates(int32_t M, int64_t N, const double* __restrict__ Ys,
     k[3 + 1 * 3 + c] = o2 * e0 - o0 * e2;
     k[3 + 2 * 3 + c] = o0 * e1 - o1 * e0;
   }
+}
+
+__global__ void k_rk_rates(int32_t M, int64_t N, const double* __restrict__ Ys,
+                           const double* __restrict__ sol, double* __restrict__ K) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < M) body_rates(b, N, Ys, sol, K);
 }
 
 // Y += dt/6 (K1 + 2 K2 + 2 K3 + K4), then modified Gram-Schmidt on the
@@ -290,8 +308,7 @@ __global__ void k_rk_combine(int32_t M, double* __restrict__ Y, const double* __
 }
 
 // Fold one stage's solve status into the step report.
-__global__ void k_state_accumulate(SolveState* total, const SolveState* stage) {
-  if (threadIdx.x != 0) return;
+__device__ inline void accumulate_state(SolveState* total, const SolveState* stage) {
   total->iterations = max(total->iterations, stage->iterations);
   total->failed |= stage->failed || (!stage->converged && stage->method_used != NRS_FP64_LU);
   total->singular |= stage->singular;
@@ -301,6 +318,27 @@ __global__ void k_state_accumulate(SolveState* total, const SolveState* stage) {
   total->corr = fmax(total->corr, stage->corr);
   total->method_used = stage->method_used;
   total->converged = !total->failed;
+}
+
+__global__ void k_state_accumulate(SolveState* total, const SolveState* stage) {
+  if (threadIdx.x == 0) accumulate_state(total, stage);
+}
+
+// Bodies up to which one workgroup ends a stage (12 state words per body).
+constexpr int32_t kStageEndBodies = 1024;
+
+// The end of an RK stage solve in one workgroup: the stage's status folded
+// into the step report, the rates K of the free bodies from the solution
+// (as k_rk_rates), and with Y != NULL the next stage's state Ys = Y + a K.
+__global__ void k_stage_end(SolveState* total, const SolveState* stage, int32_t M, int64_t N,
+                            double* __restrict__ Ys, const double* __restrict__ sol,
+                            double* __restrict__ K, const double* __restrict__ Y, double a) {
+  if (threadIdx.x == 0) accumulate_state(total, stage);
+  for (int b = threadIdx.x; b < M; b += blockDim.x) body_rates(b, N, Ys, sol, K);
+  if (Y) {
+    __syncthreads();  // every rate is written and every read of Ys done
+    for (int64_t i = threadIdx.x; i < 12 * (int64_t)M; i += blockDim.x) Ys[i] = Y[i] + a * K[i];
+  }
 }
 
 inline dim3 grid1(int64_t n, int b) { return dim3((unsigned)((n + b - 1) / b)); }
@@ -445,6 +483,28 @@ hipError_t launch_dp_error(int64_t n, const double* Y, const double* Yn, const R
 hipError_t launch_rk_combine(int32_t M, double* Y, const double* K1, const double* K2,
                              const double* K3, const double* K4, double dt, hipStream_t s) {
   hipLaunchKernelGGL(k_rk_combine, grid1(M, 64), dim3(64), 0, s, M, Y, K1, K2, K3, K4, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_begin(SolveState* st, int32_t method, int32_t* a, int64_t na, int32_t* b,
+                              int64_t nb, hipStream_t s) {
+  const int64_t m = std::max<int64_t>(1, std::max(na, nb));
+  hipLaunchKernelGGL(k_solve_begin, grid1(m, 256), dim3(256), 0, s, st, method, a, na, b, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_end(SolveState* total, const SolveState* stage, int32_t M, int64_t N,
+                            double* Ys, const double* sol, double* K, const double* Y, double a,
+                            hipStream_t s) {
+  if (M > kStageEndBodies) {  // many bodies: the three steps as full-grid launches
+    hipLaunchKernelGGL(k_state_accumulate, dim3(1), dim3(64), 0, s, total, stage);
+    hipLaunchKernelGGL(k_rk_rates, grid1(M, 256), dim3(256), 0, s, M, N, Ys, sol, K);
+    if (Y)
+      hipLaunchKernelGGL(k_rk_stage_state, grid1(12 * (int64_t)M, 256), dim3(256), 0, s, M, Y, K,
+                         a, Ys);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_stage_end, dim3(1), dim3(256), 0, s, total, stage, M, N, Ys, sol, K, Y, a);
   return hipGetLastError();
 }
 
