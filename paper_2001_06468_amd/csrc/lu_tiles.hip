@@ -173,6 +173,29 @@ __device__ inline float pivot_inverse<float>(float piv) {
   return __builtin_amdgcn_rcpf(piv);   // hardware reciprocal (1 ulp)
 }
 
+// x <- L^-1 x for a unit lower 16 x 16 block whose row k (entries k2 > k)
+// starts at L + k * rs; the rows are read as 16-byte vectors (L and rs keep
+// them 16-byte aligned), all of them independent of x, so the loads run
+// ahead of the substitution.
+template <class T>
+__device__ inline void unit_lower_subst16(T (&x)[16], const T* L, int rs) {
+  constexpr int VW = 16 / sizeof(T);
+  typedef T vq __attribute__((ext_vector_type(VW)));
+#pragma unroll
+  for (int k = 0; k < 15; ++k) {
+    const vq* r = reinterpret_cast<const vq*>(L + k * rs);
+    T q[16];
+#pragma unroll
+    for (int h = (k + 1) / VW; h < 16 / VW; ++h) {
+      const vq v = r[h];
+#pragma unroll
+      for (int e = 0; e < VW; ++e) q[h * VW + e] = v[e];
+    }
+#pragma unroll
+    for (int k2 = k + 1; k2 < 16; ++k2) x[k2] -= q[k2] * x[k];
+  }
+}
+
 // Partial pivoting inside the diagonal tile held in S.Cs, blocked by panels of
 // kPW columns; called by all four waves.  Rows stay at their physical place
 // (S.pos[r] = logical index of physical row r once it has been the pivot, TB
@@ -246,34 +269,41 @@ __device__ __attribute__((noinline)) void diag_factor(Shared<T>& S, const LuSys<
     if (ct < TB / kPW) {
       const int c = ct * kPW + (lane & 15), g = lane >> 4;
       if (lane < kPW) {  // U12 = L11^-1 C on the panel's pivot rows, column c
+        int pr[kPW];
+#pragma unroll
+        for (int k = 0; k < kPW; ++k) pr[k] = c * kCS + S.perm[c0 + k];
         T x[kPW];
 #pragma unroll
-        for (int k = 0; k < kPW; ++k) x[k] = S.Cs[c * kCS + S.perm[c0 + k]];
+        for (int k = 0; k < kPW; ++k) x[k] = S.Cs[pr[k]];
+        unit_lower_subst16<T>(x, Lp, kPW);
 #pragma unroll
-        for (int k = 0; k < kPW; ++k)
-#pragma unroll
-          for (int k2 = k + 1; k2 < kPW; ++k2) x[k2] -= Lp[k * kPW + k2] * x[k];
-#pragma unroll
-        for (int k = 0; k < kPW; ++k) S.Cs[c * kCS + S.perm[c0 + k]] = x[k];
+        for (int k = 0; k < kPW; ++k) S.Cs[pr[k]] = x[k];
       }
       wave_sync();
-      // C -= L21 U12 on rows that are not yet pivots (others: L = 0)
+      // C -= L21 U12 on rows that are not yet pivots (others: L = 0); every
+      // operand is read before the first product
       const uint64_t live = S.live[b & 1];
       acc_t acc[TB / 16];
 #pragma unroll
       for (int rt = 0; rt < TB / 16; ++rt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[rt][r] = S.Cs[c * kCS + rt * 16 + Mf<T>::row(lane, r)];
+      T bu[kPW / 4], av[kPW / 4][TB / 16];
 #pragma unroll
       for (int ks = 0; ks < kPW / 4; ++ks) {
         const int kk = c0 + ks * 4 + g;
-        const T bu = S.Cs[c * kCS + S.perm[kk]];
+        bu[ks] = S.Cs[c * kCS + S.perm[kk]];
 #pragma unroll
         for (int rt = 0; rt < TB / 16; ++rt) {
           const int row = rt * 16 + (lane & 15);
-          const T a = (live >> row) & 1 ? -S.Cs[kk * kCS + row] : T(0);
-          acc[rt] = Mf<T>::run(a, bu, acc[rt]);
+          const T v = S.Cs[kk * kCS + row];
+          av[ks][rt] = (live >> row) & 1 ? -v : T(0);
         }
+      }
+#pragma unroll
+      for (int ks = 0; ks < kPW / 4; ++ks) {
+#pragma unroll
+        for (int rt = 0; rt < TB / 16; ++rt) acc[rt] = Mf<T>::run(av[ks][rt], bu[ks], acc[rt]);
       }
 #pragma unroll
       for (int rt = 0; rt < TB / 16; ++rt)
@@ -316,27 +346,38 @@ __device__ __attribute__((noinline)) void col_solve(Shared<T>& S) {
       T x[16];
 #pragma unroll
       for (int k = 0; k < 16; ++k) x[k] = col[rb + k];
-#pragma unroll
-      for (int k = 0; k < 16; ++k)
-#pragma unroll
-        for (int k2 = k + 1; k2 < 16; ++k2) x[k2] -= S.Ws[(rb + k) * kLS + rb + k2] * x[k];
+      unit_lower_subst16<T>(x, S.Ws + rb * kLS + rb, kLS);
 #pragma unroll
       for (int k = 0; k < 16; ++k) col[rb + k] = x[k];
     }
     wave_sync();
+    // the row blocks below (q < nr), every operand read before the first product
+    const int nr = TB / 16 - 1 - b;
+    acc_t acc[TB / 16 - 1];
+    T av[4][TB / 16 - 1], bv[4];
 #pragma unroll
-    for (int rt = b + 1; rt < TB / 16; ++rt) {
-      acc_t acc;
+    for (int q = 0; q < TB / 16 - 1; ++q)
+      if (q < nr)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = col[rt * 16 + Mf<T>::row(lane, r)];
+        for (int r = 0; r < 4; ++r) acc[q][r] = col[(b + 1 + q) * 16 + Mf<T>::row(lane, r)];
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        const int k = rb + ks * 4 + g;
-        acc = Mf<T>::run(-S.Ws[k * kLS + rt * 16 + (lane & 15)], col[k], acc);
-      }
+    for (int ks = 0; ks < 4; ++ks) {
+      const int k = rb + ks * 4 + g;
+      bv[ks] = col[k];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) col[rt * 16 + Mf<T>::row(lane, r)] = acc[r];
+      for (int q = 0; q < TB / 16 - 1; ++q)
+        if (q < nr) av[ks][q] = -S.Ws[k * kLS + (b + 1 + q) * 16 + (lane & 15)];
     }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (int q = 0; q < TB / 16 - 1; ++q)
+        if (q < nr) acc[q] = Mf<T>::run(av[ks][q], bv[ks], acc[q]);
+#pragma unroll
+    for (int q = 0; q < TB / 16 - 1; ++q)
+      if (q < nr)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) col[(b + 1 + q) * 16 + Mf<T>::row(lane, r)] = acc[q][r];
   }
 }
 
@@ -358,29 +399,42 @@ __device__ __attribute__((noinline)) void row_solve(Shared<T>& S) {
       T y[16];
 #pragma unroll
       for (int k = 0; k < 16; ++k) y[k] = S.Cs[(cb + k) * kCS + r0 + lane];
-#pragma unroll
-      for (int k = 0; k < 16; ++k)
-#pragma unroll
-        for (int k2 = k + 1; k2 < 16; ++k2) y[k2] -= y[k] * S.Ws[(cb + k) * kLS + cb + k2];
+      // y Uh^-1: row k of the block's Uh holds the multipliers of y[k]
+      unit_lower_subst16<T>(y, S.Ws + cb * kLS + cb, kLS);
 #pragma unroll
       for (int k = 0; k < 16; ++k) S.Cs[(cb + k) * kCS + r0 + lane] = y[k];
     }
     wave_sync();
+    // the column blocks to the right (q < nc), every operand read before the
+    // first product
+    const int nc = TB / 16 - 1 - b;
+    acc_t acc[TB / 16 - 1];
+    T av[4], bv[4][TB / 16 - 1];
 #pragma unroll
-    for (int ct = b + 1; ct < TB / 16; ++ct) {
-      T* cc = S.Cs + (ct * 16 + (lane & 15)) * kCS + r0;
-      acc_t acc;
+    for (int q = 0; q < TB / 16 - 1; ++q)
+      if (q < nc)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = cc[Mf<T>::row(lane, r)];
+        for (int r = 0; r < 4; ++r)
+          acc[q][r] = S.Cs[((b + 1 + q) * 16 + (lane & 15)) * kCS + r0 + Mf<T>::row(lane, r)];
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        const int k = cb + ks * 4 + g;
-        acc = Mf<T>::run(-S.Cs[k * kCS + r0 + (lane & 15)], S.Ws[k * kLS + ct * 16 + (lane & 15)],
-                         acc);
-      }
+    for (int ks = 0; ks < 4; ++ks) {
+      const int k = cb + ks * 4 + g;
+      av[ks] = -S.Cs[k * kCS + r0 + (lane & 15)];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) cc[Mf<T>::row(lane, r)] = acc[r];
+      for (int q = 0; q < TB / 16 - 1; ++q)
+        if (q < nc) bv[ks][q] = S.Ws[k * kLS + (b + 1 + q) * 16 + (lane & 15)];
     }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (int q = 0; q < TB / 16 - 1; ++q)
+        if (q < nc) acc[q] = Mf<T>::run(av[ks], bv[ks][q], acc[q]);
+#pragma unroll
+    for (int q = 0; q < TB / 16 - 1; ++q)
+      if (q < nc)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          S.Cs[((b + 1 + q) * 16 + (lane & 15)) * kCS + r0 + Mf<T>::row(lane, r)] = acc[q][r];
   }
   wave_sync();
 #pragma unroll
