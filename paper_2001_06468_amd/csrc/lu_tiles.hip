@@ -159,7 +159,8 @@ struct Shared {
   alignas(16) T Cs[2 * TB * TB];
   alignas(16) T Ws[2 * TB * TB];
 };
-static_assert(TB * kCS <= 2 * TB * TB && TB * kLS <= 2 * TB * TB, "working tiles fit a stage");
+static_assert(TB * kCS <= 2 * TB * TB && TB * kLS + 4 * 272 <= 2 * TB * TB,
+              "working tiles (and the diagonal-block inverses) fit a stage");
 
 template <class T>
 __device__ inline T* stage_of(Shared<T>& S, int stage) { return stage ? S.Ws : S.Cs; }
@@ -174,22 +175,22 @@ __device__ inline float pivot_inverse<float>(float piv) {
 }
 
 // x <- L^-1 x for a unit lower 16 x 16 block whose row k (entries k2 > k)
-// starts at L + k * rs; the rows are read as 16-byte vectors (L and rs keep
-// them 16-byte aligned), all of them independent of x, so the loads run
-// ahead of the substitution.
-template <class T>
-__device__ inline void unit_lower_subst16(T (&x)[16], const T* L, int rs) {
+// starts at L + k * rs, in arithmetic C; the rows are read as 16-byte
+// vectors (L and rs keep them 16-byte aligned), all of them independent of
+// x, so the loads run ahead of the substitution.
+template <class T, class C = T>
+__device__ inline void unit_lower_subst16(C (&x)[16], const T* L, int rs) {
   constexpr int VW = 16 / sizeof(T);
   typedef T vq __attribute__((ext_vector_type(VW)));
 #pragma unroll
   for (int k = 0; k < 15; ++k) {
     const vq* r = reinterpret_cast<const vq*>(L + k * rs);
-    T q[16];
+    C q[16];
 #pragma unroll
     for (int h = (k + 1) / VW; h < 16 / VW; ++h) {
       const vq v = r[h];
 #pragma unroll
-      for (int e = 0; e < VW; ++e) q[h * VW + e] = v[e];
+      for (int e = 0; e < VW; ++e) q[h * VW + e] = (C)v[e];
     }
 #pragma unroll
     for (int k2 = k + 1; k2 < 16; ++k2) x[k2] -= q[k2] * x[k];
@@ -322,14 +323,21 @@ __device__ __attribute__((noinline)) void diag_factor(Shared<T>& S, const LuSys<
 
 // U_mj = L_mm^-1 P_m C, in place in the working tile S.Cs; L_mm (unit lower)
 // is staged column-major in S.Ws, the permutation in S.perm.  Called by all
-// four waves; wave w owns columns 16w..16w+15 and needs no other wave: per
-// block of 16 rows, a substitution with the diagonal block (one lane per
-// column) and then the rows below on the matrix cores.
+// four waves.  First wave w inverts diagonal block w of L_mm (a substitution
+// on the identity in FP64, one lane per column, rounded once) into S.Ws past
+// the staged tile, so that multiplying by the inverse is as accurate as the
+// substitution it replaces (with the inverse formed in FP32 the refinement
+// of a small channel system stopped one sweep early at a 4e-8 force error);
+// then
+// wave w owns columns 16w..16w+15: per block of 16 rows, X_b = D_b^-1 R_b
+// and the update of the rows below, both on the matrix cores, so the
+// sequential part of the solve is one 16-step substitution instead of four.
 template <class T>
 __device__ __attribute__((noinline)) void col_solve(Shared<T>& S) {
   typedef typename Mf<T>::acc_t acc_t;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4;
-  T* col = S.Cs + (w * 16 + (lane & 15)) * kCS;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, li = lane & 15;
+  T* col = S.Cs + (w * 16 + li) * kCS;
+  T* DI = S.Ws + TB * kLS;  // inverses of the diagonal blocks: block b, (i, k) at b*272 + i*17 + k
   {  // rows to logical order in this wave's columns (all loads before stores)
     T t[TB / 4];
 #pragma unroll
@@ -338,17 +346,34 @@ __device__ __attribute__((noinline)) void col_solve(Shared<T>& S) {
 #pragma unroll
     for (int q = 0; q < TB / 4; ++q) col[g + 4 * q] = t[q];
   }
+  if (lane < 16) {  // wave w: column `lane` of the inverse of diagonal block w (in FP64)
+    double x[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = k == lane ? 1.0 : 0.0;
+    unit_lower_subst16<T, double>(x, S.Ws + w * 16 * kLS + w * 16, kLS);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) DI[w * 272 + k * 17 + lane] = (T)x[k];
+  }
+  __syncthreads();
 #pragma unroll
   for (int b = 0; b < TB / 16; ++b) {
     const int rb = b * 16;
     wave_sync();
-    if (lane < 16) {
-      T x[16];
+    {  // X_b = D_b^-1 (rows rb.. of the right-hand side) on the matrix cores
+      T av[4], bv[4];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = col[rb + k];
-      unit_lower_subst16<T>(x, S.Ws + rb * kLS + rb, kLS);
+      for (int ks = 0; ks < 4; ++ks) {
+        av[ks] = DI[b * 272 + li * 17 + ks * 4 + g];
+        bv[ks] = col[rb + ks * 4 + g];
+      }
+      acc_t x;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) col[rb + k] = x[k];
+      for (int r = 0; r < 4; ++r) x[r] = T(0);
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) x = Mf<T>::run(av[ks], bv[ks], x);
+      wave_sync();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) col[rb + Mf<T>::row(lane, r)] = x[r];
     }
     wave_sync();
     // the row blocks below (q < nr), every operand read before the first product
@@ -366,7 +391,7 @@ __device__ __attribute__((noinline)) void col_solve(Shared<T>& S) {
       bv[ks] = col[k];
 #pragma unroll
       for (int q = 0; q < TB / 16 - 1; ++q)
-        if (q < nr) av[ks][q] = -S.Ws[k * kLS + (b + 1 + q) * 16 + (lane & 15)];
+        if (q < nr) av[ks][q] = -S.Ws[k * kLS + (b + 1 + q) * 16 + li];
     }
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks)
@@ -383,26 +408,45 @@ __device__ __attribute__((noinline)) void col_solve(Shared<T>& S) {
 
 // L_im = C U_mm^-1, in place in S.Cs.  With U = D Uh (D its diagonal, Uh unit
 // upper), Y = C Uh^-1 and L = Y D^-1.  S.Ws holds Uh row-major, S.row the
-// reciprocals of D.  Called by all four waves; wave w owns rows 16w..16w+15:
-// per block of 16 columns, a substitution with the diagonal block (one lane
-// per row) and then the columns to the right on the matrix cores.
+// reciprocals of D.  Called by all four waves.  First wave w inverts
+// diagonal block w of Uh (one lane per row, in FP64 and rounded once, as in
+// col_solve) into S.Ws past the staged tile;
+// then wave w owns rows 16w..16w+15: per block of 16 columns, Y_b = R_b
+// Uh_b^-1 and the update of the columns to the right on the matrix cores.
 template <class T>
 __device__ __attribute__((noinline)) void row_solve(Shared<T>& S) {
   typedef typename Mf<T>::acc_t acc_t;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, li = lane & 15;
   const int r0 = w * 16;
+  T* UI = S.Ws + TB * kLS;  // inverses of Uh's diagonal blocks: block b, (k, j) at b*272 + k*17 + j
+  if (lane < 16) {  // wave w: row `lane` of the inverse of diagonal block w (in FP64)
+    double y[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) y[k] = k == lane ? 1.0 : 0.0;
+    unit_lower_subst16<T, double>(y, S.Ws + w * 16 * kLS + w * 16, kLS);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) UI[w * 272 + lane * 17 + k] = (T)y[k];
+  }
+  __syncthreads();
 #pragma unroll
   for (int b = 0; b < TB / 16; ++b) {
     const int cb = b * 16;
     wave_sync();
-    if (lane < 16) {
-      T y[16];
+    {  // Y_b = (columns cb.. of the right-hand side) Uh_b^-1 on the matrix cores
+      T av[4], bv[4];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) y[k] = S.Cs[(cb + k) * kCS + r0 + lane];
-      // y Uh^-1: row k of the block's Uh holds the multipliers of y[k]
-      unit_lower_subst16<T>(y, S.Ws + cb * kLS + cb, kLS);
+      for (int ks = 0; ks < 4; ++ks) {
+        av[ks] = S.Cs[(cb + ks * 4 + g) * kCS + r0 + li];
+        bv[ks] = UI[b * 272 + (ks * 4 + g) * 17 + li];
+      }
+      acc_t y;
 #pragma unroll
-      for (int k = 0; k < 16; ++k) S.Cs[(cb + k) * kCS + r0 + lane] = y[k];
+      for (int r = 0; r < 4; ++r) y[r] = T(0);
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) y = Mf<T>::run(av[ks], bv[ks], y);
+      wave_sync();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) S.Cs[(cb + li) * kCS + r0 + Mf<T>::row(lane, r)] = y[r];
     }
     wave_sync();
     // the column blocks to the right (q < nc), every operand read before the
@@ -415,14 +459,14 @@ __device__ __attribute__((noinline)) void row_solve(Shared<T>& S) {
       if (q < nc)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          acc[q][r] = S.Cs[((b + 1 + q) * 16 + (lane & 15)) * kCS + r0 + Mf<T>::row(lane, r)];
+          acc[q][r] = S.Cs[((b + 1 + q) * 16 + li) * kCS + r0 + Mf<T>::row(lane, r)];
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int k = cb + ks * 4 + g;
-      av[ks] = -S.Cs[k * kCS + r0 + (lane & 15)];
+      av[ks] = -S.Cs[k * kCS + r0 + li];
 #pragma unroll
       for (int q = 0; q < TB / 16 - 1; ++q)
-        if (q < nc) bv[ks][q] = S.Ws[k * kLS + (b + 1 + q) * 16 + (lane & 15)];
+        if (q < nc) bv[ks][q] = S.Ws[k * kLS + (b + 1 + q) * 16 + li];
     }
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks)
@@ -434,13 +478,13 @@ __device__ __attribute__((noinline)) void row_solve(Shared<T>& S) {
       if (q < nc)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          S.Cs[((b + 1 + q) * 16 + (lane & 15)) * kCS + r0 + Mf<T>::row(lane, r)] = acc[q][r];
+          S.Cs[((b + 1 + q) * 16 + li) * kCS + r0 + Mf<T>::row(lane, r)] = acc[q][r];
   }
   wave_sync();
 #pragma unroll
   for (int q = 0; q < TB / 4; ++q) {
     const int c = g + 4 * q;
-    T* e = &S.Cs[c * kCS + r0 + (lane & 15)];
+    T* e = &S.Cs[c * kCS + r0 + li];
     *e = *e * S.row[c];
   }
 }
