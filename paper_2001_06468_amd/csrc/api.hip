@@ -161,7 +161,7 @@ bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, Sol
   sb.eqc = f32 ? ar.take<float>(n) : nullptr;
   sb.eqmax = f32 ? ar.take<uint32_t>(n) : nullptr;
   sb.equil = false;
-  sb.lu_done = ar.take<int32_t>(lu_tiles_nt(n) * lu_tiles_nt(n));
+  sb.lu_done = ar.take<int32_t>(with64 ? lu_done_ints(n) : lu_done_flag_ints(n));
   sb.AT = sb.V = sb.gw0 = sb.gw1 = sb.gpart = nullptr;
   sb.gst = nullptr;
   sb.Z = sb.fzv = sb.fax = nullptr;
@@ -544,7 +544,7 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
   const bool fact = method != NRS_GMRES_BLOCK;
   NRS_HIP(ctx, launch_solve_begin(sb.st, method, fact ? sb.tsync : nullptr,
                                   fact ? trsv_sync_ints(n) : 0, fact ? sb.lu_done : nullptr,
-                                  fact ? lu_tiles_nt(n) * lu_tiles_nt(n) : 0, s));
+                                  fact ? lu_done_flag_ints(n) : 0, s));
   NRS_HIP(ctx, launch_build_csr(N, Q, pb.X, pb.w, pb.nu, sb.srt, sb.st, s));
   // the right-hand side with the body check; the FP32 forms that factor the
   // unscaled matrix also get its FP32 copy here
@@ -591,7 +591,7 @@ nrs_status solve_core(nrs_ctx* ctx, const nrs_problem& pb, const double* u, cons
     NRS_HIP(ctx, launch_state_init(sb.st, NRS_FP64_LU, s));
     if (method == NRS_GMRES_BLOCK) {
       NRS_HIP(ctx, launch_fill_i32(sb.tsync, 0, trsv_sync_ints(n), s));
-      NRS_HIP(ctx, launch_fill_i32(sb.lu_done, 0, lu_tiles_nt(n) * lu_tiles_nt(n), s));
+      NRS_HIP(ctx, launch_fill_i32(sb.lu_done, 0, lu_done_flag_ints(n), s));
     }
     if ((st = run_fp64_lu(ctx, pb, sb, sol, true, s)) != NRS_OK) return st;
     if ((st = read_state(ctx, sb.st, h)) != NRS_OK) return st;

@@ -197,7 +197,7 @@ nrs_status enqueue_batch(nrs_ctx* ctx, int32_t B, const nrs_problem* problems,
     const int64_t n = 3 * p.N + 6 * (int64_t)p.M;
     hipStream_t s = lane_stream(ctx, k);
     NRS_BHIP(ctx, launch_solve_begin(sb.st, NRS_FP32_IR, sb.tsync, trsv_sync_ints(n), sb.lu_done,
-                                     lu_tiles_nt(n) * lu_tiles_nt(n), s));
+                                     lu_done_flag_ints(n), s));
     NRS_BHIP(ctx, launch_build_csr(p.N, p.Q, p.X, p.w, p.nu, sb.srt, sb.st, s));
     // the right-hand side, its FP32 copy and the body check in one launch
     NRS_BHIP(ctx, launch_rhs(p.N, p.M, u[k], ftext ? ftext[k] : nullptr, sb.b, s,

@@ -40,16 +40,16 @@ constexpr int kLuThreads = 256;
 constexpr int kLS = 80;  // LDS row stride of the MFMA staging tiles
 constexpr int kCS = 65;  // LDS column stride of the working tile
 constexpr int64_t kLuSpin = 1 << 22;
-// A single FP32 system of at most this many tile rows runs one workgroup per
-// CU: its launch reserves kLuSoloPad bytes of unused dynamic LDS, so a
-// workgroup needs more than half of the CU's 160 KB.  Its time is the latency
+// A single FP32 system of at most kLuSoloTiles tile rows runs one workgroup
+// per CU: its launch reserves kLuSoloPad bytes of dynamic LDS (the row tile
+// a diagonal task solves itself, 64 x 65 floats), so a workgroup needs more
+// than half of the CU's 160 KB.  Its time is the latency
 // of the diagonal chain, and a second workgroup on the chain task's CU slows
 // the pivot steps; at larger orders the update throughput of two workgroups
 // per CU wins (measured, two per CU -> one: n = 3150 1.83 -> 1.73 ms, n = 6300
 // 4.10 -> 3.67 ms, n = 8000 5.69 -> 5.65 ms, n = 10,000 8.78 -> 10.0 ms,
 // n = 14,244 21.6 -> 25.4 ms).
-constexpr int64_t kLuSoloTiles = 112;
-constexpr unsigned kLuSoloPad = 16 * 1024;
+constexpr unsigned kLuSoloPad = 17 * 1024;
 // s_waitcnt operand that waits for vmcnt = 0 and leaves expcnt and lgkmcnt at
 // their maxima (gfx9 layout: vmcnt in bits 3:0 and 15:14, expcnt 6:4,
 // lgkmcnt 11:8).
@@ -164,6 +164,10 @@ static_assert(TB * kCS <= 2 * TB * TB && TB * kLS + 4 * 272 <= 2 * TB * TB,
 
 template <class T>
 __device__ inline T* stage_of(Shared<T>& S, int stage) { return stage ? S.Ws : S.Cs; }
+
+// Dynamic LDS of the one-workgroup-per-CU launches: the row tile that the
+// diagonal task of the next band solves itself (64 columns of kCS floats).
+extern __shared__ __align__(16) float lu_xtile[];
 
 template <class T>
 __device__ inline T pivot_inverse(T piv) {
@@ -413,9 +417,11 @@ __device__ __attribute__((noinline)) void col_solve(Shared<T>& S) {
 // col_solve) into S.Ws past the staged tile;
 // then wave w owns rows 16w..16w+15: per block of 16 columns, Y_b = R_b
 // Uh_b^-1 and the update of the columns to the right on the matrix cores.
-template <class T>
+template <class T, bool XT = false>
 __device__ __attribute__((noinline)) void row_solve(Shared<T>& S) {
   typedef typename Mf<T>::acc_t acc_t;
+  // XT: the tile is the hand-over tile in dynamic LDS instead of S.Cs
+  T* const Ct = XT ? reinterpret_cast<T*>(lu_xtile) : S.Cs;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, li = lane & 15;
   const int r0 = w * 16;
   T* UI = S.Ws + TB * kLS;  // inverses of Uh's diagonal blocks: block b, (k, j) at b*272 + k*17 + j
@@ -436,7 +442,7 @@ __device__ __attribute__((noinline)) void row_solve(Shared<T>& S) {
       T av[4], bv[4];
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
-        av[ks] = S.Cs[(cb + ks * 4 + g) * kCS + r0 + li];
+        av[ks] = Ct[(cb + ks * 4 + g) * kCS + r0 + li];
         bv[ks] = UI[b * 272 + (ks * 4 + g) * 17 + li];
       }
       acc_t y;
@@ -446,7 +452,7 @@ __device__ __attribute__((noinline)) void row_solve(Shared<T>& S) {
       for (int ks = 0; ks < 4; ++ks) y = Mf<T>::run(av[ks], bv[ks], y);
       wave_sync();
 #pragma unroll
-      for (int r = 0; r < 4; ++r) S.Cs[(cb + li) * kCS + r0 + Mf<T>::row(lane, r)] = y[r];
+      for (int r = 0; r < 4; ++r) Ct[(cb + li) * kCS + r0 + Mf<T>::row(lane, r)] = y[r];
     }
     wave_sync();
     // the column blocks to the right (q < nc), every operand read before the
@@ -459,11 +465,11 @@ __device__ __attribute__((noinline)) void row_solve(Shared<T>& S) {
       if (q < nc)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          acc[q][r] = S.Cs[((b + 1 + q) * 16 + li) * kCS + r0 + Mf<T>::row(lane, r)];
+          acc[q][r] = Ct[((b + 1 + q) * 16 + li) * kCS + r0 + Mf<T>::row(lane, r)];
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int k = cb + ks * 4 + g;
-      av[ks] = -S.Cs[k * kCS + r0 + li];
+      av[ks] = -Ct[k * kCS + r0 + li];
 #pragma unroll
       for (int q = 0; q < TB / 16 - 1; ++q)
         if (q < nc) bv[ks][q] = S.Ws[k * kLS + (b + 1 + q) * 16 + li];
@@ -478,13 +484,13 @@ __device__ __attribute__((noinline)) void row_solve(Shared<T>& S) {
       if (q < nc)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          S.Cs[((b + 1 + q) * 16 + li) * kCS + r0 + Mf<T>::row(lane, r)] = acc[q][r];
+          Ct[((b + 1 + q) * 16 + li) * kCS + r0 + Mf<T>::row(lane, r)] = acc[q][r];
   }
   wave_sync();
 #pragma unroll
   for (int q = 0; q < TB / 4; ++q) {
     const int c = g + 4 * q;
-    T* e = &S.Cs[c * kCS + r0 + li];
+    T* e = &Ct[c * kCS + r0 + li];
     *e = *e * S.row[c];
   }
 }
@@ -546,6 +552,42 @@ __device__ inline int64_t published_run(const LuSys<T>& sy, int64_t i, int64_t j
 // columns of 4 rows) each touch 64 different banks.
 __device__ inline int us_at(int k, int c) { return k * TB + (c ^ (((k & 3) << 4) | (k >> 2))); }
 
+// U(k, j) into the U part of an FP32 update stage Lb, in the layout the
+// update loop's issue() gives it (the L part untouched).
+__device__ inline void dma_u_part(float* Lb, const float* A, int64_t lda, int64_t n, int64_t k,
+                                  int64_t j, int w, int lane) {
+  const int pl = lane & 15, sub = lane >> 4;
+#pragma unroll
+  for (int q4 = 0; q4 < 4; ++q4) {
+    const int q = w * 4 + q4, kc = 4 * q + sub;
+    const int64_t cg = min(j * TB + kc, n - 1);
+    const float* gu = A + (k * TB + 4 * (pl ^ (kc & 15))) + cg * lda;
+    __builtin_amdgcn_global_load_lds(gu, Lb + TB * TB + q * 256, 16, 0, 0);
+  }
+}
+
+// Uh = D^-1 U of the finished diagonal tile of band mb, row-major in S.Ws,
+// and the reciprocals of D in S.row, for row_solve.
+template <class T>
+__device__ inline void stage_uh(Shared<T>& S, const LuSys<T>& sy, int64_t mb) {
+  const int tid = threadIdx.x;
+  T ua[TB * TB / kLuThreads];
+#pragma unroll
+  for (int q = 0; q < TB * TB / kLuThreads; ++q) {
+    const int e = tid + q * kLuThreads, r = e % TB, c = e / TB;
+    ua[q] = ld_pad(sy.A, sy.lda, sy.n, mb * TB + r, mb * TB + c);
+  }
+  if (tid < TB) S.row[tid] = ld_pad(sy.A, sy.lda, sy.n, mb * TB + tid, mb * TB + tid);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < TB * TB / kLuThreads; ++q) {
+    const int e = tid + q * kLuThreads, r = e % TB, c = e / TB;
+    S.Ws[r * kLS + c] = ua[q] / S.row[r];
+  }
+  __syncthreads();
+  if (tid < TB) S.row[tid] = T(1) / S.row[tid];
+}
+
 // One tile task: update, then factor / solve, store, publish.
 template <class T, bool B16>
 __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
@@ -558,6 +600,10 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
     const int64_t nt = sy.nt, n = sy.n, lda = sy.lda;
     T* A = sy.A;
     const int qi = (w >> 1) * 32, qj = (w & 1) * 32;
+    // one-workgroup-per-CU FP32 system: the diagonal task of band m >= 1
+    // solves the row tile (m, m - 1) itself and applies its last term from LDS
+    const bool xover = std::is_same<T, float>::value && !B16 && sy.pre && i == j && m >= 1;
+    const int64_t kmax = xover ? m - 1 : m;  // update terms taken from memory
     // this task's tile of A (only this task ever writes it), loaded up front
     // so that the subtraction after the last update does not wait on memory
     T a_ij[16];
@@ -646,11 +692,11 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
         lb1 = TB * TB + (qj + 16 + li) * TB + sub;
       }
       int64_t kend = 0;
-      for (int64_t k = 0; k < m; ++k) {
+      for (int64_t k = 0; k < kmax; ++k) {
         const int stage = (int)((k + m) & 1);
         if (k >= kend) {
           if (w == 0) {
-            const int64_t e = published_run(sy, i, j, k, m, err, lane);
+            const int64_t e = published_run(sy, i, j, k, kmax, err, lane);
             if (lane == 0) S.task[2] = (int32_t)e;
           }
           __syncthreads();
@@ -702,6 +748,54 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
             acc[1][0] = Mf<T>::run(a1[t], b0[t], acc[1][0]);
             acc[1][1] = Mf<T>::run(a1[t], b1[t], acc[1][1]);
             __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+          }
+        }
+      }
+      if constexpr (!B16) {
+        if (xover) {
+          // The last term L(m, p) U(p, m), p = m - 1: L(m, p) is solved here
+          // from the row task's tile before its solve (handed over long
+          // before it is needed), so the solved tile's store, flag and load
+          // leave the diagonal chain; U(p, m) comes from its column task.
+          const int64_t p = m - 1;
+          __syncthreads();  // the last term taken from memory has been read
+          if (tid == 0) {
+            wait_flag(&sy.preflag[p], err);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __builtin_amdgcn_s_waitcnt(kWaitVmem);
+          }
+          __syncthreads();
+          {
+            const float* src = sy.pre + p * (TB * TB);
+            for (int c = w; c < TB; c += kLuThreads / TB) lu_xtile[c * kCS + lane] = src[c * TB + lane];
+          }
+          if (tid == 0) {
+            wait_flag(&sy.done[p * nt + p], err);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __builtin_amdgcn_s_waitcnt(kWaitVmem);
+          }
+          __syncthreads();
+          stage_uh<T>(S, sy, p);
+          __syncthreads();
+          row_solve<T, true>(S);  // lu_xtile <- L(m, p)
+          if (tid == 0) {
+            wait_flag(&sy.done[p * nt + m], err);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __builtin_amdgcn_s_waitcnt(kWaitVmem);
+          }
+          __syncthreads();  // also: the solve's reads of S.Ws are done
+          dma_u_part(S.Ws, A, lda, n, p, j, w, lane);  // U(p, m) into the U part of stage 1
+          __builtin_amdgcn_s_waitcnt(kWaitVmem);
+          __syncthreads();
+#pragma unroll
+          for (int t = 0; t < TB / 4; ++t) {
+            const int kk = 4 * t + sub, ub = 4 * (t ^ li);
+            const float a0 = lu_xtile[kk * kCS + qi + li], a1 = lu_xtile[kk * kCS + qi + 16 + li];
+            const float b0 = S.Ws[lb0 + ub], b1 = S.Ws[lb1 + ub];
+            acc[0][0] = Mf<T>::run(a0, b0, acc[0][0]);
+            acc[0][1] = Mf<T>::run(a0, b1, acc[0][1]);
+            acc[1][0] = Mf<T>::run(a1, b0, acc[1][0]);
+            acc[1][1] = Mf<T>::run(a1, b1, acc[1][1]);
           }
         }
       }
@@ -771,6 +865,17 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
           S.Cs[cc * kCS + rr] =
               (i * TB + rr < n && j * TB + cc < n) ? v - acc[a][b][r] : v;
         }
+    if constexpr (std::is_same<T, float>::value && !B16) {
+      if (sy.pre && i == j + 1) {
+        // the tile before its solve, for the diagonal task of band i
+        __syncthreads();
+        float* dst = sy.pre + j * (TB * TB);
+        for (int c = w; c < TB; c += kLuThreads / TB) dst[c * TB + lane] = S.Cs[c * kCS + lane];
+        __builtin_amdgcn_s_waitcnt(kWaitVmem);  // this wave's stores have landed
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(&sy.preflag[j], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
     if (i != j) {
       if (tid == 0) {
         wait_flag(&sy.done[m * nt + m], err);
@@ -804,23 +909,7 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
       col_solve<T>(S);
     } else {
       // L_im = C U_mm^-1; Uh = D^-1 U staged row-major, 1 / diag in S.row
-      {
-        T ua[TB * TB / kLuThreads];
-#pragma unroll
-        for (int q = 0; q < TB * TB / kLuThreads; ++q) {
-          const int e = tid + q * kLuThreads, r = e % TB, c = e / TB;
-          ua[q] = ld_pad(A, lda, n, m * TB + r, m * TB + c);
-        }
-        if (tid < TB) S.row[tid] = ld_pad(A, lda, n, m * TB + tid, m * TB + tid);
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < TB * TB / kLuThreads; ++q) {
-          const int e = tid + q * kLuThreads, r = e % TB, c = e / TB;
-          S.Ws[r * kLS + c] = ua[q] / S.row[r];
-        }
-        __syncthreads();
-        if (tid < TB) S.row[tid] = T(1) / S.row[tid];
-      }
+      stage_uh<T>(S, sy, m);
       __syncthreads();
       row_solve<T>(S);
     }
@@ -929,6 +1018,8 @@ __global__ __launch_bounds__(kLuThreads, MINB) void k_lu_tiles(LuBatch<T> bt, in
       const LuSys<T> sy = bt.sys ? bt.sys[q] : bt.one;
       const int64_t nf = (int64_t)sy.nt * sy.nt;
       for (int64_t e = tid; e < nf; e += kLuThreads) sy.done[e] = 0;
+      if (sy.preflag)
+        for (int64_t e = tid; e < sy.nt; e += kLuThreads) sy.preflag[e] = 0;
     }
     __syncthreads();
     if (tid == 0) {
@@ -996,6 +1087,11 @@ hipError_t lu_factor_any(int64_t n, int32_t scope, T* A, int64_t lda, int32_t* i
   bt.one.done = done;
   bt.one.sing = sing;
   bt.one.sh = std::is_same<T, float>::value ? sh : nullptr;
+  if (std::is_same<T, float>::value && sh == nullptr && nt >= 2 && nt <= kLuHandoverTiles) {
+    // the row-tile hand-over area after the flags (lu_done_ints)
+    bt.one.preflag = done + nt * nt;
+    bt.one.pre = reinterpret_cast<T*>(done + (lu_done_flag_ints(n) + 63) / 64 * 64);
+  }
   bt.sys = nullptr;
   bt.pref = nullptr;
   bt.B = 1;

@@ -206,7 +206,8 @@ struct SolveBuffers {
 };
 
 size_t solve_workspace_bytes(int64_t N, int64_t Q, int32_t M, int32_t method);
-// with64 = false leaves out the FP64 matrix (batched FP32 solves)
+// with64 = false leaves out the FP64 matrix and the tile LU's row-tile
+// hand-over area (batched FP32 solves)
 bool carve_solve(Arena& ar, int64_t N, int64_t Q, int32_t M, int32_t method, SolveBuffers& sb,
                  bool with64 = true);
 
@@ -226,6 +227,11 @@ struct LuSys {
   // [column][k]); when set (FP32 only), the trailing updates take these as
   // matrix-core inputs (BF16 in, FP32 accumulate).  NULL: FP32 updates.
   uint16_t* sh = nullptr;
+  // Single FP32 system run one workgroup per CU (NULL otherwise): the row
+  // tile (m + 1, m) before its solve, 64 x 64 column-major at m * 4096, and
+  // its flag, so that the diagonal task of band m + 1 solves it itself.
+  T* pre = nullptr;
+  int32_t* preflag = nullptr;
 };
 template <class T>
 struct LuBatch {
@@ -454,10 +460,27 @@ inline int64_t lu_tiles_nt(int64_t n) { return (n + 63) / 64; }
 // with BF16 update inputs) the BF16 tile copies, 256-byte aligned.
 constexpr int64_t kLuHeadInts = 64;
 constexpr int64_t kLuTimeoutWord = 2;
-inline int64_t lu_factor_sync_ints(int64_t n) {
+// A single FP32 system of at most kLuSoloTiles tile rows runs the tile LU one
+// workgroup per CU; up to kLuHandoverTiles tile rows its diagonal tasks also
+// solve the preceding row tile themselves (LuSys::pre).  Measured, FP32 LU
+// without -> with the hand-over: n = 2048 0.99 -> 0.97 ms, n = 3150 1.52 ->
+// 1.48 ms, n = 4096 1.97 -> 1.93 ms, n = 5000 2.46 -> 2.45 ms, but n = 6300
+// 3.39 -> 3.60 ms (the hand-over store then delays the row tile's own solve,
+// which later tasks of the band wait for).
+constexpr int64_t kLuSoloTiles = 112;
+constexpr int64_t kLuHandoverTiles = 80;
+// Tile-LU synchronisation words: nt * nt tile flags, then (nt <=
+// kLuHandoverTiles) nt hand-over flags, all zero before a launch; then the
+// hand-over tiles, nt x 4096 FP32 words from a 64-word boundary.
+inline int64_t lu_done_flag_ints(int64_t n) {
   const int64_t nt = lu_tiles_nt(n);
-  return kLuHeadInts + (nt * nt + 63) / 64 * 64;
+  return nt * nt + (nt <= kLuHandoverTiles ? nt : 0);
 }
+inline int64_t lu_done_ints(int64_t n) {
+  const int64_t nt = lu_tiles_nt(n);
+  return (lu_done_flag_ints(n) + 63) / 64 * 64 + (nt <= kLuHandoverTiles ? nt * 4096 : 0);
+}
+inline int64_t lu_factor_sync_ints(int64_t n) { return kLuHeadInts + lu_done_ints(n); }
 template <class T>
 hipError_t launch_lu_solve(int64_t n, int32_t scope, const T* LU, int64_t lda,
                            const int32_t* perm, const T* b, T* x, int32_t* sync, int32_t* err,
