@@ -588,8 +588,9 @@ __device__ inline void stage_uh(Shared<T>& S, const LuSys<T>& sy, int64_t mb) {
   if (tid < TB) S.row[tid] = T(1) / S.row[tid];
 }
 
-// One tile task: update, then factor / solve, store, publish.
-template <class T, bool B16>
+// One tile task: update, then factor / solve, store, publish.  XO: the
+// launch runs one workgroup per CU and may hand row tiles over (LuSys::pre).
+template <class T, bool B16, bool XO>
 __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
                                                    int64_t j, int64_t m, int32_t* err) {
   typedef typename Mf<T>::acc_t acc_t;
@@ -602,7 +603,7 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
     const int qi = (w >> 1) * 32, qj = (w & 1) * 32;
     // one-workgroup-per-CU FP32 system: the diagonal task of band m >= 1
     // solves the row tile (m, m - 1) itself and applies its last term from LDS
-    const bool xover = std::is_same<T, float>::value && !B16 && sy.pre && i == j && m >= 1;
+    const bool xover = XO && std::is_same<T, float>::value && !B16 && sy.pre && i == j && m >= 1;
     const int64_t kmax = xover ? m - 1 : m;  // update terms taken from memory
     // this task's tile of A (only this task ever writes it), loaded up front
     // so that the subtraction after the last update does not wait on memory
@@ -751,7 +752,7 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
           }
         }
       }
-      if constexpr (!B16) {
+      if constexpr (XO && !B16) {
         if (xover) {
           // The last term L(m, p) U(p, m), p = m - 1: L(m, p) is solved here
           // from the row task's tile before its solve (handed over long
@@ -865,7 +866,7 @@ __device__ inline void run_task(Shared<T>& S, const LuSys<T>& sy, int64_t i,
           S.Cs[cc * kCS + rr] =
               (i * TB + rr < n && j * TB + cc < n) ? v - acc[a][b][r] : v;
         }
-    if constexpr (std::is_same<T, float>::value && !B16) {
+    if constexpr (XO && std::is_same<T, float>::value && !B16) {
       if (sy.pre && i == j + 1) {
         // the tile before its solve, for the diagonal task of band i
         __syncthreads();
@@ -1005,7 +1006,7 @@ __global__ __launch_bounds__(kLuThreads, MINB) void k_lu_tiles(LuBatch<T> bt, in
       j = m;
     }
     const LuSys<T> sy = bt.sys ? bt.sys[s] : bt.one;
-    run_task<T, B16>(S, sy, i, j, m, err);
+    run_task<T, B16, MINB == 1>(S, sy, i, j, m, err);
     if (i == j) diag_ipiv<T>(S, sy, m);
   }
   // the last workgroup to finish clears the ticket and every flag
