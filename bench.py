@@ -36,7 +36,7 @@ PEAK_FP64_TFLOPS = 78.6
 # HBM bytes per launch of the tile LU at n = 3150 from the FETCH_SIZE and
 # WRITE_SIZE counter runs (calibrated against a 256 MiB copy), valid only for
 # the kernel source they were taken on (first 16 hex digits of its SHA-256).
-LU_TRAFFIC = {"source_sha256_16": "f19e8e75f92bc803", "bytes_per_launch": 908382675, "n": 3150}
+LU_TRAFFIC = {"source_sha256_16": "ac86c9aaff497af9", "bytes_per_launch": 909496904, "n": 3150}
 # HBM bytes per nrs_field_velocity call (sources + pair sum + chunk sum) on the
 # tracer workload, from the same two counter runs, valid for that field.hip.
 FIELD_TRAFFIC = {"source_sha256_16": "7f18d8d2f998ad7c", "bytes_per_call": 24459390, "Q": 73248,
@@ -47,7 +47,7 @@ FIELD_TRAFFIC = {"source_sha256_16": "7f18d8d2f998ad7c", "bytes_per_call": 24459
 # scaled by what it reads for a kernel of known work run in the same
 # process), valid only for the kernel source they were taken on.
 COUNTERS = {
-    "lu": {"source": "lu_tiles.hip", "source_sha256_16": "f19e8e75f92bc803", "n": 3150,
+    "lu": {"source": "lu_tiles.hip", "source_sha256_16": "ac86c9aaff497af9", "n": 3150,
            "mfma_flops_per_launch": 2.202e10, "mfma_busy": 0.093,
            "calibration": "FP32 4096^3 matrix product: 0.954 busy at 150 TFLOP/s"},
     "assembly": {"source": "assemble.hip", "source_sha256_16": "cd14792605c821f9", "N": 1000,
