@@ -205,6 +205,34 @@ __global__ void k_csr_count(int64_t N, int64_t Q, const int32_t* __restrict__ nu
 // st (may be NULL): argument error when some nu was outside [0, N) (counted
 // in cnt[N + 1]).
 constexpr int kScanBlock = 1024;
+
+// Exclusive scan of one value per thread over a kScanBlock workgroup: a
+// shuffle scan inside each wavefront, then the wavefronts' totals scanned by
+// wavefront 0 (two barriers); *total receives the sum over the workgroup.
+__device__ inline int32_t block_exclusive_scan(int32_t v, int32_t* wtot, int32_t* total) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int32_t x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) wtot[wv] = x;
+  __syncthreads();
+  if (wv == 0) {
+    int32_t t = lane < kScanBlock / 64 ? wtot[lane] : 0;
+#pragma unroll
+    for (int off = 1; off < kScanBlock / 64; off <<= 1) {
+      const int32_t y = __shfl_up(t, off, 64);
+      if (lane >= off) t += y;
+    }
+    if (lane < kScanBlock / 64) wtot[lane] = t;
+  }
+  __syncthreads();
+  *total = wtot[kScanBlock / 64 - 1];
+  return x - v + (wv ? wtot[wv - 1] : 0);
+}
+
 __global__ __launch_bounds__(kScanBlock) void k_csr_scan(int64_t N, int32_t* cnt, int32_t* seg,
                                                          SolveState* st) {
   if (threadIdx.x == 0 && st && cnt[N + 1] > 0) {
@@ -212,28 +240,21 @@ __global__ __launch_bounds__(kScanBlock) void k_csr_scan(int64_t N, int32_t* cnt
     st->failed = 1;
     st->stop = 1;
   }
-  __shared__ int32_t part[kScanBlock];
+  __shared__ int32_t wtot[kScanBlock / 64];
   const int tid = threadIdx.x;
   const int64_t per = (N + kScanBlock - 1) / kScanBlock;
   const int64_t a = tid * per, b = min<int64_t>(N, a + per);
   int32_t sum = 0;
   for (int64_t i = a; i < b; ++i) sum += cnt[i];
-  part[tid] = sum;
-  __syncthreads();
-  for (int off = 1; off < kScanBlock; off <<= 1) {
-    int32_t v = tid >= off ? part[tid - off] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  int32_t run = part[tid] - sum;
+  int32_t total;
+  int32_t run = block_exclusive_scan(sum, wtot, &total);
   for (int64_t i = a; i < b; ++i) {
     const int32_t c = cnt[i];
     seg[i] = run;
     cnt[i] = run;
     run += c;
   }
-  if (tid == kScanBlock - 1) seg[N] = part[tid];
+  if (tid == kScanBlock - 1) seg[N] = total;
 }
 
 // Count, scan and scatter in one workgroup with the counters in LDS, for
@@ -248,7 +269,7 @@ __global__ __launch_bounds__(kScanBlock) void k_csr_small(int64_t N, int64_t Q,
                                                           int32_t* __restrict__ perm,
                                                           SolveState* st) {
   __shared__ int32_t c[kCsrSmallN + 2];
-  __shared__ int32_t part[kScanBlock];
+  __shared__ int32_t wtot[kScanBlock / 64];
   const int tid = threadIdx.x;
   for (int64_t i = tid; i < N + 2; i += kScanBlock) c[i] = 0;
   __syncthreads();
@@ -266,22 +287,15 @@ __global__ __launch_bounds__(kScanBlock) void k_csr_small(int64_t N, int64_t Q,
   const int64_t a = tid * per, b = min<int64_t>(N, a + per);
   int32_t sum = 0;
   for (int64_t i = a; i < b; ++i) sum += c[i];
-  part[tid] = sum;
-  __syncthreads();
-  for (int off = 1; off < kScanBlock; off <<= 1) {
-    const int32_t v = tid >= off ? part[tid - off] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  int32_t run = part[tid] - sum;
+  int32_t total;
+  int32_t run = block_exclusive_scan(sum, wtot, &total);
   for (int64_t i = a; i < b; ++i) {
     const int32_t k = c[i];
     seg[i] = run;
     c[i] = run;
     run += k;
   }
-  if (tid == kScanBlock - 1) seg[N] = part[tid];
+  if (tid == kScanBlock - 1) seg[N] = total;
   __syncthreads();
   for (int64_t q = tid; q < Q; q += kScanBlock) {
     const int32_t v = nu[q];
