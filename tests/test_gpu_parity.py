@@ -339,6 +339,33 @@ def test_lu_tiles_repeatable(ctx):
                 assert torch.equal(A, first[0]) and torch.equal(perm, first[1]), (n, bf, rep)
 
 
+
+@pytest.mark.parametrize("n", [5120, 5184])
+def test_lu_tiles_row_handover_boundary(ctx, n):
+    """Single FP32 systems of up to 80 tile rows hand each diagonal task the
+    preceding row tile to solve itself; n = 5120 (80 tile rows) takes that
+    path, n = 5184 (81) the plain one.  Both factor P A = L U to FP32
+    accuracy, and repeated calls are bit-identical."""
+    rng = np.random.default_rng(n)
+    A0 = rng.normal(size=(n, n)) + 3 * np.sqrt(n) * np.eye(n)
+    lda = nrs.lda_for(n)
+    Ad = torch.zeros((n, lda), dtype=torch.float32)
+    Ad[:, :n] = torch.from_numpy(A0.T.copy()).to(torch.float32)
+    Ad = Ad.to(DEV)
+    outs = []
+    for rep in range(2):
+        A = Ad.clone()
+        ipiv = torch.empty(n, dtype=torch.int32, device=DEV)
+        perm = torch.empty(n, dtype=torch.int32, device=DEV)
+        sing = torch.zeros(1, dtype=torch.int32, device=DEV)
+        nrs.nrs_lu_factor(ctx, A, lda, ipiv, perm, sing, lu_ws(ctx, n, A), pivot_scope=1)
+        assert sing.item() == 0
+        outs.append((A.cpu(), perm.cpu()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    LU = outs[0][0].numpy().astype(np.float64)[:, :n].T
+    A0c = A0.astype(np.float32).astype(np.float64)
+    _lu_check(A0c, LU, outs[0][1].numpy(), 1, tol=3e-6)
+
 SOLVE_CASES = [
     ("sphere_c1", lambda: synth.sphere_scene(4, 16)),
     ("filaments_M1", lambda: synth.filament_scene(1, seed=0)),
