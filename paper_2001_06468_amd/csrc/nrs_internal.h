@@ -518,9 +518,6 @@ hipError_t launch_convert_f32(int64_t n, const double* a, float* b, hipStream_t 
 // and column then in [1, 2)); dr [n], dc [n] out; rmax [n] scratch.
 hipError_t launch_equilibrate(int64_t n, float* A, int64_t lda, float* dr, float* dc,
                               uint32_t* rmax, hipStream_t s);
-hipError_t launch_check_body(int64_t N, int32_t M, const int32_t* body, SolveState* st,
-                             hipStream_t s);
-hipError_t launch_state_accumulate(SolveState* total, const SolveState* stage, hipStream_t s);
 // a solve's status record and its two synchronisation-word arrays in one launch
 hipError_t launch_solve_begin(SolveState* st, int32_t method, int32_t* a, int64_t na, int32_t* b,
                               int64_t nb, hipStream_t s);
@@ -532,8 +529,6 @@ hipError_t launch_stage_end(SolveState* total, const SolveState* stage, int32_t 
 // time stepping
 hipError_t launch_rk_stage_state(int32_t M, const double* Y, const double* K, double a,
                                  double* Ys, hipStream_t s);
-hipError_t launch_rk_rates(int32_t M, int64_t N, const double* Ys, const double* sol, double* K,
-                           hipStream_t s);
 hipError_t launch_rk_combine(int32_t M, double* Y, const double* K1, const double* K2,
                              const double* K3, const double* K4, double dt, hipStream_t s);
 // Y + h sum_j c[j] K[j] (j < count <= 7), passed by value to the kernels

@@ -239,16 +239,6 @@ __global__ void k_convert(int64_t n, const double* __restrict__ a, T* __restrict
 
 
 // body[m] must lie in [-1, M): anything else is an argument error.
-__global__ void k_check_body(int64_t N, int32_t M, const int32_t* __restrict__ body,
-                             SolveState* st) {
-  const int64_t m = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (m < N && (body[m] < -1 || body[m] >= M)) {
-    st->nonfinite = 2;
-    st->failed = 1;
-    st->stop = 1;
-  }
-}
-
 // ---- time stepping ----
 
 __global__ void k_rk_stage_state(int32_t M, const double* __restrict__ Y,
@@ -417,22 +407,10 @@ hipError_t launch_equilibrate(int64_t n, float* A, int64_t lda, float* dr, float
 }
 
 
-hipError_t launch_check_body(int64_t N, int32_t M, const int32_t* body, SolveState* st,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(k_check_body, grid1(N, 256), dim3(256), 0, s, N, M, body, st);
-  return hipGetLastError();
-}
-
 hipError_t launch_rk_stage_state(int32_t M, const double* Y, const double* K, double a,
                                  double* Ys, hipStream_t s) {
   hipLaunchKernelGGL(k_rk_stage_state, grid1(12 * (int64_t)M, 256), dim3(256), 0, s, M, Y, K, a,
                      Ys);
-  return hipGetLastError();
-}
-
-hipError_t launch_rk_rates(int32_t M, int64_t N, const double* Ys, const double* sol, double* K,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_rk_rates, grid1(M, 64), dim3(64), 0, s, M, N, Ys, sol, K);
   return hipGetLastError();
 }
 
@@ -510,11 +488,6 @@ hipError_t launch_stage_end(SolveState* total, const SolveState* stage, int32_t 
     return hipGetLastError();
   }
   hipLaunchKernelGGL(k_stage_end, dim3(1), dim3(256), 0, s, total, stage, M, N, Ys, sol, K, Y, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_state_accumulate(SolveState* total, const SolveState* stage, hipStream_t s) {
-  hipLaunchKernelGGL(k_state_accumulate, dim3(1), dim3(64), 0, s, total, stage);
   return hipGetLastError();
 }
 
