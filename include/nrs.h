@@ -268,13 +268,15 @@ nrs_status nrs_workspace_size(nrs_ctx* ctx, int64_t N, int64_t Q, int32_t M,
  * blocks of the swimming problem (Sec. 2 and Sec. 4): columns -1 (U) and
  * -(e_i x r_m) (Omega), force rows W_m, moment rows W_m (r_m x .), zero
  * 6M x 6M block, r_m = x_m - x0.  A: device, n x lda elements of the chosen
- * precision.  Writes every entry of the leading n x n block. */
+ * precision.  Writes every entry of the leading n x n block.  Quadrature
+ * points whose nu is outside [0, N) contribute nothing (no error is
+ * reported; nrs_solve reports them as NRS_E_ARG). */
 nrs_status nrs_assemble(nrs_ctx* ctx, const nrs_problem* pb, int32_t precision,
                         void* A, int64_t lda, void* ws, size_t ws_bytes);
 
 /* Matrix-free FP64 product y = A v with A as in nrs_assemble (the NEAREST
  * operator of Sec. 3 eq. 23 evaluated on the fly plus the rigid-body rows).
- * v, y: [n] device. */
+ * v, y: [n] device.  Out-of-range nu as in nrs_assemble. */
 nrs_status nrs_apply(nrs_ctx* ctx, const nrs_problem* pb, const double* v, double* y,
                      void* ws, size_t ws_bytes);
 

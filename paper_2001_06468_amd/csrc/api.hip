@@ -750,8 +750,9 @@ nrs_status nrs_assemble(nrs_ctx* ctx, const nrs_problem* pb, int32_t precision, 
   if (!carve_solve(ar, pb->N, pb->Q, pb->M, precision == 32 ? NRS_FP32_IR : NRS_FP64_LU, sb))
     return fail(ctx, NRS_E_WORKSPACE, "workspace too small");
   hipStream_t s = ctx->stream;
-  NRS_HIP(ctx, launch_state_init(sb.st, NRS_FP64_LU, s));
-  NRS_HIP(ctx, launch_build_csr(pb->N, pb->Q, pb->X, pb->w, pb->nu, sb.srt, sb.st, s));
+  // no status record: the call reports nothing from the device, and
+  // quadrature points whose nu is out of range are left out of the layout
+  NRS_HIP(ctx, launch_build_csr(pb->N, pb->Q, pb->X, pb->w, pb->nu, sb.srt, nullptr, s));
   if (precision == 32)
     NRS_HIP(ctx, launch_assemble<float>(*pb, sb.srt, static_cast<float*>(A), lda, s,
                                         asm_shape_for(ctx, pb->N, pb->Q, 32)));
@@ -772,8 +773,7 @@ nrs_status nrs_apply(nrs_ctx* ctx, const nrs_problem* pb, const double* v, doubl
   if (!carve_solve(ar, pb->N, pb->Q, pb->M, NRS_FP64_LU, sb))
     return fail(ctx, NRS_E_WORKSPACE, "workspace too small");
   hipStream_t s = ctx->stream;
-  NRS_HIP(ctx, launch_state_init(sb.st, NRS_FP64_LU, s));
-  NRS_HIP(ctx, launch_build_csr(pb->N, pb->Q, pb->X, pb->w, pb->nu, sb.srt, sb.st, s));
+  NRS_HIP(ctx, launch_build_csr(pb->N, pb->Q, pb->X, pb->w, pb->nu, sb.srt, nullptr, s));
   NRS_HIP(ctx, launch_apply(*pb, sb.srt, v, y, sb.part, sb.chunks, nullptr, s));
   return NRS_OK;
 }
