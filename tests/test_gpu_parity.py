@@ -125,6 +125,34 @@ def test_apply_fp64(ctx, name, scene):
     assert np.max(np.abs(y.cpu().numpy() - ref)) <= 1e-13 * scale
 
 
+def test_assemble_and_apply_skip_out_of_range_nu(ctx):
+    """Quadrature points whose nu is outside [0, N) contribute nothing: the
+    FP64 assembly and the matrix-free product equal the oracle's system of
+    the same scene with those points removed."""
+    name, scene = SCENES[0]
+    pb, host = prepare(scene, 0.3)
+    N, Q = scene["N"], scene["Q"]
+    nu = host["nu"].copy()
+    bad = np.array([0, Q // 3, Q - 1])
+    nu[bad] = [-1, N, N + 7]
+    keep = np.setdiff1d(np.arange(Q), bad)
+    trimmed = dict(host, X=host["X"][:, keep], w=host["w"][keep], nu=host["nu"][keep])
+    A_ref, _ = oracle_system(scene, trimmed)
+    pbad = nrs.Problem(T(host["x"]), T(host["X"]), T(host["w"]), T(nu, torch.int32),
+                       T(scene["body"], torch.int32), T(host["Y"]) if scene["M"] else None,
+                       scene["eps"], scene["mu"])
+    n = pb.n
+    lda = nrs.lda_for(n)
+    A = torch.full((n, lda), float("nan"), dtype=torch.float64, device=DEV)
+    nrs.nrs_assemble(ctx, pbad, 64, A, lda, workspace(ctx, pbad, nrs.NRS_FP64_LU))
+    G = A.cpu().numpy()[:, :n].T
+    assert np.max(np.abs(G - A_ref)) <= 1e-13 * np.max(np.abs(A_ref))
+    v = np.random.default_rng(5).normal(size=n)
+    y = torch.empty(n, dtype=torch.float64, device=DEV)
+    nrs.nrs_apply(ctx, pbad, T(v), y, workspace(ctx, pbad, nrs.NRS_FP64_LU))
+    assert np.max(np.abs(y.cpu().numpy() - A_ref @ v)) <= 1e-13 * np.max(np.abs(A_ref) @ np.abs(v))
+
+
 def _lu_check(A0, LU, perm, scope, nb=64, tol=1e-12):
     """scope 0: A0[perm] = L U.  scope 1 (static block pivoting): A0 = Lt U,
     where Lt is L with the rows of each diagonal tile L_mm put back at their
